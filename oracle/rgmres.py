@@ -1,0 +1,346 @@
+"""Oracle: plain, slow FP64 CPU reference for restarted GMRES(m) with an SVD recycle space.
+
+TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+benchmark's CPU-baseline leg may import this module.  The GPU library never
+imports, calls or links it, and it shares no code with the GPU library.
+
+Method (Pitton & Heltai, "Accelerating the iterative solution of
+convection-diffusion problems using singular value decomposition"):
+
+* Krylov projection template and GMRES as the minimal-residual choice of the
+  constraint space (section 3, the search-space template and the paragraph
+  that picks C_k = A S_k for GMRES).
+* Recycle basis W (the paper's V_s, n x k, orthonormal columns), with
+  E = W^T A W (section 3.2, the definition of E_s) and the oblique projector
+  P = I - A W E^{-1} W^T (section 3.2, eq. (left_deflation), and the second
+  projector choice in section 3.3).
+* Initial guess by Galerkin projection onto span(W): x0 = W E^{-1} W^T b
+  (section 4.2, eqs. (projection_guess), (projection_t_s)); generalised here
+  to a caller-supplied x0 as x0 + W E^{-1} W^T (b - A x0).
+* Krylov operator P A and initial vector r0 = P r0 (Table 1, rows
+  "augmented oblique" and "deflated oblique"; with the projected guess the two
+  rows start from the same vector, eq. (equivalence_oblique)).
+* Recycle space = leading left singular vectors of the last s solutions,
+  recomputed every ell solves (section 5.2, Algorithm 1, eqs. (best_rank_s),
+  (opt_svd)).
+
+Readings where the paper is silent (each also listed in the design notes):
+* right Jacobi preconditioning D^{-1} (operator P A D^{-1}, x = x0 + D^{-1} V y),
+  so the GMRES residual is the true deflated residual;
+* Arnoldi orthogonalisation is classical Gram-Schmidt applied twice (CGS2);
+* every cycle ends with the correction x += W E^{-1} W^T r, r <- P r, so the
+  explicit stop test ||b - A x|| <= tol ||b|| applies to the true residual
+  (the stopping rule of section 6.1);
+* E is factorised with partial pivoting; if its 1-norm condition number
+  exceeds 1e13 recycling is dropped for that solve (section 5.2 notes E may
+  be singular and takes no measure);
+* the snapshot ring holds the s most recent solutions; the numerical rank
+  uses sigma_i > sigma_1 * max(n, c) * eps64 and k_eff = min(k, rank).
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import List, Optional
+
+import numpy as np
+import scipy.linalg
+
+PLAIN, AUG_OBLIQUE, DEFL_OBLIQUE = 0, 1, 2
+PRECOND_NONE, PRECOND_JACOBI = 0, 1
+
+FLAG_RECYCLE_DROPPED = 1
+FLAG_BREAKDOWN_LUCKY = 2
+FLAG_NONFINITE = 4
+
+EPS64 = np.finfo(np.float64).eps
+E_COND_MAX = 1e13
+LUCKY_REL = 1e-14
+
+
+@dataclasses.dataclass
+class Config:
+    restart_m: int = 30
+    recycle_k: int = 0
+    snapshots_s: int = 0
+    svd_interval: int = 1
+    method: int = AUG_OBLIQUE
+    precond: int = PRECOND_NONE
+    max_iters: int = 10000
+    select_smallest: bool = False
+
+
+@dataclasses.dataclass
+class Result:
+    x: np.ndarray
+    iterations: int
+    cycles: int
+    k_eff: int
+    converged: bool
+    flags: int
+    rel_res_true: float
+    res_history: List[float]        # explicit ||r||/||b|| at the end of every cycle
+    implicit_history: List[float]   # |g_{j+1}|/||b|| after every Arnoldi step
+
+
+# ---------------------------------------------------------------------------
+# Building blocks
+# ---------------------------------------------------------------------------
+
+
+def jacobi_inverse(A) -> np.ndarray:
+    """1 / diag(A): the diagonal (Jacobi) preconditioner, applied on the right."""
+    d = A.diagonal().astype(np.float64)
+    return 1.0 / d
+
+
+def recycle_setup(A, W: np.ndarray):
+    """Z = A W and E = W^T A W (section 3.2, E_s = V_s^T A V_s).
+
+    Returns (Z, E, cond1) with cond1 the 1-norm condition number of E.
+    Z is formed one column at a time with the sparse matvec.
+    """
+    k = W.shape[1]
+    Z = np.empty_like(W)
+    for i in range(k):
+        Z[:, i] = A @ W[:, i]
+    E = W.T @ Z
+    cond1 = float(np.linalg.cond(E, 1)) if k > 0 else 1.0
+    return Z, E, cond1
+
+
+def oblique_project(W, Z, E, v):
+    """P v = v - A W E^{-1} W^T v  (section 3.2, the deflation projector M_D)."""
+    return v - Z @ np.linalg.solve(E, W.T @ v)
+
+
+def projection_correction(W, Z, E, x, r):
+    """x <- x + W E^{-1} W^T r, r <- r - A W E^{-1} W^T r  (section 4.2, eq. (projection_t_s)).
+
+    With x = 0, r = b this is exactly the Galerkin projection guess of the
+    paper; applied to a later residual it solves for the span(W) component.
+    """
+    c = np.linalg.solve(E, W.T @ r)
+    return x + W @ c, r - Z @ c
+
+
+def krylov_update(x, dinv, V, y):
+    """x <- x + D^{-1} V y: the Krylov correction of one cycle mapped back through the
+    right preconditioner (section 3, right preconditioning A M y = b, x = M^{-1} y)."""
+    return x + dinv * (V @ y)
+
+
+def givens(a: float, b: float):
+    """Rotation (c, s) with [c s; -s c] [a; b] = [rho; 0], rho = hypot(a, b)."""
+    rho = float(np.hypot(a, b))
+    if rho == 0.0:
+        return 1.0, 0.0, 0.0
+    return a / rho, b / rho, rho
+
+
+@dataclasses.dataclass
+class Cycle:
+    """Result of one GMRES cycle: basis V (n x (j+1)), Hessenberg H ((j+1) x j),
+    triangularised R, rotated rhs g, steps taken j, flags."""
+    V: np.ndarray
+    H: np.ndarray
+    R: np.ndarray
+    g: np.ndarray
+    steps: int
+    lucky: bool
+    implicit: List[float]
+
+
+def arnoldi_cycle(op, r0: np.ndarray, m: int, stop_abs: float, max_steps: int) -> Cycle:
+    """One restart cycle of GMRES on the operator `op` starting from r0.
+
+    Arnoldi with classical Gram-Schmidt applied twice, Hessenberg least
+    squares by Givens rotations (section 3: minimal residual over the Krylov
+    space K_j(op, r0)).  Stops after m steps, when the rotated residual
+    |g_{j+1}| <= stop_abs, on a lucky breakdown, or after max_steps steps.
+    """
+    n = r0.size
+    beta = float(np.linalg.norm(r0))
+    V = np.zeros((n, m + 1))
+    H = np.zeros((m + 1, m))
+    R = np.zeros((m + 1, m))
+    cs = np.zeros(m)
+    sn = np.zeros(m)
+    g = np.zeros(m + 1)
+    g[0] = beta
+    V[:, 0] = r0 / beta
+    implicit = []
+    j = 0
+    lucky = False
+    while j < m and j < max_steps:
+        w = op(V[:, j])
+        h1 = V[:, : j + 1].T @ w
+        w = w - V[:, : j + 1] @ h1
+        h2 = V[:, : j + 1].T @ w
+        w = w - V[:, : j + 1] @ h2
+        hcol = np.zeros(j + 2)
+        hcol[: j + 1] = h1 + h2
+        hcol[j + 1] = np.linalg.norm(w)
+        H[: j + 2, j] = hcol
+        colnorm = float(np.linalg.norm(hcol))
+        rcol = hcol.copy()
+        for i in range(j):
+            t = cs[i] * rcol[i] + sn[i] * rcol[i + 1]
+            rcol[i + 1] = -sn[i] * rcol[i] + cs[i] * rcol[i + 1]
+            rcol[i] = t
+        c, s, rho = givens(rcol[j], rcol[j + 1])
+        cs[j], sn[j] = c, s
+        rcol[j] = rho
+        rcol[j + 1] = 0.0
+        R[: j + 2, j] = rcol
+        g[j + 1] = -s * g[j]
+        g[j] = c * g[j]
+        implicit.append(abs(g[j + 1]))
+        steps = j + 1
+        if hcol[j + 1] <= LUCKY_REL * colnorm:
+            lucky = True
+            j = steps
+            break
+        V[:, j + 1] = w / hcol[j + 1]
+        j = steps
+        if abs(g[j]) <= stop_abs or steps >= max_steps:
+            break
+    return Cycle(V[:, : j + 1], H[: j + 1, :j], R[: j + 1, :j], g[: j + 1], j, lucky, implicit)
+
+
+# ---------------------------------------------------------------------------
+# One solve
+# ---------------------------------------------------------------------------
+
+
+def solve(A, b: np.ndarray, x0: Optional[np.ndarray], tol: float, cfg: Config,
+          W: Optional[np.ndarray] = None) -> Result:
+    """Solve A x = b to ||b - A x||_2 <= tol ||b||_2 with recycled GMRES(m).
+
+    A: scipy CSR matrix (used only for A @ v and its diagonal).  W: recycle
+    basis (n x k_eff, orthonormal columns) or None.
+    """
+    b = np.asarray(b, dtype=np.float64)
+    n = b.size
+    bnorm = float(np.linalg.norm(b))
+    if not np.isfinite(bnorm):
+        return Result(np.full(n, np.nan), 0, 0, 0, False, FLAG_NONFINITE, float("nan"), [], [])
+    if bnorm == 0.0:
+        return Result(np.zeros(n), 0, 0, 0, True, 0, 0.0, [0.0], [])
+    flags = 0
+    dinv = jacobi_inverse(A) if cfg.precond == PRECOND_JACOBI else np.ones(n)
+    use_w = cfg.method != PLAIN and W is not None and W.shape[1] > 0
+    Z = E = None
+    k_eff = 0
+    if use_w:
+        Z, E, cond1 = recycle_setup(A, W)
+        if not np.isfinite(cond1) or cond1 > E_COND_MAX:
+            flags |= FLAG_RECYCLE_DROPPED
+            use_w = False
+        else:
+            k_eff = W.shape[1]
+    x = np.zeros(n) if x0 is None else np.array(x0, dtype=np.float64)
+    r = b - A @ x
+    if use_w:
+        x, r = projection_correction(W, Z, E, x, r)
+
+    def op(v):
+        w = A @ (dinv * v)
+        if use_w:
+            w = oblique_project(W, Z, E, w)
+        return w
+
+    stop_abs = tol * bnorm
+    its = 0
+    cycles = 0
+    hist: List[float] = []
+    implicit: List[float] = []
+    rnorm = float(np.linalg.norm(r))
+    if not np.isfinite(rnorm):
+        return Result(x, 0, 0, k_eff, False, flags | FLAG_NONFINITE, float("nan"), [], [])
+    while True:
+        if rnorm <= stop_abs:
+            return Result(x, its, cycles, k_eff, True, flags, rnorm / bnorm, hist, implicit)
+        if its >= cfg.max_iters:
+            return Result(x, its, cycles, k_eff, False, flags, rnorm / bnorm, hist, implicit)
+        cyc = arnoldi_cycle(op, r, cfg.restart_m, stop_abs, cfg.max_iters - its)
+        cycles += 1
+        its += cyc.steps
+        implicit += [v / bnorm for v in cyc.implicit]
+        if cyc.lucky:
+            flags |= FLAG_BREAKDOWN_LUCKY
+        j = cyc.steps
+        y = scipy.linalg.solve_triangular(cyc.R[:j, :j], cyc.g[:j], lower=False)
+        x = krylov_update(x, dinv, cyc.V[:, :j], y)
+        r = b - A @ x
+        if use_w:
+            x, r = projection_correction(W, Z, E, x, r)
+        rnorm = float(np.linalg.norm(r))
+        hist.append(rnorm / bnorm)
+        if not np.isfinite(rnorm):
+            return Result(x, its, cycles, k_eff, False, flags | FLAG_NONFINITE, float("nan"), hist, implicit)
+
+
+# ---------------------------------------------------------------------------
+# Recycle-space update (Algorithm 1)
+# ---------------------------------------------------------------------------
+
+
+def svd_basis(X: np.ndarray, k: int, smallest: bool = False):
+    """Leading (or trailing) left singular vectors of the snapshot matrix X.
+
+    Returns (W, sigma, rank): W has k_eff = min(k, rank) orthonormal columns,
+    rank = #{sigma_i > sigma_1 * max(n, c) * eps64} (no direction below the
+    numerical rank is ever kept).  Section 5.2, eqs. (best_rank_s), (opt_svd).
+    """
+    n, c = X.shape
+    if c == 0:
+        return np.zeros((n, 0)), np.zeros(0), 0
+    U, sig, _ = np.linalg.svd(X, full_matrices=False)
+    if sig[0] == 0.0 or not np.isfinite(sig[0]):
+        return np.zeros((n, 0)), sig, 0
+    rank = int(np.sum(sig > sig[0] * max(n, c) * EPS64))
+    k_eff = min(k, rank)
+    if smallest:
+        return U[:, rank - k_eff: rank].copy(), sig, rank
+    return U[:, :k_eff].copy(), sig, rank
+
+
+class RecycleState:
+    """Snapshot ring and recycle basis of one sequence (section 5.2, Algorithm 1)."""
+
+    def __init__(self, n: int, cfg: Config):
+        self.n = n
+        self.cfg = cfg
+        self.ring: List[np.ndarray] = []
+        self.count = 0
+        self.W = np.zeros((n, 0))
+        self.sigma = np.zeros(0)
+        self.rank = 0
+
+    def update(self, x: np.ndarray):
+        """Store x among the s most recent solutions; every ell solves recompute W."""
+        s = self.cfg.snapshots_s
+        if s <= 0 or self.cfg.recycle_k <= 0:
+            self.count += 1
+            return
+        self.ring.append(np.array(x, dtype=np.float64))
+        if len(self.ring) > s:
+            self.ring.pop(0)
+        self.count += 1
+        if self.count % max(1, self.cfg.svd_interval) == 0:
+            X = np.stack(self.ring, axis=1)
+            self.W, self.sigma, self.rank = svd_basis(X, self.cfg.recycle_k, self.cfg.select_smallest)
+
+
+def run_sequence(A_list, b_list, tol: float, cfg: Config, x_init=None):
+    """Solve a sequence with x0 = previous solution, updating the recycle space after each solve."""
+    n = b_list[0].size
+    st = RecycleState(n, cfg)
+    x_prev = np.zeros(n) if x_init is None else x_init
+    results = []
+    for A, b in zip(A_list, b_list):
+        res = solve(A, b, x_prev, tol, cfg, st.W)
+        results.append(res)
+        st.update(res.x)
+        x_prev = res.x
+    return results, st

@@ -1,0 +1,386 @@
+"""Seeded synthetic workload: sequences of convection-diffusion systems A_i x = b_i.
+
+This module is the input generator shared by the tests, the benchmark and the
+GPU solver's callers.  It holds finite-element assembly only, none of the
+solver's arithmetic (no Krylov method, projector or SVD lives here).
+
+What it builds (paper, section 2, eq. (def_Axb), and section 6.1): a scalar
+equation u_t + div(0.5 u^2 beta) - eps Lap(u) = 0 on the unit square with a
+solenoidal field beta, so the convection term is u beta.grad(u).  Time is
+advanced by backward Euler and the non-linear term is linearised by lagging
+its coefficient (Picard): step i solves
+
+    (v, u^i)/dt + eps (grad v, grad u^i) + (v, u^{i-1} beta.grad u^i) = (v, u^{i-1})/dt
+
+so every step yields one non-symmetric sparse system whose matrix and
+right-hand side depend on the previous solution (section 2, the closing
+paragraph of the problem definition).
+
+Discretisation: continuous Q_p Lagrange elements (p = 1, 2, 3) on a uniform
+N x N quad mesh, equispaced support points, Gauss-Legendre quadrature with
+p + 2 points per direction, consistent mass.  Global nodes are numbered
+lexicographically, index = J * (N p + 1) + I with I along x.  Homogeneous
+Dirichlet data: boundary rows become identity rows, boundary columns are
+dropped from interior rows, boundary right-hand-side entries are zero.
+
+Matrices are CSR with int32 row pointers / column indices, sorted columns,
+no duplicates and an explicit diagonal in every row.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Callable, Optional
+
+import numpy as np
+
+# ---------------------------------------------------------------------------
+# Problem descriptions
+# ---------------------------------------------------------------------------
+
+
+@dataclasses.dataclass(frozen=True)
+class Problem:
+    """One PDE / mesh / time-step setting.
+
+    beta: 'const' uses beta_const everywhere; 'rotating' uses
+    beta = 2 pi (-(y - 1/2), x - 1/2) (a rigid rotation about the centre).
+    """
+
+    p: int
+    N: int
+    eps: float
+    dt: float
+    beta: str = "const"
+    beta_const: tuple = (1.0, 0.5)
+
+    @property
+    def n1(self) -> int:
+        return self.N * self.p + 1
+
+    @property
+    def n(self) -> int:
+        return self.n1 * self.n1
+
+
+# Shapes and parameters of the five workload families (sizes as in the
+# synthetic configurations this library is measured on).
+C1 = Problem(p=1, N=32, eps=1e-2, dt=1e-2, beta="const")
+C2 = Problem(p=2, N=256, eps=1e-3, dt=5e-3, beta="const")
+C3 = Problem(p=3, N=512, eps=1e-4, dt=5e-3, beta="rotating")
+
+# Reduced shapes of the same families, small enough for the CPU oracle.
+C2_SMALL = Problem(p=2, N=32, eps=1e-3, dt=5e-3, beta="const")
+C3_SMALL = Problem(p=3, N=16, eps=1e-4, dt=5e-3, beta="rotating")
+
+
+# ---------------------------------------------------------------------------
+# 1-D Lagrange basis and quadrature
+# ---------------------------------------------------------------------------
+
+
+def lagrange_1d(p: int, x: np.ndarray):
+    """Values and derivatives of the p+1 equispaced Lagrange polynomials on [0, 1].
+
+    Returns (V, D) with V[q, a] = phi_a(x_q), D[q, a] = phi_a'(x_q).
+    """
+    nodes = np.linspace(0.0, 1.0, p + 1)
+    x = np.asarray(x, dtype=np.float64)
+    V = np.ones((x.size, p + 1))
+    D = np.zeros((x.size, p + 1))
+    for a in range(p + 1):
+        den = 1.0
+        for b in range(p + 1):
+            if b != a:
+                den *= nodes[a] - nodes[b]
+        for b in range(p + 1):
+            if b != a:
+                V[:, a] *= x - nodes[b]
+        # derivative: sum over the dropped factor
+        for c in range(p + 1):
+            if c == a:
+                continue
+            term = np.ones_like(x)
+            for b in range(p + 1):
+                if b != a and b != c:
+                    term *= x - nodes[b]
+            D[:, a] += term
+        V[:, a] /= den
+        D[:, a] /= den
+    return V, D
+
+
+def gauss_01(nq: int):
+    """Gauss-Legendre points and weights mapped to [0, 1]."""
+    xg, wg = np.polynomial.legendre.leggauss(nq)
+    return 0.5 * (xg + 1.0), 0.5 * wg
+
+
+@dataclasses.dataclass
+class ElementTables:
+    """Reference-element tables for Q_p on the unit square.
+
+    Local node i = b * (p+1) + a (a along x); quadrature point q = qy * nq1 + qx.
+    """
+
+    p: int
+    nl: int
+    nq: int
+    xi: np.ndarray      # (nq,) reference x of each quadrature point
+    eta: np.ndarray     # (nq,) reference y
+    w: np.ndarray       # (nq,) weights (sum 1)
+    phi: np.ndarray     # (nq, nl)
+    dxi: np.ndarray     # (nq, nl) d/dxi
+    deta: np.ndarray    # (nq, nl) d/deta
+    mass_ref: np.ndarray    # (nl, nl) integral phi_i phi_j on the unit square
+    stiff_ref: np.ndarray   # (nl, nl) integral grad phi_i . grad phi_j
+
+
+def element_tables(p: int) -> ElementTables:
+    nq1 = p + 2
+    xq, wq = gauss_01(nq1)
+    V, D = lagrange_1d(p, xq)
+    nl = (p + 1) ** 2
+    nq = nq1 * nq1
+    qx = np.tile(np.arange(nq1), nq1)
+    qy = np.repeat(np.arange(nq1), nq1)
+    la = np.tile(np.arange(p + 1), p + 1)
+    lb = np.repeat(np.arange(p + 1), p + 1)
+    phi = V[qx][:, la] * V[qy][:, lb]
+    dxi = D[qx][:, la] * V[qy][:, lb]
+    deta = V[qx][:, la] * D[qy][:, lb]
+    w = wq[qx] * wq[qy]
+    mass_ref = (phi * w[:, None]).T @ phi
+    stiff_ref = (dxi * w[:, None]).T @ dxi + (deta * w[:, None]).T @ deta
+    return ElementTables(p, nl, nq, xq[qx], xq[qy], w, phi, dxi, deta, mass_ref, stiff_ref)
+
+
+# ---------------------------------------------------------------------------
+# Sparsity pattern (tensor product of 1-D element connectivity)
+# ---------------------------------------------------------------------------
+
+
+@dataclasses.dataclass
+class Pattern:
+    problem: Problem
+    n: int
+    nnz: int
+    row_ptr: np.ndarray   # int32 (n+1,)
+    col_idx: np.ndarray   # int32 (nnz,)
+    boundary: np.ndarray  # bool (n,)
+    diag_pos: np.ndarray  # int64 (n,) CSR index of each diagonal entry
+    emap: np.ndarray      # int64 (E, nl*nl): CSR index of each element-matrix entry, -1 if dropped
+    elem_nodes: np.ndarray  # int64 (E, nl) global node of each local node
+    elem_origin: np.ndarray  # (E, 2) lower-left corner (x, y) of each element
+
+    def rows(self) -> np.ndarray:
+        """Row index of every stored entry (int64, nnz)."""
+        return np.repeat(np.arange(self.n, dtype=np.int64), np.diff(self.row_ptr.astype(np.int64)))
+
+
+def _range_1d(p: int, N: int):
+    """For each 1-D node, the contiguous range [lo, hi] of nodes sharing an element."""
+    n1 = N * p + 1
+    I = np.arange(n1)
+    e = I // p
+    vertex = (I % p) == 0
+    lo = np.where(vertex, np.maximum(I - p, 0), e * p)
+    hi = np.where(vertex, np.minimum(I + p, n1 - 1), (e + 1) * p)
+    return lo.astype(np.int64), hi.astype(np.int64)
+
+
+def build_pattern(prob: Problem) -> Pattern:
+    p, N = prob.p, prob.N
+    n1 = prob.n1
+    n = n1 * n1
+    lo, hi = _range_1d(p, N)
+    len1 = hi - lo + 1
+    # full (no Dirichlet elimination) pattern: row (I, J) couples to I' in [lo(I), hi(I)], J' in [lo(J), hi(J)]
+    Jg, Ig = np.divmod(np.arange(n, dtype=np.int64), n1)
+    rowlen_full = len1[Ig] * len1[Jg]
+    rp_full = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(rowlen_full, out=rp_full[1:])
+    nnz_full = int(rp_full[-1])
+    rows = np.repeat(np.arange(n, dtype=np.int64), rowlen_full)
+    off = np.arange(nnz_full, dtype=np.int64) - rp_full[rows]
+    Ir, Jr = Ig[rows], Jg[rows]
+    L = len1[Ir]
+    cI = lo[Ir] + off % L
+    cJ = lo[Jr] + off // L
+    del off, L
+    cols = cJ * n1 + cI
+    boundary1 = np.zeros(n1, dtype=bool)
+    boundary1[0] = boundary1[-1] = True
+    bnd = (boundary1[Ig] | boundary1[Jg])
+    keep = np.where(bnd[rows], cols == rows, ~(boundary1[cI] | boundary1[cJ]))
+    del cI, cJ, Ir, Jr
+    newidx = np.cumsum(keep, dtype=np.int64) - 1
+    newidx[~keep] = -1
+    col_idx = cols[keep].astype(np.int32)
+    rowlen = np.bincount(rows[keep], minlength=n)
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(rowlen, out=row_ptr[1:])
+    nnz = int(row_ptr[-1])
+    # diagonal positions
+    diag_full = rp_full[:-1] + (Jg - lo[Jg]) * len1[Ig] + (Ig - lo[Ig])
+    diag_pos = newidx[diag_full]
+    assert np.all(diag_pos >= 0)
+    # element -> CSR map
+    ex, ey = np.meshgrid(np.arange(N), np.arange(N))
+    ex = ex.ravel().astype(np.int64)
+    ey = ey.ravel().astype(np.int64)
+    la = np.tile(np.arange(p + 1), p + 1)
+    lb = np.repeat(np.arange(p + 1), p + 1)
+    Iloc = ex[:, None] * p + la[None, :]       # (E, nl)
+    Jloc = ey[:, None] * p + lb[None, :]
+    elem_nodes = Jloc * n1 + Iloc
+    nl = (p + 1) ** 2
+    # entry (i, j): row node (Iloc[i], Jloc[i]), col node (Iloc[j], Jloc[j])
+    Ri, Rj = Iloc[:, :, None], Jloc[:, :, None]
+    Ci, Cj = Iloc[:, None, :], Jloc[:, None, :]
+    full_pos = rp_full[Rj * n1 + Ri] + (Cj - lo[Rj]) * len1[Ri] + (Ci - lo[Ri])
+    emap = newidx[full_pos].reshape(N * N, nl * nl)
+    h = 1.0 / N
+    origin = np.stack([ex * h, ey * h], axis=1)
+    return Pattern(prob, n, nnz, row_ptr.astype(np.int32), col_idx, bnd, diag_pos,
+                   emap, elem_nodes, origin)
+
+
+# ---------------------------------------------------------------------------
+# Assembly
+# ---------------------------------------------------------------------------
+
+
+class Assembler:
+    """Assembles A(u_prev) and b(u_prev) for one Problem on one Pattern."""
+
+    def __init__(self, prob: Problem, pattern: Optional[Pattern] = None):
+        self.prob = prob
+        self.pat = pattern if pattern is not None else build_pattern(prob)
+        self.tab = element_tables(prob.p)
+        h = 1.0 / prob.N
+        self.h = h
+        t = self.tab
+        mass_e = (h * h) * t.mass_ref
+        # static element matrix: M/dt + eps K  (the same on every element of a uniform mesh)
+        self.static_e = (mass_e / prob.dt + prob.eps * t.stiff_ref).ravel()
+        self.mass_e = mass_e.ravel()
+        # B_x[q, i*nl + j] = phi_i(q) dphi_j/dxi(q)
+        nl = t.nl
+        self.Bx = (t.phi[:, :, None] * t.dxi[:, None, :]).reshape(t.nq, nl * nl)
+        self.By = (t.phi[:, :, None] * t.deta[:, None, :]).reshape(t.nq, nl * nl)
+        pat = self.pat
+        keep = pat.emap >= 0
+        self._keep = keep
+        self._map = pat.emap[keep]
+        self._mass_vals = None
+
+    def _beta_at_quad(self):
+        """beta_x, beta_y at every (element, quadrature point)."""
+        t, prob = self.tab, self.prob
+        if prob.beta == "const":
+            bx, by = prob.beta_const
+            return float(bx), float(by)
+        if prob.beta == "rotating":
+            org = self.pat.elem_origin
+            x = org[:, 0:1] + self.h * t.xi[None, :]
+            y = org[:, 1:2] + self.h * t.eta[None, :]
+            return -2.0 * math.pi * (y - 0.5), 2.0 * math.pi * (x - 0.5)
+        raise ValueError(prob.beta)
+
+    def element_values(self, u_prev: np.ndarray) -> np.ndarray:
+        """(E, nl*nl) element matrices of A(u_prev)."""
+        t = self.tab
+        U = u_prev[self.pat.elem_nodes]            # (E, nl)
+        Uq = U @ t.phi.T                           # (E, nq)
+        bx, by = self._beta_at_quad()
+        scale = self.h * t.w[None, :] * Uq         # dx = h^2 dxi, grad = grad_ref / h
+        ax = scale * bx
+        ay = scale * by
+        vals = ax @ self.Bx
+        vals += ay @ self.By
+        vals += self.static_e[None, :]
+        return vals
+
+    def matrix_values(self, u_prev: np.ndarray) -> np.ndarray:
+        """CSR values of A(u_prev) (float64, nnz)."""
+        ev = self.element_values(u_prev)
+        vals = np.bincount(self._map, weights=ev[self._keep], minlength=self.pat.nnz)
+        pat = self.pat
+        bdiag = pat.diag_pos[pat.boundary]
+        vals[bdiag] = 1.0
+        return vals
+
+    def mass_values(self) -> np.ndarray:
+        """CSR values of the (Dirichlet-eliminated) consistent mass matrix; boundary rows zero."""
+        if self._mass_vals is None:
+            E = self.pat.emap.shape[0]
+            ev = np.broadcast_to(self.mass_e[None, :], (E, self.mass_e.size))
+            vals = np.bincount(self._map, weights=ev[self._keep], minlength=self.pat.nnz)
+            vals[self.pat.diag_pos[self.pat.boundary]] = 0.0
+            self._mass_vals = vals
+        return self._mass_vals
+
+    def rhs(self, u_prev: np.ndarray) -> np.ndarray:
+        """b(u_prev) = M u_prev / dt on interior rows, 0 on the boundary."""
+        import scipy.sparse as sp
+        pat = self.pat
+        M = sp.csr_matrix((self.mass_values(), pat.col_idx, pat.row_ptr), shape=(pat.n, pat.n))
+        b = (M @ u_prev) / self.prob.dt
+        b[pat.boundary] = 0.0
+        return b
+
+    def csr(self, vals: np.ndarray):
+        import scipy.sparse as sp
+        pat = self.pat
+        return sp.csr_matrix((vals, pat.col_idx, pat.row_ptr), shape=(pat.n, pat.n))
+
+    def system(self, u_prev: np.ndarray):
+        """(vals, b) of step i given u^{i-1}."""
+        return self.matrix_values(u_prev), self.rhs(u_prev)
+
+
+def initial_condition(prob: Problem, seed: int, pattern: Optional[Pattern] = None) -> np.ndarray:
+    """Gaussian bump of amplitude 1 and width 0.1, centre ~ U[0.25, 0.75]^2, zero on the boundary."""
+    rng = np.random.default_rng(seed)
+    c = rng.uniform(0.25, 0.75, size=2)
+    n1 = prob.n1
+    xs = np.linspace(0.0, 1.0, n1)
+    X, Y = np.meshgrid(xs, xs)          # Y rows -> J, X cols -> I: ravel gives J*n1+I
+    u = np.exp(-((X - c[0]) ** 2 + (Y - c[1]) ** 2) / (2 * 0.1 ** 2)).ravel()
+    bnd = np.zeros((n1, n1), dtype=bool)
+    bnd[0, :] = bnd[-1, :] = bnd[:, 0] = bnd[:, -1] = True
+    u[bnd.ravel()] = 0.0
+    return u
+
+
+def direct_solver(asm: Assembler):
+    """Sparse direct solve (SuperLU) used only to advance the generator's own trajectory."""
+    import scipy.sparse.linalg as spla
+
+    def solve(vals, b):
+        return spla.spsolve(asm.csr(vals).tocsc(), b)
+
+    return solve
+
+
+def march(prob: Problem, steps: int, seed: int,
+          advance: Optional[Callable[[np.ndarray, np.ndarray], np.ndarray]] = None,
+          asm: Optional[Assembler] = None):
+    """Generate `steps` systems along a trajectory.
+
+    The trajectory u^0, u^1, ... is advanced with `advance(vals, b) -> u`
+    (default: a sparse direct solve), so the systems are the same whichever
+    iterative solver is later run on them.  Returns (asm, list of (vals, b),
+    list of trajectory states u^1..u^steps).
+    """
+    asm = asm if asm is not None else Assembler(prob)
+    adv = advance if advance is not None else direct_solver(asm)
+    u = initial_condition(prob, seed, asm.pat)
+    systems, states = [], []
+    for _ in range(steps):
+        vals, b = asm.system(u)
+        systems.append((vals, b))
+        u = adv(vals, b)
+        states.append(u)
+    return asm, systems, states

@@ -1,0 +1,354 @@
+"""Pins for the FP64 oracle: each check ties it to the paper or to mathematics,
+never to itself (dense direct solves, brute-force minimal residuals over an
+explicit Krylov basis, exact algebraic identities, closed-form special cases,
+and library SVD properties).  CPU only."""
+import numpy as np
+import pytest
+import scipy.linalg
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from oracle import rgmres as O
+from paper_1807_09467_amd import workload as WL
+
+
+def rand_system(n, seed, density=0.2, shift=4.0):
+    rng = np.random.default_rng(seed)
+    R = sp.random(n, n, density=density, random_state=rng, format="csr")
+    R.data = rng.standard_normal(R.nnz)
+    A = (sp.identity(n, format="csr") * shift + R).tocsr()
+    A.sort_indices()
+    b = rng.standard_normal(n)
+    return A, b
+
+
+def orthonormal(n, k, seed):
+    rng = np.random.default_rng(seed)
+    Q, _ = np.linalg.qr(rng.standard_normal((n, k)))
+    return Q
+
+
+def c1_system(step=3, seed=0):
+    asm, systems, states = WL.march(WL.C1, step, seed)
+    vals, b = systems[-1]
+    return asm.csr(vals), b, states[-1]
+
+
+# -- GMRES core -------------------------------------------------------------
+
+
+@pytest.mark.parametrize("precond", [O.PRECOND_NONE, O.PRECOND_JACOBI])
+def test_unrestarted_gmres_equals_dense_solve(precond):
+    """m >= n: GMRES is a direct method (section 1); compare with LU."""
+    A, b = rand_system(40, 1)
+    cfg = O.Config(restart_m=60, method=O.PLAIN, precond=precond)
+    res = O.solve(A, b, None, 1e-13, cfg)
+    xd = np.linalg.solve(A.toarray(), b)
+    kappa = np.linalg.cond(A.toarray())
+    assert res.converged
+    assert np.linalg.norm(res.x - xd) / np.linalg.norm(xd) <= kappa * 1e-13
+    assert res.iterations <= 40
+
+
+def test_restarted_gmres_matches_scipy():
+    """GMRES(m) with m < n: same solution as SciPy's restarted GMRES (independent implementation)."""
+    A, b, _ = c1_system()
+    cfg = O.Config(restart_m=10, method=O.PLAIN)
+    res = O.solve(A, b, None, 1e-12, cfg)
+    xs, info = spla.gmres(A, b, rtol=1e-12, atol=0.0, restart=10, maxiter=500)
+    assert info == 0
+    xd = spla.spsolve(A.tocsc(), b)
+    kappa = np.linalg.cond(A.toarray())
+    assert np.linalg.norm(res.x - xd) / np.linalg.norm(xd) <= kappa * 1e-12
+    assert np.linalg.norm(res.x - xs) / np.linalg.norm(xd) <= 2 * kappa * 1e-12
+
+
+def krylov_min_residual(op, r0, j):
+    """min_z ||r0 - op-Krylov(z)|| over z in K_j(op, r0) by brute force (power basis + QR + lstsq)."""
+    K = np.empty((r0.size, j))
+    v = r0 / np.linalg.norm(r0)
+    for i in range(j):
+        K[:, i] = v
+        v = op(v)
+        v = v / np.linalg.norm(v)
+    Q, _ = np.linalg.qr(K)
+    AQ = np.column_stack([op(Q[:, i]) for i in range(j)])
+    y, *_ = np.linalg.lstsq(AQ, r0, rcond=None)
+    return np.linalg.norm(r0 - AQ @ y)
+
+
+@pytest.mark.parametrize("recycle", [False, True])
+def test_implicit_residual_is_krylov_minimum(recycle):
+    """|g_{j+1}| after j steps equals the minimal residual over K_j (minimal-residual condition, section 3)."""
+    A, b, x_true = c1_system(step=4)
+    n = b.size
+    dinv = O.jacobi_inverse(A)
+    if recycle:
+        W = orthonormal(n, 3, 7)
+        Z, E, _ = O.recycle_setup(A, W)
+        _, r0 = O.projection_correction(W, Z, E, np.zeros(n), b.copy())
+        op = lambda v: O.oblique_project(W, Z, E, A @ (dinv * v))
+    else:
+        r0 = b.copy()
+        op = lambda v: A @ (dinv * v)
+    cyc = O.arnoldi_cycle(op, r0, 8, 0.0, 8)
+    for j in range(1, 9):
+        ref = krylov_min_residual(op, r0, j)
+        assert abs(cyc.implicit[j - 1] - ref) <= 1e-9 * np.linalg.norm(r0) + 1e-8 * ref
+
+
+@pytest.mark.parametrize("recycle", [False, True])
+def test_arnoldi_relation_and_orthogonality(recycle):
+    """op V_m = V_{m+1} H_m and V^T V = I for the CGS2 Arnoldi basis."""
+    A, b, _ = c1_system()
+    n = b.size
+    dinv = O.jacobi_inverse(A)
+    if recycle:
+        W = orthonormal(n, 4, 3)
+        Z, E, _ = O.recycle_setup(A, W)
+        op = lambda v: O.oblique_project(W, Z, E, A @ (dinv * v))
+        _, r0 = O.projection_correction(W, Z, E, np.zeros(n), b.copy())
+    else:
+        op = lambda v: A @ (dinv * v)
+        r0 = b
+    m = 25
+    cyc = O.arnoldi_cycle(op, r0, m, 0.0, m)
+    V, H = cyc.V, cyc.H
+    assert V.shape[1] == m + 1 and H.shape == (m + 1, m)
+    OV = np.column_stack([op(V[:, i]) for i in range(m)])
+    anorm = spla.norm(A) * np.abs(dinv).max()
+    assert np.linalg.norm(OV - V @ H) <= 1e-13 * anorm * m
+    assert np.abs(V.T @ V - np.eye(m + 1)).max() <= 1e-14 * m
+    if recycle:
+        # range(P) = ker(W^T): the first Krylov vectors carry no W component (later ones pick up
+        # rounding amplified by 1/h_{j+1,j}, which does not change the iterates measurably)
+        assert np.abs(W.T @ V[:, :3]).max() <= 1e-12
+
+
+def test_residual_history_monotone():
+    A, b, _ = c1_system()
+    cfg = O.Config(restart_m=5, method=O.PLAIN)
+    res = O.solve(A, b, None, 1e-11, cfg)
+    imp = np.array(res.implicit_history)
+    # within a cycle the minimal residual never grows; across restarts the explicit one never grows
+    for c in range(0, imp.size, 5):
+        seg = imp[c:c + 5]
+        assert np.all(np.diff(seg) <= 1e-14)
+    hist = np.array(res.res_history)
+    assert np.all(np.diff(hist) <= 1e-12 * hist[:-1])
+
+
+# -- projector and projection guess ----------------------------------------------
+
+
+def test_oblique_projector_identities():
+    """P^2 = P, P A W = 0 (section 3.2: M_D A V_s = 0), W^T P = 0."""
+    A, b = rand_system(60, 2)
+    W = orthonormal(60, 5, 11)
+    Z, E, _ = O.recycle_setup(A, W)
+    rng = np.random.default_rng(0)
+    V = rng.standard_normal((60, 7))
+    P = lambda v: O.oblique_project(W, Z, E, v)
+    PV = np.column_stack([P(V[:, i]) for i in range(7)])
+    PPV = np.column_stack([P(PV[:, i]) for i in range(7)])
+    assert np.abs(PPV - PV).max() <= 1e-12 * np.abs(V).max()
+    PAW = np.column_stack([P(A @ W[:, i]) for i in range(5)])
+    assert np.abs(PAW).max() <= 1e-12 * spla.norm(A)
+    assert np.abs(W.T @ PV).max() <= 1e-12 * np.abs(V).max()
+
+
+def test_projection_guess_exact_when_solution_in_span():
+    """x* in span(W) -> x0 = W E^{-1} W^T b = x* and no Arnoldi step (section 4.2)."""
+    A, _ = rand_system(50, 3)
+    W = orthonormal(50, 4, 5)
+    c = np.array([1.0, -2.0, 0.5, 3.0])
+    x_star = W @ c
+    b = A @ x_star
+    cfg = O.Config(restart_m=20, recycle_k=4, snapshots_s=4)
+    res = O.solve(A, b, None, 1e-12, cfg, W)
+    assert res.iterations == 0 and res.converged
+    assert np.linalg.norm(res.x - x_star) <= 1e-13 * np.linalg.norm(x_star) * np.linalg.cond(A.toarray())
+
+
+def test_correction_leaves_residual_orthogonal_to_W():
+    A, b, _ = c1_system()
+    W = orthonormal(b.size, 5, 9)
+    res = O.solve(A, b, None, 1e-9, O.Config(restart_m=10, recycle_k=5, snapshots_s=5), W)
+    r = b - A @ res.x
+    assert np.abs(W.T @ r).max() <= 1e-13 * np.linalg.norm(b) * 100
+    assert np.linalg.norm(r) <= 1e-9 * np.linalg.norm(b)
+
+
+def test_augmented_and_deflated_oblique_coincide_without_preconditioner():
+    """(I - A W E^{-1} W^T)^2 b = (I - A W E^{-1} W^T) b, eq. (equivalence_oblique): the two Table 1
+    rows then run the same iteration."""
+    A, b, _ = c1_system()
+    W = orthonormal(b.size, 5, 21)
+    Z, E, _ = O.recycle_setup(A, W)
+    Pb = O.oblique_project(W, Z, E, b)
+    PPb = O.oblique_project(W, Z, E, Pb)
+    assert np.linalg.norm(PPb - Pb) <= 1e-13 * np.linalg.norm(b)
+    ra = O.solve(A, b, None, 1e-10, O.Config(restart_m=20, recycle_k=5, snapshots_s=5, method=O.AUG_OBLIQUE), W)
+    rd = O.solve(A, b, None, 1e-10, O.Config(restart_m=20, recycle_k=5, snapshots_s=5, method=O.DEFL_OBLIQUE), W)
+    assert ra.iterations == rd.iterations
+    assert np.array_equal(ra.x, rd.x)
+
+
+def test_invariant_subspace_reduces_to_complement_block():
+    """W spanning an invariant subspace of A (block-diagonal A, W = first block's coordinates):
+    the residual has no component left in span(W) and the recycled solve is plain GMRES on the
+    second block (section 3.2, the invariant-subspace estimate)."""
+    A1, b1 = rand_system(12, 4)
+    A2, b2 = rand_system(30, 5)
+    A = sp.block_diag([A1, A2], format="csr")
+    b = np.concatenate([b1, b2])
+    W = np.zeros((42, 12))
+    W[:12, :] = orthonormal(12, 12, 2)
+    res = O.solve(A, b, None, 1e-11, O.Config(restart_m=50, recycle_k=12, snapshots_s=12), W)
+    res2 = O.solve(A2, b2, None, 1e-11 * np.linalg.norm(b) / np.linalg.norm(b2), O.Config(restart_m=50, method=O.PLAIN))
+    assert res.converged
+    assert res.iterations == res2.iterations
+    r = b - A @ res.x
+    assert np.linalg.norm(r[:12]) <= 1e-13 * np.linalg.norm(b)
+    assert np.linalg.norm(res.x[:12] - np.linalg.solve(A1.toarray(), b1)) <= 1e-12 * np.linalg.norm(b1) * 100
+
+
+def test_recycling_reduces_iterations_on_sequence():
+    """The method's purpose (section 6): recycling the SVD space of previous solutions cuts
+    Arnoldi steps on a slowly varying sequence."""
+    asm, systems, _ = WL.march(WL.C3_SMALL, 10, 0)
+    A_list = [asm.csr(v) for v, _ in systems]
+    b_list = [b for _, b in systems]
+    plain, _ = O.run_sequence(A_list, b_list, 1e-10, O.Config(restart_m=50, method=O.PLAIN, precond=1))
+    rec, _ = O.run_sequence(A_list, b_list, 1e-10, O.Config(restart_m=50, recycle_k=16, snapshots_s=32, precond=1))
+    assert sum(r.iterations for r in rec[5:]) < 0.75 * sum(r.iterations for r in plain[5:])
+    for r, p in zip(rec, plain):
+        assert r.converged and p.converged
+        assert np.linalg.norm(r.x - p.x) <= 1e-8 * np.linalg.norm(p.x)
+
+
+# -- SVD recycle space ----------------------------------------------------------------
+
+
+def test_svd_basis_eckart_young_and_rank():
+    rng = np.random.default_rng(3)
+    n, c, k = 300, 12, 5
+    X = rng.standard_normal((n, c)) @ np.diag(2.0 ** -np.arange(c)) @ orthonormal(c, c, 1).T
+    W, sig, rank = O.svd_basis(X, k)
+    assert rank == c and W.shape == (n, k)
+    assert np.abs(W.T @ W - np.eye(k)).max() <= 1e-14
+    # Eckart-Young (eqs. best_rank_s / opt_svd): the residual of the rank-k projection
+    res = np.linalg.norm(X - W @ (W.T @ X), "fro") ** 2
+    assert abs(res - np.sum(sig[k:] ** 2)) <= 1e-12 * np.sum(sig ** 2)
+    # singular values are those of X (X^T X eigenvalues, an independent route)
+    ev = np.sort(np.linalg.eigvalsh(X.T @ X))[::-1]
+    assert np.allclose(sig ** 2, ev, rtol=1e-10, atol=1e-12 * ev[0])
+    # span is invariant under a permutation of the snapshot columns
+    Wp, _, _ = O.svd_basis(X[:, rng.permutation(c)], k)
+    s = np.linalg.svd(W.T @ Wp, compute_uv=False)
+    assert s.min() >= 1 - 1e-12
+
+
+def test_svd_basis_rank_cut_on_duplicate_snapshots():
+    rng = np.random.default_rng(4)
+    x = rng.standard_normal(100)
+    y = rng.standard_normal(100)
+    X = np.column_stack([x, y, x, 2 * y, x + y])
+    W, sig, rank = O.svd_basis(X, 4)
+    assert rank == 2 and W.shape[1] == 2
+    B, _ = np.linalg.qr(np.column_stack([x, y]))
+    assert np.linalg.svd(W.T @ B, compute_uv=False).min() >= 1 - 1e-12
+    W0, _, r0 = O.svd_basis(np.zeros((50, 3)), 2)
+    assert r0 == 0 and W0.shape == (50, 0)
+
+
+def test_ring_keeps_most_recent_s_and_interval():
+    cfg = O.Config(recycle_k=2, snapshots_s=3, svd_interval=2)
+    st = O.RecycleState(10, cfg)
+    e = np.eye(10)
+    st.update(e[0])
+    assert st.W.shape[1] == 0           # no SVD before the first interval boundary
+    st.update(e[1])
+    assert st.W.shape[1] == 2
+    for i in range(2, 6):
+        st.update(e[i])
+    assert len(st.ring) == 3 and np.array_equal(st.ring[0], e[3])
+    # span of W is within the span of the 3 most recent snapshots
+    assert np.abs(st.W[:3]).max() == 0.0
+
+
+# -- degenerate and failure cases -----------------------------------------------------
+
+
+def test_zero_rhs_and_nonfinite():
+    A, b = rand_system(20, 6)
+    res = O.solve(A, np.zeros(20), np.ones(20), 1e-8, O.Config())
+    assert res.converged and res.iterations == 0 and not res.x.any()
+    bn = b.copy()
+    bn[3] = np.nan
+    res = O.solve(A, bn, None, 1e-8, O.Config())
+    assert not res.converged and res.flags & O.FLAG_NONFINITE
+
+
+def test_singular_E_drops_recycling():
+    A, b = rand_system(30, 7)
+    w = orthonormal(30, 1, 0)
+    W = np.column_stack([w, w])          # duplicate columns -> E singular
+    res = O.solve(A, b, None, 1e-10, O.Config(restart_m=30, recycle_k=2, snapshots_s=2), W)
+    assert res.flags & O.FLAG_RECYCLE_DROPPED and res.k_eff == 0 and res.converged
+
+
+def test_max_iters_not_converged():
+    A, b, _ = c1_system()
+    res = O.solve(A, b, None, 1e-12, O.Config(restart_m=30, method=O.PLAIN, max_iters=3))
+    assert not res.converged and res.iterations == 3
+    assert res.rel_res_true > 1e-12
+
+
+# -- planted mistakes: each plausible error in the oracle is caught by a pin ----------
+
+
+def _pins_pass():
+    try:
+        test_unrestarted_gmres_equals_dense_solve(O.PRECOND_JACOBI)
+        test_oblique_projector_identities()
+        test_projection_guess_exact_when_solution_in_span()
+        test_implicit_residual_is_krylov_minimum(True)
+        test_correction_leaves_residual_orthogonal_to_W()
+    except AssertionError:
+        return False
+    return True
+
+
+def test_pins_pass_on_unmodified_oracle():
+    assert _pins_pass()
+
+
+@pytest.mark.parametrize("mutation", ["projector_uses_W", "guess_transposed_E", "givens_sign",
+                                      "update_without_preconditioner", "operator_perturbed",
+                                      "correction_sign"])
+def test_planted_mistakes_are_caught(monkeypatch, mutation):
+    if mutation == "projector_uses_W":
+        monkeypatch.setattr(O, "oblique_project", lambda W, Z, E, v: v - W @ np.linalg.solve(E, W.T @ v))
+    elif mutation == "guess_transposed_E":
+        def bad(W, Z, E, x, r):
+            c = np.linalg.solve(E.T, W.T @ r)
+            return x + W @ c, r - Z @ c
+        monkeypatch.setattr(O, "projection_correction", bad)
+    elif mutation == "correction_sign":
+        def bad(W, Z, E, x, r):
+            c = np.linalg.solve(E, W.T @ r)
+            return x - W @ c, r - Z @ c
+        monkeypatch.setattr(O, "projection_correction", bad)
+    elif mutation == "givens_sign":
+        orig = O.givens
+        monkeypatch.setattr(O, "givens", lambda a, b: (lambda c, s, r: (c, -s, r))(*orig(a, b)))
+    elif mutation == "update_without_preconditioner":
+        monkeypatch.setattr(O, "krylov_update", lambda x, dinv, V, y: x + V @ y)
+    elif mutation == "operator_perturbed":
+        orig_cycle = O.arnoldi_cycle
+
+        def cycle(op, r0, m, stop_abs, max_steps):
+            return orig_cycle(lambda v: op(v) + 1e-3 * v, r0, m, stop_abs, max_steps)
+        monkeypatch.setattr(O, "arnoldi_cycle", cycle)
+    assert not _pins_pass()
