@@ -1,0 +1,196 @@
+/*
+ * rsolve.h -- C-ABI of the recycled GMRES(m) solver for sequences of sparse
+ * non-symmetric systems A_i x_i = b_i (one system per time step), built for
+ * AMD Instinct MI355X (gfx950).
+ *
+ * Method (Pitton & Heltai, "Accelerating the iterative solution of
+ * convection-diffusion problems using singular value decomposition"):
+ *   - the systems form a sequence whose matrix and right-hand side may depend
+ *     on the previous solution, and arrive one at a time (section 2, the
+ *     closing paragraph of the problem statement); n is fixed per sequence
+ *     (section 4, opening of the initial-guess discussion);
+ *   - each solve is restarted GMRES(m) (section 3, minimal-residual choice
+ *     C_k = A S_k) accelerated by a recycle basis W (the paper's V_s): the
+ *     Krylov operator is P A with the oblique projector
+ *     P = I - A W (W^T A W)^{-1} W^T (section 3.2, eq. (left_deflation);
+ *     section 3.3, Table 1 rows "augmented oblique" / "deflated oblique"),
+ *     and the initial guess is the Galerkin projection onto span(W)
+ *     (section 4.2, eqs. (projection_guess), (projection_t_s));
+ *   - after each solve the solution is stored in a ring of the s most recent
+ *     solutions and every `svd_interval` solves W is replaced by the k
+ *     dominant left singular vectors of the ring (section 5.2, Algorithm 1).
+ *
+ * Conventions for every entry point:
+ *   - All matrix / vector pointers are DEVICE pointers (HIP, the GPU the
+ *     sequence was created on) unless the argument says "host".
+ *   - Dense vectors are float64, length n.  CSR matrices are 0-based with
+ *     int32 row pointers and column indices, columns sorted strictly
+ *     increasing within each row, and an explicitly stored diagonal entry in
+ *     every row (required by the Jacobi preconditioner).
+ *   - The caller owns every buffer it passes.  The library never allocates
+ *     device memory: all of a sequence's state lives in the caller-provided
+ *     workspace, which must stay allocated until rsolve_destroy_sequence.
+ *   - Entry points return an int status (RSOLVE_OK = 0, RSOLVE_NOT_CONVERGED
+ *     = 1, negative = error); no entry point aborts, throws or exits.
+ *   - A sequence handle is not thread-safe; distinct handles are independent
+ *     and may be used from different host threads on different streams.
+ */
+#ifndef RSOLVE_H
+#define RSOLVE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---- */
+#define RSOLVE_OK             0
+#define RSOLVE_NOT_CONVERGED  1   /* max_iters reached; x holds the last iterate, stats filled */
+#define RSOLVE_E_INVALID     -1   /* bad argument: null handle/pointer, n/nnz mismatch, tol <= 0,
+                                     config out of range, corrupt CSR (found on the device) */
+#define RSOLVE_E_NONFINITE   -2   /* NaN/Inf met in a norm (b, A or the iteration) */
+#define RSOLVE_E_WORKSPACE   -3   /* workspace too small or misaligned (256-byte alignment) */
+#define RSOLVE_E_DEVICE      -4   /* a HIP runtime call failed */
+#define RSOLVE_E_STATE       -5   /* call out of order (e.g. update before any solve) */
+
+/* ---- configuration values ---- */
+#define RSOLVE_PLAIN          0   /* GMRES(m) without recycling */
+#define RSOLVE_AUG_OBLIQUE    1   /* Table 1, augmented oblique */
+#define RSOLVE_DEFL_OBLIQUE   2   /* Table 1, deflated oblique (same iteration under right
+                                     preconditioning with the projected initial guess) */
+#define RSOLVE_PRECOND_NONE   0
+#define RSOLVE_PRECOND_JACOBI 1   /* right Jacobi: operator P A D^{-1}, x = x0 + D^{-1} V y */
+#define RSOLVE_FP64           0   /* everything in float64 */
+#define RSOLVE_FP32_IR        1   /* float32 Arnoldi cycles inside float64 iterative refinement */
+#define RSOLVE_SELECT_LARGEST 0   /* W = leading left singular vectors (Algorithm 1) */
+
+/* ---- limits ---- */
+#define RSOLVE_MAX_RESTART    128
+#define RSOLVE_MAX_RECYCLE    64
+#define RSOLVE_MAX_SNAPSHOTS  64
+
+/* ---- solve flags (rsolve_stats.flags) ---- */
+#define RSOLVE_FLAG_RECYCLE_DROPPED 1u  /* cond_1(W^T A W) > 1e13: this solve ran without W */
+#define RSOLVE_FLAG_BREAKDOWN_LUCKY 2u  /* h_{j+1,j} <= 1e-14 ||h_j||: Krylov space invariant */
+#define RSOLVE_FLAG_NONFINITE       4u
+
+/* ---- rsolve_csr.flags ---- */
+#define RSOLVE_SAME_PATTERN 1u  /* row_ptr/col_idx are those of the previous solve of this
+                                   sequence (same content): skip validation and pattern setup */
+
+typedef struct rsolve_seq rsolve_seq;
+
+typedef struct {
+    int32_t restart_m;     /* GMRES restart length m, 1..RSOLVE_MAX_RESTART */
+    int32_t recycle_k;     /* recycle dimension k, 0..RSOLVE_MAX_RECYCLE (0 = plain) */
+    int32_t snapshots_s;   /* snapshot ring size s, k <= s <= RSOLVE_MAX_SNAPSHOTS (0 if k = 0) */
+    int32_t svd_interval;  /* ell >= 1: recompute W every ell updates (Algorithm 1) */
+    int32_t method;        /* RSOLVE_PLAIN / RSOLVE_AUG_OBLIQUE / RSOLVE_DEFL_OBLIQUE */
+    int32_t precond;       /* RSOLVE_PRECOND_NONE / RSOLVE_PRECOND_JACOBI */
+    int32_t precision;     /* RSOLVE_FP64 / RSOLVE_FP32_IR */
+    int32_t max_iters;     /* cap on Arnoldi steps per solve (>= 1) */
+    int32_t select;        /* RSOLVE_SELECT_LARGEST */
+    int32_t reserved;      /* must be 0 */
+    double  inner_tol;     /* FP32_IR only: an FP32 cycle stops once its residual estimate has
+                              dropped by this factor (0 < inner_tol < 1); ignored for FP64 */
+} rsolve_config;
+
+typedef struct {
+    int64_t n;             /* rows = columns */
+    int64_t nnz;           /* stored entries, n <= nnz <= nnz_max of the sequence */
+    const int32_t* row_ptr;  /* device, n + 1 entries, row_ptr[0] = 0, row_ptr[n] = nnz */
+    const int32_t* col_idx;  /* device, nnz entries */
+    const double*  val;      /* device, nnz entries */
+    uint32_t flags;        /* RSOLVE_SAME_PATTERN or 0 */
+    uint32_t reserved;     /* must be 0 */
+} rsolve_csr;
+
+typedef struct {
+    int32_t iterations;    /* Arnoldi steps (one SpMV each) over all cycles of this solve */
+    int32_t cycles;        /* GMRES cycles (restarts + 1); FP32_IR: refinement steps */
+    int32_t k_eff;         /* recycle columns used by this solve */
+    int32_t converged;     /* 1 if ||b - A x||_2 <= tol ||b||_2 (checked explicitly in FP64) */
+    uint32_t flags;        /* RSOLVE_FLAG_* */
+    int32_t reserved;
+    double rel_res_true;   /* ||b - A x||_2 / ||b||_2 of the returned x (FP64) */
+    double rel_res_implicit; /* last Givens residual estimate / ||b||_2 */
+    double t_setup_ms;     /* validation, Jacobi scaling, A W, W^T A W, LU, initial guess */
+    double t_cycles_ms;    /* Arnoldi cycles and end-of-cycle corrections */
+    double t_total_ms;     /* wall time of the call (host clock, call entry to return) */
+} rsolve_stats;
+
+/*
+ * Bytes of device workspace a sequence needs for systems of size n with at
+ * most nnz_max stored entries.  Returns 0 if the configuration is invalid.
+ * Layout (all 256-byte aligned, column-major tall blocks with leading
+ * dimension ld = n rounded up to 64): Krylov basis V (m+1 columns), recycle
+ * basis W and A W (k columns each), snapshot ring (s columns), work vectors,
+ * scaled matrix values (nnz_max), float32 shadows in FP32_IR mode, TSQR
+ * levels, per-block reduction partials and a control block.
+ */
+size_t rsolve_workspace_bytes(const rsolve_config* cfg, int64_t n, int64_t nnz_max);
+
+/*
+ * Create a sequence.  `hip_stream` is a hipStream_t (NULL = the null stream)
+ * on which every kernel of this sequence is enqueued; `workspace` is a device
+ * buffer of at least rsolve_workspace_bytes(cfg, n, nnz_max) bytes, 256-byte
+ * aligned, owned by the caller.  The HIP device current on the calling thread
+ * must be the one that owns the workspace.  Errors: E_INVALID (cfg, n, out),
+ * E_WORKSPACE, E_DEVICE.
+ */
+int rsolve_create_sequence(const rsolve_config* cfg, int64_t n, int64_t nnz_max,
+                           void* hip_stream, void* workspace, size_t ws_bytes,
+                           rsolve_seq** out);
+
+/*
+ * Solve A x = b until ||b - A x||_2 <= tol ||b||_2 (stopping rule of
+ * section 6.1; the check is an explicit FP64 residual).  x0 may be NULL
+ * (zero start) and x may alias x0.  The initial guess is
+ * x0 + W E^{-1} W^T (b - A x0) when the sequence holds a recycle basis; with
+ * x0 = NULL this is the projection guess W E^{-1} W^T b of section 4.2.
+ * Synchronous: returns after x and *st are final.  A's buffers need only stay
+ * valid for the duration of the call.  b = 0 gives x = 0 and 0 iterations.
+ * Returns OK, NOT_CONVERGED (x = last iterate), E_INVALID (bad pointers, n
+ * mismatch, nnz out of range, tol <= 0, corrupt CSR), E_NONFINITE, E_DEVICE.
+ */
+int rsolve_solve(rsolve_seq* s, const rsolve_csr* A, const double* b, const double* x0,
+                 double* x, double tol, rsolve_stats* st);
+
+/*
+ * Algorithm 1 of section 5.2: store x (device, n entries; NULL = the last
+ * solution returned by rsolve_solve) in the ring of the s most recent
+ * solutions; when the number of stored solutions is a multiple of
+ * svd_interval, replace W by the min(k, numerical rank) leading left singular
+ * vectors of the ring (numerical rank: sigma_i > sigma_1 * max(n, c) * 2^-52
+ * with c the number of stored columns).  Synchronous.  Errors: E_STATE (x =
+ * NULL before any solve), E_INVALID, E_NONFINITE (non-finite snapshot),
+ * E_DEVICE.
+ */
+int rsolve_update_recycle(rsolve_seq* s, const double* x);
+
+/*
+ * Read the recycle state: *k_eff = current number of columns of W, *rank =
+ * numerical rank of the ring at the last SVD, sigma_host (host, may be NULL)
+ * receives min(cap, c) singular values in descending order.  If W_out
+ * (device, may be NULL) is given, W is copied there column-major with leading
+ * dimension ld_out >= n.  Synchronous.
+ */
+int rsolve_get_recycle(rsolve_seq* s, int32_t* k_eff, int32_t* rank, double* sigma_host,
+                       int32_t cap, double* W_out, int64_t ld_out);
+
+/* Destroy the handle.  Does not free the workspace (the caller owns it). */
+int rsolve_destroy_sequence(rsolve_seq* s);
+
+/* Static, human-readable text for a status code. */
+const char* rsolve_status_string(int status);
+
+/* Static text describing the last error seen by this host thread (may be ""). */
+const char* rsolve_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RSOLVE_H */

@@ -1,0 +1,739 @@
+// Host engine and C-ABI of the rsolve library: one sequence = one time-stepping
+// sequence of systems, solved by restarted GMRES(m) with the oblique projector
+// of the recycle basis W (section 3.2, eq. (left_deflation); Table 1 rows
+// "augmented / deflated oblique"), the projection initial guess (section 4.2),
+// and the SVD snapshot-ring update (section 5.2, Algorithm 1).
+//
+// All device work of a sequence goes to its stream.  Within a GMRES cycle the
+// host enqueues every Arnoldi step without waiting: the Givens kernel sets a
+// device flag when the cycle must stop and later kernels of the cycle return
+// at once.  The host synchronises once per cycle (explicit FP64 residual).
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstddef>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+
+#include "../../include/rsolve.h"
+#include "../../include/rsolve_kernels.h"
+#include "kernels.hpp"
+
+using namespace rs;
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+void set_err(const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+}
+
+constexpr size_t ALIGN = 256;
+inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+inline int64_t pad64(int64_t n) { return (n + 63) / 64 * 64; }
+
+// Sequential carving of the caller's workspace (base == nullptr: size only).
+struct Carver {
+    char* base;
+    size_t off = 0;
+    template <class T>
+    T* take(size_t count) {
+        off = align_up(off, ALIGN);
+        T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+        off += count * sizeof(T);
+        return p;
+    }
+};
+
+#define HIP_TRY(expr)                                                                  \
+    do {                                                                               \
+        hipError_t e_ = (expr);                                                        \
+        if (e_ != hipSuccess) {                                                        \
+            set_err("%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, __LINE__); \
+            return RSOLVE_E_DEVICE;                                                    \
+        }                                                                              \
+    } while (0)
+
+constexpr size_t CTL_HEAD = offsetof(Ctl, g);   // fields the host reads after a sync
+
+int cfg_check(const rsolve_config* c) {
+    if (!c) return RSOLVE_E_INVALID;
+    if (c->restart_m < 1 || c->restart_m > RSOLVE_MAX_RESTART) return RSOLVE_E_INVALID;
+    if (c->recycle_k < 0 || c->recycle_k > RSOLVE_MAX_RECYCLE) return RSOLVE_E_INVALID;
+    if (c->snapshots_s < 0 || c->snapshots_s > RSOLVE_MAX_SNAPSHOTS) return RSOLVE_E_INVALID;
+    if (c->recycle_k > 0 && c->snapshots_s < c->recycle_k) return RSOLVE_E_INVALID;
+    if (c->svd_interval < 1) return RSOLVE_E_INVALID;
+    if (c->method < RSOLVE_PLAIN || c->method > RSOLVE_DEFL_OBLIQUE) return RSOLVE_E_INVALID;
+    if (c->precond != RSOLVE_PRECOND_NONE && c->precond != RSOLVE_PRECOND_JACOBI) return RSOLVE_E_INVALID;
+    if (c->precision != RSOLVE_FP64 && c->precision != RSOLVE_FP32_IR) return RSOLVE_E_INVALID;
+    if (c->max_iters < 1) return RSOLVE_E_INVALID;
+    if (c->select != RSOLVE_SELECT_LARGEST || c->reserved != 0) return RSOLVE_E_INVALID;
+    if (c->precision == RSOLVE_FP32_IR && !(c->inner_tol > 0.0 && c->inner_tol < 1.0)) return RSOLVE_E_INVALID;
+    return RSOLVE_OK;
+}
+
+int env_int(const char* name, int dflt) {
+    const char* v = getenv(name);
+    if (!v || !*v) return dflt;
+    return atoi(v);
+}
+
+int pick_lpr(int64_t n, int64_t nnz) {
+    const int forced = env_int("RSOLVE_LPR", 0);
+    if (forced == 2 || forced == 4 || forced == 8 || forced == 16 || forced == 32) return forced;
+    const double avg = n > 0 ? (double)nnz / (double)n : 1.0;
+    if (avg <= 10.0) return 4;
+    if (avg <= 20.0) return 8;
+    return 16;
+}
+
+int pick_nblk(int64_t npad) {
+    const int forced = env_int("RSOLVE_NBLK", 0);
+    if (forced > 0) return std::min(forced, NBLK_MAX);
+    int64_t b = (npad + BLOCK * 4 - 1) / (BLOCK * 4);
+    return (int)std::max<int64_t>(1, std::min<int64_t>(b, NBLK_MAX));
+}
+
+int pick_gblk(int64_t n) {
+    int64_t b = (n + 4095) / 4096;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(b, 256));
+}
+
+}  // namespace
+
+struct rsolve_seq {
+    rsolve_config cfg;
+    int64_t n = 0, ld = 0, nnz_max = 0;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    char* ws = nullptr;
+    size_t ws_bytes = 0;
+    Ctl* ctl = nullptr;
+    Ctl* hctl = nullptr;     // pinned host mirror of the control header
+    double* hsig = nullptr;  // pinned host copy of the singular values
+    int32_t* err = nullptr;
+    int32_t* herr = nullptr;
+    int32_t* diag_pos = nullptr;
+    double *V = nullptr, *W = nullptr, *Z = nullptr, *X = nullptr, *xw = nullptr, *dinv = nullptr;
+    double* wb[2] = {nullptr, nullptr};
+    double *vals = nullptr, *partial = nullptr, *gpart = nullptr;
+    double* tsq[2] = {nullptr, nullptr};
+    int64_t tsq_ld = 0;
+    float *V32 = nullptr, *W32 = nullptr, *Z32 = nullptr, *vals32 = nullptr;
+    float* w32[2] = {nullptr, nullptr};
+    int nblk = 1, gblk = 1, lpr = 8;
+    const int32_t* pat_rp = nullptr;
+    const int32_t* pat_ci = nullptr;
+    int64_t pat_nnz = -1;
+    bool pat_ok = false;
+    int k_w = 0, rank = 0, nsig = 0;
+    int64_t count = 0;
+    double sigma[SMAX];
+    bool have_x = false;
+};
+
+namespace {
+
+// Lays the sequence's buffers out in the workspace; returns the bytes used.
+size_t layout(rsolve_seq* s, const rsolve_config& c, int64_t n, int64_t nnz_max, char* base) {
+    Carver cv{base};
+    const int64_t ld = pad64(n);
+    const bool ir = c.precision == RSOLVE_FP32_IR;
+    const bool jac = c.precond == RSOLVE_PRECOND_JACOBI;
+    const int m = c.restart_m, k = c.recycle_k, sn = c.snapshots_s;
+    Ctl* ctl = cv.take<Ctl>(1);
+    int32_t* err = cv.take<int32_t>(8);
+    int32_t* dp = cv.take<int32_t>((size_t)n);
+    double* V = ir ? nullptr : cv.take<double>((size_t)(m + 1) * ld);
+    float* V32 = ir ? cv.take<float>((size_t)(m + 1) * ld) : nullptr;
+    double* W = k ? cv.take<double>((size_t)k * ld) : nullptr;
+    double* Z = k ? cv.take<double>((size_t)k * ld) : nullptr;
+    float* W32 = (k && ir) ? cv.take<float>((size_t)k * ld) : nullptr;
+    float* Z32 = (k && ir) ? cv.take<float>((size_t)k * ld) : nullptr;
+    double* X = (k && sn) ? cv.take<double>((size_t)sn * ld) : nullptr;
+    double* wb0 = cv.take<double>((size_t)ld);
+    double* wb1 = cv.take<double>((size_t)ld);
+    float* w320 = ir ? cv.take<float>((size_t)ld) : nullptr;
+    float* w321 = ir ? cv.take<float>((size_t)ld) : nullptr;
+    double* xw = cv.take<double>((size_t)ld);
+    double* dinv = jac ? cv.take<double>((size_t)ld) : nullptr;
+    double* vals = (jac && !ir) ? cv.take<double>((size_t)nnz_max) : nullptr;
+    float* vals32 = ir ? cv.take<float>((size_t)nnz_max) : nullptr;
+    double* partial = cv.take<double>((size_t)NBLK_MAX * (MMAX + 2 * KMAX + 1));
+    double* gpart = cv.take<double>((size_t)256 * KMAX * KMAX);
+    int64_t tsq_rows = 0, tsq_ld = 0;
+    double *t0 = nullptr, *t1 = nullptr;
+    if (k && sn) {
+        tsq_rows = ((n + TSQR_PANEL - 1) / TSQR_PANEL) * sn;
+        tsq_ld = pad64(tsq_rows);
+        t0 = cv.take<double>((size_t)tsq_ld * sn);
+        t1 = cv.take<double>((size_t)tsq_ld * sn);
+    }
+    if (s) {
+        s->ld = ld;
+        s->ctl = ctl;
+        s->err = err;
+        s->diag_pos = dp;
+        s->V = V;
+        s->V32 = V32;
+        s->W = W;
+        s->Z = Z;
+        s->W32 = W32;
+        s->Z32 = Z32;
+        s->X = X;
+        s->wb[0] = wb0;
+        s->wb[1] = wb1;
+        s->w32[0] = w320;
+        s->w32[1] = w321;
+        s->xw = xw;
+        s->dinv = dinv;
+        s->vals = vals;
+        s->vals32 = vals32;
+        s->partial = partial;
+        s->gpart = gpart;
+        s->tsq[0] = t0;
+        s->tsq[1] = t1;
+        s->tsq_ld = tsq_ld;
+    }
+    return align_up(cv.off, ALIGN);
+}
+
+inline double* ctl_h1(Ctl* c) { return reinterpret_cast<double*>(reinterpret_cast<char*>(c) + offsetof(Ctl, h1)); }
+inline double* ctl_h2(Ctl* c) { return reinterpret_cast<double*>(reinterpret_cast<char*>(c) + offsetof(Ctl, h2)); }
+inline double* ctl_cw(Ctl* c) { return reinterpret_cast<double*>(reinterpret_cast<char*>(c) + offsetof(Ctl, cw)); }
+inline double* ctl_red(Ctl* c) { return reinterpret_cast<double*>(reinterpret_cast<char*>(c) + offsetof(Ctl, red)); }
+inline double* ctl_sigma(Ctl* c) {
+    return reinterpret_cast<double*>(reinterpret_cast<char*>(c) + offsetof(Ctl, sigma));
+}
+
+int read_head(rsolve_seq* s) {
+    HIP_TRY(hipMemcpyAsync(s->hctl, s->ctl, CTL_HEAD, hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    return RSOLVE_OK;
+}
+
+// One Arnoldi step j of the current cycle on storage type T.
+template <typename T>
+void arnoldi_step(rsolve_seq* s, int j, const int32_t* rp, const int32_t* ci, const T* vals, T* V, T* const* wbuf,
+                  const T* Wt, const T* Zt, int k) {
+    hipStream_t st = s->stream;
+    const int64_t ld = s->ld;
+    T* win = wbuf[j & 1];
+    T* wout = wbuf[(j + 1) & 1];
+    T* vj = V + (int64_t)j * ld;
+    launch_spmv_arnoldi<T>(s->lpr, s->n, rp, ci, vals, win, vj, wout, s->ctl, st);
+    const int nv = j + 1;
+    if (k > 0) {
+        const T* bases[3] = {V, Wt, Zt};
+        const T* vecs[3] = {wout, wout, vj};
+        const int counts[3] = {nv, k, k};
+        launch_dots<T>(ld, ld, bases, vecs, counts, 3, s->partial, s->nblk, s->ctl, st);
+    } else {
+        const T* bases[1] = {V};
+        const T* vecs[1] = {wout};
+        const int counts[1] = {nv};
+        launch_dots<T>(ld, ld, bases, vecs, counts, 1, s->partial, s->nblk, s->ctl, st);
+    }
+    launch_reduce_pass1(s->partial, s->nblk, nv, k, s->ctl, st);
+    if (nv <= 64) {
+        launch_update_dots<T>(ld, V, ld, nv, Zt, k, wout, ctl_h1(s->ctl), ctl_cw(s->ctl), s->partial, s->nblk, s->ctl,
+                              st);
+    } else {
+        launch_update<T>(ld, V, ld, nv, Zt, k, wout, ctl_h1(s->ctl), ctl_cw(s->ctl), s->nblk, s->ctl, st);
+        const T* bases[1] = {V};
+        const T* vecs[1] = {wout};
+        const int counts[1] = {nv};
+        launch_dots<T>(ld, ld, bases, vecs, counts, 1, s->partial, s->nblk, s->ctl, st);
+    }
+    launch_reduce(s->partial, s->nblk, nv, ctl_h2(s->ctl), s->ctl, 0, 0, false, true, st);
+    launch_update_norm<T>(ld, V, ld, nv, wout, ctl_h2(s->ctl), s->partial, s->nblk, s->ctl, st);
+    launch_givens(s->partial, s->nblk, j, s->ctl, st);
+}
+
+// r (wb[0]) = b - A xw, then the span(W) correction x += W E^{-1} W^T r, r -= A W E^{-1} W^T r
+// (section 4.2, eq. (projection_t_s)), then ctl->rnorm = ||r||.
+void residual_and_correct(rsolve_seq* s, const rsolve_csr* A, const double* b, int k) {
+    hipStream_t st = s->stream;
+    launch_residual(s->lpr, s->n, A->row_ptr, A->col_idx, A->val, s->xw, b, s->wb[0], st);
+    if (k > 0) {
+        const double* bases[1] = {s->W};
+        const double* vecs[1] = {s->wb[0]};
+        const int counts[1] = {k};
+        launch_dots<double>(s->ld, s->ld, bases, vecs, counts, 1, s->partial, s->nblk, nullptr, st);
+        launch_reduce(s->partial, s->nblk, k, ctl_red(s->ctl), s->ctl, 0, k, true, false, st);
+    }
+    launch_correct(s->ld, s->W, s->Z, s->ld, k, s->xw, s->wb[0], s->ctl, s->partial, s->nblk, st);
+    launch_finish_norm(s->partial, s->nblk, s->ctl, 0, st);
+}
+
+double ms_since(std::chrono::steady_clock::time_point t0) {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t rsolve_workspace_bytes(const rsolve_config* cfg, int64_t n, int64_t nnz_max) {
+    if (cfg_check(cfg) != RSOLVE_OK || n < 1 || nnz_max < n || nnz_max > INT32_MAX) return 0;
+    return layout(nullptr, *cfg, n, nnz_max, nullptr);
+}
+
+int rsolve_create_sequence(const rsolve_config* cfg, int64_t n, int64_t nnz_max, void* hip_stream, void* workspace,
+                           size_t ws_bytes, rsolve_seq** out) {
+    g_err[0] = 0;
+    if (!out) return RSOLVE_E_INVALID;
+    *out = nullptr;
+    if (cfg_check(cfg) != RSOLVE_OK) {
+        set_err("invalid configuration");
+        return RSOLVE_E_INVALID;
+    }
+    if (n < 1 || nnz_max < n || nnz_max > INT32_MAX) {
+        set_err("invalid n=%lld / nnz_max=%lld", (long long)n, (long long)nnz_max);
+        return RSOLVE_E_INVALID;
+    }
+    const size_t need = layout(nullptr, *cfg, n, nnz_max, nullptr);
+    if (!workspace || ws_bytes < need || (reinterpret_cast<uintptr_t>(workspace) % ALIGN) != 0) {
+        set_err("workspace needs %zu bytes (got %zu) aligned to %zu", need, ws_bytes, ALIGN);
+        return RSOLVE_E_WORKSPACE;
+    }
+    rsolve_seq* s = new rsolve_seq();
+    s->cfg = *cfg;
+    s->n = n;
+    s->nnz_max = nnz_max;
+    s->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    s->ws = static_cast<char*>(workspace);
+    s->ws_bytes = ws_bytes;
+    layout(s, *cfg, n, nnz_max, s->ws);
+    s->nblk = pick_nblk(s->ld);
+    s->gblk = pick_gblk(s->ld);
+    hipError_t e = hipGetDevice(&s->device);
+    if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&s->hctl), CTL_HEAD + 64, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&s->hsig), sizeof(double) * SMAX, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&s->herr), sizeof(int32_t) * 8, hipHostMallocDefault);
+    // zero the whole workspace once: padding rows of every tall buffer stay zero forever
+    if (e == hipSuccess) e = hipMemsetAsync(s->ws, 0, need, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) {
+        set_err("create: %s", hipGetErrorString(e));
+        if (s->hctl) (void)hipHostFree(s->hctl);
+        if (s->hsig) (void)hipHostFree(s->hsig);
+        if (s->herr) (void)hipHostFree(s->herr);
+        delete s;
+        return RSOLVE_E_DEVICE;
+    }
+    *out = s;
+    return RSOLVE_OK;
+}
+
+int rsolve_destroy_sequence(rsolve_seq* s) {
+    if (!s) return RSOLVE_E_INVALID;
+    if (s->stream || true) (void)hipStreamSynchronize(s->stream);
+    if (s->hctl) (void)hipHostFree(s->hctl);
+    if (s->hsig) (void)hipHostFree(s->hsig);
+    if (s->herr) (void)hipHostFree(s->herr);
+    delete s;
+    return RSOLVE_OK;
+}
+
+int rsolve_solve(rsolve_seq* s, const rsolve_csr* A, const double* b, const double* x0, double* x, double tol,
+                 rsolve_stats* st) {
+    const auto t0 = std::chrono::steady_clock::now();
+    g_err[0] = 0;
+    if (!s || !A || !b || !x) {
+        set_err("null argument");
+        return RSOLVE_E_INVALID;
+    }
+    if (!(tol > 0.0) || !std::isfinite(tol)) {
+        set_err("tol must be positive and finite");
+        return RSOLVE_E_INVALID;
+    }
+    if (A->n != s->n || A->nnz < A->n || A->nnz > s->nnz_max || !A->row_ptr || !A->col_idx || !A->val ||
+        A->reserved != 0) {
+        set_err("matrix header does not match the sequence (n=%lld nnz=%lld)", (long long)A->n, (long long)A->nnz);
+        return RSOLVE_E_INVALID;
+    }
+    HIP_TRY(hipSetDevice(s->device));
+    hipStream_t stm = s->stream;
+    const int64_t n = s->n, ld = s->ld;
+    const rsolve_config& c = s->cfg;
+    const bool ir = c.precision == RSOLVE_FP32_IR;
+    const bool jac = c.precond == RSOLVE_PRECOND_JACOBI;
+    s->have_x = false;
+
+    // a1: pattern validation (device) unless the caller vouches for an unchanged pattern
+    const bool same = (A->flags & RSOLVE_SAME_PATTERN) && s->pat_ok && s->pat_rp == A->row_ptr &&
+                      s->pat_ci == A->col_idx && s->pat_nnz == A->nnz;
+    if (!same) {
+        s->pat_ok = false;
+        HIP_TRY(hipMemsetAsync(s->err, 0, sizeof(int32_t) * 8, stm));
+        launch_validate(n, A->nnz, A->row_ptr, A->col_idx, s->diag_pos, s->err, stm);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipMemcpyAsync(s->herr, s->err, sizeof(int32_t) * 4, hipMemcpyDeviceToHost, stm));
+        HIP_TRY(hipStreamSynchronize(stm));
+        if (s->herr[0] || s->herr[1] || s->herr[2] || s->herr[3]) {
+            set_err("corrupt CSR: row_ptr=%d col_range=%d col_order=%d no_diag=%d", s->herr[0], s->herr[1],
+                    s->herr[2], s->herr[3]);
+            return RSOLVE_E_INVALID;
+        }
+        s->pat_rp = A->row_ptr;
+        s->pat_ci = A->col_idx;
+        s->pat_nnz = A->nnz;
+        s->pat_ok = true;
+        s->lpr = pick_lpr(n, A->nnz);
+    }
+    HIP_TRY(hipMemsetAsync(s->ctl, 0, CTL_HEAD, stm));
+
+    // ||b||
+    launch_norm2(n, b, s->partial, s->nblk, stm);
+    launch_finish_norm(s->partial, s->nblk, s->ctl, 1, stm);
+
+    // a1: Jacobi scaling A D^{-1} (and the FP32 copy in mixed mode)
+    const double* kv64 = A->val;
+    if (jac) {
+        launch_diag_inv(n, s->diag_pos, A->val, s->dinv, stm);
+        if (ir) launch_scale_values(A->nnz, A->col_idx, A->val, s->dinv, nullptr, s->vals32, stm);
+        else {
+            launch_scale_values(A->nnz, A->col_idx, A->val, s->dinv, s->vals, nullptr, stm);
+            kv64 = s->vals;
+        }
+    } else if (ir) {
+        launch_scale_values(A->nnz, A->col_idx, A->val, nullptr, nullptr, s->vals32, stm);
+    }
+
+    // a2: recycle setup A W, E = W^T A W, LU(E)
+    int k = (c.method != RSOLVE_PLAIN) ? s->k_w : 0;
+    uint32_t flags = 0;
+    if (k > 0) {
+        launch_spmm(s->lpr, n, A->row_ptr, A->col_idx, A->val, s->W, ld, k, s->Z, stm);
+        launch_gram_tn(ld, s->W, ld, k, s->Z, ld, k, s->gpart, s->gblk, stm);
+        launch_gram_reduce(s->gpart, s->gblk, k * k, ctl_red(s->ctl), stm);
+        launch_small_lu(ctl_red(s->ctl), k, s->ctl, stm);
+        if (ir) launch_to_f32(k * ld, s->Z, s->Z32, stm);
+    }
+    // a3: r = b - A x0
+    launch_copy_pad(n, ld, x0, s->xw, stm);
+    HIP_TRY(hipGetLastError());
+    int rc = read_head(s);
+    if (rc) return rc;
+    const double bnorm = s->hctl->bnorm;
+    if (!std::isfinite(bnorm)) {
+        set_err("non-finite right-hand side");
+        return RSOLVE_E_NONFINITE;
+    }
+    if (bnorm == 0.0) {
+        HIP_TRY(hipMemsetAsync(x, 0, sizeof(double) * n, stm));
+        HIP_TRY(hipMemsetAsync(s->xw, 0, sizeof(double) * ld, stm));
+        HIP_TRY(hipStreamSynchronize(stm));
+        s->have_x = true;
+        if (st) {
+            memset(st, 0, sizeof(*st));
+            st->converged = 1;
+            st->t_total_ms = ms_since(t0);
+        }
+        return RSOLVE_OK;
+    }
+    if (k > 0 && (s->hctl->lu_fail || !(s->hctl->cond1 <= 1e13))) {
+        k = 0;
+        flags |= RSOLVE_FLAG_RECYCLE_DROPPED;
+    }
+    residual_and_correct(s, A, b, k);
+    HIP_TRY(hipGetLastError());
+    const double stop_abs = tol * bnorm;
+    const double t_setup = ms_since(t0);
+
+    int its = 0, cycles = 0;
+    bool converged = false;
+    int status = RSOLVE_OK;
+    double gimp = 0.0;
+    const int m = c.restart_m;
+    const float* W32 = s->W32;
+    const float* Z32 = s->Z32;
+    for (;;) {
+        rc = read_head(s);
+        if (rc) return rc;
+        const double rnorm = s->hctl->rnorm;
+        if (s->hctl->nonfinite || !std::isfinite(rnorm)) {
+            flags |= RSOLVE_FLAG_NONFINITE;
+            status = RSOLVE_E_NONFINITE;
+            set_err("non-finite value in the iteration");
+            break;
+        }
+        if (rnorm <= stop_abs) {
+            converged = true;
+            break;
+        }
+        if (its >= c.max_iters) {
+            status = RSOLVE_NOT_CONVERGED;
+            break;
+        }
+        const int max_steps = std::min(m, c.max_iters - its);
+        const double cyc_stop = ir ? std::max(c.inner_tol * rnorm, stop_abs) : stop_abs;
+        launch_cycle_init(s->ctl, max_steps, cyc_stop, stm);
+        if (ir) {
+            launch_to_f32(ld, s->wb[0], s->w32[0], stm);
+            for (int j = 0; j < max_steps; ++j)
+                arnoldi_step<float>(s, j, A->row_ptr, A->col_idx, s->vals32, s->V32, s->w32, W32, Z32, k);
+        } else {
+            for (int j = 0; j < max_steps; ++j)
+                arnoldi_step<double>(s, j, A->row_ptr, A->col_idx, kv64, s->V, s->wb, s->W, s->Z, k);
+        }
+        launch_cycle_solve(s->ctl, stm);
+        if (ir) launch_x_update<float>(n, s->V32, ld, jac ? s->dinv : nullptr, s->xw, s->ctl, stm);
+        else launch_x_update<double>(n, s->V, ld, jac ? s->dinv : nullptr, s->xw, s->ctl, stm);
+        residual_and_correct(s, A, b, k);
+        HIP_TRY(hipGetLastError());
+        rc = read_head(s);
+        if (rc) return rc;
+        its += s->hctl->steps;
+        cycles += 1;
+        gimp = s->hctl->gimp;
+        if (s->hctl->lucky) flags |= RSOLVE_FLAG_BREAKDOWN_LUCKY;
+        if (s->hctl->steps == 0) {
+            // a cycle that cannot take a step cannot make progress
+            status = RSOLVE_NOT_CONVERGED;
+            break;
+        }
+    }
+    HIP_TRY(hipMemcpyAsync(x, s->xw, sizeof(double) * n, hipMemcpyDeviceToDevice, stm));
+    HIP_TRY(hipStreamSynchronize(stm));
+    s->have_x = true;
+    if (st) {
+        st->iterations = its;
+        st->cycles = cycles;
+        st->k_eff = k;
+        st->converged = converged ? 1 : 0;
+        st->flags = flags;
+        st->reserved = 0;
+        st->rel_res_true = s->hctl->rnorm / bnorm;
+        st->rel_res_implicit = gimp / bnorm;
+        st->t_setup_ms = t_setup;
+        st->t_total_ms = ms_since(t0);
+        st->t_cycles_ms = st->t_total_ms - t_setup;
+    }
+    return status;
+}
+
+int rsolve_update_recycle(rsolve_seq* s, const double* x) {
+    g_err[0] = 0;
+    if (!s) return RSOLVE_E_INVALID;
+    const double* src = x;
+    if (!src) {
+        if (!s->have_x) {
+            set_err("no solution to store yet");
+            return RSOLVE_E_STATE;
+        }
+        src = s->xw;
+    }
+    const rsolve_config& c = s->cfg;
+    if (c.recycle_k == 0 || c.snapshots_s == 0) {
+        s->count++;
+        return RSOLVE_OK;
+    }
+    HIP_TRY(hipSetDevice(s->device));
+    hipStream_t stm = s->stream;
+    const int64_t n = s->n, ld = s->ld;
+    const int slot = (int)(s->count % c.snapshots_s);
+    HIP_TRY(hipMemcpyAsync(s->X + (int64_t)slot * ld, src, sizeof(double) * n, hipMemcpyDeviceToDevice, stm));
+    s->count++;
+    if (s->count % c.svd_interval != 0) {
+        HIP_TRY(hipStreamSynchronize(stm));
+        return RSOLVE_OK;
+    }
+    const int cc = (int)std::min<int64_t>(s->count, c.snapshots_s);
+    // TSQR of the ring X (n x cc) down to one cc x cc R factor
+    const double* M = s->X;
+    int64_t ldm = ld, rows = n;
+    int lvl = 0;
+    const double* R = nullptr;
+    for (;;) {
+        const int P = (int)((rows + TSQR_PANEL - 1) / TSQR_PANEL);
+        double* out = s->tsq[lvl & 1];
+        launch_tsqr_level(rows, M, ldm, cc, out, s->tsq_ld, P, stm);
+        R = out;
+        if (P == 1) break;
+        M = out;
+        ldm = s->tsq_ld;
+        rows = (int64_t)P * cc;
+        ++lvl;
+    }
+    HIP_TRY(hipMemsetAsync(s->ctl, 0, CTL_HEAD, stm));
+    launch_jacobi_svd(R, s->tsq_ld, cc, c.recycle_k, n, s->ctl, stm);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(s->hsig, ctl_sigma(s->ctl), sizeof(double) * cc, hipMemcpyDeviceToHost, stm));
+    int rc = read_head(s);
+    if (rc) return rc;
+    for (int i = 0; i < cc; ++i) s->sigma[i] = s->hsig[i];
+    s->nsig = cc;
+    s->rank = s->hctl->rank;
+    if (s->hctl->nonfinite) {
+        s->k_w = 0;
+        set_err("non-finite snapshot");
+        return RSOLVE_E_NONFINITE;
+    }
+    const int keff = s->hctl->k_eff;
+    if (keff > 0) {
+        launch_form_w(n, ld, s->X, ld, cc, keff, s->ctl, s->W, ld, stm);
+        launch_gram_tn(ld, s->W, ld, keff, s->W, ld, keff, s->gpart, s->gblk, stm);
+        launch_gram_reduce(s->gpart, s->gblk, keff * keff, ctl_red(s->ctl), stm);
+        launch_cholesky(keff, s->ctl, stm);
+        launch_trsm_rows(ld, s->W, ld, keff, s->ctl, stm);
+        if (s->W32) launch_to_f32(keff * ld, s->W, s->W32, stm);
+        HIP_TRY(hipGetLastError());
+        rc = read_head(s);
+        if (rc) return rc;
+        if (s->hctl->lu_fail) {
+            s->k_w = 0;
+            return RSOLVE_OK;
+        }
+    }
+    s->k_w = keff;
+    return RSOLVE_OK;
+}
+
+int rsolve_get_recycle(rsolve_seq* s, int32_t* k_eff, int32_t* rank, double* sigma_host, int32_t cap, double* W_out,
+                       int64_t ld_out) {
+    if (!s) return RSOLVE_E_INVALID;
+    if (k_eff) *k_eff = s->k_w;
+    if (rank) *rank = s->rank;
+    if (sigma_host)
+        for (int i = 0; i < std::min<int>(cap, s->nsig); ++i) sigma_host[i] = s->sigma[i];
+    if (W_out && s->k_w > 0) {
+        if (ld_out < s->n) return RSOLVE_E_INVALID;
+        HIP_TRY(hipSetDevice(s->device));
+        HIP_TRY(hipMemcpy2DAsync(W_out, sizeof(double) * ld_out, s->W, sizeof(double) * s->ld, sizeof(double) * s->n,
+                                 s->k_w, hipMemcpyDeviceToDevice, s->stream));
+        HIP_TRY(hipStreamSynchronize(s->stream));
+    }
+    return RSOLVE_OK;
+}
+
+const char* rsolve_status_string(int status) {
+    switch (status) {
+        case RSOLVE_OK: return "ok";
+        case RSOLVE_NOT_CONVERGED: return "not converged";
+        case RSOLVE_E_INVALID: return "invalid argument";
+        case RSOLVE_E_NONFINITE: return "non-finite value";
+        case RSOLVE_E_WORKSPACE: return "workspace too small or misaligned";
+        case RSOLVE_E_DEVICE: return "HIP runtime error";
+        case RSOLVE_E_STATE: return "call out of order";
+        default: return "unknown status";
+    }
+}
+
+const char* rsolve_last_error(void) { return g_err; }
+
+// ---------------------------------------------------------------------------
+// kernel-level entry points
+// ---------------------------------------------------------------------------
+
+int rsolve_spmv(const rsolve_csr* A, const double* x, double* y, void* hip_stream) {
+    if (!A || !x || !y || !A->row_ptr || !A->col_idx || !A->val || A->n < 1) return RSOLVE_E_INVALID;
+    launch_spmv(pick_lpr(A->n, A->nnz), A->n, A->row_ptr, A->col_idx, A->val, x, y,
+                reinterpret_cast<hipStream_t>(hip_stream));
+    HIP_TRY(hipGetLastError());
+    return RSOLVE_OK;
+}
+
+namespace {
+struct KWs {
+    Ctl* ctl;
+    double* gpart;
+    double* t0;
+    double* t1;
+    int64_t tld;
+};
+size_t kws_layout(int64_t n, int cols, char* base, KWs* o) {
+    Carver cv{base};
+    Ctl* ctl = cv.take<Ctl>(1);
+    double* gp = cv.take<double>((size_t)256 * KMAX * KMAX);
+    const int64_t rows = ((n + TSQR_PANEL - 1) / TSQR_PANEL) * std::max(cols, 1);
+    const int64_t tld = pad64(rows);
+    double* t0 = cv.take<double>((size_t)tld * std::max(cols, 1));
+    double* t1 = cv.take<double>((size_t)tld * std::max(cols, 1));
+    if (o) *o = KWs{ctl, gp, t0, t1, tld};
+    return align_up(cv.off, ALIGN);
+}
+}  // namespace
+
+size_t rsolve_kernel_workspace_bytes(int64_t n, int32_t cols) {
+    if (n < 1 || cols < 0 || cols > 64) return 0;
+    return kws_layout(n, cols, nullptr, nullptr);
+}
+
+int rsolve_gram_tn(int64_t n, const double* A, int64_t lda, int32_t p, const double* B, int64_t ldb, int32_t q,
+                   double* C_host, void* workspace, size_t ws_bytes, void* hip_stream) {
+    if (n < 1 || !A || !B || !C_host || p < 1 || q < 1 || p > 64 || q > 64 || lda < n || ldb < n)
+        return RSOLVE_E_INVALID;
+    const int cols = std::max(p, q);
+    if (!workspace || ws_bytes < kws_layout(n, cols, nullptr, nullptr) ||
+        (reinterpret_cast<uintptr_t>(workspace) % ALIGN))
+        return RSOLVE_E_WORKSPACE;
+    KWs w;
+    kws_layout(n, cols, static_cast<char*>(workspace), &w);
+    hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+    const int gblk = pick_gblk(n);
+    launch_gram_tn(n, A, lda, p, B, ldb, q, w.gpart, gblk, st);
+    launch_gram_reduce(w.gpart, gblk, p * q, ctl_red(w.ctl), st);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(C_host, ctl_red(w.ctl), sizeof(double) * p * q, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return RSOLVE_OK;
+}
+
+int rsolve_snapshot_svd(int64_t n, const double* X, int64_t ldx, int32_t c, int32_t k, double* W_out, int64_t ldw,
+                        double* sigma_host, int32_t* k_eff, int32_t* rank, void* workspace, size_t ws_bytes,
+                        void* hip_stream) {
+    if (n < 1 || !X || c < 1 || c > 64 || k < 0 || k > 64 || ldx < n || (k > 0 && (!W_out || ldw < n)))
+        return RSOLVE_E_INVALID;
+    if (!workspace || ws_bytes < kws_layout(n, c, nullptr, nullptr) ||
+        (reinterpret_cast<uintptr_t>(workspace) % ALIGN))
+        return RSOLVE_E_WORKSPACE;
+    KWs w;
+    kws_layout(n, c, static_cast<char*>(workspace), &w);
+    hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+    HIP_TRY(hipMemsetAsync(w.ctl, 0, sizeof(Ctl), st));
+    const double* M = X;
+    int64_t ldm = ldx, rows = n;
+    const double* R = nullptr;
+    int lvl = 0;
+    for (;;) {
+        const int P = (int)((rows + TSQR_PANEL - 1) / TSQR_PANEL);
+        double* out = (lvl & 1) ? w.t1 : w.t0;
+        launch_tsqr_level(rows, M, ldm, c, out, w.tld, P, st);
+        R = out;
+        if (P == 1) break;
+        M = out;
+        ldm = w.tld;
+        rows = (int64_t)P * c;
+        ++lvl;
+    }
+    launch_jacobi_svd(R, w.tld, c, k, n, w.ctl, st);
+    HIP_TRY(hipGetLastError());
+    Ctl head;
+    HIP_TRY(hipMemcpyAsync(&head, w.ctl, CTL_HEAD, hipMemcpyDeviceToHost, st));
+    if (sigma_host) HIP_TRY(hipMemcpyAsync(sigma_host, ctl_sigma(w.ctl), sizeof(double) * c, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (rank) *rank = head.rank;
+    if (k_eff) *k_eff = head.k_eff;
+    const int keff = head.k_eff;
+    if (keff > 0) {
+        launch_form_w(n, n, X, ldx, c, keff, w.ctl, W_out, ldw, st);
+        const int gblk = pick_gblk(n);
+        launch_gram_tn(n, W_out, ldw, keff, W_out, ldw, keff, w.gpart, gblk, st);
+        launch_gram_reduce(w.gpart, gblk, keff * keff, ctl_red(w.ctl), st);
+        launch_cholesky(keff, w.ctl, st);
+        launch_trsm_rows(n, W_out, ldw, keff, w.ctl, st);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipStreamSynchronize(st));
+    }
+    return RSOLVE_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,473 @@
+// Dense kernels of the recycle space (section 5.2, Algorithm 1) and of the
+// projector setup (section 3.2, E = W^T A W):
+//   * tall-skinny C = A^T B on the float64 matrix cores (v_mfma_f64_16x16x4f64);
+//   * LU with partial pivoting of E and its 1-norm condition number;
+//   * one level of a Householder TSQR (panels of 256 rows, R factors stacked);
+//   * one-sided (Hestenes) Jacobi SVD of the final small R;
+//   * W = X V_k Sigma_k^{-1}, then W <- W L^{-T} with L L^T = W^T W.
+#include "kernels.hpp"
+
+namespace rs {
+
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------------------
+// C = A^T B on MFMA.  Each wavefront consumes 4 rows per MFMA: the A operand is
+// the 16 x 4 block (A^T)[i][row] (lane = i + 16 * row), the B operand the 4 x 16
+// block B[row][j] (lane = j + 16 * row).  The 16 x 16 result block holds
+// C[lane / 16 + 4 r][lane % 16] in element r of each lane.
+// ---------------------------------------------------------------------------
+template <int TP, int TQ>
+__global__ __launch_bounds__(BLOCK) void k_gram_tn(int64_t n, const double* __restrict__ A, int64_t lda, int p,
+                                                   const double* __restrict__ B, int64_t ldb, int q,
+                                                   double* __restrict__ partial, int nblk) {
+    __shared__ double acc_s[TP * 16 * TQ * 16];
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int wv = threadIdx.x / WAVE;
+    const int li = lane & 15, lk = lane >> 4;
+    d4 acc[TP][TQ];
+#pragma unroll
+    for (int a = 0; a < TP; ++a)
+#pragma unroll
+        for (int b = 0; b < TQ; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+    const int64_t ngroups = (n + 3) / 4;
+    for (int64_t g4 = (int64_t)blockIdx.x * 4 + wv; g4 < ngroups; g4 += (int64_t)nblk * 4) {
+        const int64_t row = g4 * 4 + lk;
+        const bool rok = row < n;
+        double av[TP], bv[TQ];
+#pragma unroll
+        for (int a = 0; a < TP; ++a) {
+            const int col = a * 16 + li;
+            av[a] = (rok && col < p) ? A[(int64_t)col * lda + row] : 0.0;
+        }
+#pragma unroll
+        for (int b = 0; b < TQ; ++b) {
+            const int col = b * 16 + li;
+            bv[b] = (rok && col < q) ? B[(int64_t)col * ldb + row] : 0.0;
+        }
+#pragma unroll
+        for (int a = 0; a < TP; ++a)
+#pragma unroll
+            for (int b = 0; b < TQ; ++b)
+                acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+    }
+    // fixed-order combination of the 4 wavefronts
+    constexpr int LD = TP * 16;
+    for (int w = 0; w < BLOCK / WAVE; ++w) {
+        if (wv == w) {
+#pragma unroll
+            for (int a = 0; a < TP; ++a)
+#pragma unroll
+                for (int b = 0; b < TQ; ++b)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int i = a * 16 + (lane >> 4) + 4 * r;
+                        const int j = b * 16 + (lane & 15);
+                        const double v = acc[a][b][r];
+                        if (w == 0) acc_s[i + LD * j] = v;
+                        else acc_s[i + LD * j] += v;
+                    }
+        }
+        __syncthreads();
+    }
+    const int pq = p * q;
+    for (int e = threadIdx.x; e < pq; e += BLOCK) {
+        const int i = e % p, j = e / p;
+        partial[(int64_t)blockIdx.x * pq + e] = acc_s[i + LD * j];
+    }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_gram_reduce(const double* __restrict__ partial, int nblk, int pq,
+                                                       double* __restrict__ dst) {
+    for (int e = threadIdx.x; e < pq; e += BLOCK) {
+        double s = 0.0;
+        for (int b = 0; b < nblk; ++b) s += partial[(int64_t)b * pq + e];
+        dst[e] = s;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// LU with partial pivoting of E (k x k <= 64), one wavefront, lane = row.
+// cond1 = ||E||_1 ||E^{-1}||_1 with the inverse formed column by column.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(WAVE) void k_small_lu(const double* __restrict__ src, int k, Ctl* __restrict__ ctl) {
+    constexpr int LDM = KMAX + 1;
+    __shared__ double M[KMAX * LDM];
+    __shared__ double X[KMAX * KMAX];
+    __shared__ int perm[KMAX];
+    const int lane = threadIdx.x;
+    for (int t = lane; t < k * k; t += WAVE) {
+        const int i = t % k, j = t / k;  // src column-major
+        M[i * LDM + j] = src[t];
+    }
+    if (lane < k) perm[lane] = lane;
+    __syncthreads();
+    // ||E||_1: column sums
+    double cs = 0.0;
+    if (lane < k)
+        for (int i = 0; i < k; ++i) cs += fabs(M[i * LDM + lane]);
+    const double norm1 = wave_max(lane < k ? cs : 0.0);
+    int fail = 0;
+    for (int j = 0; j < k; ++j) {
+        // pivot search among rows >= j (first index on ties)
+        double v = (lane >= j && lane < k) ? fabs(M[lane * LDM + j]) : -1.0;
+        int idx = lane;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const double ov = __shfl_xor(v, o, WAVE);
+            const int oi = __shfl_xor(idx, o, WAVE);
+            if (ov > v || (ov == v && oi < idx)) {
+                v = ov;
+                idx = oi;
+            }
+        }
+        const int pr = idx;
+        if (pr != j) {
+            for (int c = lane; c < k; c += WAVE) {
+                const double t = M[j * LDM + c];
+                M[j * LDM + c] = M[pr * LDM + c];
+                M[pr * LDM + c] = t;
+            }
+            if (lane == 0) {
+                const int t = perm[j];
+                perm[j] = perm[pr];
+                perm[pr] = t;
+            }
+        }
+        __syncthreads();
+        const double d = M[j * LDM + j];
+        if (d == 0.0 || !isfinite(d)) {
+            fail = 1;
+            break;
+        }
+        if (lane > j && lane < k) {
+            const double l = M[lane * LDM + j] / d;
+            M[lane * LDM + j] = l;
+            for (int c = j + 1; c < k; ++c) M[lane * LDM + c] -= l * M[j * LDM + c];
+        }
+        __syncthreads();
+    }
+    double cond = INFINITY;
+    if (!fail) {
+        // column `lane` of E^{-1}: solve L U x = P e_lane
+        if (lane < k) {
+            for (int i = 0; i < k; ++i) {
+                double s = (perm[i] == lane) ? 1.0 : 0.0;
+                for (int j = 0; j < i; ++j) s -= M[i * LDM + j] * X[j * KMAX + lane];
+                X[i * KMAX + lane] = s;
+            }
+            for (int i = k - 1; i >= 0; --i) {
+                double s = X[i * KMAX + lane];
+                for (int j = i + 1; j < k; ++j) s -= M[i * LDM + j] * X[j * KMAX + lane];
+                X[i * KMAX + lane] = s / M[i * LDM + i];
+            }
+        }
+        __syncthreads();
+        double ics = 0.0;
+        if (lane < k)
+            for (int i = 0; i < k; ++i) ics += fabs(X[i * KMAX + lane]);
+        const double inorm1 = wave_max(lane < k ? ics : 0.0);
+        cond = norm1 * inorm1;
+        if (!isfinite(cond)) cond = INFINITY;
+    }
+    for (int t = lane; t < k * k; t += WAVE) ctl->E[t] = M[(t / k) * LDM + (t % k)];
+    if (lane < k) ctl->piv[lane] = perm[lane];
+    if (lane == 0) {
+        ctl->cond1 = cond;
+        ctl->lu_fail = fail;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// One TSQR level.  Block p factors rows [p*256, p*256+256) of M (zero beyond
+// `rows`, columns padded with zeros up to C) by Householder reflections; thread
+// t holds row t of the panel in registers.  The column being eliminated is
+// always a[0]: after each reflection the finished column is written out (rows
+// t <= cc of R) and the register array shifts down by one, so every register
+// index is a compile-time constant.  Output: the c x c R factor of panel p in
+// rows [p*c, p*c + c) of S.
+// ---------------------------------------------------------------------------
+template <int C>
+__global__ __launch_bounds__(TSQR_PANEL) void k_tsqr_level(int64_t rows, const double* __restrict__ M, int64_t ldm,
+                                                           int c, double* __restrict__ S, int64_t lds) {
+    __shared__ double red[TSQR_PANEL / WAVE][C];
+    __shared__ double bc;
+    const int t = threadIdx.x;
+    const int wv = t / WAVE;
+    const int64_t row = (int64_t)blockIdx.x * TSQR_PANEL + t;
+    const int64_t orow = (int64_t)blockIdx.x * c + t;
+    double a[C];
+#pragma unroll
+    for (int j = 0; j < C; ++j) a[j] = (row < rows && j < c) ? M[(int64_t)j * ldm + row] : 0.0;
+    for (int cc = 0; cc < c; ++cc) {
+        // squared norm of the current column on rows >= cc
+        double s = (t >= cc) ? a[0] * a[0] : 0.0;
+        s = wave_sum(s);
+        __syncthreads();
+        if ((t & (WAVE - 1)) == 0) red[wv][0] = s;
+        if (t == cc) bc = a[0];
+        __syncthreads();
+        const double nrm2 = (red[0][0] + red[1][0]) + (red[2][0] + red[3][0]);
+        const double alpha = bc;
+        if (nrm2 > 0.0) {  // uniform; a zero column needs no reflection
+            const double nrm = sqrt(nrm2);
+            const double beta = (alpha >= 0.0) ? -nrm : nrm;
+            const double tau = (beta - alpha) / beta;
+            const double v = (t > cc) ? a[0] / (alpha - beta) : ((t == cc) ? 1.0 : 0.0);
+            double pr[C];
+            pr[0] = 0.0;
+#pragma unroll
+            for (int j = 1; j < C; ++j) pr[j] = v * a[j];
+            wave_tr_reduce<C>(pr);
+            __syncthreads();
+            if (wave_tr_owner<C>()) {
+#pragma unroll
+                for (int i = 0; i < wave_tr_left<C>(); ++i) red[wv][wave_tr_col<C>(i)] = pr[i];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int j = 1; j < C; ++j) {
+                const double d = (red[0][j] + red[1][j]) + (red[2][j] + red[3][j]);
+                a[j] -= tau * v * d;
+            }
+            if (t == cc) a[0] = beta;
+            else if (t > cc) a[0] = 0.0;
+        }
+        if (t < c) S[(int64_t)cc * lds + orow] = (t <= cc) ? a[0] : 0.0;
+#pragma unroll
+        for (int j = 0; j + 1 < C; ++j) a[j] = a[j + 1];
+        a[C - 1] = 0.0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// One-sided Jacobi SVD of R (c x c <= 64) in one block: columns are rotated in
+// pairs (round-robin ordering, 8 threads per pair) until all pairs are
+// numerically orthogonal; the rotations accumulate in V, so R V = U Sigma.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(BLOCK) void k_jacobi_svd(const double* __restrict__ R, int64_t ld, int c, int k,
+                                                      int64_t n, Ctl* __restrict__ ctl) {
+    constexpr int LDC = SMAX + 1;
+    __shared__ double Ac[(SMAX + 1) * LDC];   // column j at Ac[j * LDC + i]
+    __shared__ double Vc[(SMAX + 1) * LDC];
+    __shared__ double sig[SMAX + 1];
+    __shared__ int order[SMAX + 1];
+    __shared__ int rotated;
+    const int tid = threadIdx.x;
+    const int cp = (c + 1) & ~1;  // even number of players (a zero column pads odd c)
+    for (int t = tid; t < cp * cp; t += BLOCK) {
+        const int i = t % cp, j = t / cp;
+        Ac[j * LDC + i] = (i < c && j < c) ? R[(int64_t)j * ld + i] : 0.0;
+        Vc[j * LDC + i] = (i == j) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    const double tol = (double)(c > 1 ? c : 1) * 2.220446049250313e-16;
+    const int grp = tid >> 3, sub = tid & 7;
+    for (int sweep = 0; sweep < 60 && cp >= 2; ++sweep) {
+        if (tid == 0) rotated = 0;
+        __syncthreads();
+        for (int rnd = 0; rnd < cp - 1; ++rnd) {
+            if (grp < cp / 2) {
+                const int ia = grp, ib = cp - 1 - grp;
+                const int P = (ia == 0) ? 0 : 1 + ((ia - 1 + rnd) % (cp - 1));
+                const int Q = 1 + ((ib - 1 + rnd) % (cp - 1));
+                double al = 0.0, be = 0.0, ga = 0.0;
+                for (int i = sub; i < cp; i += 8) {
+                    const double x = Ac[P * LDC + i], y = Ac[Q * LDC + i];
+                    al += x * x;
+                    be += y * y;
+                    ga += x * y;
+                }
+#pragma unroll
+                for (int o = 4; o > 0; o >>= 1) {
+                    al += __shfl_xor(al, o, WAVE);
+                    be += __shfl_xor(be, o, WAVE);
+                    ga += __shfl_xor(ga, o, WAVE);
+                }
+                if (ga != 0.0 && fabs(ga) > tol * sqrt(al) * sqrt(be)) {
+                    const double zeta = (be - al) / (2.0 * ga);
+                    const double tt = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+                    const double cs = 1.0 / sqrt(1.0 + tt * tt);
+                    const double sn = cs * tt;
+                    for (int i = sub; i < cp; i += 8) {
+                        const double x = Ac[P * LDC + i], y = Ac[Q * LDC + i];
+                        Ac[P * LDC + i] = cs * x - sn * y;
+                        Ac[Q * LDC + i] = sn * x + cs * y;
+                        const double vx = Vc[P * LDC + i], vy = Vc[Q * LDC + i];
+                        Vc[P * LDC + i] = cs * vx - sn * vy;
+                        Vc[Q * LDC + i] = sn * vx + cs * vy;
+                    }
+                    if (sub == 0) rotated = 1;
+                }
+            }
+            __syncthreads();
+        }
+        if (!rotated) break;
+        __syncthreads();
+    }
+    // singular values = column norms, sorted descending (stable on ties)
+    if (tid < c) {
+        double s = 0.0;
+        for (int i = 0; i < c; ++i) s += Ac[tid * LDC + i] * Ac[tid * LDC + i];
+        sig[tid] = sqrt(s);
+    }
+    __syncthreads();
+    if (tid < c) {
+        int pos = 0;
+        for (int i = 0; i < c; ++i)
+            if (sig[i] > sig[tid] || (sig[i] == sig[tid] && i < tid)) ++pos;
+        order[pos] = tid;
+    }
+    __syncthreads();
+    const double s1 = (c > 0) ? sig[order[0]] : 0.0;
+    const double thr = s1 * (double)(n > c ? n : c) * 2.220446049250313e-16;
+    int rank = 0;
+    for (int i = 0; i < c; ++i)
+        if (sig[order[i]] > thr) ++rank;
+    if (!(s1 > 0.0) || !isfinite(s1)) rank = 0;
+    const int keff = rank < k ? rank : k;
+    for (int i = tid; i < c; i += BLOCK) ctl->sigma[i] = sig[order[i]];
+    for (int t = tid; t < c * keff; t += BLOCK) {
+        const int i = t / keff, j = t % keff;
+        ctl->T[i * KMAX + j] = Vc[order[j] * LDC + i] / sig[order[j]];
+    }
+    if (tid == 0) {
+        ctl->rank = rank;
+        ctl->k_eff = keff;
+        ctl->nonfinite = isfinite(s1) ? 0 : 1;
+    }
+}
+
+// W = X T (T = V_k Sigma_k^{-1}, c x k row-major in ctl); rows in [n, npad) are zeroed.
+template <int C>
+__global__ __launch_bounds__(BLOCK) void k_form_w(int64_t n, int64_t npad, const double* __restrict__ X,
+                                                  int64_t ldx, int c, int k, const Ctl* __restrict__ ctl,
+                                                  double* __restrict__ W, int64_t ldw) {
+    __shared__ double Ts[C * KMAX];
+    for (int t = threadIdx.x; t < c * k; t += BLOCK) Ts[(t / k) * KMAX + (t % k)] = ctl->T[(t / k) * KMAX + (t % k)];
+    __syncthreads();
+    const int64_t r = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (r >= npad) return;
+    double x[C];
+#pragma unroll
+    for (int i = 0; i < C; ++i) x[i] = (r < n && i < c) ? X[(int64_t)i * ldx + r] : 0.0;
+    for (int j = 0; j < k; ++j) {
+        double s = 0.0;
+#pragma unroll
+        for (int i = 0; i < C; ++i)
+            if (i < c) s += x[i] * Ts[i * KMAX + j];
+        W[(int64_t)j * ldw + r] = s;
+    }
+}
+
+// Cholesky of G = ctl->red (k x k, column-major) into ctl->L (row-major lower), one wavefront.
+__global__ __launch_bounds__(WAVE) void k_cholesky(int k, Ctl* __restrict__ ctl) {
+    constexpr int LDM = KMAX + 1;
+    __shared__ double G[KMAX * LDM];
+    const int lane = threadIdx.x;
+    for (int t = lane; t < k * k; t += WAVE) G[(t % k) * LDM + (t / k)] = ctl->red[t];
+    __syncthreads();
+    int fail = 0;
+    for (int j = 0; j < k; ++j) {
+        // G[j][j] holds the updated pivot
+        const double d = G[j * LDM + j];
+        if (!(d > 0.0)) {
+            fail = 1;
+            break;
+        }
+        const double ljj = sqrt(d);
+        __syncthreads();
+        if (lane == j) G[j * LDM + j] = ljj;
+        if (lane > j && lane < k) G[lane * LDM + j] /= ljj;
+        __syncthreads();
+        if (lane > j && lane < k) {
+            const double lij = G[lane * LDM + j];
+            for (int c2 = j + 1; c2 <= lane; ++c2) G[lane * LDM + c2] -= lij * G[c2 * LDM + j];
+        }
+        __syncthreads();
+    }
+    for (int t = lane; t < k * k; t += WAVE) {
+        const int i = t / k, j = t % k;
+        ctl->L[i * KMAX + j] = (j <= i) ? G[i * LDM + j] : 0.0;
+    }
+    if (lane == 0) ctl->lu_fail = fail;
+}
+
+// W[r, :] <- (L^{-1} W[r, :]^T)^T for every row: column-oriented forward
+// substitution with L in LDS; the unknown being finished is always w[0] and the
+// register array shifts down after each step.
+template <int K>
+__global__ __launch_bounds__(BLOCK) void k_trsm_rows(int64_t npad, double* __restrict__ W, int64_t ldw, int k,
+                                                     const Ctl* __restrict__ ctl) {
+    __shared__ double Ls[K * K];
+    for (int t = threadIdx.x; t < k * k; t += BLOCK) Ls[(t / k) * K + (t % k)] = ctl->L[(t / k) * KMAX + (t % k)];
+    __syncthreads();
+    const int64_t r = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (r >= npad) return;
+    double w[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) w[j] = (j < k) ? W[(int64_t)j * ldw + r] : 0.0;
+    for (int j = 0; j < k; ++j) {
+        const double xj = w[0] / Ls[j * K + j];
+        W[(int64_t)j * ldw + r] = xj;
+#pragma unroll
+        for (int i = 1; i < K; ++i)
+            if (j + i < k) w[i] -= Ls[(j + i) * K + j] * xj;
+#pragma unroll
+        for (int i = 0; i + 1 < K; ++i) w[i] = w[i + 1];
+        w[K - 1] = 0.0;
+    }
+}
+
+}  // namespace
+
+void launch_gram_tn(int64_t n, const double* A, int64_t lda, int p, const double* B, int64_t ldb, int q,
+                    double* partial, int nblk, hipStream_t st) {
+    const int tp = (p + 15) / 16, tq = (q + 15) / 16;
+#define RS_G(TPv, TQv) k_gram_tn<TPv, TQv><<<nblk, BLOCK, 0, st>>>(n, A, lda, p, B, ldb, q, partial, nblk)
+    if (tp <= 1 && tq <= 1) RS_G(1, 1);
+    else if (tp <= 2 && tq <= 2) RS_G(2, 2);
+    else if (tp <= 4 && tq <= 4) RS_G(4, 4);
+#undef RS_G
+}
+
+void launch_gram_reduce(const double* partial, int nblk, int pq, double* dst, hipStream_t st) {
+    k_gram_reduce<<<1, BLOCK, 0, st>>>(partial, nblk, pq, dst);
+}
+
+void launch_small_lu(const double* src, int k, Ctl* ctl, hipStream_t st) { k_small_lu<<<1, WAVE, 0, st>>>(src, k, ctl); }
+
+void launch_tsqr_level(int64_t rows, const double* M, int64_t ldm, int c, double* S, int64_t lds, int npanels,
+                       hipStream_t st) {
+    if (c <= 8) k_tsqr_level<8><<<npanels, TSQR_PANEL, 0, st>>>(rows, M, ldm, c, S, lds);
+    else if (c <= 16) k_tsqr_level<16><<<npanels, TSQR_PANEL, 0, st>>>(rows, M, ldm, c, S, lds);
+    else if (c <= 32) k_tsqr_level<32><<<npanels, TSQR_PANEL, 0, st>>>(rows, M, ldm, c, S, lds);
+    else k_tsqr_level<64><<<npanels, TSQR_PANEL, 0, st>>>(rows, M, ldm, c, S, lds);
+}
+
+void launch_jacobi_svd(const double* R, int64_t ld, int c, int k, int64_t n, Ctl* ctl, hipStream_t st) {
+    k_jacobi_svd<<<1, BLOCK, 0, st>>>(R, ld, c, k, n, ctl);
+}
+
+void launch_form_w(int64_t n, int64_t npad, const double* X, int64_t ldx, int c, int k, const Ctl* ctl, double* W,
+                   int64_t ldw, hipStream_t st) {
+    const unsigned g = (unsigned)((npad + BLOCK - 1) / BLOCK);
+    if (c <= 8) k_form_w<8><<<g, BLOCK, 0, st>>>(n, npad, X, ldx, c, k, ctl, W, ldw);
+    else if (c <= 16) k_form_w<16><<<g, BLOCK, 0, st>>>(n, npad, X, ldx, c, k, ctl, W, ldw);
+    else if (c <= 32) k_form_w<32><<<g, BLOCK, 0, st>>>(n, npad, X, ldx, c, k, ctl, W, ldw);
+    else k_form_w<64><<<g, BLOCK, 0, st>>>(n, npad, X, ldx, c, k, ctl, W, ldw);
+}
+
+void launch_cholesky(int k, Ctl* ctl, hipStream_t st) { k_cholesky<<<1, WAVE, 0, st>>>(k, ctl); }
+
+void launch_trsm_rows(int64_t npad, double* W, int64_t ldw, int k, const Ctl* ctl, hipStream_t st) {
+    const unsigned g = (unsigned)((npad + BLOCK - 1) / BLOCK);
+    if (k <= 8) k_trsm_rows<8><<<g, BLOCK, 0, st>>>(npad, W, ldw, k, ctl);
+    else if (k <= 16) k_trsm_rows<16><<<g, BLOCK, 0, st>>>(npad, W, ldw, k, ctl);
+    else if (k <= 32) k_trsm_rows<32><<<g, BLOCK, 0, st>>>(npad, W, ldw, k, ctl);
+    else k_trsm_rows<64><<<g, BLOCK, 0, st>>>(npad, W, ldw, k, ctl);
+}
+
+}  // namespace rs

@@ -1,0 +1,241 @@
+// Sparse kernels: CSR validation, Jacobi scaling, SpMV variants and the A W product.
+//
+// CSR SpMV uses LPR consecutive lanes of a 64-wide wavefront per row (LPR = 4, 8,
+// 16 or 32): a Q_p finite-element row holds 9..49 entries stored contiguously, so
+// the LPR lanes read a contiguous run of values and column indices, gather x, and
+// combine their partial sums with LPR-wide shuffles.  Accumulation is float64.
+#include "kernels.hpp"
+
+namespace rs {
+
+namespace {
+
+__global__ __launch_bounds__(BLOCK) void k_validate(int64_t n, int64_t nnz, const int32_t* __restrict__ rp,
+                                                    const int32_t* __restrict__ ci, int32_t* __restrict__ diag_pos,
+                                                    int32_t* __restrict__ err) {
+    const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (i >= n) return;
+    if (i == 0 && rp[0] != 0) err[0] = 1;
+    if (i == n - 1 && (int64_t)rp[n] != nnz) err[0] = 1;
+    const int64_t a = rp[i], b = rp[i + 1];
+    if (a < 0 || b < a || b > nnz) {
+        err[0] = 1;
+        diag_pos[i] = -1;
+        return;
+    }
+    int32_t d = -1;
+    int64_t prev = -1;
+    bool bad_col = false, bad_order = false;
+    for (int64_t k = a; k < b; ++k) {
+        const int64_t c = ci[k];
+        if (c < 0 || c >= n) bad_col = true;
+        if (c <= prev) bad_order = true;
+        if (c == i) d = (int32_t)k;
+        prev = c;
+    }
+    if (bad_col) err[1] = 1;
+    if (bad_order) err[2] = 1;
+    if (d < 0) err[3] = 1;
+    diag_pos[i] = d;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_diag_inv(int64_t n, const int32_t* __restrict__ dp,
+                                                    const double* __restrict__ val, double* __restrict__ dinv) {
+    const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (i >= n) return;
+    dinv[i] = 1.0 / val[dp[i]];
+}
+
+__global__ __launch_bounds__(BLOCK) void k_scale_values(int64_t nnz, const int32_t* __restrict__ ci,
+                                                        const double* __restrict__ val,
+                                                        const double* __restrict__ dinv, double* __restrict__ o64,
+                                                        float* __restrict__ o32) {
+    const int64_t k = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (k >= nnz) return;
+    double v = val[k];
+    if (dinv) v *= dinv[ci[k]];
+    if (o64) o64[k] = v;
+    if (o32) o32[k] = (float)v;
+}
+
+template <int LPR>
+__device__ __forceinline__ double group_sum(double v) {
+#pragma unroll
+    for (int o = LPR / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
+    return v;
+}
+
+// y = s * A win ; vout = s * win  (row-wise, s = ctl->inv_h)
+template <typename T, int LPR>
+__global__ __launch_bounds__(BLOCK) void k_spmv_arnoldi(int64_t n, const int32_t* __restrict__ rp,
+                                                        const int32_t* __restrict__ ci, const T* __restrict__ val,
+                                                        const T* __restrict__ win, T* __restrict__ vout,
+                                                        T* __restrict__ y, const Ctl* __restrict__ ctl) {
+    if (ctl->done) return;
+    const double s = ctl->inv_h;
+    const int64_t gt = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    const int64_t row = gt / LPR;
+    const int sub = (int)(gt % LPR);
+    double acc = 0.0;
+    const bool active = row < n;
+    if (active) {
+        const int a = rp[row], b = rp[row + 1];
+        for (int k = a + sub; k < b; k += LPR) acc += to_d(val[k]) * to_d(win[ci[k]]);
+    }
+    acc = group_sum<LPR>(acc);
+    if (active && sub == 0) {
+        y[row] = (T)(s * acc);
+        vout[row] = (T)(s * to_d(win[row]));
+    }
+}
+
+template <int LPR>
+__global__ __launch_bounds__(BLOCK) void k_residual(int64_t n, const int32_t* __restrict__ rp,
+                                                    const int32_t* __restrict__ ci, const double* __restrict__ val,
+                                                    const double* __restrict__ x, const double* __restrict__ b,
+                                                    double* __restrict__ r) {
+    const int64_t gt = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    const int64_t row = gt / LPR;
+    const int sub = (int)(gt % LPR);
+    double acc = 0.0;
+    const bool active = row < n;
+    if (active) {
+        const int a = rp[row], e = rp[row + 1];
+        for (int k = a + sub; k < e; k += LPR) acc += val[k] * x[ci[k]];
+    }
+    acc = group_sum<LPR>(acc);
+    if (active && sub == 0) r[row] = (b ? b[row] : 0.0) - acc;
+}
+
+template <int LPR>
+__global__ __launch_bounds__(BLOCK) void k_spmv(int64_t n, const int32_t* __restrict__ rp,
+                                                const int32_t* __restrict__ ci, const double* __restrict__ val,
+                                                const double* __restrict__ x, double* __restrict__ y) {
+    const int64_t gt = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    const int64_t row = gt / LPR;
+    const int sub = (int)(gt % LPR);
+    double acc = 0.0;
+    const bool active = row < n;
+    if (active) {
+        const int a = rp[row], e = rp[row + 1];
+        for (int k = a + sub; k < e; k += LPR) acc += val[k] * x[ci[k]];
+    }
+    acc = group_sum<LPR>(acc);
+    if (active && sub == 0) y[row] = acc;
+}
+
+// Z[:, c] = A W[:, c], c < k <= KC: the row's values and indices are read once for all k columns.
+template <int LPR, int KC>
+__global__ __launch_bounds__(BLOCK) void k_spmm(int64_t n, const int32_t* __restrict__ rp,
+                                                const int32_t* __restrict__ ci, const double* __restrict__ val,
+                                                const double* __restrict__ W, int64_t ld, int k,
+                                                double* __restrict__ Z) {
+    const int64_t gt = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    const int64_t row = gt / LPR;
+    const int sub = (int)(gt % LPR);
+    double acc[KC];
+#pragma unroll
+    for (int c = 0; c < KC; ++c) acc[c] = 0.0;
+    const bool active = row < n;
+    if (active) {
+        const int a = rp[row], e = rp[row + 1];
+        for (int j = a + sub; j < e; j += LPR) {
+            const double v = val[j];
+            const int64_t col = ci[j];
+#pragma unroll
+            for (int c = 0; c < KC; ++c)
+                if (c < k) acc[c] += v * W[c * ld + col];
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < KC; ++c) acc[c] = group_sum<LPR>(acc[c]);
+    if (active && sub == 0) {
+#pragma unroll
+        for (int c = 0; c < KC; ++c)
+            if (c < k) Z[c * ld + row] = acc[c];
+    }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_to_f32(int64_t count, const double* __restrict__ in,
+                                                  float* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (i < count) out[i] = (float)in[i];
+}
+
+inline unsigned grid_for(int64_t threads) { return (unsigned)((threads + BLOCK - 1) / BLOCK); }
+
+}  // namespace
+
+void launch_validate(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* ci, int32_t* diag_pos, int32_t* err,
+                     hipStream_t st) {
+    k_validate<<<grid_for(n), BLOCK, 0, st>>>(n, nnz, rp, ci, diag_pos, err);
+}
+
+void launch_diag_inv(int64_t n, const int32_t* dp, const double* val, double* dinv, hipStream_t st) {
+    k_diag_inv<<<grid_for(n), BLOCK, 0, st>>>(n, dp, val, dinv);
+}
+
+void launch_scale_values(int64_t nnz, const int32_t* ci, const double* val, const double* dinv, double* o64,
+                         float* o32, hipStream_t st) {
+    k_scale_values<<<grid_for(nnz), BLOCK, 0, st>>>(nnz, ci, val, dinv, o64, o32);
+}
+
+#define RS_LPR_DISPATCH(lpr, CALL) \
+    switch (lpr) {                 \
+        case 2: CALL(2); break;    \
+        case 4: CALL(4); break;    \
+        case 8: CALL(8); break;    \
+        case 16: CALL(16); break;  \
+        default: CALL(32); break;  \
+    }
+
+template <typename T>
+void launch_spmv_arnoldi(int lpr, int64_t n, const int32_t* rp, const int32_t* ci, const T* val, const T* win,
+                         T* vout, T* y, const Ctl* ctl, hipStream_t st) {
+#define RS_CALL(L) k_spmv_arnoldi<T, L><<<grid_for(n * L), BLOCK, 0, st>>>(n, rp, ci, val, win, vout, y, ctl)
+    RS_LPR_DISPATCH(lpr, RS_CALL)
+#undef RS_CALL
+}
+template void launch_spmv_arnoldi<double>(int, int64_t, const int32_t*, const int32_t*, const double*,
+                                          const double*, double*, double*, const Ctl*, hipStream_t);
+template void launch_spmv_arnoldi<float>(int, int64_t, const int32_t*, const int32_t*, const float*, const float*,
+                                         float*, float*, const Ctl*, hipStream_t);
+
+void launch_residual(int lpr, int64_t n, const int32_t* rp, const int32_t* ci, const double* val, const double* x,
+                     const double* b, double* r, hipStream_t st) {
+#define RS_CALL(L) k_residual<L><<<grid_for(n * L), BLOCK, 0, st>>>(n, rp, ci, val, x, b, r)
+    RS_LPR_DISPATCH(lpr, RS_CALL)
+#undef RS_CALL
+}
+
+void launch_spmv(int lpr, int64_t n, const int32_t* rp, const int32_t* ci, const double* val, const double* x,
+                 double* y, hipStream_t st) {
+#define RS_CALL(L) k_spmv<L><<<grid_for(n * L), BLOCK, 0, st>>>(n, rp, ci, val, x, y)
+    RS_LPR_DISPATCH(lpr, RS_CALL)
+#undef RS_CALL
+}
+
+void launch_spmm(int lpr, int64_t n, const int32_t* rp, const int32_t* ci, const double* val, const double* W,
+                 int64_t ld, int k, double* Z, hipStream_t st) {
+    // columns in chunks of 16 so the accumulators stay in registers
+    for (int c0 = 0; c0 < k; c0 += 16) {
+        const int kc = (k - c0) < 16 ? (k - c0) : 16;
+        const double* Wc = W + (int64_t)c0 * ld;
+        double* Zc = Z + (int64_t)c0 * ld;
+        if (kc <= 8) {
+#define RS_CALL(L) k_spmm<L, 8><<<grid_for(n * L), BLOCK, 0, st>>>(n, rp, ci, val, Wc, ld, kc, Zc)
+            RS_LPR_DISPATCH(lpr, RS_CALL)
+#undef RS_CALL
+        } else {
+#define RS_CALL(L) k_spmm<L, 16><<<grid_for(n * L), BLOCK, 0, st>>>(n, rp, ci, val, Wc, ld, kc, Zc)
+            RS_LPR_DISPATCH(lpr, RS_CALL)
+#undef RS_CALL
+        }
+    }
+}
+
+void launch_to_f32(int64_t count, const double* in, float* out, hipStream_t st) {
+    k_to_f32<<<grid_for(count), BLOCK, 0, st>>>(count, in, out);
+}
+
+}  // namespace rs

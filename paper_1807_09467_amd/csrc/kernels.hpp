@@ -1,0 +1,102 @@
+// Host-side launch wrappers of the rsolve kernels (one translation unit per kernel family).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.hpp"
+
+namespace rs {
+
+// ---- sparse (k_sparse.hip) ----
+// Pattern validation: err[0..3] receive nonzero on (row_ptr range, column range, unsorted or
+// duplicate columns, missing diagonal); diag_pos[i] = CSR index of A_ii.
+void launch_validate(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* ci, int32_t* diag_pos,
+                     int32_t* err, hipStream_t st);
+void launch_diag_inv(int64_t n, const int32_t* diag_pos, const double* val, double* dinv, hipStream_t st);
+// out64 / out32 (nullable) = val[k] * dinv[col[k]] (dinv nullable: plain copy / conversion)
+void launch_scale_values(int64_t nnz, const int32_t* ci, const double* val, const double* dinv, double* out64,
+                         float* out32, hipStream_t st);
+// Arnoldi product: vout[i] = s * win[i]; y[i] = s * sum_k val[k] win[col[k]], s = ctl->inv_h.
+template <typename T>
+void launch_spmv_arnoldi(int lpr, int64_t n, const int32_t* rp, const int32_t* ci, const T* val, const T* win,
+                         T* vout, T* y, const Ctl* ctl, hipStream_t st);
+// r = b - A x (float64)
+void launch_residual(int lpr, int64_t n, const int32_t* rp, const int32_t* ci, const double* val,
+                     const double* x, const double* b, double* r, hipStream_t st);
+// y = A x (float64)
+void launch_spmv(int lpr, int64_t n, const int32_t* rp, const int32_t* ci, const double* val, const double* x,
+                 double* y, hipStream_t st);
+// Z[:, c] = A W[:, c] for c < k (float64)
+void launch_spmm(int lpr, int64_t n, const int32_t* rp, const int32_t* ci, const double* val, const double* W,
+                 int64_t ld, int k, double* Z, hipStream_t st);
+// elementwise float64 -> float32 (count entries)
+void launch_to_f32(int64_t count, const double* in, float* out, hipStream_t st);
+
+// ---- Krylov cycle (k_krylov.hip) ----
+// Multi-dot sweep over up to 3 column groups: group q = columns bases[q][:, 0..counts[q]) dotted
+// with vecs[q]; partial[c * nblk + b] for the concatenated column index c.
+template <typename T>
+void launch_dots(int64_t npad, int64_t ld, const T* const* bases, const T* const* vecs, const int* counts,
+                 int ngroups, double* partial, int nblk, const Ctl* ctl, hipStream_t st);
+// pass-1 coefficients with the oblique projector folded in (see k_reduce_pass1)
+void launch_reduce_pass1(const double* partial, int nblk, int nv, int k, Ctl* ctl, hipStream_t st);
+// fixed-order sum of the partials into dst[0..ncol); if lu_solve, also ctl->cw = E^{-1} dst[nv..nv+nw)
+void launch_reduce(const double* partial, int nblk, int ncol, double* dst, Ctl* ctl, int nv, int nw,
+                   bool lu_solve, bool check_done, hipStream_t st);
+// w -= V[:, :nv] coefV + Z[:, :nz] coefZ; partial = V^T w (new)   (nv <= 64)
+template <typename T>
+void launch_update_dots(int64_t npad, const T* V, int64_t ld, int nv, const T* Z, int nz, T* w,
+                        const double* coefV, const double* coefZ, double* partial, int nblk, const Ctl* ctl,
+                        hipStream_t st);
+// w -= V[:, :nv] coefV + Z[:, :nz] coefZ (no dots); used when nv > 64
+template <typename T>
+void launch_update(int64_t npad, const T* V, int64_t ld, int nv, const T* Z, int nz, T* w, const double* coefV,
+                   const double* coefZ, int nblk, const Ctl* ctl, hipStream_t st);
+// w -= V[:, :nv] coef; partial[b] = sum over block b of w^2
+template <typename T>
+void launch_update_norm(int64_t npad, const T* V, int64_t ld, int nv, T* w, const double* coef,
+                        double* partial, int nblk, const Ctl* ctl, hipStream_t st);
+// column j of H: reduce ||w||^2, Givens update, stop test, next scale
+void launch_givens(const double* partial, int nblk, int j, Ctl* ctl, hipStream_t st);
+// start of a cycle: g = beta e1 with beta = ctl->rnorm, done/steps reset
+void launch_cycle_init(Ctl* ctl, int max_steps, double stop_abs, hipStream_t st);
+// y = R^{-1} g (ctl->steps unknowns)
+void launch_cycle_solve(Ctl* ctl, hipStream_t st);
+// x[i] += dinv[i] * sum_{c < steps} V[i, c] y[c]   (dinv nullable)
+template <typename T>
+void launch_x_update(int64_t n, const T* V, int64_t ld, const double* dinv, double* x, const Ctl* ctl,
+                     hipStream_t st);
+// x += W cw; r -= Z cw; partial = ||r||^2 per block (k may be 0: norm only)
+void launch_correct(int64_t npad, const double* W, const double* Z, int64_t ld, int k, double* x, double* r,
+                    const Ctl* ctl, double* partial, int nblk, hipStream_t st);
+// ctl->rnorm = sqrt(sum partial); ctl->nonfinite on NaN/Inf
+void launch_finish_norm(const double* partial, int nblk, Ctl* ctl, int which, hipStream_t st);
+// partial = ||v||^2 per block over n entries (caller vector, exact length)
+void launch_norm2(int64_t n, const double* v, double* partial, int nblk, hipStream_t st);
+// out[i] = in[i] for i < n, 0 for n <= i < npad
+void launch_copy_pad(int64_t n, int64_t npad, const double* in, double* out, hipStream_t st);
+
+// ---- dense (k_dense.hip) ----
+// partial[b][p*q] = A^T B over block b's rows (MFMA f64); rows >= n read as zero
+void launch_gram_tn(int64_t n, const double* A, int64_t lda, int p, const double* B, int64_t ldb, int q,
+                    double* partial, int nblk, hipStream_t st);
+// dst[p*q] (column-major) = fixed-order sum over blocks
+void launch_gram_reduce(const double* partial, int nblk, int pq, double* dst, hipStream_t st);
+// LU with partial pivoting of E (k x k, column-major in src) into ctl->E/piv, ctl->cond1
+void launch_small_lu(const double* src, int k, Ctl* ctl, hipStream_t st);
+// one TSQR level: panels of TSQR_PANEL rows of M (rows x c) -> stacked R factors S ((P*c) x c, ld_s)
+void launch_tsqr_level(int64_t rows, const double* M, int64_t ldm, int c, double* S, int64_t lds, int npanels,
+                       hipStream_t st);
+// one-sided Jacobi SVD of the c x c matrix R (column-major, ld); writes ctl->sigma, ctl->rank,
+// ctl->k_eff = min(k, rank), ctl->T = V_k Sigma_k^{-1}
+void launch_jacobi_svd(const double* R, int64_t ld, int c, int k, int64_t n, Ctl* ctl, hipStream_t st);
+// W[:, :k] = X[:, :c] T (T from ctl); rows >= n get zero
+void launch_form_w(int64_t n, int64_t npad, const double* X, int64_t ldx, int c, int k, const Ctl* ctl,
+                   double* W, int64_t ldw, hipStream_t st);
+// ctl->L = chol(G) for G = ctl->red (k x k column-major)
+void launch_cholesky(int k, Ctl* ctl, hipStream_t st);
+// W[r, :k] <- L^{-1} W[r, :k]^T (rows < npad)
+void launch_trsm_rows(int64_t npad, double* W, int64_t ldw, int k, const Ctl* ctl, hipStream_t st);
+
+}  // namespace rs

@@ -1,0 +1,278 @@
+"""ctypes binding of librsolve.so, the C-ABI declared in include/rsolve.h and
+include/rsolve_kernels.h.
+
+Argument marshalling only: every step of the solver runs in the library's HIP
+kernels.  PyTorch supplies device memory (the workspace and the caller's
+tensors) and the stream.  Importing this module does not load the library;
+`load()` does, and raises if it has not been built -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, byref, c_char_p, c_double, c_int, c_int32, c_int64, c_size_t, c_uint32, c_void_p
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "librsolve.so")
+
+OK, NOT_CONVERGED = 0, 1
+E_INVALID, E_NONFINITE, E_WORKSPACE, E_DEVICE, E_STATE = -1, -2, -3, -4, -5
+
+PLAIN, AUG_OBLIQUE, DEFL_OBLIQUE = 0, 1, 2
+PRECOND_NONE, PRECOND_JACOBI = 0, 1
+FP64, FP32_IR = 0, 1
+SAME_PATTERN = 1
+
+FLAG_RECYCLE_DROPPED = 1
+FLAG_BREAKDOWN_LUCKY = 2
+FLAG_NONFINITE = 4
+
+_METHODS = {"plain": PLAIN, "aug_oblique": AUG_OBLIQUE, "defl_oblique": DEFL_OBLIQUE}
+_PRECONDS = {"none": PRECOND_NONE, "jacobi": PRECOND_JACOBI}
+_PRECISIONS = {"fp64": FP64, "fp32_ir": FP32_IR}
+
+# every symbol the two public headers declare
+EXPORTS = [
+    "rsolve_workspace_bytes", "rsolve_create_sequence", "rsolve_solve", "rsolve_update_recycle",
+    "rsolve_get_recycle", "rsolve_destroy_sequence", "rsolve_status_string", "rsolve_last_error",
+    "rsolve_spmv", "rsolve_kernel_workspace_bytes", "rsolve_gram_tn", "rsolve_snapshot_svd",
+]
+
+
+class Config(ctypes.Structure):
+    _fields_ = [
+        ("restart_m", c_int32), ("recycle_k", c_int32), ("snapshots_s", c_int32), ("svd_interval", c_int32),
+        ("method", c_int32), ("precond", c_int32), ("precision", c_int32), ("max_iters", c_int32),
+        ("select", c_int32), ("reserved", c_int32), ("inner_tol", c_double),
+    ]
+
+
+class CSR(ctypes.Structure):
+    _fields_ = [
+        ("n", c_int64), ("nnz", c_int64), ("row_ptr", c_void_p), ("col_idx", c_void_p), ("val", c_void_p),
+        ("flags", c_uint32), ("reserved", c_uint32),
+    ]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [
+        ("iterations", c_int32), ("cycles", c_int32), ("k_eff", c_int32), ("converged", c_int32),
+        ("flags", c_uint32), ("reserved", c_int32), ("rel_res_true", c_double), ("rel_res_implicit", c_double),
+        ("t_setup_ms", c_double), ("t_cycles_ms", c_double), ("t_total_ms", c_double),
+    ]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+
+
+class RsolveError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"rsolve status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def load():
+    """Load librsolve.so (built in-tree by __graft_entry__.build()); raise if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built: run `python -c 'import __graft_entry__ as g; g.build()'`")
+    lib = ctypes.CDLL(LIB_PATH)
+    lib.rsolve_workspace_bytes.argtypes = [POINTER(Config), c_int64, c_int64]
+    lib.rsolve_workspace_bytes.restype = c_size_t
+    lib.rsolve_create_sequence.argtypes = [POINTER(Config), c_int64, c_int64, c_void_p, c_void_p, c_size_t,
+                                           POINTER(c_void_p)]
+    lib.rsolve_create_sequence.restype = c_int
+    lib.rsolve_solve.argtypes = [c_void_p, POINTER(CSR), c_void_p, c_void_p, c_void_p, c_double, POINTER(Stats)]
+    lib.rsolve_solve.restype = c_int
+    lib.rsolve_update_recycle.argtypes = [c_void_p, c_void_p]
+    lib.rsolve_update_recycle.restype = c_int
+    lib.rsolve_get_recycle.argtypes = [c_void_p, POINTER(c_int32), POINTER(c_int32), POINTER(c_double), c_int32,
+                                       c_void_p, c_int64]
+    lib.rsolve_get_recycle.restype = c_int
+    lib.rsolve_destroy_sequence.argtypes = [c_void_p]
+    lib.rsolve_destroy_sequence.restype = c_int
+    lib.rsolve_status_string.argtypes = [c_int]
+    lib.rsolve_status_string.restype = c_char_p
+    lib.rsolve_last_error.argtypes = []
+    lib.rsolve_last_error.restype = c_char_p
+    lib.rsolve_spmv.argtypes = [POINTER(CSR), c_void_p, c_void_p, c_void_p]
+    lib.rsolve_spmv.restype = c_int
+    lib.rsolve_kernel_workspace_bytes.argtypes = [c_int64, c_int32]
+    lib.rsolve_kernel_workspace_bytes.restype = c_size_t
+    lib.rsolve_gram_tn.argtypes = [c_int64, c_void_p, c_int64, c_int32, c_void_p, c_int64, c_int32,
+                                   POINTER(c_double), c_void_p, c_size_t, c_void_p]
+    lib.rsolve_gram_tn.restype = c_int
+    lib.rsolve_snapshot_svd.argtypes = [c_int64, c_void_p, c_int64, c_int32, c_int32, c_void_p, c_int64,
+                                        POINTER(c_double), POINTER(c_int32), POINTER(c_int32), c_void_p, c_size_t,
+                                        c_void_p]
+    lib.rsolve_snapshot_svd.restype = c_int
+    _lib = lib
+    return lib
+
+
+def _check(status, allow=(OK,)):
+    if status in allow:
+        return status
+    lib = load()
+    raise RsolveError(status, f"{lib.rsolve_status_string(status).decode()}: {lib.rsolve_last_error().decode()}")
+
+
+def make_config(restart_m=30, recycle_k=0, snapshots_s=0, svd_interval=1, method="aug_oblique", precond="none",
+                precision="fp64", max_iters=10000, inner_tol=1e-5) -> Config:
+    return Config(restart_m, recycle_k, snapshots_s, svd_interval, _METHODS[method], _PRECONDS[precond],
+                  _PRECISIONS[precision], max_iters, 0, 0, float(inner_tol))
+
+
+def workspace_bytes(cfg: Config, n: int, nnz_max: int) -> int:
+    return int(load().rsolve_workspace_bytes(byref(cfg), n, nnz_max))
+
+
+def _ptr(t, dtype, numel=None, name="tensor"):
+    import torch
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} must have {numel} entries, got {t.numel()}")
+    return t.data_ptr()
+
+
+def _stream_handle(stream):
+    return c_void_p(stream.cuda_stream) if stream is not None else c_void_p(0)
+
+
+class Sequence:
+    """One time-stepping sequence (rsolve_create_sequence ... rsolve_destroy_sequence)."""
+
+    def __init__(self, n, nnz_max, device=None, stream=None, **cfg):
+        import torch
+        self.lib = load()
+        self.cfg = make_config(**cfg)
+        self.n = int(n)
+        self.nnz_max = int(nnz_max)
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        nbytes = workspace_bytes(self.cfg, self.n, self.nnz_max)
+        if nbytes == 0:
+            raise RsolveError(E_INVALID, "invalid configuration or sizes")
+        self.workspace_bytes = nbytes
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = c_void_p()
+        with torch.cuda.device(self.device):
+            _check(self.lib.rsolve_create_sequence(byref(self.cfg), self.n, self.nnz_max,
+                                                   _stream_handle(self.stream), c_void_p(self.ws.data_ptr()),
+                                                   nbytes, byref(h)))
+        self.handle = h
+
+    def solve(self, row_ptr, col_idx, val, b, x0=None, x=None, tol=1e-8, same_pattern=False, check=True):
+        """Solve A x = b; returns (x, stats dict, status)."""
+        import torch
+        n = self.n
+        nnz = int(val.numel())
+        A = CSR(n, nnz, _ptr(row_ptr, torch.int32, n + 1, "row_ptr"), _ptr(col_idx, torch.int32, nnz, "col_idx"),
+                _ptr(val, torch.float64, nnz, "val"), SAME_PATTERN if same_pattern else 0, 0)
+        if x is None:
+            x = torch.empty(n, dtype=torch.float64, device=self.device)
+        st = Stats()
+        with torch.cuda.device(self.device):
+            status = self.lib.rsolve_solve(self.handle, byref(A), c_void_p(_ptr(b, torch.float64, n, "b")),
+                                           c_void_p(_ptr(x0, torch.float64, n, "x0")),
+                                           c_void_p(_ptr(x, torch.float64, n, "x")), float(tol), byref(st))
+        if check:
+            _check(status, allow=(OK, NOT_CONVERGED))
+        return x, st.as_dict(), status
+
+    def update(self, x=None, check=True):
+        import torch
+        with torch.cuda.device(self.device):
+            status = self.lib.rsolve_update_recycle(self.handle, c_void_p(_ptr(x, torch.float64, self.n, "x")))
+        if check:
+            _check(status)
+        return status
+
+    def recycle(self, with_basis=False):
+        import torch
+        k = c_int32()
+        r = c_int32()
+        cap = 64
+        sig = (c_double * cap)()
+        _check(self.lib.rsolve_get_recycle(self.handle, byref(k), byref(r), sig, cap, None, 0))
+        out = {"k_eff": k.value, "rank": r.value, "sigma": [sig[i] for i in range(cap)]}
+        if with_basis:
+            W = torch.zeros((max(k.value, 0), self.n), dtype=torch.float64, device=self.device)
+            if k.value > 0:
+                with torch.cuda.device(self.device):
+                    _check(self.lib.rsolve_get_recycle(self.handle, byref(k), byref(r), None, 0,
+                                                       c_void_p(W.data_ptr()), self.n))
+            out["W"] = W
+        return out
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            self.lib.rsolve_destroy_sequence(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def spmv(row_ptr, col_idx, val, x, y=None, stream=None):
+    import torch
+    lib = load()
+    n = int(row_ptr.numel()) - 1
+    nnz = int(val.numel())
+    if y is None:
+        y = torch.empty(n, dtype=torch.float64, device=x.device)
+    A = CSR(n, nnz, _ptr(row_ptr, torch.int32, n + 1, "row_ptr"), _ptr(col_idx, torch.int32, nnz, "col_idx"),
+            _ptr(val, torch.float64, nnz, "val"), 0, 0)
+    _check(lib.rsolve_spmv(byref(A), c_void_p(_ptr(x, torch.float64, n, "x")), c_void_p(_ptr(y, torch.float64, n, "y")),
+                           _stream_handle(stream)))
+    return y
+
+
+def _kernel_ws(n, cols, device):
+    import torch
+    nbytes = int(load().rsolve_kernel_workspace_bytes(n, cols))
+    return torch.empty(nbytes, dtype=torch.uint8, device=device), nbytes
+
+
+def gram_tn(A, B, stream=None):
+    """C = A^T B for column-major tall A (p x n storage: A[c] is column c) and B; returns a numpy array."""
+    import numpy as np
+    lib = load()
+    p, n = A.shape
+    q, n2 = B.shape
+    assert n == n2
+    ws, nbytes = _kernel_ws(n, max(p, q), A.device)
+    C = (c_double * (p * q))()
+    _check(lib.rsolve_gram_tn(n, c_void_p(A.data_ptr()), n, p, c_void_p(B.data_ptr()), n, q, C,
+                              c_void_p(ws.data_ptr()), nbytes, _stream_handle(stream)))
+    return np.frombuffer(C, dtype=np.float64).reshape(q, p).T.copy()
+
+
+def snapshot_svd(X, k, stream=None):
+    """TSQR + Jacobi SVD + basis formation on X given as (c, n) (row c = snapshot c)."""
+    import numpy as np
+    import torch
+    lib = load()
+    c, n = X.shape
+    ws, nbytes = _kernel_ws(n, c, X.device)
+    W = torch.zeros((max(k, 1), n), dtype=torch.float64, device=X.device)
+    sig = (c_double * c)()
+    ke = c_int32()
+    rk = c_int32()
+    _check(lib.rsolve_snapshot_svd(n, c_void_p(X.data_ptr()), n, c, k, c_void_p(W.data_ptr()), n, sig, byref(ke),
+                                   byref(rk), c_void_p(ws.data_ptr()), nbytes, _stream_handle(stream)))
+    return W[: ke.value], np.array(sig[:]), ke.value, rk.value

@@ -1,0 +1,107 @@
+"""C-ABI contract checks that need no GPU: the library loads, exports every
+function the public headers declare, sizes its workspace, and rejects bad
+configurations before touching the device."""
+import ctypes
+import glob
+import os
+import re
+
+import pytest
+
+from paper_1807_09467_amd import rsolve
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        text = open(h).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for m in re.finditer(r"\b(rsolve_\w+)\s*\(", text):
+            names.add(m.group(1))
+    return sorted(names)
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(rsolve.LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+    return rsolve.load()
+
+
+def test_headers_declare_the_binding_exports():
+    assert set(declared_functions()) == set(rsolve.EXPORTS)
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+        assert isinstance(getattr(lib, name), ctypes._CFuncPtr)
+
+
+def test_struct_layouts():
+    assert ctypes.sizeof(rsolve.Config) == 48
+    assert ctypes.sizeof(rsolve.CSR) == 48
+    assert ctypes.sizeof(rsolve.Stats) == 64
+
+
+def test_workspace_bytes_valid_and_monotone(lib):
+    cfg = rsolve.make_config(restart_m=30, recycle_k=5, snapshots_s=10)
+    a = rsolve.workspace_bytes(cfg, 1089, 8409)
+    b = rsolve.workspace_bytes(cfg, 4225, 37249)
+    assert 0 < a < b and a % 256 == 0
+    big = rsolve.make_config(restart_m=50, recycle_k=16, snapshots_s=32)
+    assert rsolve.workspace_bytes(big, 1089, 8409) > a
+    # mixed precision keeps float32 copies of the Krylov basis instead of float64
+    fp64 = rsolve.workspace_bytes(rsolve.make_config(restart_m=50, recycle_k=16, snapshots_s=32, precond="jacobi"),
+                                  2362369, 58789033)
+    ir = rsolve.workspace_bytes(rsolve.make_config(restart_m=50, recycle_k=16, snapshots_s=32, precond="jacobi",
+                                                   precision="fp32_ir"), 2362369, 58789033)
+    assert ir < fp64 < 4 * 2 ** 30
+
+
+@pytest.mark.parametrize("bad", [
+    dict(restart_m=0), dict(restart_m=129), dict(recycle_k=65, snapshots_s=65), dict(recycle_k=5, snapshots_s=3),
+    dict(svd_interval=0), dict(max_iters=0), dict(precision="fp32_ir", inner_tol=0.0),
+    dict(precision="fp32_ir", inner_tol=1.0),
+])
+def test_invalid_configs_rejected(lib, bad):
+    kw = dict(restart_m=30)
+    kw.update(bad)
+    cfg = rsolve.make_config(**kw)
+    assert rsolve.workspace_bytes(cfg, 100, 500) == 0
+    h = ctypes.c_void_p()
+    rc = lib.rsolve_create_sequence(ctypes.byref(cfg), 100, 500, None, None, 0, ctypes.byref(h))
+    assert rc == rsolve.E_INVALID and not h.value
+
+
+def test_bad_sizes_and_workspace(lib):
+    cfg = rsolve.make_config()
+    assert rsolve.workspace_bytes(cfg, 0, 10) == 0
+    assert rsolve.workspace_bytes(cfg, 100, 50) == 0     # nnz < n
+    h = ctypes.c_void_p()
+    rc = lib.rsolve_create_sequence(ctypes.byref(cfg), 100, 500, None, None, 0, ctypes.byref(h))
+    assert rc == rsolve.E_WORKSPACE
+    assert b"workspace" in lib.rsolve_last_error()
+    # a misaligned workspace pointer is refused before any device call
+    rc = lib.rsolve_create_sequence(ctypes.byref(cfg), 100, 500, None, ctypes.c_void_p(0x1001), 1 << 30,
+                                    ctypes.byref(h))
+    assert rc == rsolve.E_WORKSPACE
+
+
+def test_null_handles_rejected(lib):
+    st = rsolve.Stats()
+    assert lib.rsolve_solve(None, None, None, None, None, 1e-8, ctypes.byref(st)) == rsolve.E_INVALID
+    assert lib.rsolve_update_recycle(None, None) == rsolve.E_INVALID
+    assert lib.rsolve_destroy_sequence(None) == rsolve.E_INVALID
+    assert lib.rsolve_get_recycle(None, None, None, None, 0, None, 0) == rsolve.E_INVALID
+    assert lib.rsolve_kernel_workspace_bytes(0, 4) == 0
+    assert lib.rsolve_kernel_workspace_bytes(100, 65) == 0
+
+
+def test_status_strings(lib):
+    for code in (0, 1, -1, -2, -3, -4, -5):
+        assert lib.rsolve_status_string(code)
+    assert lib.rsolve_status_string(12345) == b"unknown status"

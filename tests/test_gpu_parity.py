@@ -1,0 +1,271 @@
+"""GPU parity: the HIP path (through the C-ABI) against the FP64 oracle on the
+same seeded inputs.  Bars: float64 solutions within 1e-9 relative of the
+oracle at tol 1e-10 with Arnoldi-step counts within +-2 per solve; float32-inner
+refinement within 1e-8 relative of a tight oracle solution; kernel building
+blocks against NumPy within float64 rounding bounds."""
+import numpy as np
+import pytest
+
+from oracle import rgmres as O
+from paper_1807_09467_amd import workload as WL
+
+pytestmark = pytest.mark.gpu
+
+
+def _t(a, dev):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+
+def run_pair(dev, prob, steps, tol, seed=0, precision="fp64", oracle_tol=None, **kw):
+    """Run the same generated sequence through the GPU solver and the oracle."""
+    from paper_1807_09467_amd import rsolve
+    asm, systems, _ = WL.march(prob, steps, seed)
+    pat = asm.pat
+    rp, ci = _t(pat.row_ptr, dev), _t(pat.col_idx, dev)
+    seq = rsolve.Sequence(pat.n, pat.nnz, device=dev, precision=precision, **kw)
+    ocfg = O.Config(restart_m=kw.get("restart_m", 30), recycle_k=kw.get("recycle_k", 0),
+                    snapshots_s=kw.get("snapshots_s", 0), svd_interval=kw.get("svd_interval", 1),
+                    method={"plain": O.PLAIN, "aug_oblique": O.AUG_OBLIQUE, "defl_oblique": O.DEFL_OBLIQUE}[
+                        kw.get("method", "aug_oblique")],
+                    precond=O.PRECOND_JACOBI if kw.get("precond") == "jacobi" else O.PRECOND_NONE)
+    ost = O.RecycleState(pat.n, ocfg)
+    import torch
+    xg_prev = torch.zeros(pat.n, dtype=torch.float64, device=dev)
+    xo_prev = np.zeros(pat.n)
+    out = []
+    for i, (vals, b) in enumerate(systems):
+        A = asm.csr(vals)
+        x, st, status = seq.solve(rp, ci, _t(vals, dev), _t(b, dev), x0=xg_prev, tol=tol, same_pattern=i > 0)
+        seq.update()
+        ores = O.solve(A, b, xo_prev, oracle_tol or tol, ocfg, ost.W)
+        ost.update(ores.x)
+        xg = x.cpu().numpy()
+        out.append(dict(step=i, status=status, st=st, ores=ores, xg=xg, A=A, b=b,
+                        rel=np.linalg.norm(xg - ores.x) / np.linalg.norm(ores.x),
+                        res=np.linalg.norm(b - A @ xg) / np.linalg.norm(b),
+                        rec=seq.recycle(), orec=(ost.W.shape[1], ost.rank, ost.sigma.copy())))
+        xg_prev, xo_prev = x, ores.x
+    seq.close()
+    return out
+
+
+# -- kernel building blocks ------------------------------------------------------------
+
+
+@pytest.mark.parametrize("prob", [WL.C1, WL.C2_SMALL, WL.C3_SMALL])
+def test_spmv_matches_host(gpu_ctx, prob):
+    from paper_1807_09467_amd import rsolve
+    asm = WL.Assembler(prob)
+    vals = asm.matrix_values(WL.initial_condition(prob, 2))
+    A = asm.csr(vals)
+    x = np.random.default_rng(0).standard_normal(A.shape[0])
+    y = rsolve.spmv(_t(asm.pat.row_ptr, gpu_ctx), _t(asm.pat.col_idx, gpu_ctx), _t(vals, gpu_ctx), _t(x, gpu_ctx))
+    ref = A @ x
+    assert np.abs(y.cpu().numpy() - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("n", [1, 3, 64, 1000, 10007])
+@pytest.mark.parametrize("p,q", [(1, 1), (5, 5), (16, 16), (17, 3), (33, 40), (64, 64)])
+def test_gram_tn_mfma(gpu_ctx, n, p, q):
+    from paper_1807_09467_amd import rsolve
+    rng = np.random.default_rng(n * 100 + p)
+    A = rng.standard_normal((p, n))
+    B = rng.standard_normal((q, n))
+    C = rsolve.gram_tn(_t(A, gpu_ctx), _t(B, gpu_ctx))
+    ref = A @ B.T
+    bound = 1e-14 * n * np.sqrt(np.outer((A * A).sum(1), (B * B).sum(1))) + 1e-300
+    assert np.all(np.abs(C - ref) <= bound), np.abs(C - ref).max()
+
+
+@pytest.mark.parametrize("n,c,k", [(50, 4, 3), (1089, 10, 5), (4000, 20, 10), (70001, 32, 16), (300, 64, 64)])
+def test_snapshot_svd_against_lapack(gpu_ctx, n, c, k):
+    from paper_1807_09467_amd import rsolve
+    rng = np.random.default_rng(c)
+    U, _ = np.linalg.qr(rng.standard_normal((n, c)))
+    Vt, _ = np.linalg.qr(rng.standard_normal((c, c)))
+    sig = 10.0 ** (-0.35 * np.arange(c))          # graded spectrum with relative gaps ~ 0.55
+    X = (U * sig) @ Vt.T
+    W, s_gpu, keff, rank = rsolve.snapshot_svd(_t(X.T, gpu_ctx), k)
+    s_ref = np.linalg.svd(X, compute_uv=False)
+    rank_ref = int(np.sum(s_ref > s_ref[0] * max(n, c) * np.finfo(float).eps))
+    assert rank == rank_ref and keff == min(k, rank_ref)
+    # singular values: absolute error bounded by eps * sigma_1 (backward stable QR + Jacobi)
+    assert np.all(np.abs(s_gpu - s_ref) <= 64 * c * np.finfo(float).eps * s_ref[0])
+    Wn = W.cpu().numpy().T
+    assert np.abs(Wn.T @ Wn - np.eye(keff)).max() <= 1e-13
+    # subspace of the leading keff singular vectors (principal angles), gap-scaled
+    Uk = np.linalg.svd(X, full_matrices=False)[0][:, :keff]
+    cosines = np.linalg.svd(Uk.T @ Wn, compute_uv=False)
+    gap = (s_ref[keff - 1] - s_ref[keff]) / s_ref[0] if keff < c else 1.0
+    assert 1.0 - cosines.min() <= max(1e-24 / gap ** 2, 1e-14) * 100
+
+
+def test_snapshot_svd_rank_deficient(gpu_ctx):
+    from paper_1807_09467_amd import rsolve
+    rng = np.random.default_rng(9)
+    x, y = rng.standard_normal(777), rng.standard_normal(777)
+    X = np.column_stack([x, y, x, 2 * y, x + y, 0 * x])
+    W, s_gpu, keff, rank = rsolve.snapshot_svd(_t(X.T, gpu_ctx), 4)
+    assert rank == 2 and keff == 2
+    B, _ = np.linalg.qr(np.column_stack([x, y]))
+    Wn = W.cpu().numpy().T
+    assert np.linalg.svd(B.T @ Wn, compute_uv=False).min() >= 1 - 1e-12
+
+
+# -- whole solves against the oracle ----------------------------------------------------
+
+
+def _check_parity(out, rel_bar=1e-9, its_bar=2):
+    for r in out:
+        assert r["status"] == 0, (r["step"], r["status"])
+        assert r["st"]["converged"] == 1
+        assert r["rel"] <= rel_bar, (r["step"], r["rel"])
+        assert abs(r["st"]["iterations"] - r["ores"].iterations) <= its_bar, (
+            r["step"], r["st"]["iterations"], r["ores"].iterations)
+        assert r["st"]["k_eff"] == r["ores"].k_eff, (r["step"], r["st"]["k_eff"], r["ores"].k_eff)
+
+
+def test_plain_fp64_c1(gpu_ctx):
+    out = run_pair(gpu_ctx, WL.C1, 5, 1e-10, restart_m=30, method="plain")
+    _check_parity(out)
+
+
+def test_recycled_fp64_c1_full_sequence(gpu_ctx):
+    """The small configuration in full: Q1 32x32, 20 steps, GMRES(30), k=5, s=10, tol 1e-10."""
+    out = run_pair(gpu_ctx, WL.C1, 20, 1e-10, restart_m=30, recycle_k=5, snapshots_s=10)
+    _check_parity(out)
+    # recycle state agrees: rank and singular values of the snapshot ring
+    for r in out:
+        k_gpu, rank_gpu, sig_gpu = r["rec"]["k_eff"], r["rec"]["rank"], np.array(r["rec"]["sigma"])
+        k_or, rank_or, sig_or = r["orec"]
+        assert k_gpu == k_or and rank_gpu == rank_or
+        c = len(sig_or)
+        assert np.all(np.abs(sig_gpu[:c] - sig_or) <= 1e-9 * sig_or[0])
+
+
+@pytest.mark.parametrize("prob,m,k,s", [(WL.C2_SMALL, 30, 10, 20), (WL.C3_SMALL, 50, 16, 32)])
+def test_recycled_fp64_jacobi(gpu_ctx, prob, m, k, s):
+    out = run_pair(gpu_ctx, prob, 12, 1e-10, restart_m=m, recycle_k=k, snapshots_s=s, precond="jacobi")
+    _check_parity(out)
+
+
+def test_deflated_equals_augmented(gpu_ctx):
+    a = run_pair(gpu_ctx, WL.C1, 6, 1e-10, restart_m=30, recycle_k=5, snapshots_s=10, method="aug_oblique")
+    d = run_pair(gpu_ctx, WL.C1, 6, 1e-10, restart_m=30, recycle_k=5, snapshots_s=10, method="defl_oblique")
+    for ra, rd in zip(a, d):
+        assert np.array_equal(ra["xg"], rd["xg"])
+
+
+def test_short_restart_many_cycles(gpu_ctx):
+    out = run_pair(gpu_ctx, WL.C3_SMALL, 4, 1e-10, restart_m=5, recycle_k=4, snapshots_s=6, precond="jacobi")
+    _check_parity(out, its_bar=3)
+    assert max(r["st"]["cycles"] for r in out) > 2
+
+
+def test_long_restart_over_64(gpu_ctx):
+    """Restart lengths above 64 take the split update / dot path."""
+    hard = WL.Problem(p=3, N=16, eps=1e-3, dt=0.05, beta="rotating")   # larger step: ~100 Arnoldi steps
+    out = run_pair(gpu_ctx, hard, 2, 1e-12, restart_m=100, method="plain")
+    _check_parity(out)
+    assert out[0]["st"]["iterations"] > 64
+
+
+def test_mixed_precision_c3_small(gpu_ctx):
+    """FP32 Arnoldi cycles inside FP64 refinement: the returned x meets the FP64 residual
+    test and matches the oracle solved to 1e-12 within the refinement bar."""
+    out = run_pair(gpu_ctx, WL.C3_SMALL, 10, 1e-8, precision="fp32_ir", oracle_tol=1e-12, restart_m=50,
+                   recycle_k=16, snapshots_s=32, precond="jacobi", inner_tol=1e-5)
+    for r in out:
+        assert r["status"] == 0 and r["st"]["converged"] == 1
+        assert r["res"] <= 1e-8 * (1 + 1e-6)
+        kappa = np.linalg.cond(r["A"].toarray(), 1)
+        assert r["rel"] <= max(1e-8, kappa * 1e-8 * 2), (r["step"], r["rel"], kappa)
+
+
+# -- edge cases and errors --------------------------------------------------------------
+
+
+def test_zero_rhs_and_nonfinite(gpu_ctx):
+    import torch
+    from paper_1807_09467_amd import rsolve
+    asm = WL.Assembler(WL.C1)
+    pat = asm.pat
+    vals = asm.matrix_values(WL.initial_condition(WL.C1, 0))
+    seq = rsolve.Sequence(pat.n, pat.nnz, device=gpu_ctx, restart_m=10)
+    rp, ci, v = _t(pat.row_ptr, gpu_ctx), _t(pat.col_idx, gpu_ctx), _t(vals, gpu_ctx)
+    x0 = torch.ones(pat.n, dtype=torch.float64, device=gpu_ctx)
+    x, st, status = seq.solve(rp, ci, v, torch.zeros(pat.n, dtype=torch.float64, device=gpu_ctx), x0=x0)
+    assert status == 0 and st["iterations"] == 0 and not x.any()
+    b = torch.ones(pat.n, dtype=torch.float64, device=gpu_ctx)
+    b[5] = float("nan")
+    _, _, status = seq.solve(rp, ci, v, b, check=False)
+    assert status == rsolve.E_NONFINITE
+    seq.close()
+
+
+def test_corrupt_csr_rejected(gpu_ctx):
+    from paper_1807_09467_amd import rsolve
+    asm = WL.Assembler(WL.C1)
+    pat = asm.pat
+    vals = asm.matrix_values(WL.initial_condition(WL.C1, 0))
+    b = asm.rhs(WL.initial_condition(WL.C1, 0))
+    seq = rsolve.Sequence(pat.n, pat.nnz, device=gpu_ctx, restart_m=10)
+    for mutate in ("col_out_of_range", "unsorted", "row_ptr_overflow", "no_diagonal"):
+        rp, ci = pat.row_ptr.copy(), pat.col_idx.copy()
+        if mutate == "col_out_of_range":
+            ci[100] = pat.n + 7
+        elif mutate == "unsorted":
+            a = rp[200]
+            ci[a], ci[a + 1] = ci[a + 1], ci[a]
+        elif mutate == "row_ptr_overflow":
+            rp[300] = pat.nnz + 1000
+        elif mutate == "no_diagonal":
+            r0 = 0                      # boundary row: only the diagonal is stored
+            ci[rp[r0]] = 1 if ci[rp[r0]] != 1 else 2
+        _, _, status = seq.solve(_t(rp, gpu_ctx), _t(ci, gpu_ctx), _t(vals, gpu_ctx), _t(b, gpu_ctx), check=False)
+        assert status == rsolve.E_INVALID, mutate
+    # the sequence still works afterwards
+    x, st, status = seq.solve(_t(pat.row_ptr, gpu_ctx), _t(pat.col_idx, gpu_ctx), _t(vals, gpu_ctx), _t(b, gpu_ctx),
+                              tol=1e-10)
+    assert status == 0
+    seq.close()
+
+
+def test_max_iters_not_converged(gpu_ctx):
+    from paper_1807_09467_amd import rsolve
+    asm = WL.Assembler(WL.C1)
+    pat = asm.pat
+    u = WL.initial_condition(WL.C1, 0)
+    vals, b = asm.system(u)
+    seq = rsolve.Sequence(pat.n, pat.nnz, device=gpu_ctx, restart_m=30, max_iters=3, method="plain")
+    x, st, status = seq.solve(_t(pat.row_ptr, gpu_ctx), _t(pat.col_idx, gpu_ctx), _t(vals, gpu_ctx), _t(b, gpu_ctx),
+                              tol=1e-12)
+    assert status == rsolve.NOT_CONVERGED and st["iterations"] == 3 and st["converged"] == 0
+    ores = O.solve(asm.csr(vals), b, None, 1e-12, O.Config(restart_m=30, method=O.PLAIN, max_iters=3))
+    assert np.linalg.norm(x.cpu().numpy() - ores.x) <= 1e-12 * np.linalg.norm(ores.x)
+    seq.close()
+
+
+def test_update_before_solve_is_state_error(gpu_ctx):
+    from paper_1807_09467_amd import rsolve
+    seq = rsolve.Sequence(100, 500, device=gpu_ctx, restart_m=10, recycle_k=2, snapshots_s=3)
+    assert seq.update(check=False) == rsolve.E_STATE
+    seq.close()
+
+
+def test_tiny_systems(gpu_ctx):
+    """n = 1 and a 2 x 2 system (n far from a multiple of the wavefront)."""
+    import scipy.sparse as sp
+    import torch
+    from paper_1807_09467_amd import rsolve
+    for dense in (np.array([[4.0]]), np.array([[3.0, 1.0], [-2.0, 5.0]])):
+        A = sp.csr_matrix(dense)
+        n = dense.shape[0]
+        b = np.arange(1.0, n + 1.0)
+        seq = rsolve.Sequence(n, A.nnz, device=gpu_ctx, restart_m=4)
+        x, st, status = seq.solve(_t(A.indptr.astype(np.int32), gpu_ctx), _t(A.indices.astype(np.int32), gpu_ctx),
+                                  _t(A.data, gpu_ctx), _t(b, gpu_ctx), tol=1e-14)
+        assert status == 0
+        assert np.allclose(x.cpu().numpy(), np.linalg.solve(dense, b), rtol=1e-13)
+        seq.close()
