@@ -1,0 +1,244 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the rsolve solver on one MI355X.
+
+Default workload (c4): Q3 finite elements on a 512 x 512 mesh (n = 2,362,369,
+nnz = 58,789,033), rotating velocity 2 pi (-(y - 1/2), x - 1/2), eps = 1e-4,
+dt = 5e-3, backward Euler with Picard linearisation.  `warmup + steps`
+consecutive time steps are generated on the GPU (the trajectory is advanced
+with an FP64 solve to 1e-10) and kept resident in HBM; then the timed region
+runs the recycled mixed-precision solver (float32 Arnoldi cycles inside
+float64 iterative refinement, GMRES(50), k = 16, s = 32, ell = 1, right
+Jacobi) to 1e-8 relative residual on the `steps` systems, one solve plus one
+recycle update per step.  Plain FP64 GMRES(50) with right Jacobi runs on the
+same systems as the comparison.  Prints one JSON line.
+
+python bench.py [--steps K] [--warmup W] [--workload c4|c3|c2|c1] [--gpus 1]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    # name: (problem, solver config, tol, description)
+    "c4": ("C3", dict(restart_m=50, recycle_k=16, snapshots_s=32, svd_interval=1, precond="jacobi",
+                      precision="fp32_ir", inner_tol=1e-5), 1e-8,
+           "Q3 512x512 Burgers-Picard sequence (n=2362369, nnz=58789033), recycled mixed GMRES(50) "
+           "k=16 s=32 ell=1 right Jacobi, FP32 Arnoldi + FP64 refinement, tol 1e-8"),
+    "c3": ("C3", dict(restart_m=50, recycle_k=16, snapshots_s=32, svd_interval=1, precond="jacobi",
+                      precision="fp64"), 1e-10,
+           "Q3 512x512 Burgers-Picard sequence, recycled FP64 GMRES(50) k=16 s=32 ell=1 right Jacobi, tol 1e-10"),
+    "c2": ("C2", dict(restart_m=30, recycle_k=10, snapshots_s=20, svd_interval=1, precond="jacobi",
+                      precision="fp64"), 1e-10,
+           "Q2 256x256 Burgers-Picard sequence (n=263169), recycled FP64 GMRES(30) k=10 s=20 right Jacobi, "
+           "tol 1e-10"),
+    "c1": ("C1", dict(restart_m=30, recycle_k=5, snapshots_s=10, svd_interval=1, precond="none",
+                      precision="fp64"), 1e-8,
+           "Q1 32x32 Burgers-Picard sequence (n=1089), recycled FP64 GMRES(30) k=5 s=10, tol 1e-8"),
+}
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def generate(prob, nsteps, dev):
+    """Systems of `nsteps` consecutive time steps, resident on the device."""
+    import torch
+
+    from paper_1807_09467_amd import rsolve
+    from paper_1807_09467_amd import workload as WL
+    t0 = time.time()
+    asm = WL.Assembler(prob)
+    gasm = WL.GpuAssembler(asm, dev)
+    log(f"pattern n={asm.pat.n} nnz={asm.pat.nnz} ready in {time.time() - t0:.1f}s")
+    u0 = torch.from_numpy(WL.initial_condition(prob, 0)).to(dev)
+    traj = rsolve.Sequence(asm.pat.n, asm.pat.nnz, device=dev, restart_m=50, recycle_k=16, snapshots_s=32,
+                           precond="jacobi")
+    systems = []
+    u = u0
+    for i in range(nsteps):
+        vals, b = gasm.system(u)
+        systems.append((vals, b))
+        x, st, status = traj.solve(gasm.row_ptr, gasm.col_idx, vals, b, x0=u, tol=1e-10, same_pattern=i > 0)
+        if status != 0:
+            raise RuntimeError(f"trajectory solve failed at step {i}: {status}")
+        traj.update()
+        u = x.clone()
+        log(f"generated step {i + 1}/{nsteps} ({st['iterations']} its)")
+    traj.close()
+    torch.cuda.synchronize()
+    log(f"generation done in {time.time() - t0:.1f}s")
+    return asm, gasm, u0, systems
+
+
+def run_solver(gasm, u0, systems, warmup, steps, tol, cfg, dev, profile=False, label=""):
+    """One pass over the sequence: warmup untimed solves, then `steps` timed solve+update steps."""
+    import torch
+
+    from paper_1807_09467_amd import rsolve
+    pat = gasm.asm.pat
+    seq = rsolve.Sequence(pat.n, pat.nnz, device=dev, **cfg)
+    x_prev = u0
+    lat, its, cyc, keff, rel = [], [], [], [], []
+    xs = []
+    t_start = None
+    for i, (vals, b) in enumerate(systems[: warmup + steps]):
+        if i == warmup:
+            torch.cuda.synchronize()
+            if profile:
+                seq.profile(True)
+            t_start = time.perf_counter()
+        t0 = time.perf_counter()
+        x, st, status = seq.solve(gasm.row_ptr, gasm.col_idx, vals, b, x0=x_prev, tol=tol, same_pattern=i > 0)
+        if status != 0:
+            raise RuntimeError(f"{label}: solve {i} returned {status}")
+        seq.update()
+        t1 = time.perf_counter()
+        if i >= warmup:
+            lat.append((t1 - t0) * 1e3)
+            its.append(st["iterations"])
+            cyc.append(st["cycles"])
+            keff.append(st["k_eff"])
+            rel.append(st["rel_res_true"])
+        xs.append(x)
+        x_prev = x
+        log(f"{label} step {i + 1}/{warmup + steps}: {st['iterations']} its, {st['cycles']} cycles, "
+            f"k_eff {st['k_eff']}, {1e3 * (t1 - t0):.2f} ms")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    prof = seq.profile_read() if profile else []
+    seq.close()
+    return dict(elapsed=elapsed, lat=lat, its=its, cycles=cyc, k_eff=keff, rel=rel, prof=prof, xs=xs)
+
+
+def summarize(r, steps):
+    lat = np.array(r["lat"])
+    return {
+        "solves_per_s": steps / r["elapsed"],
+        "ms_per_solve": 1e3 * r["elapsed"] / steps,
+        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
+        "avg_iterations": float(np.mean(r["its"])),
+        "avg_cycles": float(np.mean(r["cycles"])),
+        "max_rel_residual": float(np.max(r["rel"])),
+    }
+
+
+def cpu_baseline(prob, asm_host, tol):
+    """Oracle (plain FP64 GMRES(50), right Jacobi) on time step 1 of the same sequence, host cores."""
+    from threadpoolctl import threadpool_info
+
+    from oracle import rgmres as O
+    from paper_1807_09467_amd import workload as WL
+    u0 = WL.initial_condition(prob, 0)
+    vals, b = asm_host.system(u0)
+    A = asm_host.csr(vals)
+    threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+    t0 = time.perf_counter()
+    res = O.solve(A, b, u0, tol, O.Config(restart_m=50, method=O.PLAIN, precond=O.PRECOND_JACOBI))
+    dt = time.perf_counter() - t0
+    return {"value": 1.0 / dt, "unit": "solves/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"one FP64 solve (time step 1, x0 = u0, GMRES(50) right Jacobi, tol {tol:g}, "
+                      f"{res.iterations} its, {dt:.1f} s) of the same sequence; scipy CSR matvec on 1 thread, "
+                      f"OpenBLAS on {threads}"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="c4", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain FP64 comparison run")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported "
+              "(the solver path runs on a single device; see the design notes for how it would shard)",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import __graft_entry__  # noqa: F401  (path setup)
+    from paper_1807_09467_amd import rsolve
+    from paper_1807_09467_amd import workload as WL
+    rsolve.load()
+    dev = torch.device("cuda:0")
+    pname, cfg, tol, desc = WORKLOADS[args.workload]
+    prob = getattr(WL, pname)
+    nsteps = args.warmup + args.steps
+    asm, gasm, u0, systems = generate(prob, nsteps, dev)
+
+    main_run = run_solver(gasm, u0, systems, args.warmup, args.steps, tol, cfg, dev, profile=True,
+                          label="recycled")
+    main_sum = summarize(main_run, args.steps)
+    plain_sum = None
+    if not args.no_plain:
+        pcfg = dict(restart_m=cfg["restart_m"], precond=cfg["precond"], method="plain", precision="fp64")
+        plain_run = run_solver(gasm, u0, systems, args.warmup, args.steps, tol, pcfg, dev, label="plain-fp64")
+        plain_sum = summarize(plain_run, args.steps)
+        # the same systems, solved twice: both answers meet the tolerance, so they agree to kappa * tol
+        diffs = [float(torch.linalg.norm(a - b) / torch.linalg.norm(b))
+                 for a, b in zip(main_run["xs"][args.warmup:], plain_run["xs"][args.warmup:])]
+        plain_sum["max_rel_diff_vs_recycled"] = max(diffs)
+        del plain_run
+
+    # roofline of the dominant kernel (HIP events around each launch inside the library)
+    prof = main_run["prof"]
+    for e in prof:
+        e["avg_us"] = 1e3 * e["ms"] / e["launches"]
+        e["gb_per_s"] = e["bytes"] / (e["ms"] * 1e-3) / 1e9
+    dom = max(prof, key=lambda e: e["ms"]) if prof else None
+    roofline = None
+    if dom is not None:
+        roofline = {"bound": "hbm", "achieved": round(dom["gb_per_s"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(dom["gb_per_s"] / HBM_PEAK_GBS, 4), "traffic": None,
+                    "kernel": f"{dom['kernel']} (variant {dom['variant']})",
+                    "avg_launch_us": round(dom["avg_us"], 2), "launches": dom["launches"]}
+
+    cpu = None
+    if not args.no_cpu_baseline and pname == "C3":
+        log("timing the oracle on the host")
+        cpu = cpu_baseline(prob, asm, tol)
+
+    vs = None
+    out = {
+        "metric": "linear solves/sec at 1e-8 rel. residual (recycled mixed vs plain FP64); p50/p99"
+        if args.workload == "c4" else f"linear solves/sec at {tol:g} rel. residual",
+        "value": round(main_sum["solves_per_s"], 3),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(main_sum["ms_per_solve"], 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": vs,
+        "dtype": "f32+f64" if cfg.get("precision") == "fp32_ir" else "f64",
+        "data": "synthetic",
+        "config": {"workload": desc, "n": asm.pat.n, "nnz": asm.pat.nnz, "steps_generated": nsteps,
+                   "parallelism": "single GPU"},
+        "latency_ms": main_sum["latency_ms"],
+        "avg_iterations": main_sum["avg_iterations"],
+        "avg_cycles": main_sum["avg_cycles"],
+        "max_rel_residual": main_sum["max_rel_residual"],
+        "plain_fp64": plain_sum,
+        "speedup_vs_plain_fp64": (main_sum["solves_per_s"] / plain_sum["solves_per_s"]) if plain_sum else None,
+        "roofline": roofline,
+        "kernels": [{k: (round(v, 3) if isinstance(v, float) else v) for k, v in e.items()} for e in prof],
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

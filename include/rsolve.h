@@ -180,6 +180,37 @@ int rsolve_update_recycle(rsolve_seq* s, const double* x);
 int rsolve_get_recycle(rsolve_seq* s, int32_t* k_eff, int32_t* rank, double* sigma_host,
                        int32_t cap, double* W_out, int64_t ld_out);
 
+/* ---- per-kernel timing (HIP events) ---- */
+#define RSOLVE_PROF_SPMV        0   /* Arnoldi product w = A D^{-1} v (plus basis normalisation) */
+#define RSOLVE_PROF_DOTS        1   /* CGS2 pass 1: dots with V, W and the A W row F (one sweep) */
+#define RSOLVE_PROF_UPDATE_DOTS 2   /* pass-1 update w -= V h1 + A W c fused with pass-2 dots */
+#define RSOLVE_PROF_UPDATE_NORM 3   /* pass-2 update fused with ||w||^2 */
+
+typedef struct {
+    int32_t kernel;     /* RSOLVE_PROF_* */
+    int32_t variant;    /* columns the kernel instance keeps in registers = 8 << variant
+                           (dot kernels; 0 for the others) */
+    int64_t launches;   /* launches that did work (Arnoldi steps actually taken) */
+    double ms;          /* summed HIP-event time of those launches */
+    double bytes;       /* summed algorithmic bytes of those launches (each operand read or
+                           written once: values, indices, basis columns, vectors) */
+} rsolve_prof_entry;
+
+/*
+ * Switch per-kernel timing on (on != 0) or off for this sequence.  When on,
+ * every Arnoldi-step kernel of rsolve_solve is bracketed by two HIP events on
+ * the sequence's stream; durations of the launches that did work are summed
+ * after each cycle.  Adds a few microseconds per launch.  Errors: E_INVALID,
+ * E_DEVICE (event creation).
+ */
+int rsolve_profile_enable(rsolve_seq* s, int32_t on);
+
+/*
+ * Copy up to `cap` non-empty entries (host array) and their number to *count;
+ * reset != 0 clears the accumulators afterwards.
+ */
+int rsolve_profile_read(rsolve_seq* s, rsolve_prof_entry* out, int32_t cap, int32_t* count, int32_t reset);
+
 /* Destroy the handle.  Does not free the workspace (the caller owns it). */
 int rsolve_destroy_sequence(rsolve_seq* s);
 

@@ -16,6 +16,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "librsolve.so")
+GEN_OUT = os.path.join(PKG, "libqkgen.so")
 BUILD_DIR = os.path.join(PKG, "_build")
 SOURCES = ["k_sparse.hip", "k_krylov.hip", "k_dense.hip", "engine.hip"]
 ARCH = "gfx950"
@@ -58,13 +59,24 @@ def build(verbose: bool = False) -> str:
 
     with ThreadPoolExecutor(max_workers=min(len(SOURCES), os.cpu_count() or 4)) as ex:
         objs = list(ex.map(compile_one, SOURCES))
-    tmp = OUT + ".tmp"
+    _link(cc, objs, OUT)
+    # the input generator's own library (finite-element assembly on the GPU)
+    gen_src = os.path.join(PKG, "gen_csrc", "qkgen.hip")
+    gen_obj = os.path.join(BUILD_DIR, "qkgen.o")
+    r = subprocess.run([cc, *flags(), "-c", gen_src, "-o", gen_obj], capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed for qkgen.hip:\n{r.stdout}\n{r.stderr}")
+    _link(cc, [gen_obj], GEN_OUT)
+    return OUT
+
+
+def _link(cc, objs, out):
+    tmp = out + ".tmp"
     cmd = [cc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
-    os.replace(tmp, OUT)
-    return OUT
+    os.replace(tmp, out)
 
 
 if __name__ == "__main__":

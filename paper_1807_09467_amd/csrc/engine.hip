@@ -109,7 +109,7 @@ int pick_gblk(int64_t n) {
 
 struct rsolve_seq {
     rsolve_config cfg;
-    int64_t n = 0, ld = 0, nnz_max = 0;
+    int64_t n = 0, ld = 0, nnz_max = 0, nnz_cur = 0;
     hipStream_t stream = nullptr;
     int device = 0;
     char* ws = nullptr;
@@ -136,6 +136,15 @@ struct rsolve_seq {
     int64_t count = 0;
     double sigma[SMAX];
     bool have_x = false;
+    // per-kernel timing
+    static constexpr int NPK = 4, NVAR = 4;
+    bool prof_on = false;
+    hipEvent_t* pev = nullptr;           // [NPK][MMAX][2]
+    int pvar[NPK][MMAX];                 // variant recorded for step j
+    double pbytes[NPK][MMAX];            // algorithmic bytes of step j's launch
+    double pms[NPK][NVAR];
+    double pb[NPK][NVAR];
+    int64_t pcnt[NPK][NVAR];
 };
 
 namespace {
@@ -218,6 +227,37 @@ int read_head(rsolve_seq* s) {
     return RSOLVE_OK;
 }
 
+inline int var_of(int cols) { return cols <= 8 ? 0 : (cols <= 16 ? 1 : (cols <= 32 ? 2 : 3)); }
+
+struct ProfScope {
+    rsolve_seq* s;
+    int kind, j;
+    ProfScope(rsolve_seq* s_, int kind_, int j_, int var, double bytes) : s(s_), kind(kind_), j(j_) {
+        if (!s->prof_on) return;
+        s->pvar[kind][j] = var;
+        s->pbytes[kind][j] = bytes;
+        (void)hipEventRecord(s->pev[(kind * MMAX + j) * 2 + 0], s->stream);
+    }
+    ~ProfScope() {
+        if (s->prof_on) (void)hipEventRecord(s->pev[(kind * MMAX + j) * 2 + 1], s->stream);
+    }
+};
+
+// After a cycle's synchronisation: accumulate the event times of the steps that ran.
+void prof_collect(rsolve_seq* s, int steps) {
+    if (!s->prof_on) return;
+    for (int kd = 0; kd < rsolve_seq::NPK; ++kd)
+        for (int j = 0; j < steps; ++j) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, s->pev[(kd * MMAX + j) * 2], s->pev[(kd * MMAX + j) * 2 + 1]) != hipSuccess)
+                continue;
+            const int v = s->pvar[kd][j];
+            s->pms[kd][v] += ms;
+            s->pb[kd][v] += s->pbytes[kd][j];
+            s->pcnt[kd][v] += 1;
+        }
+}
+
 // One Arnoldi step j of the current cycle on storage type T.
 template <typename T>
 void arnoldi_step(rsolve_seq* s, int j, const int32_t* rp, const int32_t* ci, const T* vals, T* V, T* const* wbuf,
@@ -227,21 +267,28 @@ void arnoldi_step(rsolve_seq* s, int j, const int32_t* rp, const int32_t* ci, co
     T* win = wbuf[j & 1];
     T* wout = wbuf[(j + 1) & 1];
     T* vj = V + (int64_t)j * ld;
-    launch_spmv_arnoldi<T>(s->lpr, s->n, rp, ci, vals, win, vj, wout, s->ctl, st);
+    const double w = sizeof(T), nn = (double)s->n;
+    {
+        ProfScope ps(s, RSOLVE_PROF_SPMV, j, 0, (w + 4.0) * (double)s->nnz_cur + 4.0 * (nn + 1.0) + 3.0 * w * nn);
+        launch_spmv_arnoldi<T>(s->lpr, s->n, rp, ci, vals, win, vj, wout, s->ctl, st);
+    }
     const int nv = j + 1;
     if (k > 0) {
         const T* bases[3] = {V, Wt, Zt};
         const T* vecs[3] = {wout, wout, vj};
         const int counts[3] = {nv, k, k};
+        ProfScope ps(s, RSOLVE_PROF_DOTS, j, var_of(nv + 2 * k), (nv + 2.0 * k + 1.0) * w * nn);
         launch_dots<T>(ld, ld, bases, vecs, counts, 3, s->partial, s->nblk, s->ctl, st);
     } else {
         const T* bases[1] = {V};
         const T* vecs[1] = {wout};
         const int counts[1] = {nv};
+        ProfScope ps(s, RSOLVE_PROF_DOTS, j, var_of(nv), (nv + 1.0) * w * nn);
         launch_dots<T>(ld, ld, bases, vecs, counts, 1, s->partial, s->nblk, s->ctl, st);
     }
     launch_reduce_pass1(s->partial, s->nblk, nv, k, s->ctl, st);
     if (nv <= 64) {
+        ProfScope ps(s, RSOLVE_PROF_UPDATE_DOTS, j, var_of(nv), (nv + k + 2.0) * w * nn);
         launch_update_dots<T>(ld, V, ld, nv, Zt, k, wout, ctl_h1(s->ctl), ctl_cw(s->ctl), s->partial, s->nblk, s->ctl,
                               st);
     } else {
@@ -252,7 +299,10 @@ void arnoldi_step(rsolve_seq* s, int j, const int32_t* rp, const int32_t* ci, co
         launch_dots<T>(ld, ld, bases, vecs, counts, 1, s->partial, s->nblk, s->ctl, st);
     }
     launch_reduce(s->partial, s->nblk, nv, ctl_h2(s->ctl), s->ctl, 0, 0, false, true, st);
-    launch_update_norm<T>(ld, V, ld, nv, wout, ctl_h2(s->ctl), s->partial, s->nblk, s->ctl, st);
+    {
+        ProfScope ps(s, RSOLVE_PROF_UPDATE_NORM, j, 0, (nv + 2.0) * w * nn);
+        launch_update_norm<T>(ld, V, ld, nv, wout, ctl_h2(s->ctl), s->partial, s->nblk, s->ctl, st);
+    }
     launch_givens(s->partial, s->nblk, j, s->ctl, st);
 }
 
@@ -332,9 +382,44 @@ int rsolve_create_sequence(const rsolve_config* cfg, int64_t n, int64_t nnz_max,
     return RSOLVE_OK;
 }
 
+int rsolve_profile_enable(rsolve_seq* s, int32_t on) {
+    if (!s) return RSOLVE_E_INVALID;
+    if (on && !s->pev) {
+        HIP_TRY(hipSetDevice(s->device));
+        const int cnt = rsolve_seq::NPK * MMAX * 2;
+        s->pev = new hipEvent_t[cnt]();
+        for (int i = 0; i < cnt; ++i) HIP_TRY(hipEventCreate(&s->pev[i]));
+    }
+    s->prof_on = on != 0;
+    return RSOLVE_OK;
+}
+
+int rsolve_profile_read(rsolve_seq* s, rsolve_prof_entry* out, int32_t cap, int32_t* count, int32_t reset) {
+    if (!s || (cap > 0 && !out)) return RSOLVE_E_INVALID;
+    int c = 0;
+    for (int kd = 0; kd < rsolve_seq::NPK; ++kd)
+        for (int v = 0; v < rsolve_seq::NVAR; ++v) {
+            if (s->pcnt[kd][v] == 0) continue;
+            if (c < cap) out[c] = rsolve_prof_entry{kd, v, s->pcnt[kd][v], s->pms[kd][v], s->pb[kd][v]};
+            ++c;
+        }
+    if (count) *count = c;
+    if (reset) {
+        memset(s->pms, 0, sizeof(s->pms));
+        memset(s->pb, 0, sizeof(s->pb));
+        memset(s->pcnt, 0, sizeof(s->pcnt));
+    }
+    return RSOLVE_OK;
+}
+
 int rsolve_destroy_sequence(rsolve_seq* s) {
     if (!s) return RSOLVE_E_INVALID;
-    if (s->stream || true) (void)hipStreamSynchronize(s->stream);
+    (void)hipStreamSynchronize(s->stream);
+    if (s->pev) {
+        for (int i = 0; i < rsolve_seq::NPK * MMAX * 2; ++i)
+            if (s->pev[i]) (void)hipEventDestroy(s->pev[i]);
+        delete[] s->pev;
+    }
     if (s->hctl) (void)hipHostFree(s->hctl);
     if (s->hsig) (void)hipHostFree(s->hsig);
     if (s->herr) (void)hipHostFree(s->herr);
@@ -389,6 +474,7 @@ int rsolve_solve(rsolve_seq* s, const rsolve_csr* A, const double* b, const doub
         s->lpr = pick_lpr(n, A->nnz);
     }
     HIP_TRY(hipMemsetAsync(s->ctl, 0, CTL_HEAD, stm));
+    s->nnz_cur = A->nnz;
 
     // ||b||
     launch_norm2(n, b, s->partial, s->nblk, stm);
@@ -491,6 +577,7 @@ int rsolve_solve(rsolve_seq* s, const rsolve_csr* A, const double* b, const doub
         HIP_TRY(hipGetLastError());
         rc = read_head(s);
         if (rc) return rc;
+        prof_collect(s, s->hctl->steps);
         its += s->hctl->steps;
         cycles += 1;
         gimp = s->hctl->gimp;

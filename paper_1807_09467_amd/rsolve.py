@@ -35,7 +35,10 @@ EXPORTS = [
     "rsolve_workspace_bytes", "rsolve_create_sequence", "rsolve_solve", "rsolve_update_recycle",
     "rsolve_get_recycle", "rsolve_destroy_sequence", "rsolve_status_string", "rsolve_last_error",
     "rsolve_spmv", "rsolve_kernel_workspace_bytes", "rsolve_gram_tn", "rsolve_snapshot_svd",
+    "rsolve_profile_enable", "rsolve_profile_read",
 ]
+
+PROF_KERNELS = {0: "spmv_arnoldi", 1: "dots", 2: "update_dots", 3: "update_norm"}
 
 
 class Config(ctypes.Structure):
@@ -62,6 +65,11 @@ class Stats(ctypes.Structure):
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+
+
+class ProfEntry(ctypes.Structure):
+    _fields_ = [("kernel", c_int32), ("variant", c_int32), ("launches", c_int64), ("ms", c_double),
+                ("bytes", c_double)]
 
 
 class RsolveError(RuntimeError):
@@ -110,6 +118,10 @@ def load():
                                         POINTER(c_double), POINTER(c_int32), POINTER(c_int32), c_void_p, c_size_t,
                                         c_void_p]
     lib.rsolve_snapshot_svd.restype = c_int
+    lib.rsolve_profile_enable.argtypes = [c_void_p, c_int32]
+    lib.rsolve_profile_enable.restype = c_int
+    lib.rsolve_profile_read.argtypes = [c_void_p, POINTER(ProfEntry), c_int32, POINTER(c_int32), c_int32]
+    lib.rsolve_profile_read.restype = c_int
     _lib = lib
     return lib
 
@@ -215,6 +227,18 @@ class Sequence:
                                                        c_void_p(W.data_ptr()), self.n))
             out["W"] = W
         return out
+
+    def profile(self, on=True):
+        _check(self.lib.rsolve_profile_enable(self.handle, 1 if on else 0))
+
+    def profile_read(self, reset=False):
+        """Per-kernel HIP-event timings: list of dicts (kernel, variant, launches, ms, bytes)."""
+        cap = 32
+        arr = (ProfEntry * cap)()
+        cnt = c_int32()
+        _check(self.lib.rsolve_profile_read(self.handle, arr, cap, byref(cnt), 1 if reset else 0))
+        return [{"kernel": PROF_KERNELS[arr[i].kernel], "variant": arr[i].variant, "launches": arr[i].launches,
+                 "ms": arr[i].ms, "bytes": arr[i].bytes} for i in range(min(cnt.value, cap))]
 
     def close(self):
         if getattr(self, "handle", None) is not None and self.handle.value:

@@ -325,8 +325,9 @@ class Assembler:
         """b(u_prev) = M u_prev / dt on interior rows, 0 on the boundary."""
         import scipy.sparse as sp
         pat = self.pat
-        M = sp.csr_matrix((self.mass_values(), pat.col_idx, pat.row_ptr), shape=(pat.n, pat.n))
-        b = (M @ u_prev) / self.prob.dt
+        if getattr(self, "_mass_csr", None) is None:
+            self._mass_csr = sp.csr_matrix((self.mass_values(), pat.col_idx, pat.row_ptr), shape=(pat.n, pat.n))
+        b = (self._mass_csr @ u_prev) / self.prob.dt
         b[pat.boundary] = 0.0
         return b
 
@@ -384,3 +385,99 @@ def march(prob: Problem, steps: int, seed: int,
         u = adv(vals, b)
         states.append(u)
     return asm, systems, states
+
+
+# ---------------------------------------------------------------------------
+# GPU assembly (qkgen library): the same systems, built in device memory
+# ---------------------------------------------------------------------------
+
+_QKGEN = None
+
+
+def _qkgen():
+    """Load libqkgen.so (built next to this file by build.py)."""
+    global _QKGEN
+    if _QKGEN is None:
+        import ctypes
+        import os
+        path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libqkgen.so")
+        if not os.path.exists(path):
+            raise RuntimeError(f"{path} is not built")
+        lib = ctypes.CDLL(path)
+        c = ctypes
+        lib.qkgen_element_values.argtypes = [c.c_int64, c.c_int32, c.c_int32] + [c.c_void_p] * 7 + [
+            c.c_int32, c.c_double, c.c_double, c.c_void_p, c.c_void_p, c.c_int32, c.c_double, c.c_void_p,
+            c.c_void_p]
+        lib.qkgen_gather.argtypes = [c.c_int64, c.c_void_p, c.c_void_p, c.c_void_p, c.c_void_p, c.c_void_p]
+        lib.qkgen_set_value.argtypes = [c.c_int64, c.c_void_p, c.c_double, c.c_void_p, c.c_void_p]
+        lib.qkgen_spmv_scaled.argtypes = [c.c_int64, c.c_void_p, c.c_void_p, c.c_void_p, c.c_void_p, c.c_double,
+                                          c.c_void_p, c.c_void_p]
+        for f in (lib.qkgen_element_values, lib.qkgen_gather, lib.qkgen_set_value, lib.qkgen_spmv_scaled):
+            f.restype = c.c_int
+        _QKGEN = lib
+    return _QKGEN
+
+
+class GpuAssembler:
+    """Device-side twin of Assembler: A(u_prev) and b(u_prev) assembled on the GPU.
+
+    The contribution list of every CSR entry (element entries that add into
+    it) is built once on the host and sorted by element index, so the device
+    sum runs in a fixed order.
+    """
+
+    def __init__(self, asm: Assembler, device):
+        import torch
+        self.asm = asm
+        self.dev = torch.device(device)
+        pat, t = asm.pat, asm.tab
+        T = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a, dtype=dt)).to(self.dev)
+        self.row_ptr = T(pat.row_ptr, np.int32)
+        self.col_idx = T(pat.col_idx, np.int32)
+        self.elem_nodes = T(pat.elem_nodes, np.int32)
+        em = pat.emap.ravel()
+        keep = np.flatnonzero(em >= 0)
+        key = em[keep]
+        order = np.argsort(key, kind="stable")
+        cnt = np.bincount(key, minlength=pat.nnz)
+        cptr = np.zeros(pat.nnz + 1, dtype=np.int64)
+        np.cumsum(cnt, out=cptr[1:])
+        self.cptr = T(cptr, np.int32)
+        self.cidx = T(keep[order], np.int32)
+        del em, keep, key, order, cnt, cptr
+        self.phi = T(t.phi, np.float64)
+        self.wq = T(t.w, np.float64)
+        self.Bx = T(asm.Bx, np.float64)
+        self.By = T(asm.By, np.float64)
+        self.static_e = T(asm.static_e, np.float64)
+        self.qxi = T(t.xi, np.float64)
+        self.qeta = T(t.eta, np.float64)
+        self.mass = T(asm.mass_values(), np.float64)
+        self.bdiag = T(pat.diag_pos[pat.boundary], np.int32)
+        E = pat.elem_nodes.shape[0]
+        self.E = E
+        self.ev = torch.empty(E * t.nl * t.nl, dtype=torch.float64, device=self.dev)
+
+    def system(self, u_prev, vals_out=None, b_out=None, stream=None):
+        """Fill vals_out (nnz) and b_out (n) with A(u_prev), b(u_prev); u_prev is a device tensor."""
+        import torch
+        pat, t, prob = self.asm.pat, self.asm.tab, self.asm.prob
+        lib = _qkgen()
+        if vals_out is None:
+            vals_out = torch.empty(pat.nnz, dtype=torch.float64, device=self.dev)
+        if b_out is None:
+            b_out = torch.empty(pat.n, dtype=torch.float64, device=self.dev)
+        s = stream.cuda_stream if stream is not None else torch.cuda.current_stream(self.dev).cuda_stream
+        rot = 1 if prob.beta == "rotating" else 0
+        bx, by = (0.0, 0.0) if rot else prob.beta_const
+        p = lambda x: x.data_ptr()
+        rc = lib.qkgen_element_values(self.E, t.nl, t.nq, p(self.elem_nodes), p(u_prev), p(self.phi), p(self.wq),
+                                      p(self.Bx), p(self.By), p(self.static_e), rot, float(bx), float(by),
+                                      p(self.qxi), p(self.qeta), prob.N, self.asm.h, p(self.ev), s)
+        rc |= lib.qkgen_gather(pat.nnz, p(self.cptr), p(self.cidx), p(self.ev), p(vals_out), s)
+        rc |= lib.qkgen_set_value(int(self.bdiag.numel()), p(self.bdiag), 1.0, p(vals_out), s)
+        rc |= lib.qkgen_spmv_scaled(pat.n, p(self.row_ptr), p(self.col_idx), p(self.mass), p(u_prev),
+                                    1.0 / prob.dt, p(b_out), s)
+        if rc:
+            raise RuntimeError(f"qkgen launch failed ({rc})")
+        return vals_out, b_out
