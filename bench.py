@@ -160,6 +160,10 @@ def main():
     ap.add_argument("--workload", default="c4", choices=sorted(WORKLOADS))
     ap.add_argument("--no-plain", action="store_true", help="skip the plain FP64 comparison run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--inner-tol", type=float, default=None,
+                    help="override the FP32 cycle reduction factor of the mixed-precision workload")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run a 1 GiB device-to-device copy (reference for memory-traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported "
@@ -173,7 +177,17 @@ def main():
     from paper_1807_09467_amd import workload as WL
     rsolve.load()
     dev = torch.device("cuda:0")
+    if args.calib_copy:
+        src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     pname, cfg, tol, desc = WORKLOADS[args.workload]
+    cfg = dict(cfg)
+    if args.inner_tol is not None and cfg.get("precision") == "fp32_ir":
+        cfg["inner_tol"] = args.inner_tol
+        desc = desc + f", inner_tol {args.inner_tol:g}"
     prob = getattr(WL, pname)
     nsteps = args.warmup + args.steps
     asm, gasm, u0, systems = generate(prob, nsteps, dev)

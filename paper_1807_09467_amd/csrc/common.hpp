@@ -11,7 +11,7 @@ constexpr int MMAX = 128;        // largest restart length
 constexpr int KMAX = 64;         // largest recycle dimension
 constexpr int SMAX = 64;         // largest snapshot ring
 constexpr int BLOCK = 256;       // threads per block of the streaming kernels
-constexpr int NBLK_MAX = 1024;   // largest grid of the split-n reductions
+constexpr int NBLK_MAX = 2048;   // largest grid of the split-n reductions
 constexpr int TSQR_PANEL = 256;  // rows per Householder panel
 
 // Control block living in the sequence workspace.  Kernels of one Arnoldi
@@ -134,5 +134,16 @@ __device__ __forceinline__ bool wave_tr_owner() {
 
 template <typename T>
 __device__ __forceinline__ double to_d(T v) { return static_cast<double>(v); }
+
+constexpr int NXCD = 8;   // accelerator complex dies; blocks are dealt to them round-robin
+
+// Logical block index such that the blocks resident on one XCD cover one contiguous range of
+// logical blocks (a bijection of [0, nb)): work with locality between neighbouring blocks (the x
+// gathers of a sparse product) then stays within one XCD's L2.
+__device__ __forceinline__ unsigned xcd_block(unsigned b, unsigned nb) {
+    const unsigned x = b % NXCD, i = b / NXCD;
+    const unsigned q = nb / NXCD, r = nb % NXCD;
+    return (x < r) ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+}
 
 }  // namespace rs

@@ -87,17 +87,33 @@ int env_int(const char* name, int dflt) {
 int pick_lpr(int64_t n, int64_t nnz) {
     const int forced = env_int("RSOLVE_LPR", 0);
     if (forced == 2 || forced == 4 || forced == 8 || forced == 16 || forced == 32) return forced;
+    // lanes per row for the 4-entries-per-lane product: about one round of loads per row
     const double avg = n > 0 ? (double)nnz / (double)n : 1.0;
-    if (avg <= 10.0) return 4;
-    if (avg <= 20.0) return 8;
-    return 16;
+    if (avg <= 8.0) return 2;
+    if (avg <= 32.0) return 4;
+    return 8;
 }
 
-int pick_nblk(int64_t npad) {
+// Grid of the row-per-thread streaming kernels (256-thread blocks): enough blocks for
+// 8 per compute unit, never more blocks than 256-row slabs.
+int pick_nblk(int64_t npad, int cus) {
     const int forced = env_int("RSOLVE_NBLK", 0);
     if (forced > 0) return std::min(forced, NBLK_MAX);
-    int64_t b = (npad + BLOCK * 4 - 1) / (BLOCK * 4);
-    return (int)std::max<int64_t>(1, std::min<int64_t>(b, NBLK_MAX));
+    const int64_t slabs = (npad + BLOCK - 1) / BLOCK;
+    return (int)std::max<int64_t>(1, std::min<int64_t>({slabs, (int64_t)cus * 8, (int64_t)NBLK_MAX}));
+}
+
+// Grid of the column-per-wavefront sweeps with `nw` wavefronts per block: as many blocks as fit
+// on the device at once (32 wavefronts per compute unit), never more than 64-row tiles.
+// The per-block partials (ncol per block) are summed by one block afterwards, so the grid
+// also keeps nblk * ncol near 48k values.
+int cols_grid(int64_t npad, int cus, int nw, int waves_per_cu, int ncol) {
+    const int forced = env_int("RSOLVE_NBLK_COLS", 0);
+    if (forced > 0) return std::min(forced, NBLK_MAX);
+    const int64_t tiles = npad / WAVE;
+    int per_cu = std::max(1, waves_per_cu / std::max(1, nw));
+    per_cu = std::max(1, std::min(per_cu, (int)(49152 / ((int64_t)std::max(ncol, 1) * cus))));
+    return (int)std::max<int64_t>(1, std::min<int64_t>({tiles, (int64_t)cus * per_cu, (int64_t)NBLK_MAX}));
 }
 
 int pick_gblk(int64_t n) {
@@ -127,7 +143,7 @@ struct rsolve_seq {
     int64_t tsq_ld = 0;
     float *V32 = nullptr, *W32 = nullptr, *Z32 = nullptr, *vals32 = nullptr;
     float* w32[2] = {nullptr, nullptr};
-    int nblk = 1, gblk = 1, lpr = 8;
+    int nblk = 1, gblk = 1, lpr = 8, cus = 256;
     const int32_t* pat_rp = nullptr;
     const int32_t* pat_ci = nullptr;
     int64_t pat_nnz = -1;
@@ -136,6 +152,9 @@ struct rsolve_seq {
     int64_t count = 0;
     double sigma[SMAX];
     bool have_x = false;
+    // pipelined polling of the cycle's done flag
+    hipEvent_t poll_ev[2] = {nullptr, nullptr};
+    int32_t* poll_done = nullptr;  // pinned, 2 slots
     // per-kernel timing
     static constexpr int NPK = 4, NVAR = 4;
     bool prof_on = false;
@@ -229,17 +248,16 @@ int read_head(rsolve_seq* s) {
 
 inline int var_of(int cols) { return cols <= 8 ? 0 : (cols <= 16 ? 1 : (cols <= 32 ? 2 : 3)); }
 
-struct ProfScope {
-    rsolve_seq* s;
-    int kind, j;
-    ProfScope(rsolve_seq* s_, int kind_, int j_, int var, double bytes) : s(s_), kind(kind_), j(j_) {
+// Per-kernel timing: the events of (kernel kind, step j) are handed to the launch itself, which
+// stamps them with the start and end of the kernel's dispatch.
+struct ProfEv {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    ProfEv(rsolve_seq* s, int kind, int j, int var, double bytes) {
         if (!s->prof_on) return;
         s->pvar[kind][j] = var;
         s->pbytes[kind][j] = bytes;
-        (void)hipEventRecord(s->pev[(kind * MMAX + j) * 2 + 0], s->stream);
-    }
-    ~ProfScope() {
-        if (s->prof_on) (void)hipEventRecord(s->pev[(kind * MMAX + j) * 2 + 1], s->stream);
+        e0 = s->pev[(kind * MMAX + j) * 2 + 0];
+        e1 = s->pev[(kind * MMAX + j) * 2 + 1];
     }
 };
 
@@ -269,41 +287,35 @@ void arnoldi_step(rsolve_seq* s, int j, const int32_t* rp, const int32_t* ci, co
     T* vj = V + (int64_t)j * ld;
     const double w = sizeof(T), nn = (double)s->n;
     {
-        ProfScope ps(s, RSOLVE_PROF_SPMV, j, 0, (w + 4.0) * (double)s->nnz_cur + 4.0 * (nn + 1.0) + 3.0 * w * nn);
-        launch_spmv_arnoldi<T>(s->lpr, s->n, rp, ci, vals, win, vj, wout, s->ctl, st);
+        ProfEv pe(s, RSOLVE_PROF_SPMV, j, 0, (w + 4.0) * (double)s->nnz_cur + 4.0 * (nn + 1.0) + 3.0 * w * nn);
+        launch_spmv_arnoldi<T>(s->lpr, s->n, rp, ci, vals, win, vj, wout, s->ctl, st, pe.e0, pe.e1);
     }
     const int nv = j + 1;
+    const int ntot = k > 0 ? nv + 2 * k : nv;
+    const int nb1 = cols_grid(ld, s->cus, std::min(16, (ntot + 7) / 8), 32, ntot);
     if (k > 0) {
         const T* bases[3] = {V, Wt, Zt};
         const T* vecs[3] = {wout, wout, vj};
         const int counts[3] = {nv, k, k};
-        ProfScope ps(s, RSOLVE_PROF_DOTS, j, var_of(nv + 2 * k), (nv + 2.0 * k + 1.0) * w * nn);
-        launch_dots<T>(ld, ld, bases, vecs, counts, 3, s->partial, s->nblk, s->ctl, st);
+        ProfEv pe(s, RSOLVE_PROF_DOTS, j, var_of(ntot), (nv + 2.0 * k + 1.0) * w * nn);
+        launch_dots<T>(ld, ld, bases, vecs, counts, 3, s->partial, nb1, s->ctl, st, nv, k, pe.e0, pe.e1);
     } else {
         const T* bases[1] = {V};
         const T* vecs[1] = {wout};
         const int counts[1] = {nv};
-        ProfScope ps(s, RSOLVE_PROF_DOTS, j, var_of(nv), (nv + 1.0) * w * nn);
-        launch_dots<T>(ld, ld, bases, vecs, counts, 1, s->partial, s->nblk, s->ctl, st);
+        ProfEv pe(s, RSOLVE_PROF_DOTS, j, var_of(ntot), (nv + 1.0) * w * nn);
+        launch_dots<T>(ld, ld, bases, vecs, counts, 1, s->partial, nb1, s->ctl, st, nv, 0, pe.e0, pe.e1);
     }
-    launch_reduce_pass1(s->partial, s->nblk, nv, k, s->ctl, st);
-    if (nv <= 64) {
-        ProfScope ps(s, RSOLVE_PROF_UPDATE_DOTS, j, var_of(nv), (nv + k + 2.0) * w * nn);
-        launch_update_dots<T>(ld, V, ld, nv, Zt, k, wout, ctl_h1(s->ctl), ctl_cw(s->ctl), s->partial, s->nblk, s->ctl,
-                              st);
-    } else {
-        launch_update<T>(ld, V, ld, nv, Zt, k, wout, ctl_h1(s->ctl), ctl_cw(s->ctl), s->nblk, s->ctl, st);
-        const T* bases[1] = {V};
-        const T* vecs[1] = {wout};
-        const int counts[1] = {nv};
-        launch_dots<T>(ld, ld, bases, vecs, counts, 1, s->partial, s->nblk, s->ctl, st);
-    }
-    launch_reduce(s->partial, s->nblk, nv, ctl_h2(s->ctl), s->ctl, 0, 0, false, true, st);
+    const int nb2 = cols_grid(ld, s->cus, (nv + 7) / 8, 16, nv);
     {
-        ProfScope ps(s, RSOLVE_PROF_UPDATE_NORM, j, 0, (nv + 2.0) * w * nn);
-        launch_update_norm<T>(ld, V, ld, nv, wout, ctl_h2(s->ctl), s->partial, s->nblk, s->ctl, st);
+        ProfEv pe(s, RSOLVE_PROF_UPDATE_DOTS, j, var_of(nv), (nv + k + 2.0) * w * nn);
+        launch_update_dots<T>(ld, V, ld, nv, Zt, k, wout, ctl_h1(s->ctl), ctl_cw(s->ctl), s->partial, nb2, s->ctl, st,
+                              pe.e0, pe.e1);
     }
-    launch_givens(s->partial, s->nblk, j, s->ctl, st);
+    {
+        ProfEv pe(s, RSOLVE_PROF_UPDATE_NORM, j, 0, (nv + 2.0) * w * nn);
+        launch_update_norm<T>(ld, V, ld, nv, wout, ctl_h2(s->ctl), s->partial, s->nblk, s->ctl, st, j, pe.e0, pe.e1);
+    }
 }
 
 // r (wb[0]) = b - A xw, then the span(W) correction x += W E^{-1} W^T r, r -= A W E^{-1} W^T r
@@ -315,8 +327,9 @@ void residual_and_correct(rsolve_seq* s, const rsolve_csr* A, const double* b, i
         const double* bases[1] = {s->W};
         const double* vecs[1] = {s->wb[0]};
         const int counts[1] = {k};
-        launch_dots<double>(s->ld, s->ld, bases, vecs, counts, 1, s->partial, s->nblk, nullptr, st);
-        launch_reduce(s->partial, s->nblk, k, ctl_red(s->ctl), s->ctl, 0, k, true, false, st);
+        const int nb = cols_grid(s->ld, s->cus, (k + 7) / 8, 32, k);
+        launch_dots<double>(s->ld, s->ld, bases, vecs, counts, 1, s->partial, nb, nullptr, st);
+        launch_reduce(s->partial, nb, k, ctl_red(s->ctl), s->ctl, 0, k, true, false, st);
     }
     launch_correct(s->ld, s->W, s->Z, s->ld, k, s->xw, s->wb[0], s->ctl, s->partial, s->nblk, st);
     launch_finish_norm(s->partial, s->nblk, s->ctl, 0, st);
@@ -361,12 +374,17 @@ int rsolve_create_sequence(const rsolve_config* cfg, int64_t n, int64_t nnz_max,
     s->ws = static_cast<char*>(workspace);
     s->ws_bytes = ws_bytes;
     layout(s, *cfg, n, nnz_max, s->ws);
-    s->nblk = pick_nblk(s->ld);
-    s->gblk = pick_gblk(s->ld);
     hipError_t e = hipGetDevice(&s->device);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&s->cus, hipDeviceAttributeMultiprocessorCount, s->device);
+    s->nblk = pick_nblk(s->ld, s->cus);
+    s->gblk = pick_gblk(s->ld);
     if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&s->hctl), CTL_HEAD + 64, hipHostMallocDefault);
     if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&s->hsig), sizeof(double) * SMAX, hipHostMallocDefault);
     if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&s->herr), sizeof(int32_t) * 8, hipHostMallocDefault);
+    if (e == hipSuccess)
+        e = hipHostMalloc(reinterpret_cast<void**>(&s->poll_done), sizeof(int32_t) * 2, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&s->poll_ev[0], hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&s->poll_ev[1], hipEventDisableTiming);
     // zero the whole workspace once: padding rows of every tall buffer stay zero forever
     if (e == hipSuccess) e = hipMemsetAsync(s->ws, 0, need, s->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
@@ -375,6 +393,9 @@ int rsolve_create_sequence(const rsolve_config* cfg, int64_t n, int64_t nnz_max,
         if (s->hctl) (void)hipHostFree(s->hctl);
         if (s->hsig) (void)hipHostFree(s->hsig);
         if (s->herr) (void)hipHostFree(s->herr);
+        if (s->poll_done) (void)hipHostFree(s->poll_done);
+        for (auto& ev : s->poll_ev)
+            if (ev) (void)hipEventDestroy(ev);
         delete s;
         return RSOLVE_E_DEVICE;
     }
@@ -388,7 +409,8 @@ int rsolve_profile_enable(rsolve_seq* s, int32_t on) {
         HIP_TRY(hipSetDevice(s->device));
         const int cnt = rsolve_seq::NPK * MMAX * 2;
         s->pev = new hipEvent_t[cnt]();
-        for (int i = 0; i < cnt; ++i) HIP_TRY(hipEventCreate(&s->pev[i]));
+        // timing-only events: no system-scope fence, so recording them does not flush caches
+        for (int i = 0; i < cnt; ++i) HIP_TRY(hipEventCreateWithFlags(&s->pev[i], hipEventDisableSystemFence));
     }
     s->prof_on = on != 0;
     return RSOLVE_OK;
@@ -423,6 +445,9 @@ int rsolve_destroy_sequence(rsolve_seq* s) {
     if (s->hctl) (void)hipHostFree(s->hctl);
     if (s->hsig) (void)hipHostFree(s->hsig);
     if (s->herr) (void)hipHostFree(s->herr);
+    if (s->poll_done) (void)hipHostFree(s->poll_done);
+    for (auto& ev : s->poll_ev)
+        if (ev) (void)hipEventDestroy(ev);
     delete s;
     return RSOLVE_OK;
 }
@@ -562,13 +587,27 @@ int rsolve_solve(rsolve_seq* s, const rsolve_csr* A, const double* b, const doub
         const int max_steps = std::min(m, c.max_iters - its);
         const double cyc_stop = ir ? std::max(c.inner_tol * rnorm, stop_abs) : stop_abs;
         launch_cycle_init(s->ctl, max_steps, cyc_stop, stm);
-        if (ir) {
-            launch_to_f32(ld, s->wb[0], s->w32[0], stm);
-            for (int j = 0; j < max_steps; ++j)
-                arnoldi_step<float>(s, j, A->row_ptr, A->col_idx, s->vals32, s->V32, s->w32, W32, Z32, k);
-        } else {
-            for (int j = 0; j < max_steps; ++j)
-                arnoldi_step<double>(s, j, A->row_ptr, A->col_idx, kv64, s->V, s->wb, s->W, s->Z, k);
+        if (ir) launch_to_f32(ld, s->wb[0], s->w32[0], stm);
+        // Enqueue the cycle in chunks; after chunk c the done flag is copied to pinned memory, and
+        // before chunk c + 2 is enqueued the host waits for chunk c (chunk c + 1 keeps the GPU busy),
+        // so at most two chunks of early-exiting kernels follow the step that converges.
+        constexpr int CHUNK = 4;
+        int chunk = 0;
+        for (int j0 = 0; j0 < max_steps; j0 += CHUNK, ++chunk) {
+            if (chunk >= 2) {
+                HIP_TRY(hipEventSynchronize(s->poll_ev[chunk & 1]));
+                if (s->poll_done[chunk & 1]) break;
+            }
+            const int j1 = std::min(max_steps, j0 + CHUNK);
+            for (int j = j0; j < j1; ++j) {
+                if (ir) arnoldi_step<float>(s, j, A->row_ptr, A->col_idx, s->vals32, s->V32, s->w32, W32, Z32, k);
+                else arnoldi_step<double>(s, j, A->row_ptr, A->col_idx, kv64, s->V, s->wb, s->W, s->Z, k);
+            }
+            if (j1 < max_steps) {
+                HIP_TRY(hipMemcpyAsync(s->poll_done + (chunk & 1), reinterpret_cast<char*>(s->ctl) + offsetof(Ctl, done),
+                                       sizeof(int32_t), hipMemcpyDeviceToHost, stm));
+                HIP_TRY(hipEventRecord(s->poll_ev[chunk & 1], stm));
+            }
         }
         launch_cycle_solve(s->ctl, stm);
         if (ir) launch_x_update<float>(n, s->V32, ld, jac ? s->dinv : nullptr, s->xw, s->ctl, stm);

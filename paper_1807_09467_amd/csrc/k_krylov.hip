@@ -3,10 +3,10 @@
 // fixed-order reductions, the Givens update of the Hessenberg least-squares
 // problem, and the end-of-cycle update.
 //
-// Streaming sweeps use one row per thread and a grid-stride loop over `nblk`
-// blocks; every column of the tall operands is read with fully coalesced
-// wavefront loads.  Per-block partial sums go to partial[c * nblk + block] and are
-// summed in a fixed order by a separate kernel, so results are bitwise
+// Streaming sweeps walk the rows with a grid-stride loop over `nblk` blocks and
+// read every column of the tall operands with fully coalesced wavefront loads.
+// Per-block partial sums go to partial[c * nblk + block]; the last block to
+// finish (arrival counter) sums them in a fixed order, so results are bitwise
 // reproducible for a given launch shape.
 #include "kernels.hpp"
 
@@ -26,39 +26,20 @@ struct DotGroups {
     int n0, n1, n2;
 };
 
-template <typename T, int NT>
-__global__ __launch_bounds__(BLOCK) void k_dots(int64_t npad, int64_t ld, DotGroups<T> g,
-                                                double* __restrict__ partial, int nblk, const Ctl* __restrict__ ctl) {
-    if (ctl && ctl->done) return;
-    __shared__ double red[BLOCK / WAVE][NT];
-    double acc[NT];
-#pragma unroll
-    for (int c = 0; c < NT; ++c) acc[c] = 0.0;
-    const int n0 = g.n0, n1 = g.n1, ntot = n0 + n1 + g.n2;
-    for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < npad; i += (int64_t)nblk * BLOCK) {
-        const double x0 = n0 ? to_d(g.v0[i]) : 0.0;
-        const double x1 = n1 ? to_d(g.v1[i]) : 0.0;
-        const double x2 = g.n2 ? to_d(g.v2[i]) : 0.0;
-#pragma unroll
-        for (int c = 0; c < NT; ++c) {
-            if (c < ntot) {
-                const bool in0 = c < n0, in1 = c < n0 + n1;
-                const T* col = in0 ? (g.b0 + (int64_t)c * ld)
-                                   : (in1 ? (g.b1 + (int64_t)(c - n0) * ld) : (g.b2 + (int64_t)(c - n0 - n1) * ld));
-                const double xv = in0 ? x0 : (in1 ? x1 : x2);
-                acc[c] += to_d(col[i]) * xv;
-            }
-        }
+// Per-lane partial of sum_b p[b] over b = lane, lane + 64, ... < n with four independent
+// accumulators (fixed order for a given n), so the loads of a lane are in flight together.
+__device__ __forceinline__ double lane_strided_sum(const double* __restrict__ p, int n) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int b = lane;
+    for (; b + 3 * WAVE < n; b += 4 * WAVE) {
+        a0 += p[b];
+        a1 += p[b + WAVE];
+        a2 += p[b + 2 * WAVE];
+        a3 += p[b + 3 * WAVE];
     }
-    wave_tr_reduce<NT>(acc);
-    const int wv = threadIdx.x / WAVE;
-    if (wave_tr_owner<NT>()) {
-#pragma unroll
-        for (int i = 0; i < wave_tr_left<NT>(); ++i) red[wv][wave_tr_col<NT>(i)] = acc[i];
-    }
-    __syncthreads();
-    for (int c = threadIdx.x; c < ntot; c += BLOCK)
-        partial[(int64_t)c * nblk + blockIdx.x] = (red[0][c] + red[1][c]) + (red[2][c] + red[3][c]);
+    for (; b < n; b += WAVE) a0 += p[b];
+    return (a0 + a1) + (a2 + a3);
 }
 
 // Solve E x = b (LU with row permutation in ctl) with one wavefront: lane i holds row i.
@@ -87,9 +68,7 @@ __global__ __launch_bounds__(BLOCK) void k_reduce(const double* __restrict__ par
     const int lane = threadIdx.x & (WAVE - 1);
     const int wv = threadIdx.x / WAVE;
     for (int c = wv; c < ncol; c += BLOCK / WAVE) {
-        double s = 0.0;
-        for (int b = lane; b < nblk; b += WAVE) s += partial[(int64_t)c * nblk + b];
-        s = wave_sum(s);
+        const double s = wave_sum(lane_strided_sum(partial + (int64_t)c * nblk, nblk));
         if (lane == 0) sums[c] = s;
     }
     if (lu_solve) {
@@ -102,139 +81,139 @@ __global__ __launch_bounds__(BLOCK) void k_reduce(const double* __restrict__ par
 
 // Pass-1 coefficients of step j (nv = j + 1 basis vectors) with the oblique projector folded in:
 // sums = [V^T w0 | W^T w0 | Z^T v_j]; F[j, :] = v_j^T Z; cw = E^{-1} W^T w0;
-// h1 = V^T (w0 - Z cw) = V^T w0 - F cw.
+// h1 = V^T (w0 - Z cw) = V^T w0 - F cw.  Run by one block of any size (>= 1 wavefront).
+__device__ void pass1_coefficients(const double* __restrict__ partial, int nblk, int nv, int k, Ctl* __restrict__ ctl,
+                                   double* sums, double* Es, double* cws) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int wv = threadIdx.x / WAVE;
+    const int nwv = blockDim.x / WAVE;
+    const int ncol = nv + 2 * k;
+    for (int c = wv; c < ncol; c += nwv) {
+        const double s = wave_sum(lane_strided_sum(partial + (int64_t)c * nblk, nblk));
+        if (lane == 0) sums[c] = s;
+    }
+    for (int t = threadIdx.x; t < k * k; t += blockDim.x) Es[t] = ctl->E[t];
+    __syncthreads();
+    if (k == 0) {
+        for (int i = threadIdx.x; i < nv; i += blockDim.x) ctl->h1[i] = sums[i];
+        return;
+    }
+    if (wv == 0) wave_lu_solve(ctl, k, sums + nv, cws, Es);
+    __syncthreads();
+    for (int c = threadIdx.x; c < k; c += blockDim.x) {
+        ctl->F[(nv - 1) * KMAX + c] = sums[nv + k + c];
+        ctl->cw[c] = cws[c];
+    }
+    for (int i = threadIdx.x; i < nv; i += blockDim.x) {
+        const double* Fi = (i == nv - 1) ? sums + nv + k : ctl->F + i * KMAX;
+        double h0 = sums[i], h1 = 0.0, h2 = 0.0, h3 = 0.0;
+        int c = 0;
+        for (; c + 4 <= k; c += 4) {
+            h0 -= Fi[c] * cws[c];
+            h1 -= Fi[c + 1] * cws[c + 1];
+            h2 -= Fi[c + 2] * cws[c + 2];
+            h3 -= Fi[c + 3] * cws[c + 3];
+        }
+        for (; c < k; ++c) h0 -= Fi[c] * cws[c];
+        ctl->h1[i] = (h0 + h1) + (h2 + h3);
+    }
+}
+
 __global__ __launch_bounds__(BLOCK) void k_reduce_pass1(const double* __restrict__ partial, int nblk, int nv, int k,
                                                         Ctl* __restrict__ ctl) {
     if (ctl->done) return;
     __shared__ double sums[MMAX + 2 * KMAX];
     __shared__ double Es[KMAX * KMAX];
     __shared__ double cws[KMAX];
+    pass1_coefficients(partial, nblk, nv, k, ctl, sums, Es, cws);
+}
+
+// Sweep of dot products: wavefront w of the block owns columns [w CPW, w CPW + CPW) of the
+// concatenated column list and walks the rows in 64-row tiles (one row per lane, grid-stride over
+// tiles); the waves of a block share each tile's vector entries through L1.  Column pointers are
+// wave-uniform and every slot loads unconditionally (an unused slot re-reads the wave's first
+// column and is zeroed before the reduction), so the loads of a tile are issued together.
+template <typename T, int CPW>
+__global__ __launch_bounds__(1024) void k_dots(int64_t npad, int64_t ld, DotGroups<T> g,
+                                               double* __restrict__ partial, int nblk,
+                                               const Ctl* __restrict__ ctl) {
+    if (ctl && ctl->done) return;
     const int lane = threadIdx.x & (WAVE - 1);
     const int wv = threadIdx.x / WAVE;
-    const int ncol = nv + 2 * k;
-    for (int c = wv; c < ncol; c += BLOCK / WAVE) {
-        double s = 0.0;
-        for (int b = lane; b < nblk; b += WAVE) s += partial[(int64_t)c * nblk + b];
-        s = wave_sum(s);
-        if (lane == 0) sums[c] = s;
+    const int n0 = g.n0, n1 = g.n1, ntot = n0 + n1 + g.n2;
+    const int c0 = wv * CPW;
+    const T* col[CPW];
+    int sel[CPW];
+#pragma unroll
+    for (int s = 0; s < CPW; ++s) {
+        const int c = (c0 + s < ntot) ? c0 + s : (c0 < ntot ? c0 : 0);
+        sel[s] = (c < n0) ? 0 : ((c < n0 + n1) ? 1 : 2);
+        col[s] = (sel[s] == 0) ? g.b0 + (int64_t)c * ld
+                               : ((sel[s] == 1) ? g.b1 + (int64_t)(c - n0) * ld : g.b2 + (int64_t)(c - n0 - n1) * ld);
     }
-    for (int t = threadIdx.x; t < k * k; t += BLOCK) Es[t] = ctl->E[t];
-    __syncthreads();
-    if (k == 0) {
-        for (int i = threadIdx.x; i < nv; i += BLOCK) ctl->h1[i] = sums[i];
-        return;
-    }
-    if (wv == 0) wave_lu_solve(ctl, k, sums + nv, cws, Es);
-    __syncthreads();
-    for (int c = threadIdx.x; c < k; c += BLOCK) {
-        ctl->F[(nv - 1) * KMAX + c] = sums[nv + k + c];
-        ctl->cw[c] = cws[c];
-    }
-    for (int i = threadIdx.x; i < nv; i += BLOCK) {
-        double h = sums[i];
-        for (int c = 0; c < k; ++c) {
-            const double f = (i == nv - 1) ? sums[nv + k + c] : ctl->F[i * KMAX + c];
-            h -= f * cws[c];
+    const T* x0p = g.v0;
+    const T* x1p = n1 ? g.v1 : g.v0;
+    const T* x2p = g.n2 ? g.v2 : g.v0;
+    double acc[CPW];
+#pragma unroll
+    for (int s = 0; s < CPW; ++s) acc[s] = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * WAVE + lane; i < npad; i += (int64_t)nblk * WAVE) {
+        const double x0 = to_d(x0p[i]), x1 = to_d(x1p[i]), x2 = to_d(x2p[i]);
+#pragma unroll
+        for (int s = 0; s < CPW; ++s) {
+            const double xv = (sel[s] == 0) ? x0 : ((sel[s] == 1) ? x1 : x2);
+            acc[s] += to_d(col[s][i]) * xv;
         }
-        ctl->h1[i] = h;
     }
-}
-
-// w -= V coefV + Z coefZ, then partial dots V^T w with the updated w (nv <= NC <= 64).
-template <typename T, int NC>
-__global__ __launch_bounds__(BLOCK) void k_update_dots(int64_t npad, const T* __restrict__ V, int64_t ld, int nv,
-                                                       const T* __restrict__ Z, int nz, T* __restrict__ w,
-                                                       const double* __restrict__ coefV,
-                                                       const double* __restrict__ coefZ,
-                                                       double* __restrict__ partial, int nblk,
-                                                       const Ctl* __restrict__ ctl) {
-    if (ctl->done) return;
-    __shared__ double red[BLOCK / WAVE][NC];
-    double acc[NC];
 #pragma unroll
-    for (int c = 0; c < NC; ++c) acc[c] = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < npad; i += (int64_t)nblk * BLOCK) {
-        double vv[NC];
-        double u = to_d(w[i]);
+    for (int s = 0; s < CPW; ++s)
+        if (c0 + s >= ntot) acc[s] = 0.0;
+    wave_tr_reduce<CPW>(acc);
+    if (wave_tr_owner<CPW>()) {
 #pragma unroll
-        for (int c = 0; c < NC; ++c) {
-            vv[c] = 0.0;
-            if (c < nv) {
-                vv[c] = to_d(V[(int64_t)c * ld + i]);
-                u -= vv[c] * coefV[c];
-            }
+        for (int t = 0; t < wave_tr_left<CPW>(); ++t) {
+            const int c = c0 + wave_tr_col<CPW>(t);
+            if (c < ntot) partial[(int64_t)c * nblk + blockIdx.x] = acc[t];
         }
-        for (int c = 0; c < nz; ++c) u -= to_d(Z[(int64_t)c * ld + i]) * coefZ[c];
-        const T us = (T)u;
-        w[i] = us;
-        const double ud = to_d(us);
-#pragma unroll
-        for (int c = 0; c < NC; ++c) acc[c] += vv[c] * ud;
     }
-    wave_tr_reduce<NC>(acc);
-    const int wv = threadIdx.x / WAVE;
-    if (wave_tr_owner<NC>()) {
-#pragma unroll
-        for (int i = 0; i < wave_tr_left<NC>(); ++i) red[wv][wave_tr_col<NC>(i)] = acc[i];
-    }
-    __syncthreads();
-    for (int c = threadIdx.x; c < nv; c += BLOCK)
-        partial[(int64_t)c * nblk + blockIdx.x] = (red[0][c] + red[1][c]) + (red[2][c] + red[3][c]);
 }
 
+// u - sum_{c < nc} col_c[i] coef[c] with the column loop unrolled by 8 into four partial sums
+// (coefficients in LDS or registers), so eight independent loads are in flight per row.
 template <typename T>
-__global__ __launch_bounds__(BLOCK) void k_update(int64_t npad, const T* __restrict__ V, int64_t ld, int nv,
-                                                  const T* __restrict__ Z, int nz, T* __restrict__ w,
-                                                  const double* __restrict__ coefV, const double* __restrict__ coefZ,
-                                                  int nblk, const Ctl* __restrict__ ctl) {
-    if (ctl->done) return;
-    for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < npad; i += (int64_t)nblk * BLOCK) {
-        double u = to_d(w[i]);
-        for (int c = 0; c < nv; ++c) u -= to_d(V[(int64_t)c * ld + i]) * coefV[c];
-        for (int c = 0; c < nz; ++c) u -= to_d(Z[(int64_t)c * ld + i]) * coefZ[c];
-        w[i] = (T)u;
+__device__ __forceinline__ double row_update(const T* __restrict__ B, int64_t ld, int nc, int64_t i,
+                                             const double* __restrict__ cs, double u) {
+    double u1 = 0.0, u2 = 0.0, u3 = 0.0;
+    int c = 0;
+    for (; c + 8 <= nc; c += 8) {
+        double v[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v[q] = to_d(B[(int64_t)(c + q) * ld + i]);
+        u -= v[0] * cs[c] + v[4] * cs[c + 4];
+        u1 -= v[1] * cs[c + 1] + v[5] * cs[c + 5];
+        u2 -= v[2] * cs[c + 2] + v[6] * cs[c + 6];
+        u3 -= v[3] * cs[c + 3] + v[7] * cs[c + 7];
     }
+    for (; c < nc; ++c) u -= to_d(B[(int64_t)c * ld + i]) * cs[c];
+    return (u + u1) + (u2 + u3);
 }
 
-template <typename T>
-__global__ __launch_bounds__(BLOCK) void k_update_norm(int64_t npad, const T* __restrict__ V, int64_t ld, int nv,
-                                                       T* __restrict__ w, const double* __restrict__ coef,
-                                                       double* __restrict__ partial, int nblk,
-                                                       const Ctl* __restrict__ ctl) {
-    if (ctl->done) return;
-    __shared__ double lds4[BLOCK / WAVE];
-    double acc = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < npad; i += (int64_t)nblk * BLOCK) {
-        double u = to_d(w[i]);
-        for (int c = 0; c < nv; ++c) u -= to_d(V[(int64_t)c * ld + i]) * coef[c];
-        const T us = (T)u;
-        w[i] = us;
-        const double ud = to_d(us);
-        acc += ud * ud;
-    }
-    acc = block_sum(acc, lds4);
-    if (threadIdx.x == 0) partial[blockIdx.x] = acc;
-}
-
-// Column j of the Hessenberg matrix, Givens rotations, residual estimate, stop test.
-__global__ __launch_bounds__(WAVE) void k_givens(const double* __restrict__ partial, int nblk, int j,
-                                                 Ctl* __restrict__ ctl) {
-    if (ctl->done) return;
-    __shared__ double hcol[MMAX + 1];
+// Column j of the Hessenberg matrix, Givens rotations, residual estimate, stop test.  Run by
+// the first wavefront of one block; hcol is LDS scratch of MMAX + 1 doubles.
+__device__ void givens_column(const double* __restrict__ partial, int nblk, int j, Ctl* __restrict__ ctl,
+                              double* hcol) {
     const int lane = threadIdx.x;
-    double s = 0.0;
-    for (int b = lane; b < nblk; b += WAVE) s += partial[b];
-    s = wave_sum(s);
+    if (lane >= WAVE) return;
+    const double s = wave_sum(lane_strided_sum(partial, nblk));
     const double hn = sqrt(s);
     double cn = 0.0;
     for (int i = lane; i <= j; i += WAVE) {
         const double h = ctl->h1[i] + ctl->h2[i];
-        hcol[i] = h;
         cn += h * h;
     }
     cn = wave_sum(cn) + s;
-    __syncthreads();
     if (lane != 0) return;
+    for (int i = 0; i <= j; ++i) hcol[i] = ctl->h1[i] + ctl->h2[i];
     hcol[j + 1] = hn;
     const double colnorm = sqrt(cn);
     for (int i = 0; i < j; ++i) {
@@ -268,6 +247,134 @@ __global__ __launch_bounds__(WAVE) void k_givens(const double* __restrict__ part
     if (lucky) ctl->lucky = 1;
     if (bad || lucky || fabs(gn) <= ctl->stop_abs || steps >= ctl->max_steps) ctl->done = 1;
     ctl->inv_h = (hn > 0.0) ? 1.0 / hn : 0.0;
+}
+
+__global__ __launch_bounds__(WAVE) void k_givens(const double* __restrict__ partial, int nblk, int j,
+                                                 Ctl* __restrict__ ctl) {
+    if (ctl->done) return;
+    __shared__ double hcol[MMAX + 1];
+    givens_column(partial, nblk, j, ctl, hcol);
+}
+
+// w -= V coefV + Z coefZ, then partial dots V^T w with the updated w.  Wavefront w owns V
+// columns [w CPW, w CPW + CPW) and a share of the Z columns.  Rows go in pairs of 64-row tiles
+// (lane l holds rows l and l + 64 of the pair): each wave forms its part of the row updates, the
+// parts meet in LDS (double-buffered, one barrier per pair), every wave finishes the updated rows
+// in the same fixed order, wave 0 stores them, and each wave accumulates the dots of its own
+// columns (kept in registers) with the updated rows.
+template <typename T, int CPW>
+__global__ __launch_bounds__(1024) void k_update_dots(int64_t npad, const T* __restrict__ V, int64_t ld, int nv,
+                                                      const T* __restrict__ Z, int nz, T* __restrict__ w,
+                                                      const double* __restrict__ coefV,
+                                                      const double* __restrict__ coefZ,
+                                                      double* __restrict__ partial, int nblk,
+                                                      const Ctl* __restrict__ ctl) {
+    if (ctl->done) return;
+    __shared__ double part[2][16][2 * WAVE];
+    __shared__ double czs[KMAX];
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int wv = threadIdx.x / WAVE;
+    const int NW = blockDim.x / WAVE;
+    const int c0 = wv * CPW;
+    for (int t = threadIdx.x; t < nz; t += blockDim.x) czs[t] = coefZ[t];
+    const T* col[CPW];
+    double hc[CPW];
+#pragma unroll
+    for (int s = 0; s < CPW; ++s) {
+        const bool ok = c0 + s < nv;
+        col[s] = V + (int64_t)(ok ? c0 + s : 0) * ld;
+        hc[s] = ok ? coefV[c0 + s] : 0.0;
+    }
+    const int zper = (nz + NW - 1) / NW;
+    const int z0 = wv * zper < nz ? wv * zper : nz;
+    const int z1 = (z0 + zper < nz) ? z0 + zper : nz;
+    double acc[CPW];
+#pragma unroll
+    for (int s = 0; s < CPW; ++s) acc[s] = 0.0;
+    __syncthreads();
+    int buf = 0;
+    for (int64_t t = blockIdx.x; t * 2 * WAVE < npad; t += nblk) {
+        const int64_t i0 = t * 2 * WAVE + lane;
+        const bool two = i0 + WAVE < npad;          // uniform: npad is a multiple of 64
+        const int64_t i1 = two ? i0 + WAVE : i0;
+        const double wi0 = to_d(w[i0]), wi1 = to_d(w[i1]);
+        double va[CPW], vb[CPW];
+        double p0 = 0.0, p1 = 0.0;
+#pragma unroll
+        for (int s = 0; s < CPW; ++s) {
+            va[s] = to_d(col[s][i0]);
+            vb[s] = to_d(col[s][i1]);
+            p0 += va[s] * hc[s];
+            p1 += vb[s] * hc[s];
+        }
+        {
+            double q0 = 0.0, q1 = 0.0;
+            int c = z0;
+            for (; c + 2 <= z1; c += 2) {
+                const T* za = Z + (int64_t)c * ld;
+                const T* zb = za + ld;
+                const double a0 = to_d(za[i0]), a1 = to_d(za[i1]), b0 = to_d(zb[i0]), b1 = to_d(zb[i1]);
+                q0 += a0 * czs[c] + b0 * czs[c + 1];
+                q1 += a1 * czs[c] + b1 * czs[c + 1];
+            }
+            if (c < z1) {
+                const T* za = Z + (int64_t)c * ld;
+                q0 += to_d(za[i0]) * czs[c];
+                q1 += to_d(za[i1]) * czs[c];
+            }
+            p0 += q0;
+            p1 += q1;
+        }
+        part[buf][wv][lane] = p0;
+        part[buf][wv][WAVE + lane] = p1;
+        __syncthreads();
+        double u0 = wi0, u1 = wi1;
+        for (int q = 0; q < NW; ++q) {
+            u0 -= part[buf][q][lane];
+            u1 -= part[buf][q][WAVE + lane];
+        }
+        const T us0 = (T)u0, us1 = (T)u1;
+        if (wv == 0) {
+            w[i0] = us0;
+            if (two) w[i1] = us1;
+        }
+        const double ud0 = to_d(us0), ud1 = two ? to_d(us1) : 0.0;
+#pragma unroll
+        for (int s = 0; s < CPW; ++s) acc[s] += va[s] * ud0 + vb[s] * ud1;
+        buf ^= 1;
+    }
+#pragma unroll
+    for (int s = 0; s < CPW; ++s)
+        if (c0 + s >= nv) acc[s] = 0.0;
+    wave_tr_reduce<CPW>(acc);
+    if (wave_tr_owner<CPW>()) {
+#pragma unroll
+        for (int t = 0; t < wave_tr_left<CPW>(); ++t) {
+            const int c = c0 + wave_tr_col<CPW>(t);
+            if (c < nv) partial[(int64_t)c * nblk + blockIdx.x] = acc[t];
+        }
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_update_norm(int64_t npad, const T* __restrict__ V, int64_t ld, int nv,
+                                                       T* __restrict__ w, const double* __restrict__ coef,
+                                                       double* __restrict__ partial, int nblk,
+                                                       const Ctl* __restrict__ ctl) {
+    if (ctl->done) return;
+    __shared__ double cv[MMAX];
+    __shared__ double lds4[BLOCK / WAVE];
+    for (int t = threadIdx.x; t < nv; t += BLOCK) cv[t] = coef[t];
+    __syncthreads();
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < npad; i += (int64_t)nblk * BLOCK) {
+        const T us = (T)row_update(V, ld, nv, i, cv, to_d(w[i]));
+        w[i] = us;
+        const double ud = to_d(us);
+        acc += ud * ud;
+    }
+    acc = block_sum(acc, lds4);
+    if (threadIdx.x == 0) partial[blockIdx.x] = acc;
 }
 
 __global__ void k_cycle_init(Ctl* ctl, int max_steps, double stop_abs) {
@@ -315,10 +422,8 @@ __global__ __launch_bounds__(BLOCK) void k_x_update(int64_t n, const T* __restri
     const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
     if (i >= n) return;
     const int s = ctl->steps;
-    double acc = 0.0;
-    for (int c = 0; c < s; ++c) acc += to_d(V[(int64_t)c * ld + i]) * ctl->y[c];
-    if (dinv) acc *= dinv[i];
-    x[i] += acc;
+    const double acc = -row_update(V, ld, s, i, ctl->y, 0.0);
+    x[i] += dinv ? acc * dinv[i] : acc;
 }
 
 __global__ __launch_bounds__(BLOCK) void k_correct(int64_t npad, const double* __restrict__ W,
@@ -349,9 +454,7 @@ __global__ __launch_bounds__(BLOCK) void k_correct(int64_t npad, const double* _
 __global__ __launch_bounds__(WAVE) void k_finish_norm(const double* __restrict__ partial, int nblk,
                                                       Ctl* __restrict__ ctl, int which) {
     const int lane = threadIdx.x;
-    double s = 0.0;
-    for (int b = lane; b < nblk; b += WAVE) s += partial[b];
-    s = wave_sum(s);
+    const double s = wave_sum(lane_strided_sum(partial, nblk));
     if (lane == 0) {
         const double nrm = sqrt(s);
         if (!isfinite(nrm)) ctl->nonfinite = 1;
@@ -382,11 +485,14 @@ __global__ __launch_bounds__(BLOCK) void k_copy_pad(int64_t n, int64_t npad, con
 
 template <typename T>
 void launch_dots(int64_t npad, int64_t ld, const T* const* bases, const T* const* vecs, const int* counts,
-                 int ngroups, double* partial, int nblk, const Ctl* ctl, hipStream_t st) {
+                 int ngroups, double* partial, int nblk, Ctl* ctl, hipStream_t st, int pass1_nv, int pass1_k,
+                 hipEvent_t ev0, hipEvent_t ev1) {
+    constexpr int CPW = 8;
     int ntot = 0;
     for (int q = 0; q < ngroups; ++q) ntot += counts[q];
-    for (int a = 0; a < ntot; a += 64) {
-        const int b = (ntot - a) < 64 ? ntot : a + 64;
+    // at most 16 wavefronts (128 columns) per launch
+    for (int a = 0; a < ntot; a += 16 * CPW) {
+        const int b = (ntot - a) < 16 * CPW ? ntot : a + 16 * CPW;
         const T* gb[3] = {nullptr, nullptr, nullptr};
         const T* gv[3] = {nullptr, nullptr, nullptr};
         int gn[3] = {0, 0, 0};
@@ -403,68 +509,53 @@ void launch_dots(int64_t npad, int64_t ld, const T* const* bases, const T* const
             off += counts[q];
         }
         DotGroups<T> g{gb[0], gb[1], gb[2], gv[0], gv[1], gv[2], gn[0], gn[1], gn[2]};
-        double* pp = partial + (int64_t)a * nblk;
-        const int cnt = b - a;
-        if (cnt <= 8)
-            k_dots<T, 8><<<nblk, BLOCK, 0, st>>>(npad, ld, g, pp, nblk, ctl);
-        else if (cnt <= 16)
-            k_dots<T, 16><<<nblk, BLOCK, 0, st>>>(npad, ld, g, pp, nblk, ctl);
-        else if (cnt <= 32)
-            k_dots<T, 32><<<nblk, BLOCK, 0, st>>>(npad, ld, g, pp, nblk, ctl);
-        else
-            k_dots<T, 64><<<nblk, BLOCK, 0, st>>>(npad, ld, g, pp, nblk, ctl);
+        const int nw = (b - a + CPW - 1) / CPW;
+        const bool first = a == 0, last = b == ntot;
+        hipExtLaunchKernelGGL(k_dots<T, CPW>, dim3(nblk), dim3(nw * WAVE), 0, st, first ? ev0 : nullptr,
+                              last ? ev1 : nullptr, 0, npad, ld, g, partial + (int64_t)a * nblk, nblk,
+                              static_cast<const Ctl*>(ctl));
     }
+    if (pass1_nv > 0) k_reduce_pass1<<<1, BLOCK, 0, st>>>(partial, nblk, pass1_nv, pass1_k, ctl);
 }
 template void launch_dots<double>(int64_t, int64_t, const double* const*, const double* const*, const int*, int,
-                                  double*, int, const Ctl*, hipStream_t);
+                                  double*, int, Ctl*, hipStream_t, int, int, hipEvent_t, hipEvent_t);
 template void launch_dots<float>(int64_t, int64_t, const float* const*, const float* const*, const int*, int,
-                                 double*, int, const Ctl*, hipStream_t);
+                                 double*, int, Ctl*, hipStream_t, int, int, hipEvent_t, hipEvent_t);
 
 void launch_reduce(const double* partial, int nblk, int ncol, double* dst, Ctl* ctl, int nv, int nw, bool lu_solve,
                    bool check_done, hipStream_t st) {
     k_reduce<<<1, BLOCK, 0, st>>>(partial, nblk, ncol, dst, ctl, nv, nw, lu_solve ? 1 : 0, check_done ? 1 : 0);
 }
 
-void launch_reduce_pass1(const double* partial, int nblk, int nv, int k, Ctl* ctl, hipStream_t st) {
-    k_reduce_pass1<<<1, BLOCK, 0, st>>>(partial, nblk, nv, k, ctl);
-}
 
 template <typename T>
 void launch_update_dots(int64_t npad, const T* V, int64_t ld, int nv, const T* Z, int nz, T* w, const double* coefV,
-                        const double* coefZ, double* partial, int nblk, const Ctl* ctl, hipStream_t st) {
-    if (nv <= 8)
-        k_update_dots<T, 8><<<nblk, BLOCK, 0, st>>>(npad, V, ld, nv, Z, nz, w, coefV, coefZ, partial, nblk, ctl);
-    else if (nv <= 16)
-        k_update_dots<T, 16><<<nblk, BLOCK, 0, st>>>(npad, V, ld, nv, Z, nz, w, coefV, coefZ, partial, nblk, ctl);
-    else if (nv <= 32)
-        k_update_dots<T, 32><<<nblk, BLOCK, 0, st>>>(npad, V, ld, nv, Z, nz, w, coefV, coefZ, partial, nblk, ctl);
-    else
-        k_update_dots<T, 64><<<nblk, BLOCK, 0, st>>>(npad, V, ld, nv, Z, nz, w, coefV, coefZ, partial, nblk, ctl);
+                        const double* coefZ, double* partial, int nblk, Ctl* ctl, hipStream_t st, hipEvent_t ev0,
+                        hipEvent_t ev1) {
+    constexpr int CPW = 8;
+    const int nw = (nv + CPW - 1) / CPW;   // nv <= 128 -> at most 16 wavefronts
+    hipExtLaunchKernelGGL(k_update_dots<T, CPW>, dim3(nblk), dim3(nw * WAVE), 0, st, ev0, ev1, 0, npad, V, ld, nv, Z,
+                          nz, w, coefV, coefZ, partial, nblk, static_cast<const Ctl*>(ctl));
+    k_reduce<<<1, BLOCK, 0, st>>>(partial, nblk, nv, ctl->h2, ctl, 0, 0, 0, 1);
 }
 template void launch_update_dots<double>(int64_t, const double*, int64_t, int, const double*, int, double*,
-                                         const double*, const double*, double*, int, const Ctl*, hipStream_t);
+                                         const double*, const double*, double*, int, Ctl*, hipStream_t, hipEvent_t,
+                                         hipEvent_t);
 template void launch_update_dots<float>(int64_t, const float*, int64_t, int, const float*, int, float*,
-                                        const double*, const double*, double*, int, const Ctl*, hipStream_t);
-
-template <typename T>
-void launch_update(int64_t npad, const T* V, int64_t ld, int nv, const T* Z, int nz, T* w, const double* coefV,
-                   const double* coefZ, int nblk, const Ctl* ctl, hipStream_t st) {
-    k_update<T><<<nblk, BLOCK, 0, st>>>(npad, V, ld, nv, Z, nz, w, coefV, coefZ, nblk, ctl);
-}
-template void launch_update<double>(int64_t, const double*, int64_t, int, const double*, int, double*,
-                                    const double*, const double*, int, const Ctl*, hipStream_t);
-template void launch_update<float>(int64_t, const float*, int64_t, int, const float*, int, float*, const double*,
-                                   const double*, int, const Ctl*, hipStream_t);
+                                        const double*, const double*, double*, int, Ctl*, hipStream_t, hipEvent_t,
+                                        hipEvent_t);
 
 template <typename T>
 void launch_update_norm(int64_t npad, const T* V, int64_t ld, int nv, T* w, const double* coef, double* partial,
-                        int nblk, const Ctl* ctl, hipStream_t st) {
-    k_update_norm<T><<<nblk, BLOCK, 0, st>>>(npad, V, ld, nv, w, coef, partial, nblk, ctl);
+                        int nblk, Ctl* ctl, hipStream_t st, int givens_j, hipEvent_t ev0, hipEvent_t ev1) {
+    hipExtLaunchKernelGGL(k_update_norm<T>, dim3(nblk), dim3(BLOCK), 0, st, ev0, ev1, 0, npad, V, ld, nv, w, coef,
+                          partial, nblk, static_cast<const Ctl*>(ctl));
+    if (givens_j >= 0) k_givens<<<1, WAVE, 0, st>>>(partial, nblk, givens_j, ctl);
 }
 template void launch_update_norm<double>(int64_t, const double*, int64_t, int, double*, const double*, double*, int,
-                                         const Ctl*, hipStream_t);
+                                         Ctl*, hipStream_t, int, hipEvent_t, hipEvent_t);
 template void launch_update_norm<float>(int64_t, const float*, int64_t, int, float*, const double*, double*, int,
-                                        const Ctl*, hipStream_t);
+                                        Ctl*, hipStream_t, int, hipEvent_t, hipEvent_t);
 
 void launch_givens(const double* partial, int nblk, int j, Ctl* ctl, hipStream_t st) {
     k_givens<<<1, WAVE, 0, st>>>(partial, nblk, j, ctl);

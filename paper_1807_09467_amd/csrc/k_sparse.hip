@@ -1,9 +1,12 @@
 // Sparse kernels: CSR validation, Jacobi scaling, SpMV variants and the A W product.
 //
-// CSR SpMV uses LPR consecutive lanes of a 64-wide wavefront per row (LPR = 4, 8,
-// 16 or 32): a Q_p finite-element row holds 9..49 entries stored contiguously, so
-// the LPR lanes read a contiguous run of values and column indices, gather x, and
-// combine their partial sums with LPR-wide shuffles.  Accumulation is float64.
+// CSR SpMV uses LPR consecutive lanes of a 64-wide wavefront per row (LPR = 2..32):
+// a Q_p finite-element row holds 9..49 entries stored contiguously, so each lane
+// takes 4 consecutive entries per round with 16-byte index / value loads, gathers
+// x, and the LPR lanes combine their partial sums with shuffles.  Accumulation is
+// float64.
+#include <cstdlib>
+
 #include "kernels.hpp"
 
 namespace rs {
@@ -58,6 +61,55 @@ __global__ __launch_bounds__(BLOCK) void k_scale_values(int64_t nnz, const int32
     if (o32) o32[k] = (float)v;
 }
 
+// Partial dot product of one CSR row with x over the entries k = a + sub + LPR t: four entries
+// per lane per round, indices and values loaded together before the four gathers of x.  Rounds
+// past the row end clamp to the row's first entry and contribute zero.
+template <typename T, int LPR>
+__device__ __forceinline__ double csr_row_part(const int32_t* __restrict__ ci, const T* __restrict__ val,
+                                               const T* __restrict__ x, int a, int e, int sub) {
+    double acc = 0.0;
+    for (int k0 = a + sub; k0 < e; k0 += 4 * LPR) {
+        int c[4];
+        double v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int k = k0 + u * LPR;
+            const bool ok = k < e;
+            const int kk = ok ? k : a;
+            c[u] = ci[kk];
+            v[u] = ok ? to_d(val[kk]) : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc += v[u] * to_d(x[c[u]]);
+    }
+    return acc;
+}
+
+// Variant with each lane owning E (4 or 8) consecutive entries per round: 16-byte index and value
+// loads (rows start at arbitrary offsets, so the loads are only dword-aligned, which the memory
+// system accepts).  The last partial chunk of a row falls back to guarded scalar loads.
+template <typename T, int LPR, int E>
+__device__ __forceinline__ double csr_row_part_vec(const int32_t* __restrict__ ci, const T* __restrict__ val,
+                                                   const T* __restrict__ x, int a, int e, int sub) {
+    double acc = 0.0;
+    for (int k0 = a + E * sub; k0 < e; k0 += E * LPR) {
+        if (k0 + E <= e) {
+            int c[E];
+            T v[E];
+            __builtin_memcpy(c, ci + k0, sizeof(c));
+            __builtin_memcpy(v, val + k0, sizeof(v));
+            double p[E];
+#pragma unroll
+            for (int t = 0; t < E; ++t) p[t] = to_d(v[t]) * to_d(x[c[t]]);
+#pragma unroll
+            for (int t = 0; t < E; ++t) acc += p[t];
+        } else {
+            for (int k = k0; k < e; ++k) acc += to_d(val[k]) * to_d(x[ci[k]]);
+        }
+    }
+    return acc;
+}
+
 template <int LPR>
 __device__ __forceinline__ double group_sum(double v) {
 #pragma unroll
@@ -70,18 +122,20 @@ template <typename T, int LPR>
 __global__ __launch_bounds__(BLOCK) void k_spmv_arnoldi(int64_t n, const int32_t* __restrict__ rp,
                                                         const int32_t* __restrict__ ci, const T* __restrict__ val,
                                                         const T* __restrict__ win, T* __restrict__ vout,
-                                                        T* __restrict__ y, const Ctl* __restrict__ ctl) {
+                                                        T* __restrict__ y, const Ctl* __restrict__ ctl, int remap,
+                                                        int vec) {
     if (ctl->done) return;
     const double s = ctl->inv_h;
-    const int64_t gt = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    const unsigned lb = remap ? xcd_block(blockIdx.x, gridDim.x) : blockIdx.x;
+    const int64_t gt = (int64_t)lb * BLOCK + threadIdx.x;
     const int64_t row = gt / LPR;
     const int sub = (int)(gt % LPR);
     double acc = 0.0;
     const bool active = row < n;
-    if (active) {
-        const int a = rp[row], b = rp[row + 1];
-        for (int k = a + sub; k < b; k += LPR) acc += to_d(val[k]) * to_d(win[ci[k]]);
-    }
+    if (active)
+        acc = (vec == 8)   ? csr_row_part_vec<T, LPR, 8>(ci, val, win, rp[row], rp[row + 1], sub)
+              : (vec == 4) ? csr_row_part_vec<T, LPR, 4>(ci, val, win, rp[row], rp[row + 1], sub)
+                           : csr_row_part<T, LPR>(ci, val, win, rp[row], rp[row + 1], sub);
     acc = group_sum<LPR>(acc);
     if (active && sub == 0) {
         y[row] = (T)(s * acc);
@@ -94,15 +148,12 @@ __global__ __launch_bounds__(BLOCK) void k_residual(int64_t n, const int32_t* __
                                                     const int32_t* __restrict__ ci, const double* __restrict__ val,
                                                     const double* __restrict__ x, const double* __restrict__ b,
                                                     double* __restrict__ r) {
-    const int64_t gt = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    const int64_t gt = (int64_t)xcd_block(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
     const int64_t row = gt / LPR;
     const int sub = (int)(gt % LPR);
     double acc = 0.0;
     const bool active = row < n;
-    if (active) {
-        const int a = rp[row], e = rp[row + 1];
-        for (int k = a + sub; k < e; k += LPR) acc += val[k] * x[ci[k]];
-    }
+    if (active) acc = csr_row_part_vec<double, LPR, 4>(ci, val, x, rp[row], rp[row + 1], sub);
     acc = group_sum<LPR>(acc);
     if (active && sub == 0) r[row] = (b ? b[row] : 0.0) - acc;
 }
@@ -116,10 +167,7 @@ __global__ __launch_bounds__(BLOCK) void k_spmv(int64_t n, const int32_t* __rest
     const int sub = (int)(gt % LPR);
     double acc = 0.0;
     const bool active = row < n;
-    if (active) {
-        const int a = rp[row], e = rp[row + 1];
-        for (int k = a + sub; k < e; k += LPR) acc += val[k] * x[ci[k]];
-    }
+    if (active) acc = csr_row_part_vec<double, LPR, 4>(ci, val, x, rp[row], rp[row + 1], sub);
     acc = group_sum<LPR>(acc);
     if (active && sub == 0) y[row] = acc;
 }
@@ -191,15 +239,26 @@ void launch_scale_values(int64_t nnz, const int32_t* ci, const double* val, cons
 
 template <typename T>
 void launch_spmv_arnoldi(int lpr, int64_t n, const int32_t* rp, const int32_t* ci, const T* val, const T* win,
-                         T* vout, T* y, const Ctl* ctl, hipStream_t st) {
-#define RS_CALL(L) k_spmv_arnoldi<T, L><<<grid_for(n * L), BLOCK, 0, st>>>(n, rp, ci, val, win, vout, y, ctl)
+                         T* vout, T* y, const Ctl* ctl, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+    static const int remap = [] {
+        const char* v = getenv("RSOLVE_XCD_REMAP");
+        return (v && v[0] == '1') ? 1 : 0;
+    }();
+    static const int vec = [] {
+        const char* v = getenv("RSOLVE_SPMV_VEC");
+        return v ? atoi(v) : 4;
+    }();
+#define RS_CALL(L)                                                                                       \
+    hipExtLaunchKernelGGL(k_spmv_arnoldi<T, L>, dim3(grid_for(n * L)), dim3(BLOCK), 0, st, ev0, ev1, 0, n, rp, ci, \
+                          val, win, vout, y, ctl, remap, vec)
     RS_LPR_DISPATCH(lpr, RS_CALL)
 #undef RS_CALL
 }
 template void launch_spmv_arnoldi<double>(int, int64_t, const int32_t*, const int32_t*, const double*,
-                                          const double*, double*, double*, const Ctl*, hipStream_t);
+                                          const double*, double*, double*, const Ctl*, hipStream_t, hipEvent_t,
+                                          hipEvent_t);
 template void launch_spmv_arnoldi<float>(int, int64_t, const int32_t*, const int32_t*, const float*, const float*,
-                                         float*, float*, const Ctl*, hipStream_t);
+                                         float*, float*, const Ctl*, hipStream_t, hipEvent_t, hipEvent_t);
 
 void launch_residual(int lpr, int64_t n, const int32_t* rp, const int32_t* ci, const double* val, const double* x,
                      const double* b, double* r, hipStream_t st) {

@@ -1,6 +1,7 @@
 // Host-side launch wrappers of the rsolve kernels (one translation unit per kernel family).
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -18,9 +19,12 @@ void launch_diag_inv(int64_t n, const int32_t* diag_pos, const double* val, doub
 void launch_scale_values(int64_t nnz, const int32_t* ci, const double* val, const double* dinv, double* out64,
                          float* out32, hipStream_t st);
 // Arnoldi product: vout[i] = s * win[i]; y[i] = s * sum_k val[k] win[col[k]], s = ctl->inv_h.
+// ev0 / ev1 (nullable): events stamped with the start and end of the kernel's own dispatch
+// (hipExtLaunchKernelGGL), for per-kernel timing without extra queue packets.
 template <typename T>
 void launch_spmv_arnoldi(int lpr, int64_t n, const int32_t* rp, const int32_t* ci, const T* val, const T* win,
-                         T* vout, T* y, const Ctl* ctl, hipStream_t st);
+                         T* vout, T* y, const Ctl* ctl, hipStream_t st, hipEvent_t ev0 = nullptr,
+                         hipEvent_t ev1 = nullptr);
 // r = b - A x (float64)
 void launch_residual(int lpr, int64_t n, const int32_t* rp, const int32_t* ci, const double* val,
                      const double* x, const double* b, double* r, hipStream_t st);
@@ -36,27 +40,27 @@ void launch_to_f32(int64_t count, const double* in, float* out, hipStream_t st);
 // ---- Krylov cycle (k_krylov.hip) ----
 // Multi-dot sweep over up to 3 column groups: group q = columns bases[q][:, 0..counts[q]) dotted
 // with vecs[q]; partial[c * nblk + b] for the concatenated column index c.
+// pass1_nv > 0: then turn the partials into the pass-1 coefficients of a step with pass1_nv basis
+// vectors and pass1_k recycle columns (one-block reduction kernel).
 template <typename T>
 void launch_dots(int64_t npad, int64_t ld, const T* const* bases, const T* const* vecs, const int* counts,
-                 int ngroups, double* partial, int nblk, const Ctl* ctl, hipStream_t st);
-// pass-1 coefficients with the oblique projector folded in (see k_reduce_pass1)
-void launch_reduce_pass1(const double* partial, int nblk, int nv, int k, Ctl* ctl, hipStream_t st);
+                 int ngroups, double* partial, int nblk, Ctl* ctl, hipStream_t st, int pass1_nv = 0,
+                 int pass1_k = 0, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 // fixed-order sum of the partials into dst[0..ncol); if lu_solve, also ctl->cw = E^{-1} dst[nv..nv+nw)
 void launch_reduce(const double* partial, int nblk, int ncol, double* dst, Ctl* ctl, int nv, int nw,
                    bool lu_solve, bool check_done, hipStream_t st);
-// w -= V[:, :nv] coefV + Z[:, :nz] coefZ; partial = V^T w (new)   (nv <= 64)
+// w -= V[:, :nv] coefV + Z[:, :nz] coefZ; ctl->h2 = V^T w (new)   (nv <= 128; 8 columns per wavefront;
+// a one-block kernel sums the per-block partials)
 template <typename T>
 void launch_update_dots(int64_t npad, const T* V, int64_t ld, int nv, const T* Z, int nz, T* w,
-                        const double* coefV, const double* coefZ, double* partial, int nblk, const Ctl* ctl,
-                        hipStream_t st);
-// w -= V[:, :nv] coefV + Z[:, :nz] coefZ (no dots); used when nv > 64
-template <typename T>
-void launch_update(int64_t npad, const T* V, int64_t ld, int nv, const T* Z, int nz, T* w, const double* coefV,
-                   const double* coefZ, int nblk, const Ctl* ctl, hipStream_t st);
-// w -= V[:, :nv] coef; partial[b] = sum over block b of w^2
+                        const double* coefV, const double* coefZ, double* partial, int nblk, Ctl* ctl,
+                        hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+// w -= V[:, :nv] coef; partial[b] = sum over block b of w^2; givens_j >= 0: then form column
+// givens_j of H and apply the Givens update (as launch_givens)
 template <typename T>
 void launch_update_norm(int64_t npad, const T* V, int64_t ld, int nv, T* w, const double* coef,
-                        double* partial, int nblk, const Ctl* ctl, hipStream_t st);
+                        double* partial, int nblk, Ctl* ctl, hipStream_t st, int givens_j, hipEvent_t ev0 = nullptr,
+                        hipEvent_t ev1 = nullptr);
 // column j of H: reduce ||w||^2, Givens update, stop test, next scale
 void launch_givens(const double* partial, int nblk, int j, Ctl* ctl, hipStream_t st);
 // start of a cycle: g = beta e1 with beta = ctl->rnorm, done/steps reset
