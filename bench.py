@@ -121,6 +121,29 @@ def run_solver(gasm, u0, systems, warmup, steps, tol, cfg, dev, profile=False, l
     return dict(elapsed=elapsed, lat=lat, its=its, cycles=cyc, k_eff=keff, rel=rel, prof=prof, xs=xs)
 
 
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_spmv_arnoldi_f32-q3_512x512_recycled_mixed-hbm_traffic.md")
+TRAFFIC_SOURCES = ["paper_1807_09467_amd/csrc/k_sparse.hip", "paper_1807_09467_amd/csrc/common.hpp"]
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary, or None when
+    there is none or the kernel's sources have changed since the counters were taken."""
+    import hashlib
+    import re
+    try:
+        text = open(TRAFFIC_SUMMARY).read()
+    except OSError:
+        return None
+    m = re.search(r"^traffic_bytes_per_launch=(\d+) kernel=(\S+) sources_sha256=([0-9a-f]{64})$", text, re.M)
+    if not m or m.group(2) != kernel:
+        return None
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return float(m.group(1)) if h.hexdigest() == m.group(3) else None
+
+
 def summarize(r, steps):
     lat = np.array(r["lat"])
     return {
@@ -215,8 +238,12 @@ def main():
     roofline = None
     if dom is not None:
         roofline = {"bound": "hbm", "achieved": round(dom["gb_per_s"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(dom["gb_per_s"] / HBM_PEAK_GBS, 4), "traffic": None,
+                    "frac": round(dom["gb_per_s"] / HBM_PEAK_GBS, 4),
+                    "traffic": measured_traffic(dom["kernel"]) if pname == "C3" and cfg.get("precision") == "fp32_ir"
+                    else None,
                     "kernel": f"{dom['kernel']} (variant {dom['variant']})",
+                    "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE x2 + WRITE_SIZE x1)",
+                    "algorithmic_bytes_per_launch": round(dom["bytes"] / dom["launches"]),
                     "avg_launch_us": round(dom["avg_us"], 2), "launches": dom["launches"]}
 
     cpu = None
