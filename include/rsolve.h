@@ -180,6 +180,59 @@ int rsolve_update_recycle(rsolve_seq* s, const double* x);
 int rsolve_get_recycle(rsolve_seq* s, int32_t* k_eff, int32_t* rank, double* sigma_host,
                        int32_t cap, double* W_out, int64_t ld_out);
 
+/* ---- batched solves of many sequences in one launch ---- */
+
+/* One-block limits: an item whose sequence is FP64 with restart_m, recycle_k (and, for the
+ * update, snapshots_s <= restart_m + 1) within these limits and n <= RSOLVE_SMALL_MAX_N runs
+ * as one workgroup of a shared persistent launch; any other item runs through the
+ * multi-kernel path of rsolve_solve / rsolve_update_recycle, one after the other, while that
+ * launch is in flight. */
+#define RSOLVE_SMALL_MAX_RESTART   64
+#define RSOLVE_SMALL_MAX_RECYCLE   32
+#define RSOLVE_SMALL_MAX_SNAPSHOTS 32
+#define RSOLVE_SMALL_MAX_N         65536
+
+typedef struct {
+    rsolve_seq* seq;       /* in: distinct sequences, all on the current HIP device */
+    rsolve_csr A;          /* in: this step's matrix (device pointers, as for rsolve_solve) */
+    const double* b;       /* in: device, n */
+    const double* x0;      /* in: device, n, nullable (zero start) */
+    double* x;             /* out: device, n (may alias x0) */
+    double tol;            /* in: stop when ||b - A x||_2 <= tol ||b||_2 */
+    int32_t status;        /* out: as rsolve_solve returns for this item */
+    int32_t reserved;
+    rsolve_stats stats;    /* out: t_setup_ms = 0 and t_cycles_ms = t_total_ms = wall time of the
+                              whole batch call for the one-block items */
+} rsolve_batch_solve_item;
+
+/*
+ * Solve one system for each item; each item is exactly the computation of rsolve_solve
+ * (section 3.2 oblique projector, section 4.2 projection guess and correction, stop rule of
+ * section 6.1), taken by one workgroup that keeps every Arnoldi step, reduction, Givens
+ * rotation and restart decision on the device.  `hip_stream` (NULL = the stream of the first
+ * one-block item's sequence) carries the launch.  Synchronous.  Returns RSOLVE_OK when the
+ * batch ran (per-item outcome in items[i].status: E_INVALID for bad arguments, a sequence on
+ * another device or a sequence listed twice, E_STATE never), E_INVALID for a bad array,
+ * E_DEVICE on a HIP failure.  A corrupt CSR gives that item E_INVALID without touching the
+ * others.
+ */
+int rsolve_solve_batch(rsolve_batch_solve_item* items, int32_t count, void* hip_stream);
+
+typedef struct {
+    rsolve_seq* seq;       /* in: distinct sequences on the current device */
+    const double* x;       /* in: device, n; NULL = the last solution of this sequence */
+    int32_t status;        /* out: as rsolve_update_recycle returns for this item */
+    int32_t reserved;
+} rsolve_batch_update_item;
+
+/*
+ * Algorithm 1 of section 5.2 for each item, as rsolve_update_recycle.  One-block items take
+ * the SVD of the snapshot ring through a Householder QR of the ring (the sequence's Krylov
+ * basis is the scratch), a one-sided Jacobi SVD of R and W = Q U_R[:, :k_eff], with the same
+ * rank rule.  Synchronous; status conventions as rsolve_solve_batch.
+ */
+int rsolve_update_recycle_batch(rsolve_batch_update_item* items, int32_t count, void* hip_stream);
+
 /* ---- per-kernel timing (HIP events) ---- */
 #define RSOLVE_PROF_SPMV        0   /* Arnoldi product w = A D^{-1} v (plus basis normalisation) */
 #define RSOLVE_PROF_DOTS        1   /* CGS2 pass 1: dots with V, W and the A W row F (one sweep) */

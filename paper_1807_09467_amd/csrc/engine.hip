@@ -16,6 +16,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <vector>
 
 #include "../../include/rsolve.h"
 #include "../../include/rsolve_kernels.h"
@@ -164,6 +165,12 @@ struct rsolve_seq {
     double pms[NPK][NVAR];
     double pb[NPK][NVAR];
     int64_t pcnt[NPK][NVAR];
+    // one-block batched path: pinned job descriptors and its own pattern cache
+    SmallJob* hjob = nullptr;
+    SmallUpd* hupd = nullptr;
+    const int32_t* spat_rp = nullptr;
+    const int32_t* spat_ci = nullptr;
+    int64_t spat_nnz = -1;
 };
 
 namespace {
@@ -339,6 +346,40 @@ double ms_since(std::chrono::steady_clock::time_point t0) {
     return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }
 
+static_assert(SMALL_MMAX == RSOLVE_SMALL_MAX_RESTART && SMALL_KMAX == RSOLVE_SMALL_MAX_RECYCLE &&
+                  SMALL_SMAX == RSOLVE_SMALL_MAX_SNAPSHOTS,
+              "one-block limits of the header and the kernels agree");
+
+bool small_solve_ok(const rsolve_seq* s) {
+    const rsolve_config& c = s->cfg;
+    return c.precision == RSOLVE_FP64 && c.restart_m <= SMALL_MMAX && c.recycle_k <= SMALL_KMAX &&
+           s->n <= RSOLVE_SMALL_MAX_N;
+}
+
+bool small_update_ok(const rsolve_seq* s) {
+    const rsolve_config& c = s->cfg;
+    return c.precision == RSOLVE_FP64 && c.snapshots_s <= SMALL_SMAX && c.snapshots_s <= c.restart_m + 1 &&
+           s->n >= c.snapshots_s && s->n <= RSOLVE_SMALL_MAX_N;
+}
+
+// Argument checks shared with rsolve_solve; returns RSOLVE_OK or E_INVALID (message set).
+int check_solve_args(const rsolve_seq* s, const rsolve_csr* A, const double* b, const double* x, double tol) {
+    if (!s || !A || !b || !x) {
+        set_err("null argument");
+        return RSOLVE_E_INVALID;
+    }
+    if (!(tol > 0.0) || !std::isfinite(tol)) {
+        set_err("tol must be positive and finite");
+        return RSOLVE_E_INVALID;
+    }
+    if (A->n != s->n || A->nnz < A->n || A->nnz > s->nnz_max || !A->row_ptr || !A->col_idx || !A->val ||
+        A->reserved != 0) {
+        set_err("matrix header does not match the sequence (n=%lld nnz=%lld)", (long long)A->n, (long long)A->nnz);
+        return RSOLVE_E_INVALID;
+    }
+    return RSOLVE_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -383,6 +424,8 @@ int rsolve_create_sequence(const rsolve_config* cfg, int64_t n, int64_t nnz_max,
     if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&s->herr), sizeof(int32_t) * 8, hipHostMallocDefault);
     if (e == hipSuccess)
         e = hipHostMalloc(reinterpret_cast<void**>(&s->poll_done), sizeof(int32_t) * 2, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&s->hjob), sizeof(SmallJob), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&s->hupd), sizeof(SmallUpd), hipHostMallocDefault);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&s->poll_ev[0], hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&s->poll_ev[1], hipEventDisableTiming);
     // zero the whole workspace once: padding rows of every tall buffer stay zero forever
@@ -394,6 +437,8 @@ int rsolve_create_sequence(const rsolve_config* cfg, int64_t n, int64_t nnz_max,
         if (s->hsig) (void)hipHostFree(s->hsig);
         if (s->herr) (void)hipHostFree(s->herr);
         if (s->poll_done) (void)hipHostFree(s->poll_done);
+        if (s->hjob) (void)hipHostFree(s->hjob);
+        if (s->hupd) (void)hipHostFree(s->hupd);
         for (auto& ev : s->poll_ev)
             if (ev) (void)hipEventDestroy(ev);
         delete s;
@@ -446,6 +491,8 @@ int rsolve_destroy_sequence(rsolve_seq* s) {
     if (s->hsig) (void)hipHostFree(s->hsig);
     if (s->herr) (void)hipHostFree(s->herr);
     if (s->poll_done) (void)hipHostFree(s->poll_done);
+    if (s->hjob) (void)hipHostFree(s->hjob);
+    if (s->hupd) (void)hipHostFree(s->hupd);
     for (auto& ev : s->poll_ev)
         if (ev) (void)hipEventDestroy(ev);
     delete s;
@@ -720,6 +767,202 @@ int rsolve_update_recycle(rsolve_seq* s, const double* x) {
         }
     }
     s->k_w = keff;
+    return RSOLVE_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Batched one-block path: every qualifying item of a batch is one block of a single launch
+// (k_small.hip); the others go through the multi-kernel path, one after the other, while the
+// launch runs.
+// ---------------------------------------------------------------------------
+int rsolve_solve_batch(rsolve_batch_solve_item* items, int32_t count, void* hip_stream) {
+    const auto t0 = std::chrono::steady_clock::now();
+    g_err[0] = 0;
+    if (count < 0 || (count > 0 && !items)) {
+        set_err("invalid batch");
+        return RSOLVE_E_INVALID;
+    }
+    if (count == 0) return RSOLVE_OK;
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    // 0 = invalid, 1 = one-block launch, 2 = multi-kernel path
+    std::vector<int> route(count, 0);
+    std::vector<int> small;
+    for (int i = 0; i < count; ++i) {
+        rsolve_batch_solve_item& it = items[i];
+        it.status = RSOLVE_E_INVALID;
+        memset(&it.stats, 0, sizeof(it.stats));
+        if (check_solve_args(it.seq, &it.A, it.b, it.x, it.tol) != RSOLVE_OK) continue;
+        if (it.seq->device != dev) continue;
+        bool dup = false;
+        for (int q = 0; q < i && !dup; ++q) dup = route[q] != 0 && items[q].seq == it.seq;
+        if (dup) continue;
+        route[i] = small_solve_ok(it.seq) ? 1 : 2;
+        if (route[i] == 1) small.push_back(i);
+    }
+    hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+    if (!st && !small.empty()) st = items[small[0]].seq->stream;
+    for (size_t b0 = 0; b0 < small.size(); b0 += SMALL_BATCH) {
+        SmallBatch batch{};
+        const int cnt = (int)std::min<size_t>(SMALL_BATCH, small.size() - b0);
+        for (int q = 0; q < cnt; ++q) {
+            rsolve_batch_solve_item& it = items[small[b0 + q]];
+            rsolve_seq* s = it.seq;
+            const rsolve_config& c = s->cfg;
+            const bool same = (it.A.flags & RSOLVE_SAME_PATTERN) && s->spat_rp == it.A.row_ptr &&
+                              s->spat_ci == it.A.col_idx && s->spat_nnz == it.A.nnz;
+            SmallJob& J = *s->hjob;
+            memset(&J, 0, sizeof(J));
+            J.n = s->n;
+            J.nnz = it.A.nnz;
+            J.ld = s->ld;
+            J.rp = it.A.row_ptr;
+            J.ci = it.A.col_idx;
+            J.val = it.A.val;
+            J.b = it.b;
+            J.x0 = it.x0;
+            J.x = it.x;
+            J.tol = it.tol;
+            J.m = c.restart_m;
+            J.k = (c.method != RSOLVE_PLAIN) ? s->k_w : 0;
+            J.max_iters = c.max_iters;
+            J.jacobi = c.precond == RSOLVE_PRECOND_JACOBI ? 1 : 0;
+            J.validate = same ? 0 : 1;
+            J.W = s->W;
+            J.Z = s->Z;
+            J.V = s->V;
+            J.w = s->wb[0];
+            J.r = s->wb[1];
+            J.xw = s->xw;
+            J.dinv = s->dinv;
+            J.vals = s->vals;
+            J.F = s->partial;
+            J.status = RSOLVE_E_DEVICE;
+            batch.job[q] = s->hjob;
+            // the multi-kernel path keeps its own pattern cache (with the diagonal positions)
+            s->pat_ok = false;
+            s->have_x = false;
+        }
+        launch_small_solve(batch, cnt, st);
+        HIP_TRY(hipGetLastError());
+    }
+    // items outside the one-block limits: the multi-kernel path, while the launch runs
+    for (int i = 0; i < count; ++i) {
+        if (route[i] != 2) continue;
+        rsolve_batch_solve_item& it = items[i];
+        it.status = rsolve_solve(it.seq, &it.A, it.b, it.x0, it.x, it.tol, &it.stats);
+    }
+    if (!small.empty()) HIP_TRY(hipStreamSynchronize(st));
+    const double total = ms_since(t0);
+    for (int i : small) {
+        rsolve_batch_solve_item& it = items[i];
+        rsolve_seq* s = it.seq;
+        const SmallJob& J = *s->hjob;
+        it.status = J.status;
+        if (J.status == RSOLVE_OK || J.status == RSOLVE_NOT_CONVERGED) {
+            s->spat_rp = it.A.row_ptr;
+            s->spat_ci = it.A.col_idx;
+            s->spat_nnz = it.A.nnz;
+            s->have_x = true;
+            s->nnz_cur = it.A.nnz;
+        } else if (J.status == RSOLVE_E_INVALID) {
+            s->spat_nnz = -1;
+        }
+        rsolve_stats& o = it.stats;
+        o.iterations = J.iterations;
+        o.cycles = J.cycles;
+        o.k_eff = J.k_used;
+        o.converged = J.converged;
+        o.flags = J.flags;
+        o.rel_res_true = J.bnorm > 0.0 ? J.rnorm / J.bnorm : 0.0;
+        o.rel_res_implicit = J.bnorm > 0.0 ? J.gimp / J.bnorm : 0.0;
+        o.t_setup_ms = 0.0;
+        o.t_cycles_ms = total;
+        o.t_total_ms = total;
+    }
+    return RSOLVE_OK;
+}
+
+int rsolve_update_recycle_batch(rsolve_batch_update_item* items, int32_t count, void* hip_stream) {
+    g_err[0] = 0;
+    if (count < 0 || (count > 0 && !items)) {
+        set_err("invalid batch");
+        return RSOLVE_E_INVALID;
+    }
+    if (count == 0) return RSOLVE_OK;
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    std::vector<int> route(count, 0);
+    std::vector<int> small;
+    for (int i = 0; i < count; ++i) {
+        rsolve_batch_update_item& it = items[i];
+        it.status = RSOLVE_E_INVALID;
+        rsolve_seq* s = it.seq;
+        if (!s || s->device != dev) continue;
+        bool dup = false;
+        for (int q = 0; q < i && !dup; ++q) dup = route[q] != 0 && items[q].seq == s;
+        if (dup) continue;
+        if (!it.x && !s->have_x) {
+            it.status = RSOLVE_E_STATE;
+            continue;
+        }
+        const rsolve_config& c = s->cfg;
+        if (c.recycle_k == 0 || c.snapshots_s == 0) {
+            s->count++;
+            it.status = RSOLVE_OK;
+            continue;
+        }
+        route[i] = small_update_ok(s) ? 1 : 2;
+        if (route[i] == 1) small.push_back(i);
+    }
+    hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+    if (!st && !small.empty()) st = items[small[0]].seq->stream;
+    for (size_t b0 = 0; b0 < small.size(); b0 += SMALL_BATCH) {
+        SmallUpdBatch batch{};
+        const int cnt = (int)std::min<size_t>(SMALL_BATCH, small.size() - b0);
+        for (int q = 0; q < cnt; ++q) {
+            rsolve_batch_update_item& it = items[small[b0 + q]];
+            rsolve_seq* s = it.seq;
+            const rsolve_config& c = s->cfg;
+            SmallUpd& U = *s->hupd;
+            memset(&U, 0, sizeof(U));
+            U.n = s->n;
+            U.ld = s->ld;
+            U.src = it.x ? it.x : s->xw;
+            U.X = s->X;
+            U.Q = s->V;
+            U.W = s->W;
+            U.slot = (int32_t)(s->count % c.snapshots_s);
+            U.c = (int32_t)std::min<int64_t>(s->count + 1, c.snapshots_s);
+            U.k = c.recycle_k;
+            U.svd = ((s->count + 1) % c.svd_interval == 0) ? 1 : 0;
+            U.status = RSOLVE_E_DEVICE;
+            batch.job[q] = s->hupd;
+        }
+        launch_small_update(batch, cnt, st);
+        HIP_TRY(hipGetLastError());
+    }
+    for (int i = 0; i < count; ++i) {
+        if (route[i] != 2) continue;
+        items[i].status = rsolve_update_recycle(items[i].seq, items[i].x);
+    }
+    if (!small.empty()) HIP_TRY(hipStreamSynchronize(st));
+    for (int i : small) {
+        rsolve_batch_update_item& it = items[i];
+        rsolve_seq* s = it.seq;
+        const SmallUpd& U = *s->hupd;
+        s->count++;
+        it.status = U.status;
+        if (!U.svd) continue;
+        if (U.status == RSOLVE_OK) {
+            s->k_w = U.k_eff;
+            s->rank = U.rank;
+            s->nsig = U.c;
+            for (int q = 0; q < U.c; ++q) s->sigma[q] = U.sigma[q];
+        } else {
+            s->k_w = 0;
+        }
+    }
     return RSOLVE_OK;
 }
 

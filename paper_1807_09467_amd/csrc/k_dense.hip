@@ -6,6 +6,7 @@
 //   * one-sided (Hestenes) Jacobi SVD of the final small R;
 //   * W = X V_k Sigma_k^{-1}, then W <- W L^{-T} with L L^T = W^T W.
 #include "kernels.hpp"
+#include "svd_dev.hpp"
 
 namespace rs {
 
@@ -263,70 +264,9 @@ __global__ __launch_bounds__(BLOCK) void k_jacobi_svd(const double* __restrict__
         Vc[j * LDC + i] = (i == j) ? 1.0 : 0.0;
     }
     __syncthreads();
-    const double tol = (double)(c > 1 ? c : 1) * 2.220446049250313e-16;
-    const int grp = tid >> 3, sub = tid & 7;
-    for (int sweep = 0; sweep < 60 && cp >= 2; ++sweep) {
-        if (tid == 0) rotated = 0;
-        __syncthreads();
-        for (int rnd = 0; rnd < cp - 1; ++rnd) {
-            if (grp < cp / 2) {
-                const int ia = grp, ib = cp - 1 - grp;
-                const int P = (ia == 0) ? 0 : 1 + ((ia - 1 + rnd) % (cp - 1));
-                const int Q = 1 + ((ib - 1 + rnd) % (cp - 1));
-                double al = 0.0, be = 0.0, ga = 0.0;
-                for (int i = sub; i < cp; i += 8) {
-                    const double x = Ac[P * LDC + i], y = Ac[Q * LDC + i];
-                    al += x * x;
-                    be += y * y;
-                    ga += x * y;
-                }
-#pragma unroll
-                for (int o = 4; o > 0; o >>= 1) {
-                    al += __shfl_xor(al, o, WAVE);
-                    be += __shfl_xor(be, o, WAVE);
-                    ga += __shfl_xor(ga, o, WAVE);
-                }
-                if (ga != 0.0 && fabs(ga) > tol * sqrt(al) * sqrt(be)) {
-                    const double zeta = (be - al) / (2.0 * ga);
-                    const double tt = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-                    const double cs = 1.0 / sqrt(1.0 + tt * tt);
-                    const double sn = cs * tt;
-                    for (int i = sub; i < cp; i += 8) {
-                        const double x = Ac[P * LDC + i], y = Ac[Q * LDC + i];
-                        Ac[P * LDC + i] = cs * x - sn * y;
-                        Ac[Q * LDC + i] = sn * x + cs * y;
-                        const double vx = Vc[P * LDC + i], vy = Vc[Q * LDC + i];
-                        Vc[P * LDC + i] = cs * vx - sn * vy;
-                        Vc[Q * LDC + i] = sn * vx + cs * vy;
-                    }
-                    if (sub == 0) rotated = 1;
-                }
-            }
-            __syncthreads();
-        }
-        if (!rotated) break;
-        __syncthreads();
-    }
-    // singular values = column norms, sorted descending (stable on ties)
-    if (tid < c) {
-        double s = 0.0;
-        for (int i = 0; i < c; ++i) s += Ac[tid * LDC + i] * Ac[tid * LDC + i];
-        sig[tid] = sqrt(s);
-    }
-    __syncthreads();
-    if (tid < c) {
-        int pos = 0;
-        for (int i = 0; i < c; ++i)
-            if (sig[i] > sig[tid] || (sig[i] == sig[tid] && i < tid)) ++pos;
-        order[pos] = tid;
-    }
-    __syncthreads();
+    jacobi_svd_sweeps(Ac, Vc, cp, LDC, c, &rotated);
+    const int rank = svd_order_rank(Ac, LDC, c, n, sig, order);
     const double s1 = (c > 0) ? sig[order[0]] : 0.0;
-    const double thr = s1 * (double)(n > c ? n : c) * 2.220446049250313e-16;
-    int rank = 0;
-    for (int i = 0; i < c; ++i)
-        if (sig[order[i]] > thr) ++rank;
-    if (!(s1 > 0.0) || !isfinite(s1)) rank = 0;
     const int keff = rank < k ? rank : k;
     for (int i = tid; i < c; i += BLOCK) ctl->sigma[i] = sig[order[i]];
     for (int t = tid; t < c * keff; t += BLOCK) {

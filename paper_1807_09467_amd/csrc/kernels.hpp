@@ -103,4 +103,68 @@ void launch_cholesky(int k, Ctl* ctl, hipStream_t st);
 // W[r, :k] <- L^{-1} W[r, :k]^T (rows < npad)
 void launch_trsm_rows(int64_t npad, double* W, int64_t ldw, int k, const Ctl* ctl, hipStream_t st);
 
+// ---- one-block persistent path for small systems (k_small.hip) ----
+constexpr int SMALL_MMAX = 64;     // restart limit of the one-block solver
+constexpr int SMALL_KMAX = 32;     // recycle limit
+constexpr int SMALL_SMAX = 32;     // snapshot-ring limit of the one-block recycle update
+constexpr int SMALL_BATCH = 256;   // jobs per launch (one block each)
+
+// One solve, read by its block from pinned host memory at the start and completed (results)
+// by the block at the end.  All pointers are device pointers.
+struct SmallJob {
+    int64_t n, nnz, ld;
+    const int32_t* rp;
+    const int32_t* ci;
+    const double* val;
+    const double* b;
+    const double* x0;  // nullable: zero start
+    double* x;
+    double tol;
+    int32_t m, k, max_iters, jacobi;
+    int32_t validate, pad0;
+    // sequence storage: W, Z = A W (k columns, ld), V (m + 1 columns), two work vectors, the
+    // iterate, D^{-1}, the scaled values (nnz) and F (SMALL_MMAX x SMALL_KMAX)
+    const double* W;
+    double* Z;
+    double* V;
+    double* w;
+    double* r;
+    double* xw;
+    double* dinv;
+    double* vals;
+    double* F;
+    // results
+    int32_t status, iterations, cycles, converged;
+    uint32_t flags;
+    int32_t k_used;
+    double rnorm, bnorm, gimp;
+};
+
+// One recycle update (ring push and, when svd != 0, the new W), same conventions.
+struct SmallUpd {
+    int64_t n, ld;
+    const double* src;  // solution to store (n)
+    double* X;          // snapshot ring (ld, s columns)
+    double* Q;          // scratch, c columns of ld (the sequence's Krylov basis)
+    double* W;          // output basis (k_eff columns of ld)
+    int32_t slot, c, k, svd;
+    // results
+    int32_t status, rank, k_eff, pad0;
+    double sigma[SMALL_SMAX];
+};
+
+struct SmallBatch {
+    SmallJob* job[SMALL_BATCH];
+};
+struct SmallUpdBatch {
+    SmallUpd* job[SMALL_BATCH];
+};
+
+// Block b solves batch.job[b] (count <= SMALL_BATCH): validation, Jacobi scaling, A W, E and its
+// LU, projection guess, restarted GMRES(m) cycles with the oblique projector, all on the device.
+void launch_small_solve(const SmallBatch& batch, int count, hipStream_t st);
+// Block b stores job[b].src in the ring and, if requested, replaces W (Householder QR of the
+// ring, Jacobi SVD of R, W = Q U_k).
+void launch_small_update(const SmallUpdBatch& batch, int count, hipStream_t st);
+
 }  // namespace rs

@@ -35,8 +35,10 @@ EXPORTS = [
     "rsolve_workspace_bytes", "rsolve_create_sequence", "rsolve_solve", "rsolve_update_recycle",
     "rsolve_get_recycle", "rsolve_destroy_sequence", "rsolve_status_string", "rsolve_last_error",
     "rsolve_spmv", "rsolve_kernel_workspace_bytes", "rsolve_gram_tn", "rsolve_snapshot_svd",
-    "rsolve_profile_enable", "rsolve_profile_read",
+    "rsolve_profile_enable", "rsolve_profile_read", "rsolve_solve_batch", "rsolve_update_recycle_batch",
 ]
+
+SMALL_MAX_RESTART, SMALL_MAX_RECYCLE, SMALL_MAX_SNAPSHOTS, SMALL_MAX_N = 64, 32, 32, 65536
 
 PROF_KERNELS = {0: "spmv_arnoldi", 1: "dots", 2: "update_dots", 3: "update_norm"}
 
@@ -70,6 +72,15 @@ class Stats(ctypes.Structure):
 class ProfEntry(ctypes.Structure):
     _fields_ = [("kernel", c_int32), ("variant", c_int32), ("launches", c_int64), ("ms", c_double),
                 ("bytes", c_double)]
+
+
+class BatchSolveItem(ctypes.Structure):
+    _fields_ = [("seq", c_void_p), ("A", CSR), ("b", c_void_p), ("x0", c_void_p), ("x", c_void_p), ("tol", c_double),
+                ("status", c_int32), ("reserved", c_int32), ("stats", Stats)]
+
+
+class BatchUpdateItem(ctypes.Structure):
+    _fields_ = [("seq", c_void_p), ("x", c_void_p), ("status", c_int32), ("reserved", c_int32)]
 
 
 class RsolveError(RuntimeError):
@@ -122,6 +133,10 @@ def load():
     lib.rsolve_profile_enable.restype = c_int
     lib.rsolve_profile_read.argtypes = [c_void_p, POINTER(ProfEntry), c_int32, POINTER(c_int32), c_int32]
     lib.rsolve_profile_read.restype = c_int
+    lib.rsolve_solve_batch.argtypes = [POINTER(BatchSolveItem), c_int32, c_void_p]
+    lib.rsolve_solve_batch.restype = c_int
+    lib.rsolve_update_recycle_batch.argtypes = [POINTER(BatchUpdateItem), c_int32, c_void_p]
+    lib.rsolve_update_recycle_batch.restype = c_int
     _lib = lib
     return lib
 
@@ -185,13 +200,18 @@ class Sequence:
                                                    nbytes, byref(h)))
         self.handle = h
 
+    def csr(self, row_ptr, col_idx, val, same_pattern=False):
+        import torch
+        n = self.n
+        nnz = int(val.numel())
+        return CSR(n, nnz, _ptr(row_ptr, torch.int32, n + 1, "row_ptr"), _ptr(col_idx, torch.int32, nnz, "col_idx"),
+                   _ptr(val, torch.float64, nnz, "val"), SAME_PATTERN if same_pattern else 0, 0)
+
     def solve(self, row_ptr, col_idx, val, b, x0=None, x=None, tol=1e-8, same_pattern=False, check=True):
         """Solve A x = b; returns (x, stats dict, status)."""
         import torch
         n = self.n
-        nnz = int(val.numel())
-        A = CSR(n, nnz, _ptr(row_ptr, torch.int32, n + 1, "row_ptr"), _ptr(col_idx, torch.int32, nnz, "col_idx"),
-                _ptr(val, torch.float64, nnz, "val"), SAME_PATTERN if same_pattern else 0, 0)
+        A = self.csr(row_ptr, col_idx, val, same_pattern)
         if x is None:
             x = torch.empty(n, dtype=torch.float64, device=self.device)
         st = Stats()
@@ -250,6 +270,60 @@ class Sequence:
             self.close()
         except Exception:
             pass
+
+
+def solve_batch(jobs, stream=None, check=True):
+    """One solve per job in a single batched call (rsolve_solve_batch).
+
+    jobs: list of dicts with keys seq (Sequence), row_ptr, col_idx, val, b, and optionally x0, x,
+    tol (1e-8), same_pattern (False).  Returns a list of (x, stats dict, status)."""
+    import torch
+    lib = load()
+    items = (BatchSolveItem * max(len(jobs), 1))()
+    outs = []
+    for i, j in enumerate(jobs):
+        seq = j["seq"]
+        x = j.get("x")
+        if x is None:
+            x = torch.empty(seq.n, dtype=torch.float64, device=seq.device)
+        outs.append(x)
+        it = items[i]
+        it.seq = seq.handle
+        it.A = seq.csr(j["row_ptr"], j["col_idx"], j["val"], j.get("same_pattern", False))
+        it.b = _ptr(j["b"], torch.float64, seq.n, "b")
+        it.x0 = _ptr(j.get("x0"), torch.float64, seq.n, "x0")
+        it.x = _ptr(x, torch.float64, seq.n, "x")
+        it.tol = float(j.get("tol", 1e-8))
+    dev = jobs[0]["seq"].device if jobs else None
+    if dev is not None:
+        with torch.cuda.device(dev):
+            _check(lib.rsolve_solve_batch(items, len(jobs), _stream_handle(stream)))
+    res = []
+    for i in range(len(jobs)):
+        st = items[i].status
+        if check:
+            _check(st, allow=(OK, NOT_CONVERGED))
+        res.append((outs[i], items[i].stats.as_dict(), st))
+    return res
+
+
+def update_batch(seqs, xs=None, stream=None, check=True):
+    """rsolve_update_recycle for every sequence in one batched call; returns the statuses."""
+    import torch
+    lib = load()
+    items = (BatchUpdateItem * max(len(seqs), 1))()
+    for i, seq in enumerate(seqs):
+        items[i].seq = seq.handle
+        x = xs[i] if xs is not None else None
+        items[i].x = _ptr(x, torch.float64, seq.n, "x")
+    if seqs:
+        with torch.cuda.device(seqs[0].device):
+            _check(lib.rsolve_update_recycle_batch(items, len(seqs), _stream_handle(stream)))
+    out = [items[i].status for i in range(len(seqs))]
+    if check:
+        for st in out:
+            _check(st)
+    return out
 
 
 def spmv(row_ptr, col_idx, val, x, y=None, stream=None):

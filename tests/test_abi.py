@@ -47,6 +47,47 @@ def test_struct_layouts():
     assert ctypes.sizeof(rsolve.Stats) == 64
 
 
+C_LAYOUT_PROBE = r"""
+#include <stddef.h>
+#include <stdio.h>
+#include "rsolve.h"
+int main(void) {
+    printf("%zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(rsolve_config), sizeof(rsolve_csr), sizeof(rsolve_stats),
+           sizeof(rsolve_batch_solve_item), offsetof(rsolve_batch_solve_item, status),
+           offsetof(rsolve_batch_solve_item, stats), sizeof(rsolve_batch_update_item),
+           sizeof(rsolve_prof_entry));
+    return 0;
+}
+"""
+
+
+def test_struct_layouts_match_the_c_compiler(tmp_path):
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    src = tmp_path / "probe.c"
+    src.write_text(C_LAYOUT_PROBE)
+    exe = tmp_path / "probe"
+    subprocess.run([cc, "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
+    want = [ctypes.sizeof(rsolve.Config), ctypes.sizeof(rsolve.CSR), ctypes.sizeof(rsolve.Stats),
+            ctypes.sizeof(rsolve.BatchSolveItem), rsolve.BatchSolveItem.status.offset,
+            rsolve.BatchSolveItem.stats.offset, ctypes.sizeof(rsolve.BatchUpdateItem),
+            ctypes.sizeof(rsolve.ProfEntry)]
+    assert got == want
+
+
+def test_batch_calls_reject_bad_arrays(lib):
+    assert lib.rsolve_solve_batch(None, 1, None) == rsolve.E_INVALID
+    assert lib.rsolve_solve_batch(None, -1, None) == rsolve.E_INVALID
+    assert lib.rsolve_update_recycle_batch(None, 2, None) == rsolve.E_INVALID
+    # an empty batch is a no-op that needs no device
+    assert lib.rsolve_solve_batch(None, 0, None) == rsolve.OK
+    assert lib.rsolve_update_recycle_batch(None, 0, None) == rsolve.OK
+
+
 def test_workspace_bytes_valid_and_monotone(lib):
     cfg = rsolve.make_config(restart_m=30, recycle_k=5, snapshots_s=10)
     a = rsolve.workspace_bytes(cfg, 1089, 8409)
