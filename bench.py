@@ -47,6 +47,16 @@ WORKLOADS = {
 }
 
 
+# batched workloads: many independent sequences of one small configuration, one launch per time step
+BATCH_WORKLOADS = {
+    "c1b": ("C1", 256, dict(restart_m=30, recycle_k=5, snapshots_s=10, svd_interval=1, precond="none",
+                            precision="fp64"), 1e-8,
+            "256 independent Q1 32x32 Burgers-Picard sequences (n=1089, nnz=8409 each; bump centres from seeds "
+            "0..255), recycled FP64 GMRES(30) k=5 s=10 ell=1, tol 1e-8, all sequences' solves of a time step in "
+            "one batched launch (one workgroup per sequence), then one batched recycle update"),
+}
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -144,6 +154,166 @@ def measured_traffic(kernel):
     return float(m.group(1)) if h.hexdigest() == m.group(3) else None
 
 
+def generate_batched(prob, nseq, nsteps, dev):
+    """`nsteps` systems of `nseq` independent sequences (seeds 0..nseq-1), resident on the device; the
+    trajectories advance with batched FP64 solves to 1e-10."""
+    import torch
+
+    from paper_1807_09467_amd import rsolve
+    from paper_1807_09467_amd import workload as WL
+    t0 = time.time()
+    asm = WL.Assembler(prob)
+    gasm = WL.GpuAssembler(asm, dev)
+    pat = asm.pat
+    trajs = [rsolve.Sequence(pat.n, pat.nnz, device=dev, restart_m=30, method="plain") for _ in range(nseq)]
+    u0s = [torch.from_numpy(WL.initial_condition(prob, q)).to(dev) for q in range(nseq)]
+    us = list(u0s)
+    systems = [[None] * nsteps for _ in range(nseq)]
+    for i in range(nsteps):
+        jobs = []
+        for q in range(nseq):
+            vals, b = gasm.system(us[q])
+            systems[q][i] = (vals, b)
+            jobs.append(dict(seq=trajs[q], row_ptr=gasm.row_ptr, col_idx=gasm.col_idx, val=vals, b=b, x0=us[q],
+                             tol=1e-10, same_pattern=i > 0))
+        us = [r[0] for r in rsolve.solve_batch(jobs)]
+        log(f"generated step {i + 1}/{nsteps} of {nseq} sequences")
+    for t in trajs:
+        t.close()
+    torch.cuda.synchronize()
+    log(f"generation done in {time.time() - t0:.1f}s")
+    return asm, gasm, u0s, systems
+
+
+def run_batched(gasm, u0s, systems, warmup, steps, tol, cfg, dev, mode, label=""):
+    """All sequences advance one time step per round: `mode` "batch" = one rsolve_solve_batch plus one
+    rsolve_update_recycle_batch per round; "sequential" = rsolve_solve + rsolve_update_recycle per sequence."""
+    import torch
+
+    from paper_1807_09467_amd import rsolve
+    pat = gasm.asm.pat
+    nseq = len(systems)
+    seqs = [rsolve.Sequence(pat.n, pat.nnz, device=dev, **cfg) for _ in range(nseq)]
+    x_prev = list(u0s)
+    lat, its, rel, xs_last = [], [], [], None
+    t_start = None
+    for i in range(warmup + steps):
+        if i == warmup:
+            torch.cuda.synchronize()
+            t_start = time.perf_counter()
+        t0 = time.perf_counter()
+        if mode == "batch":
+            jobs = [dict(seq=seqs[q], row_ptr=gasm.row_ptr, col_idx=gasm.col_idx, val=systems[q][i][0],
+                         b=systems[q][i][1], x0=x_prev[q], tol=tol, same_pattern=i > 0) for q in range(nseq)]
+            res = rsolve.solve_batch(jobs)
+            rsolve.update_batch(seqs)
+            t1 = time.perf_counter()
+            step_lat = [(t1 - t0) * 1e3] * nseq
+        else:
+            res, step_lat = [], []
+            for q in range(nseq):
+                ta = time.perf_counter()
+                res.append(seqs[q].solve(gasm.row_ptr, gasm.col_idx, systems[q][i][0], systems[q][i][1],
+                                         x0=x_prev[q], tol=tol, same_pattern=i > 0))
+                seqs[q].update()
+                step_lat.append((time.perf_counter() - ta) * 1e3)
+            t1 = time.perf_counter()
+        for q, (x, st, status) in enumerate(res):
+            if status != 0:
+                raise RuntimeError(f"{label}: sequence {q} step {i} returned {status}")
+            if i >= warmup:
+                its.append(st["iterations"])
+                rel.append(st["rel_res_true"])
+        if i >= warmup:
+            lat.extend(step_lat)
+        x_prev = [r[0] for r in res]
+        log(f"{label} round {i + 1}/{warmup + steps}: {nseq} solves in {1e3 * (t1 - t0):.2f} ms, "
+            f"mean {np.mean([r[1]['iterations'] for r in res]):.1f} its")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    for sq in seqs:
+        sq.close()
+    return dict(elapsed=elapsed, lat=lat, its=its, rel=rel, xs=x_prev, cycles=[0], solves=nseq * steps)
+
+
+def bench_batched(args):
+    import torch
+
+    from paper_1807_09467_amd import workload as WL
+    dev = torch.device("cuda:0")
+    pname, nseq, cfg, tol, desc = BATCH_WORKLOADS[args.workload]
+    prob = getattr(WL, pname)
+    nsteps = args.warmup + args.steps
+    asm, gasm, u0s, systems = generate_batched(prob, nseq, nsteps, dev)
+    main = run_batched(gasm, u0s, systems, args.warmup, args.steps, tol, cfg, dev, "batch", "recycled-batched")
+    plain_cfg = dict(restart_m=cfg["restart_m"], precond=cfg["precond"], method="plain", precision="fp64")
+    plain = run_batched(gasm, u0s, systems, args.warmup, args.steps, tol, plain_cfg, dev, "batch", "plain-batched")
+    seqr = run_batched(gasm, u0s, systems, args.warmup, args.steps, tol, cfg, dev, "sequential",
+                       "recycled-multikernel")
+
+    def summ(r):
+        lat = np.array(r["lat"])
+        return {"solves_per_s": r["solves"] / r["elapsed"], "ms_per_round": 1e3 * r["elapsed"] / args.steps,
+                "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
+                "avg_iterations": float(np.mean(r["its"])), "max_rel_residual": float(np.max(r["rel"]))}
+
+    m, pl, sq = summ(main), summ(plain), summ(seqr)
+    diffs = [float(torch.linalg.norm(a - b) / torch.linalg.norm(b)) for a, b in zip(main["xs"], plain["xs"])]
+    pl["max_rel_diff_vs_recycled"] = max(diffs)
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline_small(prob, asm, cfg, tol)
+    out = {
+        "metric": f"linear solves/sec at {tol:g} rel. residual",
+        "value": round(m["solves_per_s"], 3),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(m["ms_per_round"], 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": desc, "n": asm.pat.n, "nnz": asm.pat.nnz, "sequences": nseq,
+                   "steps_generated": nsteps, "parallelism": "single GPU"},
+        "latency_ms": m["latency_ms"],
+        "avg_iterations": m["avg_iterations"],
+        "max_rel_residual": m["max_rel_residual"],
+        "plain_fp64_batched": pl,
+        "recycled_multikernel_sequential": sq,
+        "speedup_vs_plain_fp64": m["solves_per_s"] / pl["solves_per_s"],
+        "roofline": None,
+        "roofline_note": "latency-bound: each sequence's working set (< 1 MB) stays in the caches",
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline_small(prob, asm_host, cfg, tol):
+    """Oracle (recycled FP64 GMRES, the workload's configuration) over the first 10 steps of one sequence."""
+    from threadpoolctl import threadpool_info
+
+    from oracle import rgmres as O
+    from paper_1807_09467_amd import workload as WL
+    _, systems, _ = WL.march(prob, 10, 0, asm=asm_host)
+    ocfg = O.Config(restart_m=cfg["restart_m"], recycle_k=cfg["recycle_k"], snapshots_s=cfg["snapshots_s"],
+                    svd_interval=cfg["svd_interval"], method=O.AUG_OBLIQUE, precond=O.PRECOND_NONE)
+    st = O.RecycleState(asm_host.pat.n, ocfg)
+    threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+    x = WL.initial_condition(prob, 0)
+    t0 = time.perf_counter()
+    for vals, b in systems:
+        res = O.solve(asm_host.csr(vals), b, x, tol, ocfg, st.W)
+        st.update(res.x)
+        x = res.x
+    dt = time.perf_counter() - t0
+    return {"value": len(systems) / dt, "unit": "solves/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"10 solves plus recycle updates of sequence 0 ({dt:.2f} s); scipy CSR matvec on 1 thread, "
+                      f"OpenBLAS on {threads}"}
+
+
 def summarize(r, steps):
     lat = np.array(r["lat"])
     return {
@@ -180,7 +350,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="c4", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="c4", choices=sorted(WORKLOADS) + sorted(BATCH_WORKLOADS))
     ap.add_argument("--no-plain", action="store_true", help="skip the plain FP64 comparison run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--inner-tol", type=float, default=None,
@@ -199,6 +369,8 @@ def main():
     from paper_1807_09467_amd import rsolve
     from paper_1807_09467_amd import workload as WL
     rsolve.load()
+    if args.workload in BATCH_WORKLOADS:
+        return bench_batched(args)
     dev = torch.device("cuda:0")
     if args.calib_copy:
         src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
