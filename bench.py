@@ -57,6 +57,16 @@ BATCH_WORKLOADS = {
 }
 
 
+SERVE_WORKLOADS = {
+    "c5": ("independent time-stepping sequences arriving as a Poisson process (200/s); per sequence Q1-Q3 "
+           "(uniform), mesh 64^2-384^2 in steps of 32 (n 4,225-1,329,409), eps log-uniform in [1e-4, 1e-1], "
+           "10-60 steps, dt 5e-3, beta (1, 0.5), bump centre seeded; GMRES(30) right Jacobi tol 1e-8; recycled "
+           "mixed: k=10 s=20 ell=1, FP32 Arnoldi + FP64 refinement (one-block sizes batched in FP64); plain: "
+           "FP64 GMRES(30); served by the rsolve server (HBM-pool admission, continuous batching of small "
+           "sequences, large sequences overlapped on worker streams)"),
+}
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -194,8 +204,9 @@ def run_batched(gasm, u0s, systems, warmup, steps, tol, cfg, dev, mode, label=""
     pat = gasm.asm.pat
     nseq = len(systems)
     seqs = [rsolve.Sequence(pat.n, pat.nnz, device=dev, **cfg) for _ in range(nseq)]
+    plan = rsolve.BatchPlan(seqs, [gasm.row_ptr] * nseq, [gasm.col_idx] * nseq, tol=tol) if mode == "batch" else None
     x_prev = list(u0s)
-    lat, its, rel, xs_last = [], [], [], None
+    lat, its, rel = [], [], []
     t_start = None
     for i in range(warmup + steps):
         if i == warmup:
@@ -203,12 +214,14 @@ def run_batched(gasm, u0s, systems, warmup, steps, tol, cfg, dev, mode, label=""
             t_start = time.perf_counter()
         t0 = time.perf_counter()
         if mode == "batch":
-            jobs = [dict(seq=seqs[q], row_ptr=gasm.row_ptr, col_idx=gasm.col_idx, val=systems[q][i][0],
-                         b=systems[q][i][1], x0=x_prev[q], tol=tol, same_pattern=i > 0) for q in range(nseq)]
-            res = rsolve.solve_batch(jobs)
-            rsolve.update_batch(seqs)
+            outs = plan.solve([systems[q][i][0] for q in range(nseq)], [systems[q][i][1] for q in range(nseq)],
+                              x_prev, same_pattern=i > 0)
+            plan.update()
             t1 = time.perf_counter()
             step_lat = [(t1 - t0) * 1e3] * nseq
+            v = plan.view
+            res = [(outs[q], {"iterations": int(v["iterations"][q]), "rel_res_true": float(v["rel_res_true"][q])},
+                    int(v["status"][q])) for q in range(nseq)]
         else:
             res, step_lat = [], []
             for q in range(nseq):
@@ -231,9 +244,11 @@ def run_batched(gasm, u0s, systems, warmup, steps, tol, cfg, dev, mode, label=""
             f"mean {np.mean([r[1]['iterations'] for r in res]):.1f} its")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
+    xs = [x.clone() for x in x_prev]
+    del plan
     for sq in seqs:
         sq.close()
-    return dict(elapsed=elapsed, lat=lat, its=its, rel=rel, xs=x_prev, cycles=[0], solves=nseq * steps)
+    return dict(elapsed=elapsed, lat=lat, its=its, rel=rel, xs=xs, cycles=[0], solves=nseq * steps)
 
 
 def bench_batched(args):
@@ -287,6 +302,57 @@ def bench_batched(args):
         "roofline": None,
         "roofline_note": "latency-bound: each sequence's working set (< 1 MB) stays in the caches",
         "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_serving(args):
+    import torch
+
+    from paper_1807_09467_amd import serve
+    dev = torch.device("cuda:0")
+    specs = serve.serving_specs(args.sequences, rate=200.0, seed=0)
+    warm = serve.serving_specs(max(args.warmup, 0), rate=200.0, seed=12345)
+    cache = serve.AssemblerCache(dev)
+    t_setup = cache.prepare(specs + warm, log)
+    log(f"generator set-up (patterns, GPU assemblers) {t_setup:.1f}s for {len(cache.base)} (degree, mesh) pairs")
+    pool = int(args.pool_gb * 2 ** 30)
+    mixed_cfg = dict(restart_m=30, recycle_k=10, snapshots_s=20, svd_interval=1, precond="jacobi",
+                     precision="fp32_ir", inner_tol=1e-5)
+    plain_cfg = dict(restart_m=30, precond="jacobi", method="plain", precision="fp64")
+    runs = {}
+    for name, cfg in (("recycled_mixed", mixed_cfg), ("plain_fp64", plain_cfg)):
+        if warm:
+            serve.run_serving(warm, cfg, 1e-8, dev, pool, large_workers=args.workers, cache=cache)
+        _, summ, _ = serve.run_serving(specs, cfg, 1e-8, dev, pool, large_workers=args.workers, cache=cache,
+                                       log=log)
+        log(f"{name}: {summ['solves']} solves in {summ['elapsed_s']:.2f}s = {summ['solves_per_s']:.1f}/s, "
+            f"p50 {summ['latency_ms']['p50']:.2f} ms p99 {summ['latency_ms']['p99']:.2f} ms")
+        runs[name] = summ
+    m, pl = runs["recycled_mixed"], runs["plain_fp64"]
+    out = {
+        "metric": "linear solves/sec at 1e-8 rel. residual (recycled mixed vs plain FP64); p50/p99",
+        "value": round(m["solves_per_s"], 3),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": m["solves"],
+        "warmup": len(warm),
+        "ms_per_step": round(1e3 * m["elapsed_s"] / m["solves"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": SERVE_WORKLOADS["c5"], "sequences": len(specs), "solves": m["solves"],
+                   "pool_gib": args.pool_gb, "large_workers": args.workers, "parallelism": "single GPU"},
+        "latency_ms": m["latency_ms"],
+        "recycled_mixed": m,
+        "plain_fp64": pl,
+        "speedup_vs_plain_fp64": m["solves_per_s"] / pl["solves_per_s"],
+        "roofline": None,
+        "roofline_note": "mixed sizes and overlapping sequences; per-kernel rooflines are measured on the "
+                         "single-sequence workloads",
+        "cpu_baseline": None,
     }
     print(json.dumps(out), flush=True)
 
@@ -350,7 +416,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="c4", choices=sorted(WORKLOADS) + sorted(BATCH_WORKLOADS))
+    ap.add_argument("--workload", default="c4",
+                    choices=sorted(WORKLOADS) + sorted(BATCH_WORKLOADS) + sorted(SERVE_WORKLOADS))
+    ap.add_argument("--sequences", type=int, default=512, help="serving workload: sequences to replay")
+    ap.add_argument("--pool-gb", type=float, default=96.0, help="serving workload: the server's HBM pool")
+    ap.add_argument("--workers", type=int, default=4, help="serving workload: large-sequence worker streams")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain FP64 comparison run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--inner-tol", type=float, default=None,
@@ -371,6 +441,8 @@ def main():
     rsolve.load()
     if args.workload in BATCH_WORKLOADS:
         return bench_batched(args)
+    if args.workload in SERVE_WORKLOADS:
+        return bench_serving(args)
     dev = torch.device("cuda:0")
     if args.calib_copy:
         src = torch.ones(1 << 27, dtype=torch.float64, device=dev)

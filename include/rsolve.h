@@ -54,6 +54,7 @@ extern "C" {
 #define RSOLVE_E_WORKSPACE   -3   /* workspace too small or misaligned (256-byte alignment) */
 #define RSOLVE_E_DEVICE      -4   /* a HIP runtime call failed */
 #define RSOLVE_E_STATE       -5   /* call out of order (e.g. update before any solve) */
+#define RSOLVE_E_BUDGET      -6   /* serving loop: not enough free pool memory or no free slot */
 
 /* ---- configuration values ---- */
 #define RSOLVE_PLAIN          0   /* GMRES(m) without recycling */

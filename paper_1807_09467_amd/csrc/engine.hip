@@ -20,6 +20,7 @@
 
 #include "../../include/rsolve.h"
 #include "../../include/rsolve_kernels.h"
+#include "engine_internal.hpp"
 #include "kernels.hpp"
 
 using namespace rs;
@@ -381,6 +382,8 @@ int check_solve_args(const rsolve_seq* s, const rsolve_csr* A, const double* b, 
 }
 
 }  // namespace
+
+void rs::seq_set_stream(rsolve_seq* s, hipStream_t st) { s->stream = st; }
 
 extern "C" {
 
@@ -992,6 +995,7 @@ const char* rsolve_status_string(int status) {
         case RSOLVE_E_WORKSPACE: return "workspace too small or misaligned";
         case RSOLVE_E_DEVICE: return "HIP runtime error";
         case RSOLVE_E_STATE: return "call out of order";
+        case RSOLVE_E_BUDGET: return "no room in the server's pool or slots";
         default: return "unknown status";
     }
 }

@@ -15,7 +15,7 @@ from ctypes import POINTER, byref, c_char_p, c_double, c_int, c_int32, c_int64, 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "librsolve.so")
 
 OK, NOT_CONVERGED = 0, 1
-E_INVALID, E_NONFINITE, E_WORKSPACE, E_DEVICE, E_STATE = -1, -2, -3, -4, -5
+E_INVALID, E_NONFINITE, E_WORKSPACE, E_DEVICE, E_STATE, E_BUDGET = -1, -2, -3, -4, -5, -6
 
 PLAIN, AUG_OBLIQUE, DEFL_OBLIQUE = 0, 1, 2
 PRECOND_NONE, PRECOND_JACOBI = 0, 1
@@ -36,6 +36,9 @@ EXPORTS = [
     "rsolve_get_recycle", "rsolve_destroy_sequence", "rsolve_status_string", "rsolve_last_error",
     "rsolve_spmv", "rsolve_kernel_workspace_bytes", "rsolve_gram_tn", "rsolve_snapshot_svd",
     "rsolve_profile_enable", "rsolve_profile_read", "rsolve_solve_batch", "rsolve_update_recycle_batch",
+    # serving loop (rsolve_server.h; bound in serve.py)
+    "rsolve_server_create", "rsolve_server_open", "rsolve_server_submit", "rsolve_server_poll",
+    "rsolve_server_close", "rsolve_server_info_get", "rsolve_server_destroy",
 ]
 
 SMALL_MAX_RESTART, SMALL_MAX_RECYCLE, SMALL_MAX_SNAPSHOTS, SMALL_MAX_N = 64, 32, 32, 65536
@@ -305,6 +308,84 @@ def solve_batch(jobs, stream=None, check=True):
             _check(st, allow=(OK, NOT_CONVERGED))
         res.append((outs[i], items[i].stats.as_dict(), st))
     return res
+
+
+def _item_dtype():
+    """numpy view of rsolve_batch_solve_item (offsets taken from the ctypes layout)."""
+    import numpy as np
+    a, st = BatchSolveItem.A.offset, BatchSolveItem.stats.offset
+    names, fmts, offs = [], [], []
+    for name, fmt, off in [
+        ("seq", "u8", BatchSolveItem.seq.offset), ("n", "i8", a + CSR.n.offset), ("nnz", "i8", a + CSR.nnz.offset),
+        ("row_ptr", "u8", a + CSR.row_ptr.offset), ("col_idx", "u8", a + CSR.col_idx.offset),
+        ("val", "u8", a + CSR.val.offset), ("flags", "u4", a + CSR.flags.offset), ("b", "u8", BatchSolveItem.b.offset),
+        ("x0", "u8", BatchSolveItem.x0.offset), ("x", "u8", BatchSolveItem.x.offset),
+        ("tol", "f8", BatchSolveItem.tol.offset), ("status", "i4", BatchSolveItem.status.offset),
+        ("iterations", "i4", st + Stats.iterations.offset), ("cycles", "i4", st + Stats.cycles.offset),
+        ("k_eff", "i4", st + Stats.k_eff.offset), ("converged", "i4", st + Stats.converged.offset),
+        ("rel_res_true", "f8", st + Stats.rel_res_true.offset),
+    ]:
+        names.append(name), fmts.append(fmt), offs.append(off)
+    return np.dtype({"names": names, "formats": fmts, "offsets": offs, "itemsize": ctypes.sizeof(BatchSolveItem)})
+
+
+class BatchPlan:
+    """A fixed set of sequences solved together round after round (one time step each per round).
+
+    The item array is built once; each round only the value, right-hand-side, start and output
+    pointers change, written through a vectorised numpy view, so the host cost per round stays
+    small next to the launch.  Output vectors alternate between two buffers per sequence, so
+    the previous round's solution can serve as this round's x0."""
+
+    def __init__(self, seqs, row_ptrs, col_idxs, tol=1e-8, stream=None):
+        import numpy as np
+        import torch
+        self.lib = load()
+        self.seqs = list(seqs)
+        m = len(self.seqs)
+        self.items = (BatchSolveItem * max(m, 1))()
+        self.view = np.frombuffer(self.items, dtype=_item_dtype(), count=m)
+        self.upd = (BatchUpdateItem * max(m, 1))()
+        for i, sq in enumerate(self.seqs):
+            self.upd[i].seq = sq.handle
+        self.view["seq"] = [sq.handle.value for sq in self.seqs]
+        self.view["n"] = [sq.n for sq in self.seqs]
+        self.view["row_ptr"] = [_ptr(r, torch.int32, sq.n + 1, "row_ptr") for r, sq in zip(row_ptrs, self.seqs)]
+        self.view["col_idx"] = [c.data_ptr() for c in col_idxs]
+        self.view["tol"] = tol
+        self.out = [[torch.empty(sq.n, dtype=torch.float64, device=sq.device) for _ in range(2)] for sq in self.seqs]
+        self.round = 0
+        self.stream = stream
+        self.device = self.seqs[0].device if self.seqs else None
+
+    def solve(self, vals, bs, x0s, same_pattern):
+        """vals, bs, x0s: per-sequence device tensors (x0 entries may be None). Returns the outputs
+        (list of tensors); per-item status and stats are in self.view."""
+        import numpy as np
+        import torch
+        m = len(self.seqs)
+        outs = [o[self.round & 1] for o in self.out]
+        self.round += 1
+        self.view["val"] = [v.data_ptr() for v in vals]
+        self.view["nnz"] = [v.numel() for v in vals]
+        self.view["b"] = [b.data_ptr() for b in bs]
+        self.view["x0"] = [0 if x is None else x.data_ptr() for x in x0s]
+        self.view["x"] = [o.data_ptr() for o in outs]
+        self.view["flags"] = SAME_PATTERN if same_pattern else 0
+        with torch.cuda.device(self.device):
+            _check(self.lib.rsolve_solve_batch(self.items, m, _stream_handle(self.stream)))
+        bad = np.flatnonzero((self.view["status"] != OK) & (self.view["status"] != NOT_CONVERGED))
+        if bad.size:
+            i = int(bad[0])
+            raise RsolveError(int(self.view["status"][i]), f"batch item {i} failed")
+        return outs
+
+    def update(self):
+        import torch
+        with torch.cuda.device(self.device):
+            _check(self.lib.rsolve_update_recycle_batch(self.upd, len(self.seqs), _stream_handle(self.stream)))
+        for i in range(len(self.seqs)):
+            _check(self.upd[i].status)
 
 
 def update_batch(seqs, xs=None, stream=None, check=True):

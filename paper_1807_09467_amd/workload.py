@@ -458,6 +458,20 @@ class GpuAssembler:
         self.E = E
         self.ev = torch.empty(E * t.nl * t.nl, dtype=torch.float64, device=self.dev)
 
+    def variant(self, prob: Problem) -> "GpuAssembler":
+        """An assembler for another Problem on the same mesh and degree (other eps, dt or velocity):
+        shares every pattern-level device array and the element-value scratch (so its systems must
+        be assembled on the same stream as this one's)."""
+        import copy
+        import torch
+        if (prob.p, prob.N) != (self.asm.prob.p, self.asm.prob.N):
+            raise ValueError("a variant must keep the degree and the mesh")
+        v = copy.copy(self)
+        v.asm = Assembler(prob, self.asm.pat)
+        v.asm._mass_vals = self.asm._mass_vals
+        v.static_e = torch.from_numpy(np.ascontiguousarray(v.asm.static_e, dtype=np.float64)).to(self.dev)
+        return v
+
     def system(self, u_prev, vals_out=None, b_out=None, stream=None):
         """Fill vals_out (nnz) and b_out (n) with A(u_prev), b(u_prev); u_prev is a device tensor."""
         import torch

@@ -6,9 +6,10 @@ import glob
 import os
 import re
 
+import numpy as np
 import pytest
 
-from paper_1807_09467_amd import rsolve
+from paper_1807_09467_amd import rsolve, serve
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
@@ -50,12 +51,13 @@ def test_struct_layouts():
 C_LAYOUT_PROBE = r"""
 #include <stddef.h>
 #include <stdio.h>
-#include "rsolve.h"
+#include "rsolve_server.h"
 int main(void) {
-    printf("%zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(rsolve_config), sizeof(rsolve_csr), sizeof(rsolve_stats),
-           sizeof(rsolve_batch_solve_item), offsetof(rsolve_batch_solve_item, status),
+    printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(rsolve_config), sizeof(rsolve_csr),
+           sizeof(rsolve_stats), sizeof(rsolve_batch_solve_item), offsetof(rsolve_batch_solve_item, status),
            offsetof(rsolve_batch_solve_item, stats), sizeof(rsolve_batch_update_item),
-           sizeof(rsolve_prof_entry));
+           sizeof(rsolve_prof_entry), sizeof(rsolve_server_config), sizeof(rsolve_completion),
+           sizeof(rsolve_server_info));
     return 0;
 }
 """
@@ -75,8 +77,41 @@ def test_struct_layouts_match_the_c_compiler(tmp_path):
     want = [ctypes.sizeof(rsolve.Config), ctypes.sizeof(rsolve.CSR), ctypes.sizeof(rsolve.Stats),
             ctypes.sizeof(rsolve.BatchSolveItem), rsolve.BatchSolveItem.status.offset,
             rsolve.BatchSolveItem.stats.offset, ctypes.sizeof(rsolve.BatchUpdateItem),
-            ctypes.sizeof(rsolve.ProfEntry)]
+            ctypes.sizeof(rsolve.ProfEntry), ctypes.sizeof(serve.ServerConfig), ctypes.sizeof(serve.Completion),
+            ctypes.sizeof(serve.ServerInfo)]
     assert got == want
+
+
+def test_server_calls_reject_bad_arguments(lib):
+    serve._lib()
+    h = ctypes.c_void_p()
+    assert lib.rsolve_server_create(None, ctypes.byref(h)) == rsolve.E_INVALID
+    cfg = serve.ServerConfig(None, 1 << 20, 2, 64, 16, 1)          # no pool
+    assert lib.rsolve_server_create(ctypes.byref(cfg), ctypes.byref(h)) == rsolve.E_INVALID
+    cfg = serve.ServerConfig(0x1001, 1 << 20, 2, 64, 16, 1)        # misaligned pool
+    assert lib.rsolve_server_create(ctypes.byref(cfg), ctypes.byref(h)) == rsolve.E_INVALID
+    cfg = serve.ServerConfig(0x100000, 1 << 20, 0, 64, 16, 1)      # no large worker
+    assert lib.rsolve_server_create(ctypes.byref(cfg), ctypes.byref(h)) == rsolve.E_INVALID
+    cfg = serve.ServerConfig(0x100000, 1 << 20, 2, 257, 16, 1)     # batch above the launch limit
+    assert lib.rsolve_server_create(ctypes.byref(cfg), ctypes.byref(h)) == rsolve.E_INVALID
+    assert not h.value
+    cnt = ctypes.c_int32()
+    assert lib.rsolve_server_poll(None, None, 0, ctypes.byref(cnt), 0) == rsolve.E_INVALID
+    assert lib.rsolve_server_close(None, 1) == rsolve.E_INVALID
+    assert lib.rsolve_server_destroy(None) == rsolve.E_INVALID
+
+
+def test_serving_specs_are_seeded_and_in_range():
+    a = serve.serving_specs(64, seed=3)
+    b = serve.serving_specs(64, seed=3)
+    assert a == b and serve.serving_specs(64, seed=4) != a
+    arr = [s.arrival_s for s in a]
+    assert all(x < y for x, y in zip(arr, arr[1:]))
+    assert {s.p for s in a} <= {1, 2, 3} and all(64 <= s.N <= 384 and s.N % 32 == 0 for s in a)
+    assert all(1e-4 <= s.eps <= 1e-1 and 10 <= s.steps <= 60 for s in a)
+    # mean inter-arrival near 1 / rate
+    gaps = np.diff([0.0] + [s.arrival_s for s in serve.serving_specs(4000, rate=200.0, seed=1)])
+    assert abs(gaps.mean() - 5e-3) < 5e-4
 
 
 def test_batch_calls_reject_bad_arrays(lib):
@@ -143,6 +178,6 @@ def test_null_handles_rejected(lib):
 
 
 def test_status_strings(lib):
-    for code in (0, 1, -1, -2, -3, -4, -5):
+    for code in (0, 1, -1, -2, -3, -4, -5, -6):
         assert lib.rsolve_status_string(code)
     assert lib.rsolve_status_string(12345) == b"unknown status"

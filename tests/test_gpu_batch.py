@@ -228,7 +228,6 @@ def test_batch_update_subspace_against_lapack(gpu_ctx, n, c, k):
     cosines = np.linalg.svd(Uk.T @ Wn, compute_uv=False)
     gap = (s_ref[keff - 1] - s_ref[keff]) / s_ref[0] if keff < c else 1.0
     assert 1.0 - cosines.min() <= max(1e-24 / gap ** 2, 1e-14) * 100
-    del torch
     seq.close()
 
 
@@ -247,3 +246,28 @@ def test_batch_update_rank_deficient_ring(gpu_ctx):
     Wn = rec["W"].cpu().numpy().T
     assert np.linalg.svd(B.T @ Wn, compute_uv=False).min() >= 1 - 1e-12
     seq.close()
+
+
+def test_batch_plan_matches_item_by_item_calls(gpu_ctx):
+    """BatchPlan (vectorised pointer updates over a prebuilt item array) gives bitwise the same
+    answers and statistics as solve_batch with per-call job dicts."""
+    import torch
+    from paper_1807_09467_amd import rsolve
+    kw = dict(restart_m=30, recycle_k=5, snapshots_s=10)
+    a = [Stream(gpu_ctx, WL.C1, 4, seed, 1e-10, **kw) for seed in (0, 1, 2)]
+    b = [Stream(gpu_ctx, WL.C1, 4, seed, 1e-10, **kw) for seed in (0, 1, 2)]
+    plan = rsolve.BatchPlan([s.seq for s in b], [s.rp for s in b], [s.ci for s in b], tol=1e-10)
+    x_prev = [s.x_prev for s in b]
+    for i in range(4):
+        ref = rsolve.solve_batch([s.job(i) for s in a])
+        rsolve.update_batch([s.seq for s in a])
+        outs = plan.solve([s.gpu_vals[i][0] for s in b], [s.gpu_vals[i][1] for s in b], x_prev, same_pattern=i > 0)
+        plan.update()
+        for q, s in enumerate(a):
+            assert torch.equal(outs[q], ref[q][0])
+            assert int(plan.view["iterations"][q]) == ref[q][1]["iterations"]
+            assert int(plan.view["status"][q]) == 0
+            s.x_prev = ref[q][0]
+        x_prev = outs
+    for s in a + b:
+        s.seq.close()
