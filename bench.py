@@ -425,6 +425,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--inner-tol", type=float, default=None,
                     help="override the FP32 cycle reduction factor of the mixed-precision workload")
+    ap.add_argument("--no-profile", action="store_true",
+                    help="run the timed solves without per-kernel event timing (roofline then null)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a 1 GiB device-to-device copy (reference for memory-traffic counters)")
     args = ap.parse_args()
@@ -459,7 +461,7 @@ def main():
     nsteps = args.warmup + args.steps
     asm, gasm, u0, systems = generate(prob, nsteps, dev)
 
-    main_run = run_solver(gasm, u0, systems, args.warmup, args.steps, tol, cfg, dev, profile=True,
+    main_run = run_solver(gasm, u0, systems, args.warmup, args.steps, tol, cfg, dev, profile=not args.no_profile,
                           label="recycled")
     main_sum = summarize(main_run, args.steps)
     plain_sum = None

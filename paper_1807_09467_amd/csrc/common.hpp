@@ -13,6 +13,7 @@ constexpr int SMAX = 64;         // largest snapshot ring
 constexpr int BLOCK = 256;       // threads per block of the streaming kernels
 constexpr int NBLK_MAX = 2048;   // largest grid of the split-n reductions
 constexpr int TSQR_PANEL = 256;  // rows per Householder panel
+constexpr int64_t GRAM_PARTIAL = 256LL * KMAX * KMAX;  // doubles of a Gram partial buffer
 
 // Control block living in the sequence workspace.  Kernels of one Arnoldi
 // cycle read `done` and return at once when it is set, so the host can enqueue

@@ -118,9 +118,13 @@ int cols_grid(int64_t npad, int cus, int nw, int waves_per_cu, int ncol) {
     return (int)std::max<int64_t>(1, std::min<int64_t>({tiles, (int64_t)cus * per_cu, (int64_t)NBLK_MAX}));
 }
 
+// Most blocks of the Gram kernel (two per compute unit of the device); the launcher also
+// keeps one slab per block at least and the partials within their buffer.
 int pick_gblk(int64_t n) {
-    int64_t b = (n + 4095) / 4096;
-    return (int)std::max<int64_t>(1, std::min<int64_t>(b, 256));
+    (void)n;
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    return 2 * std::max(cus, 1);
 }
 
 }  // namespace
@@ -202,7 +206,7 @@ size_t layout(rsolve_seq* s, const rsolve_config& c, int64_t n, int64_t nnz_max,
     double* vals = (jac && !ir) ? cv.take<double>((size_t)nnz_max) : nullptr;
     float* vals32 = ir ? cv.take<float>((size_t)nnz_max) : nullptr;
     double* partial = cv.take<double>((size_t)NBLK_MAX * (MMAX + 2 * KMAX + 1));
-    double* gpart = cv.take<double>((size_t)256 * KMAX * KMAX);
+    double* gpart = cv.take<double>((size_t)GRAM_PARTIAL);
     int64_t tsq_rows = 0, tsq_ld = 0;
     double *t0 = nullptr, *t1 = nullptr;
     if (k && sn) {
@@ -573,8 +577,8 @@ int rsolve_solve(rsolve_seq* s, const rsolve_csr* A, const double* b, const doub
     uint32_t flags = 0;
     if (k > 0) {
         launch_spmm(s->lpr, n, A->row_ptr, A->col_idx, A->val, s->W, ld, k, s->Z, stm);
-        launch_gram_tn(ld, s->W, ld, k, s->Z, ld, k, s->gpart, s->gblk, stm);
-        launch_gram_reduce(s->gpart, s->gblk, k * k, ctl_red(s->ctl), stm);
+        const int gb = launch_gram_tn(ld, s->W, ld, k, s->Z, ld, k, s->gpart, s->gblk, stm);
+        launch_gram_reduce(s->gpart, gb, k * k, ctl_red(s->ctl), stm);
         launch_small_lu(ctl_red(s->ctl), k, s->ctl, stm);
         if (ir) launch_to_f32(k * ld, s->Z, s->Z32, stm);
     }
@@ -756,8 +760,8 @@ int rsolve_update_recycle(rsolve_seq* s, const double* x) {
     const int keff = s->hctl->k_eff;
     if (keff > 0) {
         launch_form_w(n, ld, s->X, ld, cc, keff, s->ctl, s->W, ld, stm);
-        launch_gram_tn(ld, s->W, ld, keff, s->W, ld, keff, s->gpart, s->gblk, stm);
-        launch_gram_reduce(s->gpart, s->gblk, keff * keff, ctl_red(s->ctl), stm);
+        const int gb = launch_gram_tn(ld, s->W, ld, keff, s->W, ld, keff, s->gpart, s->gblk, stm);
+        launch_gram_reduce(s->gpart, gb, keff * keff, ctl_red(s->ctl), stm);
         launch_cholesky(keff, s->ctl, stm);
         launch_trsm_rows(ld, s->W, ld, keff, s->ctl, stm);
         if (s->W32) launch_to_f32(keff * ld, s->W, s->W32, stm);
@@ -1025,7 +1029,7 @@ struct KWs {
 size_t kws_layout(int64_t n, int cols, char* base, KWs* o) {
     Carver cv{base};
     Ctl* ctl = cv.take<Ctl>(1);
-    double* gp = cv.take<double>((size_t)256 * KMAX * KMAX);
+    double* gp = cv.take<double>((size_t)GRAM_PARTIAL);
     const int64_t rows = ((n + TSQR_PANEL - 1) / TSQR_PANEL) * std::max(cols, 1);
     const int64_t tld = pad64(rows);
     double* t0 = cv.take<double>((size_t)tld * std::max(cols, 1));
@@ -1051,8 +1055,7 @@ int rsolve_gram_tn(int64_t n, const double* A, int64_t lda, int32_t p, const dou
     KWs w;
     kws_layout(n, cols, static_cast<char*>(workspace), &w);
     hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
-    const int gblk = pick_gblk(n);
-    launch_gram_tn(n, A, lda, p, B, ldb, q, w.gpart, gblk, st);
+    const int gblk = launch_gram_tn(n, A, lda, p, B, ldb, q, w.gpart, pick_gblk(n), st);
     launch_gram_reduce(w.gpart, gblk, p * q, ctl_red(w.ctl), st);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipMemcpyAsync(C_host, ctl_red(w.ctl), sizeof(double) * p * q, hipMemcpyDeviceToHost, st));
@@ -1098,8 +1101,7 @@ int rsolve_snapshot_svd(int64_t n, const double* X, int64_t ldx, int32_t c, int3
     const int keff = head.k_eff;
     if (keff > 0) {
         launch_form_w(n, n, X, ldx, c, keff, w.ctl, W_out, ldw, st);
-        const int gblk = pick_gblk(n);
-        launch_gram_tn(n, W_out, ldw, keff, W_out, ldw, keff, w.gpart, gblk, st);
+        const int gblk = launch_gram_tn(n, W_out, ldw, keff, W_out, ldw, keff, w.gpart, pick_gblk(n), st);
         launch_gram_reduce(w.gpart, gblk, keff * keff, ctl_red(w.ctl), st);
         launch_cholesky(keff, w.ctl, st);
         launch_trsm_rows(n, W_out, ldw, keff, w.ctl, st);

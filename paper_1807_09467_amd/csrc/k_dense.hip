@@ -8,6 +8,8 @@
 #include "kernels.hpp"
 #include "svd_dev.hpp"
 
+#include <algorithm>
+
 namespace rs {
 
 namespace {
@@ -15,16 +17,27 @@ namespace {
 typedef double d4 __attribute__((ext_vector_type(4)));
 
 // ---------------------------------------------------------------------------
-// C = A^T B on MFMA.  Each wavefront consumes 4 rows per MFMA: the A operand is
-// the 16 x 4 block (A^T)[i][row] (lane = i + 16 * row), the B operand the 4 x 16
-// block B[row][j] (lane = j + 16 * row).  The 16 x 16 result block holds
-// C[lane / 16 + 4 r][lane % 16] in element r of each lane.
+// C = A^T B on MFMA for tall A (n x p) and B (n x q), p, q <= 64.  A block walks slabs of R
+// rows: both slabs are staged in LDS with coalesced column loads (consecutive threads read
+// consecutive rows of one column), then each wavefront feeds R / 4 of the slab's rows to
+// v_mfma_f64_16x16x4f64, 4 rows per instruction: the A operand is the 16 x 4 block
+// (A^T)[i][row] (lane = i + 16 * row), the B operand the 4 x 16 block B[row][j]; the 16 x 16
+// result block holds C[lane / 16 + 4 r][lane % 16] in element r of each lane.  The LDS row
+// stride R + 4 puts the 16 columns x 4 rows of an operand read in distinct banks.
+// partial[e * nblk + b] = block b's share of entry e = i + p j.
 // ---------------------------------------------------------------------------
-template <int TP, int TQ>
+template <int TP, int TQ, int R>
 __global__ __launch_bounds__(BLOCK) void k_gram_tn(int64_t n, const double* __restrict__ A, int64_t lda, int p,
                                                    const double* __restrict__ B, int64_t ldb, int q,
                                                    double* __restrict__ partial, int nblk) {
-    __shared__ double acc_s[TP * 16 * TQ * 16];
+    constexpr int RS = R + 4;
+    constexpr int RW = R / (BLOCK / WAVE);   // rows per wavefront and slab
+    static_assert(RW % 4 == 0, "whole MFMA steps per wavefront");
+    constexpr int NSTAGE = (TP + TQ) * 16 * RS, NACC = TP * 16 * TQ * 16;
+    __shared__ double smem[NSTAGE > NACC ? NSTAGE : NACC];
+    double* As = smem;
+    double* Bs = smem + TP * 16 * RS;
+    double* acc_s = smem;   // reused once the last slab is done (every slab ends with a barrier)
     const int lane = threadIdx.x & (WAVE - 1);
     const int wv = threadIdx.x / WAVE;
     const int li = lane & 15, lk = lane >> 4;
@@ -33,28 +46,39 @@ __global__ __launch_bounds__(BLOCK) void k_gram_tn(int64_t n, const double* __re
     for (int a = 0; a < TP; ++a)
 #pragma unroll
         for (int b = 0; b < TQ; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
-    const int64_t ngroups = (n + 3) / 4;
-    for (int64_t g4 = (int64_t)blockIdx.x * 4 + wv; g4 < ngroups; g4 += (int64_t)nblk * 4) {
-        const int64_t row = g4 * 4 + lk;
-        const bool rok = row < n;
-        double av[TP], bv[TQ];
+    const int64_t nslab = (n + R - 1) / R;
+    for (int64_t sl = blockIdx.x; sl < nslab; sl += nblk) {
+        const int64_t r0 = sl * R;
 #pragma unroll
-        for (int a = 0; a < TP; ++a) {
-            const int col = a * 16 + li;
-            av[a] = (rok && col < p) ? A[(int64_t)col * lda + row] : 0.0;
+        for (int t0 = 0; t0 < TP * 16 * R; t0 += BLOCK) {
+            const int t = t0 + threadIdx.x, c = t / R, r = t % R;
+            const int64_t row = r0 + r;
+            As[c * RS + r] = (c < p && row < n) ? A[(int64_t)c * lda + row] : 0.0;
         }
 #pragma unroll
-        for (int b = 0; b < TQ; ++b) {
-            const int col = b * 16 + li;
-            bv[b] = (rok && col < q) ? B[(int64_t)col * ldb + row] : 0.0;
+        for (int t0 = 0; t0 < TQ * 16 * R; t0 += BLOCK) {
+            const int t = t0 + threadIdx.x, c = t / R, r = t % R;
+            const int64_t row = r0 + r;
+            Bs[c * RS + r] = (c < q && row < n) ? B[(int64_t)c * ldb + row] : 0.0;
         }
+        __syncthreads();
 #pragma unroll
-        for (int a = 0; a < TP; ++a)
+        for (int g = 0; g < RW / 4; ++g) {
+            const int rr = wv * RW + g * 4 + lk;
+            double av[TP], bv[TQ];
 #pragma unroll
-            for (int b = 0; b < TQ; ++b)
-                acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+            for (int a = 0; a < TP; ++a) av[a] = As[(a * 16 + li) * RS + rr];
+#pragma unroll
+            for (int b = 0; b < TQ; ++b) bv[b] = Bs[(b * 16 + li) * RS + rr];
+#pragma unroll
+            for (int a = 0; a < TP; ++a)
+#pragma unroll
+                for (int b = 0; b < TQ; ++b)
+                    acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+        }
+        __syncthreads();
     }
-    // fixed-order combination of the 4 wavefronts
+    // fixed-order combination of the wavefronts
     constexpr int LD = TP * 16;
     for (int w = 0; w < BLOCK / WAVE; ++w) {
         if (wv == w) {
@@ -76,16 +100,33 @@ __global__ __launch_bounds__(BLOCK) void k_gram_tn(int64_t n, const double* __re
     const int pq = p * q;
     for (int e = threadIdx.x; e < pq; e += BLOCK) {
         const int i = e % p, j = e / p;
-        partial[(int64_t)blockIdx.x * pq + e] = acc_s[i + LD * j];
+        partial[(int64_t)e * nblk + blockIdx.x] = acc_s[i + LD * j];
     }
 }
 
-__global__ __launch_bounds__(BLOCK) void k_gram_reduce(const double* __restrict__ partial, int nblk, int pq,
-                                                       double* __restrict__ dst) {
-    for (int e = threadIdx.x; e < pq; e += BLOCK) {
-        double s = 0.0;
-        for (int b = 0; b < nblk; ++b) s += partial[(int64_t)b * pq + e];
-        dst[e] = s;
+// dst[e] = sum over b of partial[e * nblk + b], each entry by a group of G lanes (power of two
+// up to the wavefront) in a fixed order: lane-strided partial sums, then a butterfly.
+__global__ __launch_bounds__(1024) void k_gram_reduce(const double* __restrict__ partial, int nblk, int pq, int G,
+                                                      double* __restrict__ dst) {
+    const int sub = threadIdx.x & (G - 1);
+    const int per_pass = 1024 / G;
+    for (int e0 = 0; e0 < pq; e0 += per_pass) {
+        const int e = e0 + threadIdx.x / G;
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        if (e < pq) {
+            const double* src = partial + (int64_t)e * nblk;
+            int b = sub;
+            for (; b + 3 * G < nblk; b += 4 * G) {
+                a0 += src[b];
+                a1 += src[b + G];
+                a2 += src[b + 2 * G];
+                a3 += src[b + 3 * G];
+            }
+            for (; b < nblk; b += G) a0 += src[b];
+        }
+        double s = (a0 + a1) + (a2 + a3);
+        for (int o = G / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, WAVE);
+        if (e < pq && sub == 0) dst[e] = s;
     }
 }
 
@@ -363,18 +404,25 @@ __global__ __launch_bounds__(BLOCK) void k_trsm_rows(int64_t npad, double* __res
 
 }  // namespace
 
-void launch_gram_tn(int64_t n, const double* A, int64_t lda, int p, const double* B, int64_t ldb, int q,
-                    double* partial, int nblk, hipStream_t st) {
+int launch_gram_tn(int64_t n, const double* A, int64_t lda, int p, const double* B, int64_t ldb, int q,
+                   double* partial, int max_blocks, hipStream_t st) {
     const int tp = (p + 15) / 16, tq = (q + 15) / 16;
-#define RS_G(TPv, TQv) k_gram_tn<TPv, TQv><<<nblk, BLOCK, 0, st>>>(n, A, lda, p, B, ldb, q, partial, nblk)
-    if (tp <= 1 && tq <= 1) RS_G(1, 1);
-    else if (tp <= 2 && tq <= 2) RS_G(2, 2);
-    else if (tp <= 4 && tq <= 4) RS_G(4, 4);
+    const int R = (tp <= 1 && tq <= 1) ? 128 : ((tp <= 2 && tq <= 2) ? 128 : 64);
+    const int64_t nslab = (n + R - 1) / R;
+    const int nblk = (int)std::max<int64_t>(
+        1, std::min<int64_t>({nslab, (int64_t)max_blocks, GRAM_PARTIAL / ((int64_t)p * q)}));
+#define RS_G(TPv, TQv, Rv) k_gram_tn<TPv, TQv, Rv><<<nblk, BLOCK, 0, st>>>(n, A, lda, p, B, ldb, q, partial, nblk)
+    if (tp <= 1 && tq <= 1) RS_G(1, 1, 128);
+    else if (tp <= 2 && tq <= 2) RS_G(2, 2, 128);
+    else RS_G(4, 4, 64);
 #undef RS_G
+    return nblk;
 }
 
 void launch_gram_reduce(const double* partial, int nblk, int pq, double* dst, hipStream_t st) {
-    k_gram_reduce<<<1, BLOCK, 0, st>>>(partial, nblk, pq, dst);
+    int G = 1;
+    while (G < WAVE && G * 2 * pq <= 1024 && G * 2 <= nblk) G *= 2;
+    k_gram_reduce<<<1, 1024, 0, st>>>(partial, nblk, pq, G, dst);
 }
 
 void launch_small_lu(const double* src, int k, Ctl* ctl, hipStream_t st) { k_small_lu<<<1, WAVE, 0, st>>>(src, k, ctl); }

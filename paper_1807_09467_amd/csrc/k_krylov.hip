@@ -42,6 +42,53 @@ __device__ __forceinline__ double lane_strided_sum(const double* __restrict__ p,
     return (a0 + a1) + (a2 + a3);
 }
 
+constexpr int RED_T = 1024;   // threads of the one-block reductions
+
+// sums[c] = sum over b of partial[c * nblk + b] for c < ncol, by every thread of a RED_T block:
+// each column gets a group of G threads (the largest power of two with G ncol <= RED_T, at most
+// nblk rounded up), each thread sums a lane-strided share with four accumulators, the group
+// combines by butterfly within a wavefront and, for groups wider than one, over LDS in wave
+// order.  All loads of a thread are independent, so the block keeps RED_T of them in flight.
+// red: LDS scratch of RED_T / WAVE doubles.  Fixed order for given (nblk, ncol).  Ends with a
+// barrier.
+__device__ void reduce_columns(const double* __restrict__ partial, int nblk, int ncol, double* sums, double* red) {
+    int G = 1;
+    while (G * 2 * ncol <= RED_T && G < nblk) G *= 2;
+    const int gw = G < WAVE ? G : WAVE;
+    const int sub = threadIdx.x & (G - 1);
+    const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
+    for (int c0 = 0; c0 < ncol; c0 += RED_T / G) {
+        const int c = c0 + threadIdx.x / G;
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        if (c < ncol) {
+            const double* src = partial + (int64_t)c * nblk;
+            int b = sub;
+            for (; b + 3 * G < nblk; b += 4 * G) {
+                a0 += src[b];
+                a1 += src[b + G];
+                a2 += src[b + 2 * G];
+                a3 += src[b + 3 * G];
+            }
+            for (; b < nblk; b += G) a0 += src[b];
+        }
+        double v = (a0 + a1) + (a2 + a3);
+        for (int o = gw / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
+        if (G > WAVE) {
+            if (lane == 0) red[wv] = v;
+            __syncthreads();
+            if (sub == 0 && c < ncol) {
+                double t = 0.0;
+                for (int q = 0; q < G / WAVE; ++q) t += red[wv + q];
+                sums[c] = t;
+            }
+            __syncthreads();
+        } else if (sub == 0 && c < ncol) {
+            sums[c] = v;
+        }
+    }
+    __syncthreads();
+}
+
 // Solve E x = b (LU with row permutation in ctl) with one wavefront: lane i holds row i.
 __device__ void wave_lu_solve(const Ctl* ctl, int k, const double* b, double* x, double* Es) {
     const int lane = threadIdx.x & (WAVE - 1);
@@ -59,23 +106,19 @@ __device__ void wave_lu_solve(const Ctl* ctl, int k, const double* b, double* x,
     if (lane < k) x[lane] = v;
 }
 
-__global__ __launch_bounds__(BLOCK) void k_reduce(const double* __restrict__ partial, int nblk, int ncol,
+__global__ __launch_bounds__(RED_T) void k_reduce(const double* __restrict__ partial, int nblk, int ncol,
                                                   double* __restrict__ dst, Ctl* __restrict__ ctl, int nv, int nw,
                                                   int lu_solve, int check_done) {
     if (check_done && ctl->done) return;
     __shared__ double sums[MMAX + KMAX];
     __shared__ double Es[KMAX * KMAX];
-    const int lane = threadIdx.x & (WAVE - 1);
+    __shared__ double red[RED_T / WAVE];
     const int wv = threadIdx.x / WAVE;
-    for (int c = wv; c < ncol; c += BLOCK / WAVE) {
-        const double s = wave_sum(lane_strided_sum(partial + (int64_t)c * nblk, nblk));
-        if (lane == 0) sums[c] = s;
-    }
     if (lu_solve) {
-        for (int t = threadIdx.x; t < nw * nw; t += BLOCK) Es[t] = ctl->E[t];
+        for (int t = threadIdx.x; t < nw * nw; t += RED_T) Es[t] = ctl->E[t];
     }
-    __syncthreads();
-    for (int c = threadIdx.x; c < ncol; c += BLOCK) dst[c] = sums[c];
+    reduce_columns(partial, nblk, ncol, sums, red);
+    for (int c = threadIdx.x; c < ncol; c += RED_T) dst[c] = sums[c];
     if (lu_solve && wv == 0) wave_lu_solve(ctl, nw, sums + nv, ctl->cw, Es);
 }
 
@@ -83,17 +126,11 @@ __global__ __launch_bounds__(BLOCK) void k_reduce(const double* __restrict__ par
 // sums = [V^T w0 | W^T w0 | Z^T v_j]; F[j, :] = v_j^T Z; cw = E^{-1} W^T w0;
 // h1 = V^T (w0 - Z cw) = V^T w0 - F cw.  Run by one block of any size (>= 1 wavefront).
 __device__ void pass1_coefficients(const double* __restrict__ partial, int nblk, int nv, int k, Ctl* __restrict__ ctl,
-                                   double* sums, double* Es, double* cws) {
-    const int lane = threadIdx.x & (WAVE - 1);
+                                   double* sums, double* Es, double* cws, double* red) {
     const int wv = threadIdx.x / WAVE;
-    const int nwv = blockDim.x / WAVE;
     const int ncol = nv + 2 * k;
-    for (int c = wv; c < ncol; c += nwv) {
-        const double s = wave_sum(lane_strided_sum(partial + (int64_t)c * nblk, nblk));
-        if (lane == 0) sums[c] = s;
-    }
     for (int t = threadIdx.x; t < k * k; t += blockDim.x) Es[t] = ctl->E[t];
-    __syncthreads();
+    reduce_columns(partial, nblk, ncol, sums, red);
     if (k == 0) {
         for (int i = threadIdx.x; i < nv; i += blockDim.x) ctl->h1[i] = sums[i];
         return;
@@ -119,13 +156,14 @@ __device__ void pass1_coefficients(const double* __restrict__ partial, int nblk,
     }
 }
 
-__global__ __launch_bounds__(BLOCK) void k_reduce_pass1(const double* __restrict__ partial, int nblk, int nv, int k,
+__global__ __launch_bounds__(RED_T) void k_reduce_pass1(const double* __restrict__ partial, int nblk, int nv, int k,
                                                         Ctl* __restrict__ ctl) {
     if (ctl->done) return;
     __shared__ double sums[MMAX + 2 * KMAX];
     __shared__ double Es[KMAX * KMAX];
     __shared__ double cws[KMAX];
-    pass1_coefficients(partial, nblk, nv, k, ctl, sums, Es, cws);
+    __shared__ double red[RED_T / WAVE];
+    pass1_coefficients(partial, nblk, nv, k, ctl, sums, Es, cws, red);
 }
 
 // Sweep of dot products: wavefront w of the block owns columns [w CPW, w CPW + CPW) of the
@@ -200,11 +238,9 @@ __device__ __forceinline__ double row_update(const T* __restrict__ B, int64_t ld
 
 // Column j of the Hessenberg matrix, Givens rotations, residual estimate, stop test.  Run by
 // the first wavefront of one block; hcol is LDS scratch of MMAX + 1 doubles.
-__device__ void givens_column(const double* __restrict__ partial, int nblk, int j, Ctl* __restrict__ ctl,
-                              double* hcol) {
+__device__ void givens_column(double s, int j, Ctl* __restrict__ ctl, double* hcol) {
     const int lane = threadIdx.x;
     if (lane >= WAVE) return;
-    const double s = wave_sum(lane_strided_sum(partial, nblk));
     const double hn = sqrt(s);
     double cn = 0.0;
     for (int i = lane; i <= j; i += WAVE) {
@@ -249,11 +285,14 @@ __device__ void givens_column(const double* __restrict__ partial, int nblk, int 
     ctl->inv_h = (hn > 0.0) ? 1.0 / hn : 0.0;
 }
 
-__global__ __launch_bounds__(WAVE) void k_givens(const double* __restrict__ partial, int nblk, int j,
-                                                 Ctl* __restrict__ ctl) {
+__global__ __launch_bounds__(RED_T) void k_givens(const double* __restrict__ partial, int nblk, int j,
+                                                  Ctl* __restrict__ ctl) {
     if (ctl->done) return;
     __shared__ double hcol[MMAX + 1];
-    givens_column(partial, nblk, j, ctl, hcol);
+    __shared__ double sums[1];
+    __shared__ double red[RED_T / WAVE];
+    reduce_columns(partial, nblk, 1, sums, red);
+    givens_column(sums[0], j, ctl, hcol);
 }
 
 // w -= V coefV + Z coefZ, then partial dots V^T w with the updated w.  Wavefront w owns V
@@ -515,7 +554,7 @@ void launch_dots(int64_t npad, int64_t ld, const T* const* bases, const T* const
                               last ? ev1 : nullptr, 0, npad, ld, g, partial + (int64_t)a * nblk, nblk,
                               static_cast<const Ctl*>(ctl));
     }
-    if (pass1_nv > 0) k_reduce_pass1<<<1, BLOCK, 0, st>>>(partial, nblk, pass1_nv, pass1_k, ctl);
+    if (pass1_nv > 0) k_reduce_pass1<<<1, RED_T, 0, st>>>(partial, nblk, pass1_nv, pass1_k, ctl);
 }
 template void launch_dots<double>(int64_t, int64_t, const double* const*, const double* const*, const int*, int,
                                   double*, int, Ctl*, hipStream_t, int, int, hipEvent_t, hipEvent_t);
@@ -524,7 +563,7 @@ template void launch_dots<float>(int64_t, int64_t, const float* const*, const fl
 
 void launch_reduce(const double* partial, int nblk, int ncol, double* dst, Ctl* ctl, int nv, int nw, bool lu_solve,
                    bool check_done, hipStream_t st) {
-    k_reduce<<<1, BLOCK, 0, st>>>(partial, nblk, ncol, dst, ctl, nv, nw, lu_solve ? 1 : 0, check_done ? 1 : 0);
+    k_reduce<<<1, RED_T, 0, st>>>(partial, nblk, ncol, dst, ctl, nv, nw, lu_solve ? 1 : 0, check_done ? 1 : 0);
 }
 
 
@@ -536,7 +575,7 @@ void launch_update_dots(int64_t npad, const T* V, int64_t ld, int nv, const T* Z
     const int nw = (nv + CPW - 1) / CPW;   // nv <= 128 -> at most 16 wavefronts
     hipExtLaunchKernelGGL(k_update_dots<T, CPW>, dim3(nblk), dim3(nw * WAVE), 0, st, ev0, ev1, 0, npad, V, ld, nv, Z,
                           nz, w, coefV, coefZ, partial, nblk, static_cast<const Ctl*>(ctl));
-    k_reduce<<<1, BLOCK, 0, st>>>(partial, nblk, nv, ctl->h2, ctl, 0, 0, 0, 1);
+    k_reduce<<<1, RED_T, 0, st>>>(partial, nblk, nv, ctl->h2, ctl, 0, 0, 0, 1);
 }
 template void launch_update_dots<double>(int64_t, const double*, int64_t, int, const double*, int, double*,
                                          const double*, const double*, double*, int, Ctl*, hipStream_t, hipEvent_t,
@@ -550,7 +589,7 @@ void launch_update_norm(int64_t npad, const T* V, int64_t ld, int nv, T* w, cons
                         int nblk, Ctl* ctl, hipStream_t st, int givens_j, hipEvent_t ev0, hipEvent_t ev1) {
     hipExtLaunchKernelGGL(k_update_norm<T>, dim3(nblk), dim3(BLOCK), 0, st, ev0, ev1, 0, npad, V, ld, nv, w, coef,
                           partial, nblk, static_cast<const Ctl*>(ctl));
-    if (givens_j >= 0) k_givens<<<1, WAVE, 0, st>>>(partial, nblk, givens_j, ctl);
+    if (givens_j >= 0) k_givens<<<1, RED_T, 0, st>>>(partial, nblk, givens_j, ctl);
 }
 template void launch_update_norm<double>(int64_t, const double*, int64_t, int, double*, const double*, double*, int,
                                          Ctl*, hipStream_t, int, hipEvent_t, hipEvent_t);
@@ -558,7 +597,7 @@ template void launch_update_norm<float>(int64_t, const float*, int64_t, int, flo
                                         Ctl*, hipStream_t, int, hipEvent_t, hipEvent_t);
 
 void launch_givens(const double* partial, int nblk, int j, Ctl* ctl, hipStream_t st) {
-    k_givens<<<1, WAVE, 0, st>>>(partial, nblk, j, ctl);
+    k_givens<<<1, RED_T, 0, st>>>(partial, nblk, j, ctl);
 }
 
 void launch_cycle_init(Ctl* ctl, int max_steps, double stop_abs, hipStream_t st) {

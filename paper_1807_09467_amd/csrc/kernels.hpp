@@ -82,9 +82,10 @@ void launch_norm2(int64_t n, const double* v, double* partial, int nblk, hipStre
 void launch_copy_pad(int64_t n, int64_t npad, const double* in, double* out, hipStream_t st);
 
 // ---- dense (k_dense.hip) ----
-// partial[b][p*q] = A^T B over block b's rows (MFMA f64); rows >= n read as zero
-void launch_gram_tn(int64_t n, const double* A, int64_t lda, int p, const double* B, int64_t ldb, int q,
-                    double* partial, int nblk, hipStream_t st);
+// partial[e * nblk + b] = block b's share of (A^T B)[e] (MFMA f64, e = i + p j); rows >= n read
+// as zero.  partial holds GRAM_PARTIAL doubles; returns nblk (<= max_blocks) for the reduction.
+int launch_gram_tn(int64_t n, const double* A, int64_t lda, int p, const double* B, int64_t ldb, int q,
+                   double* partial, int max_blocks, hipStream_t st);
 // dst[p*q] (column-major) = fixed-order sum over blocks
 void launch_gram_reduce(const double* partial, int nblk, int pq, double* dst, hipStream_t st);
 // LU with partial pivoting of E (k x k, column-major in src) into ctl->E/piv, ctl->cond1
