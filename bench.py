@@ -106,8 +106,13 @@ def run_solver(gasm, u0, systems, warmup, steps, tol, cfg, dev, profile=False, l
     import torch
 
     from paper_1807_09467_amd import rsolve
+    from paper_1807_09467_amd import autotune
     pat = gasm.asm.pat
     seq = rsolve.Sequence(pat.n, pat.nnz, device=dev, **cfg)
+    # SpMV shape: timed on the first system before anything else (not part of the timed region)
+    shape, _, _ = autotune.tune_sequence(seq, gasm.row_ptr, gasm.col_idx, systems[0][0], cache_path=None, reps=10)
+    log(f"{label} SpMV shape: {shape['lanes_per_row']} lanes/row, {shape['vec']} entries/lane, "
+        f"remap {shape['xcd_remap']}: {shape['us']:.1f} us (default {shape['default_us']:.1f} us)")
     x_prev = u0
     lat, its, cyc, keff, rel = [], [], [], [], []
     xs = []
@@ -138,7 +143,7 @@ def run_solver(gasm, u0, systems, warmup, steps, tol, cfg, dev, profile=False, l
     elapsed = time.perf_counter() - t_start
     prof = seq.profile_read() if profile else []
     seq.close()
-    return dict(elapsed=elapsed, lat=lat, its=its, cycles=cyc, k_eff=keff, rel=rel, prof=prof, xs=xs)
+    return dict(elapsed=elapsed, lat=lat, its=its, cycles=cyc, k_eff=keff, rel=rel, prof=prof, xs=xs, shape=shape)
 
 
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_spmv_arnoldi_f32-q3_512x512_recycled_mixed-hbm_traffic.md")
@@ -513,7 +518,9 @@ def main():
         "dtype": "f32+f64" if cfg.get("precision") == "fp32_ir" else "f64",
         "data": "synthetic",
         "config": {"workload": desc, "n": asm.pat.n, "nnz": asm.pat.nnz, "steps_generated": nsteps,
-                   "parallelism": "single GPU"},
+                   "parallelism": "single GPU",
+                   "spmv_shape": {k: (round(v, 2) if isinstance(v, float) else v)
+                                  for k, v in main_run["shape"].items()}},
         "latency_ms": main_sum["latency_ms"],
         "avg_iterations": main_sum["avg_iterations"],
         "avg_cycles": main_sum["avg_cycles"],

@@ -265,6 +265,36 @@ int rsolve_profile_enable(rsolve_seq* s, int32_t on);
  */
 int rsolve_profile_read(rsolve_seq* s, rsolve_prof_entry* out, int32_t cap, int32_t* count, int32_t reset);
 
+/* ---- SpMV shape of the Arnoldi product, and its autotuner ---- */
+
+typedef struct {
+    int32_t lanes_per_row;  /* lanes of a wavefront that share one CSR row: 2, 4, 8, 16 or 32 */
+    int32_t vec;            /* CSR entries a lane loads at once: 4 or 8 (one 16/32-byte load of
+                               indices and one of values), or 1 (four strided scalar loads) */
+    int32_t xcd_remap;      /* 1: consecutive row blocks go to the same accelerator die */
+    int32_t user_set;       /* rsolve_get_spmv_shape: 1 if set by rsolve_set_spmv_shape */
+    double  us;             /* rsolve_tune_spmv: mean time of one product, microseconds */
+} rsolve_spmv_shape;
+
+/*
+ * Time the Arnoldi product w = A D^{-1} v of this sequence (the kernel of section 3, in the
+ * sequence's precision: float32 values for FP32_IR, else float64) for every shape: lanes per row
+ * {2, 4, 8, 16, 32} x entries per lane {1, 4, 8} x block order {plain, XCD-aware}, `reps` timed
+ * launches each (HIP events) after one warm-up launch, on the sequence's own stream and buffers.
+ * Writes up to `cap` results in ascending time to `out` (host) and the number of candidates to
+ * *count; does not change the sequence's shape.  A's pattern is checked first (E_INVALID if
+ * corrupt).  Synchronous.  Errors: E_INVALID, E_DEVICE.
+ */
+int rsolve_tune_spmv(rsolve_seq* s, const rsolve_csr* A, int32_t reps, rsolve_spmv_shape* out, int32_t cap,
+                     int32_t* count);
+
+/* Use `shape` (lanes_per_row, vec, xcd_remap; the other fields are ignored) for this sequence's
+ * Arnoldi products from now on.  E_INVALID for a value outside the sets above. */
+int rsolve_set_spmv_shape(rsolve_seq* s, const rsolve_spmv_shape* shape);
+
+/* The shape in use (chosen from the mean row length unless set). */
+int rsolve_get_spmv_shape(rsolve_seq* s, rsolve_spmv_shape* shape);
+
 /* Destroy the handle.  Does not free the workspace (the caller owns it). */
 int rsolve_destroy_sequence(rsolve_seq* s);
 

@@ -80,15 +80,7 @@ int cfg_check(const rsolve_config* c) {
     return RSOLVE_OK;
 }
 
-int env_int(const char* name, int dflt) {
-    const char* v = getenv(name);
-    if (!v || !*v) return dflt;
-    return atoi(v);
-}
-
 int pick_lpr(int64_t n, int64_t nnz) {
-    const int forced = env_int("RSOLVE_LPR", 0);
-    if (forced == 2 || forced == 4 || forced == 8 || forced == 16 || forced == 32) return forced;
     // lanes per row for the 4-entries-per-lane product: about one round of loads per row
     const double avg = n > 0 ? (double)nnz / (double)n : 1.0;
     if (avg <= 8.0) return 2;
@@ -99,8 +91,6 @@ int pick_lpr(int64_t n, int64_t nnz) {
 // Grid of the row-per-thread streaming kernels (256-thread blocks): enough blocks for
 // 8 per compute unit, never more blocks than 256-row slabs.
 int pick_nblk(int64_t npad, int cus) {
-    const int forced = env_int("RSOLVE_NBLK", 0);
-    if (forced > 0) return std::min(forced, NBLK_MAX);
     const int64_t slabs = (npad + BLOCK - 1) / BLOCK;
     return (int)std::max<int64_t>(1, std::min<int64_t>({slabs, (int64_t)cus * 8, (int64_t)NBLK_MAX}));
 }
@@ -110,8 +100,6 @@ int pick_nblk(int64_t npad, int cus) {
 // The per-block partials (ncol per block) are summed by one block afterwards, so the grid
 // also keeps nblk * ncol near 48k values.
 int cols_grid(int64_t npad, int cus, int nw, int waves_per_cu, int ncol) {
-    const int forced = env_int("RSOLVE_NBLK_COLS", 0);
-    if (forced > 0) return std::min(forced, NBLK_MAX);
     const int64_t tiles = npad / WAVE;
     int per_cu = std::max(1, waves_per_cu / std::max(1, nw));
     per_cu = std::max(1, std::min(per_cu, (int)(49152 / ((int64_t)std::max(ncol, 1) * cus))));
@@ -150,6 +138,8 @@ struct rsolve_seq {
     float *V32 = nullptr, *W32 = nullptr, *Z32 = nullptr, *vals32 = nullptr;
     float* w32[2] = {nullptr, nullptr};
     int nblk = 1, gblk = 1, lpr = 8, cus = 256;
+    int svec = 4, sremap = 0;      // Arnoldi SpMV shape (entries per lane, XCD-aware block order)
+    bool shape_set = false;        // lpr / svec / sremap chosen by the caller (rsolve_set_spmv_shape)
     const int32_t* pat_rp = nullptr;
     const int32_t* pat_ci = nullptr;
     int64_t pat_nnz = -1;
@@ -244,6 +234,31 @@ size_t layout(rsolve_seq* s, const rsolve_config& c, int64_t n, int64_t nnz_max,
     return align_up(cv.off, ALIGN);
 }
 
+// Pattern check on the device (row pointers, column range and order, diagonal present); on
+// success the pattern is cached for RSOLVE_SAME_PATTERN calls and the SpMV lanes per row are
+// chosen for it (unless the caller fixed the shape).
+int validate_pattern(rsolve_seq* s, const rsolve_csr* A) {
+    hipStream_t stm = s->stream;
+    const int64_t n = s->n;
+    s->pat_ok = false;
+    HIP_TRY(hipMemsetAsync(s->err, 0, sizeof(int32_t) * 8, stm));
+    launch_validate(n, A->nnz, A->row_ptr, A->col_idx, s->diag_pos, s->err, stm);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(s->herr, s->err, sizeof(int32_t) * 4, hipMemcpyDeviceToHost, stm));
+    HIP_TRY(hipStreamSynchronize(stm));
+    if (s->herr[0] || s->herr[1] || s->herr[2] || s->herr[3]) {
+        set_err("corrupt CSR: row_ptr=%d col_range=%d col_order=%d no_diagonal=%d", s->herr[0], s->herr[1],
+                s->herr[2], s->herr[3]);
+        return RSOLVE_E_INVALID;
+    }
+    s->pat_rp = A->row_ptr;
+    s->pat_ci = A->col_idx;
+    s->pat_nnz = A->nnz;
+    s->pat_ok = true;
+    if (!s->shape_set) s->lpr = pick_lpr(n, A->nnz);
+    return RSOLVE_OK;
+}
+
 inline double* ctl_h1(Ctl* c) { return reinterpret_cast<double*>(reinterpret_cast<char*>(c) + offsetof(Ctl, h1)); }
 inline double* ctl_h2(Ctl* c) { return reinterpret_cast<double*>(reinterpret_cast<char*>(c) + offsetof(Ctl, h2)); }
 inline double* ctl_cw(Ctl* c) { return reinterpret_cast<double*>(reinterpret_cast<char*>(c) + offsetof(Ctl, cw)); }
@@ -300,7 +315,8 @@ void arnoldi_step(rsolve_seq* s, int j, const int32_t* rp, const int32_t* ci, co
     const double w = sizeof(T), nn = (double)s->n;
     {
         ProfEv pe(s, RSOLVE_PROF_SPMV, j, 0, (w + 4.0) * (double)s->nnz_cur + 4.0 * (nn + 1.0) + 3.0 * w * nn);
-        launch_spmv_arnoldi<T>(s->lpr, s->n, rp, ci, vals, win, vj, wout, s->ctl, st, pe.e0, pe.e1);
+        launch_spmv_arnoldi<T>(s->lpr, s->svec, s->sremap, s->n, rp, ci, vals, win, vj, wout, s->ctl, st, pe.e0,
+                               pe.e1);
     }
     const int nv = j + 1;
     const int ntot = k > 0 ? nv + 2 * k : nv;
@@ -486,6 +502,95 @@ int rsolve_profile_read(rsolve_seq* s, rsolve_prof_entry* out, int32_t cap, int3
     return RSOLVE_OK;
 }
 
+int rsolve_set_spmv_shape(rsolve_seq* s, const rsolve_spmv_shape* shape) {
+    if (!s || !shape) return RSOLVE_E_INVALID;
+    const int l = shape->lanes_per_row, v = shape->vec;
+    if ((l != 2 && l != 4 && l != 8 && l != 16 && l != 32) || (v != 1 && v != 4 && v != 8) ||
+        (shape->xcd_remap != 0 && shape->xcd_remap != 1)) {
+        set_err("invalid SpMV shape (lanes %d, vec %d, remap %d)", l, v, shape->xcd_remap);
+        return RSOLVE_E_INVALID;
+    }
+    s->lpr = l;
+    s->svec = v;
+    s->sremap = shape->xcd_remap;
+    s->shape_set = true;
+    return RSOLVE_OK;
+}
+
+int rsolve_get_spmv_shape(rsolve_seq* s, rsolve_spmv_shape* shape) {
+    if (!s || !shape) return RSOLVE_E_INVALID;
+    shape->lanes_per_row = s->lpr;
+    shape->vec = s->svec;
+    shape->xcd_remap = s->sremap;
+    shape->user_set = s->shape_set ? 1 : 0;
+    shape->us = 0.0;
+    return RSOLVE_OK;
+}
+
+int rsolve_tune_spmv(rsolve_seq* s, const rsolve_csr* A, int32_t reps, rsolve_spmv_shape* out, int32_t cap,
+                     int32_t* count) {
+    g_err[0] = 0;
+    if (!s || !A || !count || reps < 1 || reps > 1000 || cap < 0 || (cap > 0 && !out)) return RSOLVE_E_INVALID;
+    if (A->n != s->n || A->nnz < A->n || A->nnz > s->nnz_max || !A->row_ptr || !A->col_idx || !A->val ||
+        A->reserved != 0) {
+        set_err("matrix header does not match the sequence");
+        return RSOLVE_E_INVALID;
+    }
+    HIP_TRY(hipSetDevice(s->device));
+    hipStream_t stm = s->stream;
+    // the candidates read A's indices: check the pattern first, as a solve would (this also
+    // picks the default lanes per row, unless the caller set a shape)
+    const int vrc = validate_pattern(s, A);
+    if (vrc != RSOLVE_OK) return vrc;
+    s->pat_ok = false;     // the next solve checks again (the caller did not promise the pattern)
+    const bool ir = s->cfg.precision == RSOLVE_FP32_IR;
+    const int64_t n = s->n;
+    HIP_TRY(hipMemsetAsync(s->ctl, 0, CTL_HEAD, stm));
+    if (ir) launch_scale_values(A->nnz, A->col_idx, A->val, nullptr, nullptr, s->vals32, stm);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        set_err("event creation failed");
+        return RSOLVE_E_DEVICE;
+    }
+    std::vector<rsolve_spmv_shape> res;
+    const int lanes[] = {2, 4, 8, 16, 32}, vecs[] = {1, 4, 8};
+    hipError_t err = hipSuccess;
+    for (int l : lanes)
+        for (int v : vecs)
+            for (int rm = 0; rm < 2 && err == hipSuccess; ++rm) {
+                auto run = [&] {
+                    if (ir)
+                        launch_spmv_arnoldi<float>(l, v, rm, n, A->row_ptr, A->col_idx, s->vals32, s->w32[0], s->V32,
+                                                   s->w32[1], s->ctl, stm);
+                    else
+                        launch_spmv_arnoldi<double>(l, v, rm, n, A->row_ptr, A->col_idx, A->val, s->wb[0], s->V,
+                                                    s->wb[1], s->ctl, stm);
+                };
+                run();   // warm-up
+                err = hipEventRecord(e0, stm);
+                for (int r = 0; r < reps && err == hipSuccess; ++r) run();
+                if (err == hipSuccess) err = hipEventRecord(e1, stm);
+                if (err == hipSuccess) err = hipEventSynchronize(e1);
+                float ms = 0.f;
+                if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+                if (err == hipSuccess) err = hipGetLastError();
+                res.push_back(rsolve_spmv_shape{l, v, rm, 0, 1e3 * (double)ms / reps});
+            }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (err != hipSuccess) {
+        set_err("tuning run failed: %s", hipGetErrorString(err));
+        return RSOLVE_E_DEVICE;
+    }
+    std::stable_sort(res.begin(), res.end(),
+                     [](const rsolve_spmv_shape& a, const rsolve_spmv_shape& b) { return a.us < b.us; });
+    for (int i = 0; i < std::min<int>(cap, (int)res.size()); ++i) out[i] = res[i];
+    *count = (int32_t)res.size();
+    return RSOLVE_OK;
+}
+
 int rsolve_destroy_sequence(rsolve_seq* s) {
     if (!s) return RSOLVE_E_INVALID;
     (void)hipStreamSynchronize(s->stream);
@@ -535,22 +640,8 @@ int rsolve_solve(rsolve_seq* s, const rsolve_csr* A, const double* b, const doub
     const bool same = (A->flags & RSOLVE_SAME_PATTERN) && s->pat_ok && s->pat_rp == A->row_ptr &&
                       s->pat_ci == A->col_idx && s->pat_nnz == A->nnz;
     if (!same) {
-        s->pat_ok = false;
-        HIP_TRY(hipMemsetAsync(s->err, 0, sizeof(int32_t) * 8, stm));
-        launch_validate(n, A->nnz, A->row_ptr, A->col_idx, s->diag_pos, s->err, stm);
-        HIP_TRY(hipGetLastError());
-        HIP_TRY(hipMemcpyAsync(s->herr, s->err, sizeof(int32_t) * 4, hipMemcpyDeviceToHost, stm));
-        HIP_TRY(hipStreamSynchronize(stm));
-        if (s->herr[0] || s->herr[1] || s->herr[2] || s->herr[3]) {
-            set_err("corrupt CSR: row_ptr=%d col_range=%d col_order=%d no_diag=%d", s->herr[0], s->herr[1],
-                    s->herr[2], s->herr[3]);
-            return RSOLVE_E_INVALID;
-        }
-        s->pat_rp = A->row_ptr;
-        s->pat_ci = A->col_idx;
-        s->pat_nnz = A->nnz;
-        s->pat_ok = true;
-        s->lpr = pick_lpr(n, A->nnz);
+        const int vrc = validate_pattern(s, A);
+        if (vrc != RSOLVE_OK) return vrc;
     }
     HIP_TRY(hipMemsetAsync(s->ctl, 0, CTL_HEAD, stm));
     s->nnz_cur = A->nnz;

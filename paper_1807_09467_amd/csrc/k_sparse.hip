@@ -238,27 +238,20 @@ void launch_scale_values(int64_t nnz, const int32_t* ci, const double* val, cons
     }
 
 template <typename T>
-void launch_spmv_arnoldi(int lpr, int64_t n, const int32_t* rp, const int32_t* ci, const T* val, const T* win,
-                         T* vout, T* y, const Ctl* ctl, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
-    static const int remap = [] {
-        const char* v = getenv("RSOLVE_XCD_REMAP");
-        return (v && v[0] == '1') ? 1 : 0;
-    }();
-    static const int vec = [] {
-        const char* v = getenv("RSOLVE_SPMV_VEC");
-        return v ? atoi(v) : 4;
-    }();
+void launch_spmv_arnoldi(int lpr, int vec, int remap, int64_t n, const int32_t* rp, const int32_t* ci, const T* val,
+                         const T* win, T* vout, T* y, const Ctl* ctl, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
 #define RS_CALL(L)                                                                                       \
     hipExtLaunchKernelGGL(k_spmv_arnoldi<T, L>, dim3(grid_for(n * L)), dim3(BLOCK), 0, st, ev0, ev1, 0, n, rp, ci, \
                           val, win, vout, y, ctl, remap, vec)
     RS_LPR_DISPATCH(lpr, RS_CALL)
 #undef RS_CALL
 }
-template void launch_spmv_arnoldi<double>(int, int64_t, const int32_t*, const int32_t*, const double*,
+template void launch_spmv_arnoldi<double>(int, int, int, int64_t, const int32_t*, const int32_t*, const double*,
                                           const double*, double*, double*, const Ctl*, hipStream_t, hipEvent_t,
                                           hipEvent_t);
-template void launch_spmv_arnoldi<float>(int, int64_t, const int32_t*, const int32_t*, const float*, const float*,
-                                         float*, float*, const Ctl*, hipStream_t, hipEvent_t, hipEvent_t);
+template void launch_spmv_arnoldi<float>(int, int, int, int64_t, const int32_t*, const int32_t*, const float*,
+                                         const float*, float*, float*, const Ctl*, hipStream_t, hipEvent_t,
+                                         hipEvent_t);
 
 void launch_residual(int lpr, int64_t n, const int32_t* rp, const int32_t* ci, const double* val, const double* x,
                      const double* b, double* r, hipStream_t st) {

@@ -19,11 +19,13 @@ void launch_diag_inv(int64_t n, const int32_t* diag_pos, const double* val, doub
 void launch_scale_values(int64_t nnz, const int32_t* ci, const double* val, const double* dinv, double* out64,
                          float* out32, hipStream_t st);
 // Arnoldi product: vout[i] = s * win[i]; y[i] = s * sum_k val[k] win[col[k]], s = ctl->inv_h.
-// ev0 / ev1 (nullable): events stamped with the start and end of the kernel's own dispatch
-// (hipExtLaunchKernelGGL), for per-kernel timing without extra queue packets.
+// Shape: lpr lanes per row (2..32), vec entries per lane and load (4 or 8; 1 = four strided
+// scalar loads), remap = XCD-aware block order.  ev0 / ev1 (nullable): events stamped with the
+// start and end of the kernel's own dispatch (hipExtLaunchKernelGGL), for per-kernel timing
+// without extra queue packets.
 template <typename T>
-void launch_spmv_arnoldi(int lpr, int64_t n, const int32_t* rp, const int32_t* ci, const T* val, const T* win,
-                         T* vout, T* y, const Ctl* ctl, hipStream_t st, hipEvent_t ev0 = nullptr,
+void launch_spmv_arnoldi(int lpr, int vec, int remap, int64_t n, const int32_t* rp, const int32_t* ci, const T* val,
+                         const T* win, T* vout, T* y, const Ctl* ctl, hipStream_t st, hipEvent_t ev0 = nullptr,
                          hipEvent_t ev1 = nullptr);
 // r = b - A x (float64)
 void launch_residual(int lpr, int64_t n, const int32_t* rp, const int32_t* ci, const double* val,

@@ -36,6 +36,7 @@ EXPORTS = [
     "rsolve_get_recycle", "rsolve_destroy_sequence", "rsolve_status_string", "rsolve_last_error",
     "rsolve_spmv", "rsolve_kernel_workspace_bytes", "rsolve_gram_tn", "rsolve_snapshot_svd",
     "rsolve_profile_enable", "rsolve_profile_read", "rsolve_solve_batch", "rsolve_update_recycle_batch",
+    "rsolve_tune_spmv", "rsolve_set_spmv_shape", "rsolve_get_spmv_shape",
     # serving loop (rsolve_server.h; bound in serve.py)
     "rsolve_server_create", "rsolve_server_open", "rsolve_server_submit", "rsolve_server_poll",
     "rsolve_server_close", "rsolve_server_info_get", "rsolve_server_destroy",
@@ -75,6 +76,14 @@ class Stats(ctypes.Structure):
 class ProfEntry(ctypes.Structure):
     _fields_ = [("kernel", c_int32), ("variant", c_int32), ("launches", c_int64), ("ms", c_double),
                 ("bytes", c_double)]
+
+
+class SpmvShape(ctypes.Structure):
+    _fields_ = [("lanes_per_row", c_int32), ("vec", c_int32), ("xcd_remap", c_int32), ("user_set", c_int32),
+                ("us", c_double)]
+
+    def as_dict(self):
+        return {"lanes_per_row": self.lanes_per_row, "vec": self.vec, "xcd_remap": self.xcd_remap, "us": self.us}
 
 
 class BatchSolveItem(ctypes.Structure):
@@ -136,6 +145,12 @@ def load():
     lib.rsolve_profile_enable.restype = c_int
     lib.rsolve_profile_read.argtypes = [c_void_p, POINTER(ProfEntry), c_int32, POINTER(c_int32), c_int32]
     lib.rsolve_profile_read.restype = c_int
+    lib.rsolve_tune_spmv.argtypes = [c_void_p, POINTER(CSR), c_int32, POINTER(SpmvShape), c_int32, POINTER(c_int32)]
+    lib.rsolve_tune_spmv.restype = c_int
+    lib.rsolve_set_spmv_shape.argtypes = [c_void_p, POINTER(SpmvShape)]
+    lib.rsolve_set_spmv_shape.restype = c_int
+    lib.rsolve_get_spmv_shape.argtypes = [c_void_p, POINTER(SpmvShape)]
+    lib.rsolve_get_spmv_shape.restype = c_int
     lib.rsolve_solve_batch.argtypes = [POINTER(BatchSolveItem), c_int32, c_void_p]
     lib.rsolve_solve_batch.restype = c_int
     lib.rsolve_update_recycle_batch.argtypes = [POINTER(BatchUpdateItem), c_int32, c_void_p]
@@ -250,6 +265,27 @@ class Sequence:
                                                        c_void_p(W.data_ptr()), self.n))
             out["W"] = W
         return out
+
+    def tune_spmv(self, row_ptr, col_idx, val, reps=20):
+        """Time every Arnoldi SpMV shape on this matrix (rsolve_tune_spmv); fastest first."""
+        import torch
+        A = self.csr(row_ptr, col_idx, val)
+        cap = 64
+        arr = (SpmvShape * cap)()
+        cnt = c_int32()
+        with torch.cuda.device(self.device):
+            _check(self.lib.rsolve_tune_spmv(self.handle, byref(A), int(reps), arr, cap, byref(cnt)))
+        return [arr[i].as_dict() for i in range(min(cnt.value, cap))]
+
+    def set_spmv_shape(self, lanes_per_row, vec, xcd_remap=0):
+        _check(self.lib.rsolve_set_spmv_shape(self.handle, byref(SpmvShape(lanes_per_row, vec, xcd_remap, 0, 0.0))))
+
+    def spmv_shape(self):
+        sh = SpmvShape()
+        _check(self.lib.rsolve_get_spmv_shape(self.handle, byref(sh)))
+        d = sh.as_dict()
+        d["user_set"] = bool(sh.user_set)
+        return d
 
     def profile(self, on=True):
         _check(self.lib.rsolve_profile_enable(self.handle, 1 if on else 0))

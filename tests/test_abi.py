@@ -53,11 +53,11 @@ C_LAYOUT_PROBE = r"""
 #include <stdio.h>
 #include "rsolve_server.h"
 int main(void) {
-    printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(rsolve_config), sizeof(rsolve_csr),
+    printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(rsolve_config), sizeof(rsolve_csr),
            sizeof(rsolve_stats), sizeof(rsolve_batch_solve_item), offsetof(rsolve_batch_solve_item, status),
            offsetof(rsolve_batch_solve_item, stats), sizeof(rsolve_batch_update_item),
            sizeof(rsolve_prof_entry), sizeof(rsolve_server_config), sizeof(rsolve_completion),
-           sizeof(rsolve_server_info));
+           sizeof(rsolve_server_info), sizeof(rsolve_spmv_shape));
     return 0;
 }
 """
@@ -78,7 +78,7 @@ def test_struct_layouts_match_the_c_compiler(tmp_path):
             ctypes.sizeof(rsolve.BatchSolveItem), rsolve.BatchSolveItem.status.offset,
             rsolve.BatchSolveItem.stats.offset, ctypes.sizeof(rsolve.BatchUpdateItem),
             ctypes.sizeof(rsolve.ProfEntry), ctypes.sizeof(serve.ServerConfig), ctypes.sizeof(serve.Completion),
-            ctypes.sizeof(serve.ServerInfo)]
+            ctypes.sizeof(serve.ServerInfo), ctypes.sizeof(rsolve.SpmvShape)]
     assert got == want
 
 
