@@ -101,7 +101,7 @@ def generate(prob, nsteps, dev):
     return asm, gasm, u0, systems
 
 
-def run_solver(gasm, u0, systems, warmup, steps, tol, cfg, dev, profile=False, label=""):
+def run_solver(gasm, u0, systems, warmup, steps, tol, cfg, dev, profile=False, label="", graphs=False):
     """One pass over the sequence: warmup untimed solves, then `steps` timed solve+update steps."""
     import torch
 
@@ -113,6 +113,7 @@ def run_solver(gasm, u0, systems, warmup, steps, tol, cfg, dev, profile=False, l
     shape, _, _ = autotune.tune_sequence(seq, gasm.row_ptr, gasm.col_idx, systems[0][0], cache_path=None, reps=10)
     log(f"{label} SpMV shape: {shape['lanes_per_row']} lanes/row, {shape['vec']} entries/lane, "
         f"remap {shape['xcd_remap']}: {shape['us']:.1f} us (default {shape['default_us']:.1f} us)")
+    seq.graphs(graphs)
     x_prev = u0
     lat, its, cyc, keff, rel = [], [], [], [], []
     xs = []
@@ -430,6 +431,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--inner-tol", type=float, default=None,
                     help="override the FP32 cycle reduction factor of the mixed-precision workload")
+    ap.add_argument("--graphs", action="store_true",
+                    help="replay the Arnoldi steps as captured hipGraphs (needs --no-profile to take effect)")
     ap.add_argument("--no-profile", action="store_true",
                     help="run the timed solves without per-kernel event timing (roofline then null)")
     ap.add_argument("--calib-copy", action="store_true",
@@ -467,12 +470,13 @@ def main():
     asm, gasm, u0, systems = generate(prob, nsteps, dev)
 
     main_run = run_solver(gasm, u0, systems, args.warmup, args.steps, tol, cfg, dev, profile=not args.no_profile,
-                          label="recycled")
+                          label="recycled", graphs=args.graphs)
     main_sum = summarize(main_run, args.steps)
     plain_sum = None
     if not args.no_plain:
         pcfg = dict(restart_m=cfg["restart_m"], precond=cfg["precond"], method="plain", precision="fp64")
-        plain_run = run_solver(gasm, u0, systems, args.warmup, args.steps, tol, pcfg, dev, label="plain-fp64")
+        plain_run = run_solver(gasm, u0, systems, args.warmup, args.steps, tol, pcfg, dev, label="plain-fp64",
+                               graphs=args.graphs)
         plain_sum = summarize(plain_run, args.steps)
         # the same systems, solved twice: both answers meet the tolerance, so they agree to kappa * tol
         diffs = [float(torch.linalg.norm(a - b) / torch.linalg.norm(b))
@@ -518,7 +522,7 @@ def main():
         "dtype": "f32+f64" if cfg.get("precision") == "fp32_ir" else "f64",
         "data": "synthetic",
         "config": {"workload": desc, "n": asm.pat.n, "nnz": asm.pat.nnz, "steps_generated": nsteps,
-                   "parallelism": "single GPU",
+                   "parallelism": "single GPU", "graphs": bool(args.graphs and args.no_profile),
                    "spmv_shape": {k: (round(v, 2) if isinstance(v, float) else v)
                                   for k, v in main_run["shape"].items()}},
         "latency_ms": main_sum["latency_ms"],

@@ -265,6 +265,21 @@ int rsolve_profile_enable(rsolve_seq* s, int32_t on);
  */
 int rsolve_profile_read(rsolve_seq* s, rsolve_prof_entry* out, int32_t cap, int32_t* count, int32_t reset);
 
+/* ---- captured Arnoldi steps (hipGraph) ---- */
+
+/*
+ * on = 1: rsolve_solve replays the Arnoldi steps of each cycle as captured graphs, one graph
+ * per chunk of four steps, captured on first use and kept while the chunk's kernel arguments
+ * stay the same (matrix pointers, recycle dimension, precision, SpMV shape); the kernels of a
+ * chunk still return at once after the step that ends the cycle.  Ignored while per-kernel
+ * timing is on.  on = 0 (default): kernels are enqueued one by one.  Results are the same
+ * either way.
+ */
+int rsolve_enable_graphs(rsolve_seq* s, int32_t on);
+
+/* Graphs captured and graph launches so far (either pointer may be NULL). */
+int rsolve_graph_counts(rsolve_seq* s, int64_t* captures, int64_t* launches);
+
 /* ---- SpMV shape of the Arnoldi product, and its autotuner ---- */
 
 typedef struct {

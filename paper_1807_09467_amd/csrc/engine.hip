@@ -16,6 +16,8 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
+#include <tuple>
 #include <vector>
 
 #include "../../include/rsolve.h"
@@ -160,6 +162,21 @@ struct rsolve_seq {
     double pms[NPK][NVAR];
     double pb[NPK][NVAR];
     int64_t pcnt[NPK][NVAR];
+    // captured Arnoldi chunks: one graph per chunk, keyed by everything its kernels bake in
+    struct GraphKey {
+        int j0, j1, k, ir, lpr, vec, remap;
+        const void* rp;
+        const void* ci;
+        const void* vals;
+        bool operator<(const GraphKey& o) const {
+            return std::tie(j0, j1, k, ir, lpr, vec, remap, rp, ci, vals) <
+                   std::tie(o.j0, o.j1, o.k, o.ir, o.lpr, o.vec, o.remap, o.rp, o.ci, o.vals);
+        }
+    };
+    bool graphs_on = false;
+    hipStream_t cap_stream = nullptr;   // capture happens here: the caller's stream may be the null stream
+    std::map<GraphKey, hipGraphExec_t> graphs;
+    int64_t graph_captures = 0, graph_launches = 0;
     // one-block batched path: pinned job descriptors and its own pattern cache
     SmallJob* hjob = nullptr;
     SmallUpd* hupd = nullptr;
@@ -256,6 +273,48 @@ int validate_pattern(rsolve_seq* s, const rsolve_csr* A) {
     s->pat_nnz = A->nnz;
     s->pat_ok = true;
     if (!s->shape_set) s->lpr = pick_lpr(n, A->nnz);
+    return RSOLVE_OK;
+}
+
+// The executable graph of one Arnoldi chunk (kernel launches only, captured on the sequence's
+// stream in thread-local mode), captured on first use and kept while its key holds.
+template <class F>
+int chunk_graph(rsolve_seq* s, const rsolve_seq::GraphKey& key, F&& enqueue, hipGraphExec_t* out) {
+    auto it = s->graphs.find(key);
+    if (it != s->graphs.end()) {
+        *out = it->second;
+        return RSOLVE_OK;
+    }
+    if (s->graphs.size() >= 512) {   // keys of earlier matrices: start over
+        for (auto& kv : s->graphs) (void)hipGraphExecDestroy(kv.second);
+        s->graphs.clear();
+    }
+    if (!s->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking));
+    // the chunk's kernels are recorded on the capture stream (nothing runs there), then the graph
+    // is launched on the sequence's own stream
+    hipStream_t own = s->stream;
+    HIP_TRY(hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal));
+    s->stream = s->cap_stream;
+    enqueue();
+    s->stream = own;
+    hipGraph_t g = nullptr;
+    const hipError_t e1 = hipGetLastError();
+    const hipError_t e2 = hipStreamEndCapture(s->cap_stream, &g);
+    if (e1 != hipSuccess || e2 != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        set_err("graph capture failed: %s", hipGetErrorString(e1 != hipSuccess ? e1 : e2));
+        return RSOLVE_E_DEVICE;
+    }
+    hipGraphExec_t ge = nullptr;
+    const hipError_t e3 = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e3 != hipSuccess) {
+        set_err("graph instantiation failed: %s", hipGetErrorString(e3));
+        return RSOLVE_E_DEVICE;
+    }
+    s->graphs[key] = ge;
+    s->graph_captures++;
+    *out = ge;
     return RSOLVE_OK;
 }
 
@@ -591,9 +650,25 @@ int rsolve_tune_spmv(rsolve_seq* s, const rsolve_csr* A, int32_t reps, rsolve_sp
     return RSOLVE_OK;
 }
 
+int rsolve_enable_graphs(rsolve_seq* s, int32_t on) {
+    if (!s || (on != 0 && on != 1)) return RSOLVE_E_INVALID;
+    s->graphs_on = on != 0;
+    return RSOLVE_OK;
+}
+
+int rsolve_graph_counts(rsolve_seq* s, int64_t* captures, int64_t* launches) {
+    if (!s) return RSOLVE_E_INVALID;
+    if (captures) *captures = s->graph_captures;
+    if (launches) *launches = s->graph_launches;
+    return RSOLVE_OK;
+}
+
 int rsolve_destroy_sequence(rsolve_seq* s) {
     if (!s) return RSOLVE_E_INVALID;
     (void)hipStreamSynchronize(s->stream);
+    for (auto& kv : s->graphs) (void)hipGraphExecDestroy(kv.second);
+    s->graphs.clear();
+    if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
     if (s->pev) {
         for (int i = 0; i < rsolve_seq::NPK * MMAX * 2; ++i)
             if (s->pev[i]) (void)hipEventDestroy(s->pev[i]);
@@ -744,9 +819,23 @@ int rsolve_solve(rsolve_seq* s, const rsolve_csr* A, const double* b, const doub
                 if (s->poll_done[chunk & 1]) break;
             }
             const int j1 = std::min(max_steps, j0 + CHUNK);
-            for (int j = j0; j < j1; ++j) {
-                if (ir) arnoldi_step<float>(s, j, A->row_ptr, A->col_idx, s->vals32, s->V32, s->w32, W32, Z32, k);
-                else arnoldi_step<double>(s, j, A->row_ptr, A->col_idx, kv64, s->V, s->wb, s->W, s->Z, k);
+            auto enqueue = [&] {
+                for (int j = j0; j < j1; ++j) {
+                    if (ir) arnoldi_step<float>(s, j, A->row_ptr, A->col_idx, s->vals32, s->V32, s->w32, W32, Z32, k);
+                    else arnoldi_step<double>(s, j, A->row_ptr, A->col_idx, kv64, s->V, s->wb, s->W, s->Z, k);
+                }
+            };
+            if (s->graphs_on && !s->prof_on) {
+                const rsolve_seq::GraphKey key{j0, j1, k, ir ? 1 : 0, s->lpr, s->svec, s->sremap, A->row_ptr,
+                                               A->col_idx, ir ? static_cast<const void*>(s->vals32)
+                                                              : static_cast<const void*>(kv64)};
+                hipGraphExec_t ge = nullptr;
+                rc = chunk_graph(s, key, enqueue, &ge);
+                if (rc) return rc;
+                HIP_TRY(hipGraphLaunch(ge, stm));
+                s->graph_launches++;
+            } else {
+                enqueue();
             }
             if (j1 < max_steps) {
                 HIP_TRY(hipMemcpyAsync(s->poll_done + (chunk & 1), reinterpret_cast<char*>(s->ctl) + offsetof(Ctl, done),

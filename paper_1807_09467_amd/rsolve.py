@@ -36,7 +36,8 @@ EXPORTS = [
     "rsolve_get_recycle", "rsolve_destroy_sequence", "rsolve_status_string", "rsolve_last_error",
     "rsolve_spmv", "rsolve_kernel_workspace_bytes", "rsolve_gram_tn", "rsolve_snapshot_svd",
     "rsolve_profile_enable", "rsolve_profile_read", "rsolve_solve_batch", "rsolve_update_recycle_batch",
-    "rsolve_tune_spmv", "rsolve_set_spmv_shape", "rsolve_get_spmv_shape",
+    "rsolve_tune_spmv", "rsolve_set_spmv_shape", "rsolve_get_spmv_shape", "rsolve_enable_graphs",
+    "rsolve_graph_counts",
     # serving loop (rsolve_server.h; bound in serve.py)
     "rsolve_server_create", "rsolve_server_open", "rsolve_server_submit", "rsolve_server_poll",
     "rsolve_server_close", "rsolve_server_info_get", "rsolve_server_destroy",
@@ -151,6 +152,10 @@ def load():
     lib.rsolve_set_spmv_shape.restype = c_int
     lib.rsolve_get_spmv_shape.argtypes = [c_void_p, POINTER(SpmvShape)]
     lib.rsolve_get_spmv_shape.restype = c_int
+    lib.rsolve_enable_graphs.argtypes = [c_void_p, c_int32]
+    lib.rsolve_enable_graphs.restype = c_int
+    lib.rsolve_graph_counts.argtypes = [c_void_p, POINTER(c_int64), POINTER(c_int64)]
+    lib.rsolve_graph_counts.restype = c_int
     lib.rsolve_solve_batch.argtypes = [POINTER(BatchSolveItem), c_int32, c_void_p]
     lib.rsolve_solve_batch.restype = c_int
     lib.rsolve_update_recycle_batch.argtypes = [POINTER(BatchUpdateItem), c_int32, c_void_p]
@@ -286,6 +291,15 @@ class Sequence:
         d = sh.as_dict()
         d["user_set"] = bool(sh.user_set)
         return d
+
+    def graphs(self, on=True):
+        """Replay the Arnoldi steps as captured hipGraphs (rsolve_enable_graphs)."""
+        _check(self.lib.rsolve_enable_graphs(self.handle, 1 if on else 0))
+
+    def graph_counts(self):
+        c, l = c_int64(), c_int64()
+        _check(self.lib.rsolve_graph_counts(self.handle, byref(c), byref(l)))
+        return c.value, l.value
 
     def profile(self, on=True):
         _check(self.lib.rsolve_profile_enable(self.handle, 1 if on else 0))
