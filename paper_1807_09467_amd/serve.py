@@ -235,7 +235,12 @@ def run_serving(specs, solver_cfg, tol, device, pool_bytes, large_workers=4, max
                    tol, ready_event=a.ev, tag=tag)
 
     t_start = time.perf_counter()
+    t_report = t_start
     while waiting or active:
+        if log and time.perf_counter() - t_report > 10.0:
+            t_report = time.perf_counter()
+            log(f"serving: {len(records)} solves done, {len(active)} sequences active, {len(waiting)} waiting, "
+                f"{t_report - t_start:.0f}s")
         now = time.perf_counter() - t_start
         while waiting and waiting[0].arrival_s <= now:
             sp = waiting[0]
