@@ -101,7 +101,8 @@ def generate(prob, nsteps, dev):
     return asm, gasm, u0, systems
 
 
-def run_solver(gasm, u0, systems, warmup, steps, tol, cfg, dev, profile=False, label="", graphs=False):
+def run_solver(gasm, u0, systems, warmup, steps, tol, cfg, dev, profile=False, label="", graphs=False,
+               profile_kinds=None):
     """One pass over the sequence: warmup untimed solves, then `steps` timed solve+update steps."""
     import torch
 
@@ -122,7 +123,7 @@ def run_solver(gasm, u0, systems, warmup, steps, tol, cfg, dev, profile=False, l
         if i == warmup:
             torch.cuda.synchronize()
             if profile:
-                seq.profile(True)
+                seq.profile(True, kinds=profile_kinds)
             t_start = time.perf_counter()
         t0 = time.perf_counter()
         x, st, status = seq.solve(gasm.row_ptr, gasm.col_idx, vals, b, x0=x_prev, tol=tol, same_pattern=i > 0)
@@ -435,6 +436,9 @@ def main():
                     help="override the FP32 cycle reduction factor of the mixed-precision workload")
     ap.add_argument("--graphs", action="store_true",
                     help="replay the Arnoldi steps as captured hipGraphs (needs --no-profile to take effect)")
+    ap.add_argument("--profile-kinds", default="spmv_arnoldi",
+                    help="kernel kinds timed with HIP events in the timed run: comma list of spmv_arnoldi, dots, "
+                         "update_dots, update_norm, or 'all' (each timed kind is slowed by its event stamps)")
     ap.add_argument("--no-profile", action="store_true",
                     help="run the timed solves without per-kernel event timing (roofline then null)")
     ap.add_argument("--calib-copy", action="store_true",
@@ -471,8 +475,9 @@ def main():
     nsteps = args.warmup + args.steps
     asm, gasm, u0, systems = generate(prob, nsteps, dev)
 
+    kinds = None if args.profile_kinds == "all" else [k for k in args.profile_kinds.split(",") if k]
     main_run = run_solver(gasm, u0, systems, args.warmup, args.steps, tol, cfg, dev, profile=not args.no_profile,
-                          label="recycled", graphs=args.graphs)
+                          label="recycled", graphs=args.graphs, profile_kinds=kinds)
     main_sum = summarize(main_run, args.steps)
     plain_sum = None
     if not args.no_plain:

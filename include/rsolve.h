@@ -250,14 +250,17 @@ typedef struct {
                            written once: values, indices, basis columns, vectors) */
 } rsolve_prof_entry;
 
+#define RSOLVE_PROF_ALL         0xF /* every kind below: (1 << RSOLVE_PROF_SPMV) | ... */
+
 /*
- * Switch per-kernel timing on (on != 0) or off for this sequence.  When on,
- * every Arnoldi-step kernel of rsolve_solve is bracketed by two HIP events on
- * the sequence's stream; durations of the launches that did work are summed
- * after each cycle.  Adds a few microseconds per launch.  Errors: E_INVALID,
+ * Per-kernel timing for this sequence: `kinds` is a bit set (bit RSOLVE_PROF_x times that
+ * kernel kind, RSOLVE_PROF_ALL all of them, 0 switches timing off).  A timed Arnoldi-step
+ * kernel gets two HIP events stamped by its own dispatch on the sequence's stream; durations of
+ * the launches that did work are summed after each cycle.  Each timed launch costs a few
+ * microseconds of host and queue work, so time only the kinds you need.  Errors: E_INVALID,
  * E_DEVICE (event creation).
  */
-int rsolve_profile_enable(rsolve_seq* s, int32_t on);
+int rsolve_profile_enable(rsolve_seq* s, int32_t kinds);
 
 /*
  * Copy up to `cap` non-empty entries (host array) and their number to *count;

@@ -156,6 +156,7 @@ struct rsolve_seq {
     // per-kernel timing
     static constexpr int NPK = 4, NVAR = 4;
     bool prof_on = false;
+    int prof_mask = 0;                   // bit RSOLVE_PROF_* set: that kernel kind is timed
     hipEvent_t* pev = nullptr;           // [NPK][MMAX][2]
     int pvar[NPK][MMAX];                 // variant recorded for step j
     double pbytes[NPK][MMAX];            // algorithmic bytes of step j's launch
@@ -339,7 +340,7 @@ inline int var_of(int cols) { return cols <= 8 ? 0 : (cols <= 16 ? 1 : (cols <= 
 struct ProfEv {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     ProfEv(rsolve_seq* s, int kind, int j, int var, double bytes) {
-        if (!s->prof_on) return;
+        if (!(s->prof_mask & (1 << kind))) return;
         s->pvar[kind][j] = var;
         s->pbytes[kind][j] = bytes;
         e0 = s->pev[(kind * MMAX + j) * 2 + 0];
@@ -351,7 +352,7 @@ struct ProfEv {
 void prof_collect(rsolve_seq* s, int steps) {
     if (!s->prof_on) return;
     for (int kd = 0; kd < rsolve_seq::NPK; ++kd)
-        for (int j = 0; j < steps; ++j) {
+        for (int j = 0; j < steps && (s->prof_mask & (1 << kd)); ++j) {
             float ms = 0.f;
             if (hipEventElapsedTime(&ms, s->pev[(kd * MMAX + j) * 2], s->pev[(kd * MMAX + j) * 2 + 1]) != hipSuccess)
                 continue;
@@ -530,16 +531,17 @@ int rsolve_create_sequence(const rsolve_config* cfg, int64_t n, int64_t nnz_max,
     return RSOLVE_OK;
 }
 
-int rsolve_profile_enable(rsolve_seq* s, int32_t on) {
-    if (!s) return RSOLVE_E_INVALID;
-    if (on && !s->pev) {
+int rsolve_profile_enable(rsolve_seq* s, int32_t kinds) {
+    if (!s || kinds < 0 || kinds > RSOLVE_PROF_ALL) return RSOLVE_E_INVALID;
+    if (kinds && !s->pev) {
         HIP_TRY(hipSetDevice(s->device));
         const int cnt = rsolve_seq::NPK * MMAX * 2;
         s->pev = new hipEvent_t[cnt]();
         // timing-only events: no system-scope fence, so recording them does not flush caches
         for (int i = 0; i < cnt; ++i) HIP_TRY(hipEventCreateWithFlags(&s->pev[i], hipEventDisableSystemFence));
     }
-    s->prof_on = on != 0;
+    s->prof_mask = kinds;
+    s->prof_on = kinds != 0;
     return RSOLVE_OK;
 }
 

@@ -301,8 +301,18 @@ class Sequence:
         _check(self.lib.rsolve_graph_counts(self.handle, byref(c), byref(l)))
         return c.value, l.value
 
-    def profile(self, on=True):
-        _check(self.lib.rsolve_profile_enable(self.handle, 1 if on else 0))
+    def profile(self, on=True, kinds=None):
+        """Per-kernel event timing: kinds = iterable of names from PROF_KERNELS (default: all)."""
+        if not on:
+            mask = 0
+        elif kinds is None:
+            mask = 0xF
+        else:
+            names = {v: k for k, v in PROF_KERNELS.items()}
+            mask = 0
+            for k in kinds:
+                mask |= 1 << names[k]
+        _check(self.lib.rsolve_profile_enable(self.handle, mask))
 
     def profile_read(self, reset=False):
         """Per-kernel HIP-event timings: list of dicts (kernel, variant, launches, ms, bytes)."""
