@@ -418,19 +418,37 @@ class BatchPlan:
         self.stream = stream
         self.device = self.seqs[0].device if self.seqs else None
 
-    def solve(self, vals, bs, x0s, same_pattern):
-        """vals, bs, x0s: per-sequence device tensors (x0 entries may be None). Returns the outputs
-        (list of tensors); per-item status and stats are in self.view."""
+    @staticmethod
+    def pointers(tensors):
+        """Device addresses of a list of tensors as a numpy array (precompute once per round's
+        inputs to keep the per-round host work to two library calls)."""
+        import numpy as np
+        return np.fromiter((t.data_ptr() for t in tensors), dtype=np.uint64, count=len(tensors))
+
+    def solve(self, vals, bs, x0s, same_pattern, nnz=None):
+        """vals, bs: per-sequence device tensors, or numpy uint64 arrays of their addresses (then
+        nnz gives the value counts, an int or an array); x0s: tensors (entries may be None) or
+        "previous" for the outputs of the previous round.  Returns the outputs (list of tensors);
+        per-item status and stats are in self.view."""
         import numpy as np
         import torch
         m = len(self.seqs)
         outs = [o[self.round & 1] for o in self.out]
+        if not hasattr(self, "_outp"):
+            self._outp = [self.pointers([o[0] for o in self.out]), self.pointers([o[1] for o in self.out])]
+        if isinstance(vals, np.ndarray):
+            self.view["val"] = vals
+            self.view["nnz"] = nnz
+        else:
+            self.view["val"] = [v.data_ptr() for v in vals]
+            self.view["nnz"] = [v.numel() for v in vals]
+        self.view["b"] = bs if isinstance(bs, np.ndarray) else [b.data_ptr() for b in bs]
+        if isinstance(x0s, str) and x0s == "previous":
+            self.view["x0"] = self._outp[(self.round + 1) & 1]
+        else:
+            self.view["x0"] = [0 if x is None else x.data_ptr() for x in x0s]
+        self.view["x"] = self._outp[self.round & 1]
         self.round += 1
-        self.view["val"] = [v.data_ptr() for v in vals]
-        self.view["nnz"] = [v.numel() for v in vals]
-        self.view["b"] = [b.data_ptr() for b in bs]
-        self.view["x0"] = [0 if x is None else x.data_ptr() for x in x0s]
-        self.view["x"] = [o.data_ptr() for o in outs]
         self.view["flags"] = SAME_PATTERN if same_pattern else 0
         with torch.cuda.device(self.device):
             _check(self.lib.rsolve_solve_batch(self.items, m, _stream_handle(self.stream)))

@@ -261,7 +261,13 @@ def test_batch_plan_matches_item_by_item_calls(gpu_ctx):
     for i in range(4):
         ref = rsolve.solve_batch([s.job(i) for s in a])
         rsolve.update_batch([s.seq for s in a])
-        outs = plan.solve([s.gpu_vals[i][0] for s in b], [s.gpu_vals[i][1] for s in b], x_prev, same_pattern=i > 0)
+        vals = [s.gpu_vals[i][0] for s in b]
+        bs = [s.gpu_vals[i][1] for s in b]
+        if i % 2 == 0:
+            outs = plan.solve(vals, bs, x_prev, same_pattern=i > 0)
+        else:   # address arrays and the previous round's outputs as starts
+            outs = plan.solve(plan.pointers(vals), plan.pointers(bs), "previous", same_pattern=True,
+                              nnz=np.array([v.numel() for v in vals]))
         plan.update()
         for q, s in enumerate(a):
             assert torch.equal(outs[q], ref[q][0])
