@@ -438,6 +438,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--inner-tol", type=float, default=None,
                     help="override the FP32 cycle reduction factor of the mixed-precision workload")
+    ap.add_argument("--ortho", choices=["cgs2", "dcgs2"], default="cgs2",
+                    help="Arnoldi orthogonalisation of the multi-kernel solver (both runs): classical "
+                         "Gram-Schmidt twice, or the same with the second pass delayed into the next step")
     ap.add_argument("--graphs", action="store_true",
                     help="replay the Arnoldi steps as captured hipGraphs (needs --no-profile to take effect)")
     ap.add_argument("--profile-kinds", default="spmv_arnoldi",
@@ -475,6 +478,9 @@ def main():
     if args.inner_tol is not None and cfg.get("precision") == "fp32_ir":
         cfg["inner_tol"] = args.inner_tol
         desc = desc + f", inner_tol {args.inner_tol:g}"
+    cfg["ortho"] = args.ortho
+    if args.ortho != "cgs2":
+        desc = desc + f", Arnoldi {args.ortho}"
     prob = getattr(WL, pname)
     nsteps = args.warmup + args.steps
     asm, gasm, u0, systems = generate(prob, nsteps, dev)
@@ -485,7 +491,8 @@ def main():
     main_sum = summarize(main_run, args.steps)
     plain_sum = None
     if not args.no_plain:
-        pcfg = dict(restart_m=cfg["restart_m"], precond=cfg["precond"], method="plain", precision="fp64")
+        pcfg = dict(restart_m=cfg["restart_m"], precond=cfg["precond"], method="plain", precision="fp64",
+                    ortho=args.ortho)
         plain_run = run_solver(gasm, u0, systems, args.warmup, args.steps, tol, pcfg, dev, label="plain-fp64",
                                graphs=args.graphs)
         plain_sum = summarize(plain_run, args.steps)

@@ -66,6 +66,10 @@ extern "C" {
 #define RSOLVE_FP64           0   /* everything in float64 */
 #define RSOLVE_FP32_IR        1   /* float32 Arnoldi cycles inside float64 iterative refinement */
 #define RSOLVE_SELECT_LARGEST 0   /* W = leading left singular vectors (Algorithm 1) */
+#define RSOLVE_ORTHO_CGS2     0   /* classical Gram-Schmidt applied twice: three basis sweeps per step */
+#define RSOLVE_ORTHO_DCGS2    1   /* the same Arnoldi process with the second pass of each basis vector
+                                     merged into the next step: two basis sweeps per step, the
+                                     Hessenberg column and its rotation one step later */
 
 /* ---- limits ---- */
 #define RSOLVE_MAX_RESTART    128
@@ -93,7 +97,8 @@ typedef struct {
     int32_t precision;     /* RSOLVE_FP64 / RSOLVE_FP32_IR */
     int32_t max_iters;     /* cap on Arnoldi steps per solve (>= 1) */
     int32_t select;        /* RSOLVE_SELECT_LARGEST */
-    int32_t reserved;      /* must be 0 */
+    int32_t ortho;         /* RSOLVE_ORTHO_CGS2 (0) / RSOLVE_ORTHO_DCGS2 (1): Arnoldi orthogonalisation
+                              of the multi-kernel path (the one-block path always uses CGS2) */
     double  inner_tol;     /* FP32_IR only: an FP32 cycle stops once its residual estimate has
                               dropped by this factor (0 < inner_tol < 1); ignored for FP64 */
 } rsolve_config;

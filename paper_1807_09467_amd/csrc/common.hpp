@@ -50,6 +50,12 @@ struct Ctl {
     double L[KMAX * KMAX];         // cholesky factor of W^T W, row-major
     double red[SMAX * SMAX];       // small reduction results (Gram matrices)
     double F[MMAX * KMAX];         // F[i][c] = v_i^T (A W)_c, row-major with ld KMAX
+    // delayed reorthogonalisation (RSOLVE_ORTHO_DCGS2)
+    double Hs[(MMAX + 1) * MMAX];  // unrotated Hessenberg, column-major, ld MMAX+1
+    double hp[MMAX + 1];           // first-pass coefficients of the column completed next step
+    double hr[MMAX];               // reorthogonalisation coefficients of the current candidate
+    double dq[MMAX + 1];           // update coefficients of the next candidate
+    double inv_nu;                 // 1 / norm of the current candidate after reorthogonalisation
 };
 
 __device__ __forceinline__ double wave_sum(double v) {

@@ -77,7 +77,8 @@ int cfg_check(const rsolve_config* c) {
     if (c->precond != RSOLVE_PRECOND_NONE && c->precond != RSOLVE_PRECOND_JACOBI) return RSOLVE_E_INVALID;
     if (c->precision != RSOLVE_FP64 && c->precision != RSOLVE_FP32_IR) return RSOLVE_E_INVALID;
     if (c->max_iters < 1) return RSOLVE_E_INVALID;
-    if (c->select != RSOLVE_SELECT_LARGEST || c->reserved != 0) return RSOLVE_E_INVALID;
+    if (c->select != RSOLVE_SELECT_LARGEST) return RSOLVE_E_INVALID;
+    if (c->ortho != RSOLVE_ORTHO_CGS2 && c->ortho != RSOLVE_ORTHO_DCGS2) return RSOLVE_E_INVALID;
     if (c->precision == RSOLVE_FP32_IR && !(c->inner_tol > 0.0 && c->inner_tol < 1.0)) return RSOLVE_E_INVALID;
     return RSOLVE_OK;
 }
@@ -160,18 +161,19 @@ struct rsolve_seq {
     hipEvent_t* pev = nullptr;           // [NPK][MMAX][2]
     int pvar[NPK][MMAX];                 // variant recorded for step j
     double pbytes[NPK][MMAX];            // algorithmic bytes of step j's launch
+    bool pset[NPK][MMAX] = {};           // events of step j recorded since the last collection
     double pms[NPK][NVAR];
     double pb[NPK][NVAR];
     int64_t pcnt[NPK][NVAR];
     // captured Arnoldi chunks: one graph per chunk, keyed by everything its kernels bake in
     struct GraphKey {
-        int j0, j1, k, ir, lpr, vec, remap;
+        int j0, j1, k, ir, lpr, vec, remap, dg, allowed;
         const void* rp;
         const void* ci;
         const void* vals;
         bool operator<(const GraphKey& o) const {
-            return std::tie(j0, j1, k, ir, lpr, vec, remap, rp, ci, vals) <
-                   std::tie(o.j0, o.j1, o.k, o.ir, o.lpr, o.vec, o.remap, o.rp, o.ci, o.vals);
+            return std::tie(j0, j1, k, ir, lpr, vec, remap, dg, allowed, rp, ci, vals) <
+                   std::tie(o.j0, o.j1, o.k, o.ir, o.lpr, o.vec, o.remap, o.dg, o.allowed, o.rp, o.ci, o.vals);
         }
     };
     bool graphs_on = false;
@@ -340,9 +342,10 @@ inline int var_of(int cols) { return cols <= 8 ? 0 : (cols <= 16 ? 1 : (cols <= 
 struct ProfEv {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     ProfEv(rsolve_seq* s, int kind, int j, int var, double bytes) {
-        if (!(s->prof_mask & (1 << kind))) return;
+        if (!(s->prof_mask & (1 << kind)) || j >= MMAX) return;
         s->pvar[kind][j] = var;
         s->pbytes[kind][j] = bytes;
+        s->pset[kind][j] = true;
         e0 = s->pev[(kind * MMAX + j) * 2 + 0];
         e1 = s->pev[(kind * MMAX + j) * 2 + 1];
     }
@@ -353,6 +356,9 @@ void prof_collect(rsolve_seq* s, int steps) {
     if (!s->prof_on) return;
     for (int kd = 0; kd < rsolve_seq::NPK; ++kd)
         for (int j = 0; j < steps && (s->prof_mask & (1 << kd)); ++j) {
+            // only kernels that ran in this cycle (the two schemes use different kinds); an event
+            // never recorded would leave an error behind in the runtime
+            if (!s->pset[kd][j]) continue;
             float ms = 0.f;
             if (hipEventElapsedTime(&ms, s->pev[(kd * MMAX + j) * 2], s->pev[(kd * MMAX + j) * 2 + 1]) != hipSuccess)
                 continue;
@@ -361,6 +367,7 @@ void prof_collect(rsolve_seq* s, int steps) {
             s->pb[kd][v] += s->pbytes[kd][j];
             s->pcnt[kd][v] += 1;
         }
+    memset(s->pset, 0, sizeof(s->pset));
 }
 
 // One Arnoldi step j of the current cycle on storage type T.
@@ -403,6 +410,38 @@ void arnoldi_step(rsolve_seq* s, int j, const int32_t* rp, const int32_t* ci, co
     {
         ProfEv pe(s, RSOLVE_PROF_UPDATE_NORM, j, 0, (nv + 2.0) * w * nn);
         launch_update_norm<T>(ld, V, ld, nv, wout, ctl_h2(s->ctl), s->partial, s->nblk, s->ctl, st, j, pe.e0, pe.e1);
+    }
+}
+
+// One step j of a cycle with delayed reorthogonalisation (RSOLVE_ORTHO_DCGS2): z = A D^{-1} u
+// (skipped on the closing step j = allowed), the sweep over [V_j, W, A W, u] with u and z, the
+// reduction that completes column j-1, and the update sweep writing v_j and the next candidate.
+template <typename T>
+void dcgs2_step(rsolve_seq* s, int j, int allowed, const int32_t* rp, const int32_t* ci, const T* vals, T* V,
+                T* const* wbuf, const T* Wt, const T* Zt, int k) {
+    hipStream_t st = s->stream;
+    const int64_t ld = s->ld;
+    T* u = wbuf[0];
+    T* z = wbuf[1];
+    const bool has_z = j < allowed;
+    const double w = sizeof(T), nn = (double)s->n;
+    if (has_z) {
+        ProfEv pe(s, RSOLVE_PROF_SPMV, j, 0, (w + 4.0) * (double)s->nnz_cur + 4.0 * (nn + 1.0) + 2.0 * w * nn);
+        launch_spmv_arnoldi<T>(s->lpr, s->svec, s->sremap, s->n, rp, ci, vals, u, nullptr, z, s->ctl, st, pe.e0,
+                               pe.e1);
+    }
+    const int ncol = j + 2 * k + 1;
+    const int cpw = ncol > 64 ? 8 : 4;   // as the sweep's launcher chooses
+    const int nb1 = std::min(cols_grid(ld, s->cus, std::min(16, (ncol + cpw - 1) / cpw), 32, 2 * ncol),
+                             NBLK_MAX * (MMAX + 2 * KMAX + 1) / (2 * ncol));   // partials fit their buffer
+    {
+        ProfEv pe(s, RSOLVE_PROF_DOTS, has_z ? j : MMAX, var_of(ncol), (ncol + 1.0) * w * nn);
+        launch_dots2<T>(ld, ld, V, j, Wt, Zt, k, u, has_z ? z : u, s->partial, nb1, s->ctl, st, pe.e0, pe.e1);
+    }
+    launch_dcgs2_reduce(s->partial, nb1, j, k, has_z, s->ctl, st);
+    if (has_z) {
+        ProfEv pe(s, RSOLVE_PROF_UPDATE_DOTS, j, var_of(j + 1), (j + k + 4.0) * w * nn);
+        launch_dcgs2_update<T>(ld, V, ld, j, Zt, k, u, z, s->nblk, s->ctl, st, pe.e0, pe.e1);
     }
 }
 
@@ -808,29 +847,40 @@ int rsolve_solve(rsolve_seq* s, const rsolve_csr* A, const double* b, const doub
         }
         const int max_steps = std::min(m, c.max_iters - its);
         const double cyc_stop = ir ? std::max(c.inner_tol * rnorm, stop_abs) : stop_abs;
-        launch_cycle_init(s->ctl, max_steps, cyc_stop, stm);
+        const bool dg = c.ortho == RSOLVE_ORTHO_DCGS2;
+        launch_cycle_init(s->ctl, max_steps, cyc_stop, stm, dg);
         if (ir) launch_to_f32(ld, s->wb[0], s->w32[0], stm);
         // Enqueue the cycle in chunks; after chunk c the done flag is copied to pinned memory, and
         // before chunk c + 2 is enqueued the host waits for chunk c (chunk c + 1 keeps the GPU busy),
         // so at most two chunks of early-exiting kernels follow the step that converges.
+        // with delayed reorthogonalisation step max_steps closes the last column (no product)
+        const int nsteps = dg ? max_steps + 1 : max_steps;
         constexpr int CHUNK = 4;
         int chunk = 0;
-        for (int j0 = 0; j0 < max_steps; j0 += CHUNK, ++chunk) {
+        for (int j0 = 0; j0 < nsteps; j0 += CHUNK, ++chunk) {
             if (chunk >= 2) {
                 HIP_TRY(hipEventSynchronize(s->poll_ev[chunk & 1]));
                 if (s->poll_done[chunk & 1]) break;
             }
-            const int j1 = std::min(max_steps, j0 + CHUNK);
+            const int j1 = std::min(nsteps, j0 + CHUNK);
             auto enqueue = [&] {
                 for (int j = j0; j < j1; ++j) {
-                    if (ir) arnoldi_step<float>(s, j, A->row_ptr, A->col_idx, s->vals32, s->V32, s->w32, W32, Z32, k);
-                    else arnoldi_step<double>(s, j, A->row_ptr, A->col_idx, kv64, s->V, s->wb, s->W, s->Z, k);
+                    if (dg) {
+                        if (ir) dcgs2_step<float>(s, j, max_steps, A->row_ptr, A->col_idx, s->vals32, s->V32, s->w32,
+                                                  W32, Z32, k);
+                        else dcgs2_step<double>(s, j, max_steps, A->row_ptr, A->col_idx, kv64, s->V, s->wb, s->W,
+                                                s->Z, k);
+                    } else {
+                        if (ir) arnoldi_step<float>(s, j, A->row_ptr, A->col_idx, s->vals32, s->V32, s->w32, W32, Z32, k);
+                        else arnoldi_step<double>(s, j, A->row_ptr, A->col_idx, kv64, s->V, s->wb, s->W, s->Z, k);
+                    }
                 }
             };
             if (s->graphs_on && !s->prof_on) {
-                const rsolve_seq::GraphKey key{j0, j1, k, ir ? 1 : 0, s->lpr, s->svec, s->sremap, A->row_ptr,
-                                               A->col_idx, ir ? static_cast<const void*>(s->vals32)
-                                                              : static_cast<const void*>(kv64)};
+                const rsolve_seq::GraphKey key{j0, j1, k, ir ? 1 : 0, s->lpr, s->svec, s->sremap, dg ? 1 : 0,
+                                               dg ? max_steps : 0, A->row_ptr, A->col_idx,
+                                               ir ? static_cast<const void*>(s->vals32)
+                                                  : static_cast<const void*>(kv64)};
                 hipGraphExec_t ge = nullptr;
                 rc = chunk_graph(s, key, enqueue, &ge);
                 if (rc) return rc;
@@ -839,7 +889,7 @@ int rsolve_solve(rsolve_seq* s, const rsolve_csr* A, const double* b, const doub
             } else {
                 enqueue();
             }
-            if (j1 < max_steps) {
+            if (j1 < nsteps) {
                 HIP_TRY(hipMemcpyAsync(s->poll_done + (chunk & 1), reinterpret_cast<char*>(s->ctl) + offsetof(Ctl, done),
                                        sizeof(int32_t), hipMemcpyDeviceToHost, stm));
                 HIP_TRY(hipEventRecord(s->poll_ev[chunk & 1], stm));

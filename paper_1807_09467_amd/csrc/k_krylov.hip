@@ -416,12 +416,12 @@ __global__ __launch_bounds__(BLOCK) void k_update_norm(int64_t npad, const T* __
     if (threadIdx.x == 0) partial[blockIdx.x] = acc;
 }
 
-__global__ void k_cycle_init(Ctl* ctl, int max_steps, double stop_abs) {
+__global__ void k_cycle_init(Ctl* ctl, int max_steps, double stop_abs, int unit_scale) {
     if (threadIdx.x != 0) return;
     const double beta = ctl->rnorm;
     ctl->beta = beta;
     ctl->g[0] = beta;
-    ctl->inv_h = 1.0 / beta;
+    ctl->inv_h = unit_scale ? 1.0 : 1.0 / beta;
     ctl->steps = 0;
     ctl->done = 0;
     ctl->lucky = 0;
@@ -520,6 +520,256 @@ __global__ __launch_bounds__(BLOCK) void k_copy_pad(int64_t n, int64_t npad, con
     if (i < npad) out[i] = (in && i < n) ? in[i] : 0.0;
 }
 
+// ---------------------------------------------------------------------------
+// Arnoldi with delayed reorthogonalisation (two sweeps per step).  Step j holds the candidate
+// u for basis vector j, orthogonalised once against V_j = [v_0 .. v_{j-1}] and not normalised,
+// and z = A D^{-1} u.  One sweep forms V_j^T u, V_j^T z, W^T z, (A W)^T u, u.u and u.z; from them
+// the reduction completes Hessenberg column j-1 (its second-pass part V_j^T u and subdiagonal
+// ||u - V_j V_j^T u||), rotates it, and derives column j's first-pass coefficients for
+// P A D^{-1} v_j through the Arnoldi relation; one update sweep then writes v_j and the next
+// candidate.  In exact arithmetic this is the CGS2 Arnoldi process; the second pass of each
+// vector is merged into the next step.
+// ---------------------------------------------------------------------------
+
+// Sweep of the columns [V_j, W, A W, u], each dotted with u and with z (CPW columns per
+// wavefront, 64-row tiles): partial[(2c + e) nblk + b], e = 0 for u, 1 for z.
+template <typename T, int CPW>
+__global__ __launch_bounds__(1024) void k_dots2(int64_t npad, int64_t ld, const T* __restrict__ V, int nq,
+                                                const T* __restrict__ W, const T* __restrict__ Z, int k,
+                                                const T* __restrict__ u, const T* __restrict__ z, int c_begin,
+                                                int c_end, double* __restrict__ partial, int nblk,
+                                                const Ctl* __restrict__ ctl) {
+    if (ctl->done) return;
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int wv = threadIdx.x / WAVE;
+    const int c0 = c_begin + wv * CPW;
+    const T* col[CPW];
+#pragma unroll
+    for (int s = 0; s < CPW; ++s) {
+        int c = c0 + s < c_end ? c0 + s : (c0 < c_end ? c0 : c_begin);
+        col[s] = c < nq ? V + (int64_t)c * ld
+                        : (c < nq + k ? W + (int64_t)(c - nq) * ld : (c < nq + 2 * k ? Z + (int64_t)(c - nq - k) * ld : u));
+    }
+    // 16-byte loads: VEC consecutive rows per lane (npad is a multiple of 64)
+    constexpr int VEC = 16 / sizeof(T);
+    double acc[2 * CPW];
+#pragma unroll
+    for (int s = 0; s < 2 * CPW; ++s) acc[s] = 0.0;
+    const int64_t nvec = npad / VEC;
+    for (int64_t q = (int64_t)blockIdx.x * WAVE + lane; q < nvec; q += (int64_t)nblk * WAVE) {
+        const int64_t i = q * VEC;
+        T xu[VEC], xz[VEC];
+        __builtin_memcpy(xu, u + i, sizeof(xu));
+        __builtin_memcpy(xz, z + i, sizeof(xz));
+#pragma unroll
+        for (int s = 0; s < CPW; ++s) {
+            T v[VEC];
+            __builtin_memcpy(v, col[s] + i, sizeof(v));
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) {
+                acc[2 * s] += to_d(v[e]) * to_d(xu[e]);
+                acc[2 * s + 1] += to_d(v[e]) * to_d(xz[e]);
+            }
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < CPW; ++s)
+        if (c0 + s >= c_end) acc[2 * s] = acc[2 * s + 1] = 0.0;
+    wave_tr_reduce<2 * CPW>(acc);
+    if (wave_tr_owner<2 * CPW>()) {
+#pragma unroll
+        for (int t = 0; t < wave_tr_left<2 * CPW>(); ++t) {
+            const int q = wave_tr_col<2 * CPW>(t);   // q = 2 s + e
+            const int c = c0 + q / 2;
+            if (c < c_end) partial[(int64_t)(2 * c + (q & 1)) * nblk + blockIdx.x] = acc[t];
+        }
+    }
+}
+
+// One block: reduce the sweep, complete and rotate column j-1, prepare step j's update.
+// has_z = 0 on the closing step of a cycle (no product was taken): only column j-1 completes.
+__global__ __launch_bounds__(RED_T) void k_dcgs2_reduce(const double* __restrict__ partial, int nblk, int j, int k,
+                                                        int has_z, Ctl* __restrict__ ctl) {
+    if (ctl->done) return;
+    constexpr int LDH = MMAX + 1;
+    constexpr int LDR = MMAX + 1;
+    __shared__ double sums[2 * (MMAX + 2 * KMAX + 1)];
+    __shared__ double red[RED_T / WAVE];
+    __shared__ double Es[KMAX * KMAX];
+    __shared__ double cws[KMAX];
+    __shared__ double wz[KMAX];
+    __shared__ double Qz[MMAX + 1];
+    __shared__ double hcol[MMAX + 2];
+    __shared__ double scal[4];
+    __shared__ int stop;
+    const int tid = threadIdx.x;
+    const int wv = tid / WAVE, lane = tid & (WAVE - 1);
+    const int ncol = j + 2 * k + 1;
+    for (int t = tid; t < k * k; t += RED_T) Es[t] = ctl->E[t];
+    reduce_columns(partial, nblk, 2 * ncol, sums, red);
+    // sums[2 c] = col_c . u, sums[2 c + 1] = col_c . z; columns: V (0..j-1), W, A W, u
+    const double* su = sums;
+    if (wv == 0) {
+        double hh = 0.0;
+        for (int l = lane; l < j; l += WAVE) hh += su[2 * l] * su[2 * l];
+        hh = wave_sum(hh);
+        const double uu = su[2 * (j + 2 * k)];
+        const double nu = (j == 0) ? ctl->beta : sqrt(fmax(uu - hh, 0.0));
+        if (lane == 0) {
+            scal[0] = nu;
+            stop = 0;
+        }
+        if (j >= 1) {
+            // column j-1: first-pass part from the previous step plus the second-pass part
+            double cn = 0.0;
+            for (int l = lane; l < j; l += WAVE) {
+                const double h = ctl->hp[l] + su[2 * l];
+                hcol[l] = h;
+                cn += h * h;
+            }
+            cn = wave_sum(cn) + nu * nu;
+            if (lane == 0) {
+                hcol[j] = nu;
+                const int jc = j - 1;
+                for (int l = 0; l <= j; ++l) ctl->Hs[l + LDH * jc] = hcol[l];
+                double a = hcol[0];
+                for (int l = 0; l < jc; ++l) {
+                    const double c = ctl->cs[l], sn = ctl->sn[l], b = hcol[l + 1];
+                    ctl->R[l + LDR * jc] = c * a + sn * b;
+                    a = -sn * a + c * b;
+                }
+                const double rho = hypot(a, nu);
+                double c = 1.0, sn = 0.0;
+                if (rho != 0.0) {
+                    c = a / rho;
+                    sn = nu / rho;
+                }
+                ctl->cs[jc] = c;
+                ctl->sn[jc] = sn;
+                ctl->R[jc + LDR * jc] = rho;
+                const double gj = ctl->g[jc];
+                const double gn = -sn * gj;
+                ctl->g[jc + 1] = gn;
+                ctl->g[jc] = c * gj;
+                ctl->steps = j;
+                ctl->gimp = fabs(gn);
+                const bool lucky = !(nu > 1e-14 * sqrt(cn));
+                const bool bad = !isfinite(nu) || !isfinite(gn) || !isfinite(rho);
+                if (bad) ctl->nonfinite = 1;
+                if (lucky) ctl->lucky = 1;
+                if (bad || lucky || fabs(gn) <= ctl->stop_abs || j >= ctl->max_steps || !has_z) {
+                    ctl->done = 1;
+                    stop = 1;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    if (stop || !has_z) return;
+    const double nu = scal[0];
+    const double inv = 1.0 / nu;
+    // c = E^{-1} W^T z (the oblique projector's coefficients for z)
+    if (k > 0 && wv == 0) {
+        if (lane < k) wz[lane] = su[2 * (j + lane) + 1];   // W^T z, contiguous for the solve
+        __builtin_amdgcn_wave_barrier();
+        wave_lu_solve(ctl, k, wz, cws, Es);
+    }
+    __syncthreads();
+    // F row j, V_j^T (P z), u^T (P z)
+    for (int c = tid; c < k; c += RED_T) {
+        double f = su[2 * (j + k + c)];           // u . (A W)_c
+        for (int l = 0; l < j; ++l) f -= su[2 * l] * ctl->F[l * KMAX + c];
+        ctl->F[j * KMAX + c] = f * inv;
+        ctl->cw[c] = cws[c];
+    }
+    for (int l = tid; l < j; l += RED_T) {
+        double q = su[2 * l + 1];                  // v_l . z
+        for (int c = 0; c < k; ++c) q -= ctl->F[l * KMAX + c] * cws[c];
+        Qz[l] = q;
+    }
+    if (tid == 0) {
+        double uz = su[2 * (j + 2 * k) + 1];       // u . z
+        for (int c = 0; c < k; ++c) uz -= su[2 * (j + k + c)] * cws[c];
+        scal[1] = uz;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double q = scal[1];
+        for (int l = 0; l < j; ++l) q -= su[2 * l] * Qz[l];
+        Qz[j] = q * inv;                            // v_j . (P z)
+        ctl->inv_nu = inv;
+    }
+    __syncthreads();
+    // first-pass coefficients g of column j and the update coefficients d = H h / nu + g, with
+    // h = V_j^T u the second-pass coefficients of v_j and H the unrotated Hessenberg (j+1 x j)
+    for (int i = tid; i <= j; i += RED_T) {
+        double hh = 0.0;
+        for (int l = (i > 0 ? i - 1 : 0); l < j; ++l) hh += ctl->Hs[i + LDH * l] * su[2 * l];
+        const double g = (Qz[i] - hh) * inv;
+        ctl->hp[i] = g;
+        ctl->dq[i] = hh * inv + g;
+    }
+    for (int l = tid; l < j; l += RED_T) ctl->hr[l] = su[2 * l];
+}
+
+// v_j = (u - V_j hr) / nu; u <- (z - (A W) cw) / nu - V_j dq[0..j) - v_j dq[j]   (row per thread)
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_dcgs2_update(int64_t npad, T* __restrict__ V, int64_t ld, int j,
+                                                        const T* __restrict__ Z, int k, T* __restrict__ u,
+                                                        const T* __restrict__ z, int nblk, const Ctl* __restrict__ ctl) {
+    if (ctl->done) return;
+    __shared__ double hr[MMAX], dq[MMAX + 1], cw[KMAX];
+    for (int t = threadIdx.x; t < j; t += BLOCK) hr[t] = ctl->hr[t];
+    for (int t = threadIdx.x; t <= j; t += BLOCK) dq[t] = ctl->dq[t];
+    for (int t = threadIdx.x; t < k; t += BLOCK) cw[t] = ctl->cw[t];
+    const double inv = ctl->inv_nu;
+    __syncthreads();
+    T* vj = V + (int64_t)j * ld;
+    // VEC consecutive rows per thread, 16-byte loads and stores (npad is a multiple of 64)
+    constexpr int VEC = 16 / sizeof(T);
+    const int64_t nvec = npad / VEC;
+    for (int64_t q = (int64_t)blockIdx.x * BLOCK + threadIdx.x; q < nvec; q += (int64_t)nblk * BLOCK) {
+        const int64_t i = q * VEC;
+        T t[VEC];
+        double a[VEC], b[VEC];
+        __builtin_memcpy(t, u + i, sizeof(t));
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+            a[e] = to_d(t[e]);
+            b[e] = 0.0;
+        }
+#pragma unroll 4
+        for (int l = 0; l < j; ++l) {
+            T v[VEC];
+            __builtin_memcpy(v, V + (int64_t)l * ld + i, sizeof(v));
+            const double h = hr[l], d = dq[l];
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) {
+                a[e] -= to_d(v[e]) * h;
+                b[e] += to_d(v[e]) * d;
+            }
+        }
+        T qs[VEC];
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) qs[e] = (T)(a[e] * inv);
+        __builtin_memcpy(vj + i, qs, sizeof(qs));
+        __builtin_memcpy(t, z + i, sizeof(t));
+        double zc[VEC];
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) zc[e] = to_d(t[e]);
+#pragma unroll 4
+        for (int c = 0; c < k; ++c) {
+            T w[VEC];
+            __builtin_memcpy(w, Z + (int64_t)c * ld + i, sizeof(w));
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) zc[e] -= to_d(w[e]) * cw[c];
+        }
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) t[e] = (T)(zc[e] * inv - b[e] - to_d(qs[e]) * dq[j]);
+        __builtin_memcpy(u + i, t, sizeof(t));
+    }
+}
+
 }  // namespace
 
 template <typename T>
@@ -600,9 +850,54 @@ void launch_givens(const double* partial, int nblk, int j, Ctl* ctl, hipStream_t
     k_givens<<<1, RED_T, 0, st>>>(partial, nblk, j, ctl);
 }
 
-void launch_cycle_init(Ctl* ctl, int max_steps, double stop_abs, hipStream_t st) {
-    k_cycle_init<<<1, 1, 0, st>>>(ctl, max_steps, stop_abs);
+void launch_cycle_init(Ctl* ctl, int max_steps, double stop_abs, hipStream_t st, bool unit_scale) {
+    k_cycle_init<<<1, 1, 0, st>>>(ctl, max_steps, stop_abs, unit_scale ? 1 : 0);
 }
+
+template <typename T>
+void launch_dots2(int64_t npad, int64_t ld, const T* V, int nq, const T* W, const T* Z, int k, const T* u,
+                  const T* z, double* partial, int nblk, Ctl* ctl, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+    const int ncol = nq + 2 * k + 1;
+    // four columns per wavefront up to 64 columns, eight up to 128; at most 16 wavefronts per
+    // launch, and u, z are read again by each further launch
+    const int cpw = ncol > 64 ? 8 : 4;
+    const int nl = (ncol + 16 * cpw - 1) / (16 * cpw);
+    const int per = (ncol + nl - 1) / nl;   // columns per launch, balanced
+    for (int a = 0; a < ncol; a += per) {
+        const int b = (ncol - a) < per ? ncol : a + per;
+        const int nw = (b - a + cpw - 1) / cpw;
+        const bool first = a == 0, last = b == ncol;
+        if (cpw == 8)
+            hipExtLaunchKernelGGL(k_dots2<T, 8>, dim3(nblk), dim3(nw * WAVE), 0, st, first ? ev0 : nullptr,
+                                  last ? ev1 : nullptr, 0, npad, ld, V, nq, W, Z, k, u, z, a, b, partial, nblk,
+                                  static_cast<const Ctl*>(ctl));
+        else
+            hipExtLaunchKernelGGL(k_dots2<T, 4>, dim3(nblk), dim3(nw * WAVE), 0, st, first ? ev0 : nullptr,
+                                  last ? ev1 : nullptr, 0, npad, ld, V, nq, W, Z, k, u, z, a, b, partial, nblk,
+                                  static_cast<const Ctl*>(ctl));
+    }
+}
+template void launch_dots2<double>(int64_t, int64_t, const double*, int, const double*, const double*, int,
+                                   const double*, const double*, double*, int, Ctl*, hipStream_t, hipEvent_t,
+                                   hipEvent_t);
+template void launch_dots2<float>(int64_t, int64_t, const float*, int, const float*, const float*, int,
+                                  const float*, const float*, double*, int, Ctl*, hipStream_t, hipEvent_t,
+                                  hipEvent_t);
+
+void launch_dcgs2_reduce(const double* partial, int nblk, int j, int k, bool has_z, Ctl* ctl, hipStream_t st) {
+    k_dcgs2_reduce<<<1, RED_T, 0, st>>>(partial, nblk, j, k, has_z ? 1 : 0, ctl);
+}
+
+template <typename T>
+void launch_dcgs2_update(int64_t npad, T* V, int64_t ld, int j, const T* Z, int k, T* u, const T* z, int nblk,
+                         const Ctl* ctl, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+    hipExtLaunchKernelGGL(k_dcgs2_update<T>, dim3(nblk), dim3(BLOCK), 0, st, ev0, ev1, 0, npad, V, ld, j, Z, k, u, z,
+                          nblk, ctl);
+}
+template void launch_dcgs2_update<double>(int64_t, double*, int64_t, int, const double*, int, double*,
+                                          const double*, int, const Ctl*, hipStream_t, hipEvent_t, hipEvent_t);
+template void launch_dcgs2_update<float>(int64_t, float*, int64_t, int, const float*, int, float*, const float*, int,
+                                         const Ctl*, hipStream_t, hipEvent_t, hipEvent_t);
 
 void launch_cycle_solve(Ctl* ctl, hipStream_t st) { k_cycle_solve<<<1, WAVE, 0, st>>>(ctl); }
 

@@ -139,7 +139,7 @@ __global__ __launch_bounds__(BLOCK) void k_spmv_arnoldi(int64_t n, const int32_t
     acc = group_sum<LPR>(acc);
     if (active && sub == 0) {
         y[row] = (T)(s * acc);
-        vout[row] = (T)(s * to_d(win[row]));
+        if (vout) vout[row] = (T)(s * to_d(win[row]));
     }
 }
 

@@ -65,8 +65,20 @@ void launch_update_norm(int64_t npad, const T* V, int64_t ld, int nv, T* w, cons
                         hipEvent_t ev1 = nullptr);
 // column j of H: reduce ||w||^2, Givens update, stop test, next scale
 void launch_givens(const double* partial, int nblk, int j, Ctl* ctl, hipStream_t st);
-// start of a cycle: g = beta e1 with beta = ctl->rnorm, done/steps reset
-void launch_cycle_init(Ctl* ctl, int max_steps, double stop_abs, hipStream_t st);
+// start of a cycle: g = beta e1 with beta = ctl->rnorm, done/steps reset; the first Arnoldi
+// product scales its input by 1/beta, or by 1 with unit_scale (delayed reorthogonalisation)
+void launch_cycle_init(Ctl* ctl, int max_steps, double stop_abs, hipStream_t st, bool unit_scale = false);
+// Delayed reorthogonalisation, step j: the sweep over [V_j (nq = j columns), W, A W, u] dotted
+// with u and z; the one-block reduction (completes and rotates column j-1, sets done, prepares
+// step j; has_z = false on the closing step); the update sweep (v_j and the next candidate u).
+template <typename T>
+void launch_dots2(int64_t npad, int64_t ld, const T* V, int nq, const T* W, const T* Z, int k, const T* u,
+                  const T* z, double* partial, int nblk, Ctl* ctl, hipStream_t st, hipEvent_t ev0 = nullptr,
+                  hipEvent_t ev1 = nullptr);
+void launch_dcgs2_reduce(const double* partial, int nblk, int j, int k, bool has_z, Ctl* ctl, hipStream_t st);
+template <typename T>
+void launch_dcgs2_update(int64_t npad, T* V, int64_t ld, int j, const T* Z, int k, T* u, const T* z, int nblk,
+                         const Ctl* ctl, hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 // y = R^{-1} g (ctl->steps unknowns)
 void launch_cycle_solve(Ctl* ctl, hipStream_t st);
 // x[i] += dinv[i] * sum_{c < steps} V[i, c] y[c]   (dinv nullable)

@@ -52,7 +52,7 @@ class Config(ctypes.Structure):
     _fields_ = [
         ("restart_m", c_int32), ("recycle_k", c_int32), ("snapshots_s", c_int32), ("svd_interval", c_int32),
         ("method", c_int32), ("precond", c_int32), ("precision", c_int32), ("max_iters", c_int32),
-        ("select", c_int32), ("reserved", c_int32), ("inner_tol", c_double),
+        ("select", c_int32), ("ortho", c_int32), ("inner_tol", c_double),
     ]
 
 
@@ -171,10 +171,13 @@ def _check(status, allow=(OK,)):
     raise RsolveError(status, f"{lib.rsolve_status_string(status).decode()}: {lib.rsolve_last_error().decode()}")
 
 
+_ORTHOS = {"cgs2": 0, "dcgs2": 1}
+
+
 def make_config(restart_m=30, recycle_k=0, snapshots_s=0, svd_interval=1, method="aug_oblique", precond="none",
-                precision="fp64", max_iters=10000, inner_tol=1e-5) -> Config:
+                precision="fp64", max_iters=10000, inner_tol=1e-5, ortho="cgs2") -> Config:
     return Config(restart_m, recycle_k, snapshots_s, svd_interval, _METHODS[method], _PRECONDS[precond],
-                  _PRECISIONS[precision], max_iters, 0, 0, float(inner_tol))
+                  _PRECISIONS[precision], max_iters, 0, _ORTHOS[ortho], float(inner_tol))
 
 
 def workspace_bytes(cfg: Config, n: int, nnz_max: int) -> int:
@@ -320,7 +323,11 @@ class Sequence:
         arr = (ProfEntry * cap)()
         cnt = c_int32()
         _check(self.lib.rsolve_profile_read(self.handle, arr, cap, byref(cnt), 1 if reset else 0))
-        return [{"kernel": PROF_KERNELS[arr[i].kernel], "variant": arr[i].variant, "launches": arr[i].launches,
+        # with the delayed scheme, kind 1 is the two-vector sweep and kind 2 the combined update
+        names = dict(PROF_KERNELS)
+        if self.cfg.ortho == 1:
+            names.update({1: "dots2", 2: "dcgs2_update"})
+        return [{"kernel": names[arr[i].kernel], "variant": arr[i].variant, "launches": arr[i].launches,
                  "ms": arr[i].ms, "bytes": arr[i].bytes} for i in range(min(cnt.value, cap))]
 
     def close(self):

@@ -153,6 +153,16 @@ def test_invalid_configs_rejected(lib, bad):
     assert rc == rsolve.E_INVALID and not h.value
 
 
+def test_ortho_field(lib):
+    """The orthogonalisation scheme is 0 (CGS2) or 1 (delayed); anything else is refused."""
+    ok = rsolve.make_config(restart_m=30, ortho="dcgs2")
+    assert ok.ortho == 1 and rsolve.workspace_bytes(ok, 100, 500) > 0
+    for v in (2, -1):
+        cfg = rsolve.make_config(restart_m=30)
+        cfg.ortho = v
+        assert rsolve.workspace_bytes(cfg, 100, 500) == 0
+
+
 def test_bad_sizes_and_workspace(lib):
     cfg = rsolve.make_config()
     assert rsolve.workspace_bytes(cfg, 0, 10) == 0

@@ -19,6 +19,9 @@ def _t(a, dev):
     dict(restart_m=30, recycle_k=8, snapshots_s=12, precond="jacobi"),
     dict(restart_m=50, recycle_k=16, snapshots_s=32, precond="jacobi", precision="fp32_ir", inner_tol=1e-5),
     dict(restart_m=10, recycle_k=4, snapshots_s=6, precond="none"),
+    dict(restart_m=30, recycle_k=8, snapshots_s=12, precond="jacobi", ortho="dcgs2"),
+    dict(restart_m=50, recycle_k=16, snapshots_s=32, precond="jacobi", precision="fp32_ir", inner_tol=1e-5,
+         ortho="dcgs2"),
 ])
 def test_graph_replay_equals_eager(gpu_ctx, kw):
     import torch
