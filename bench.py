@@ -112,7 +112,7 @@ def run_solver(gasm, u0, systems, warmup, steps, tol, cfg, dev, profile=False, l
     seq = rsolve.Sequence(pat.n, pat.nnz, device=dev, **cfg)
     # SpMV shape: timed on the first system before anything else (not part of the timed region)
     shape, _, _ = autotune.tune_sequence(seq, gasm.row_ptr, gasm.col_idx, systems[0][0], cache_path=None, reps=10)
-    log(f"{label} SpMV shape: {shape['lanes_per_row']} lanes/row, {shape['vec']} entries/lane, "
+    log(f"{label} SpMV shape: {shape['format']}, {shape['lanes_per_row']} lanes/row, {shape['vec']} entries/lane, "
         f"remap {shape['xcd_remap']}: {shape['us']:.1f} us (default {shape['default_us']:.1f} us)")
     seq.graphs(graphs)
     x_prev = u0

@@ -290,32 +290,49 @@ int rsolve_graph_counts(rsolve_seq* s, int64_t* captures, int64_t* launches);
 
 /* ---- SpMV shape of the Arnoldi product, and its autotuner ---- */
 
+#define RSOLVE_SPMV_CSR    0   /* the caller's CSR pattern with the sequence's values */
+#define RSOLVE_SPMV_BANDED 1   /* the sequence's banded padded copy: every row padded to whole
+                                  chunks of `vec` entries, columns stored as 16-bit offsets
+                                  col - row, the entries of each round of `lanes_per_row` chunks
+                                  dealt round-robin over the row's lanes.  Needs |col - row| <=
+                                  32767 for every entry; built once per pattern, values copied
+                                  into it once per solve; (w + 2) bytes per entry instead of
+                                  (w + 4) (w = 4 in FP32_IR mode, else 8) */
+
 typedef struct {
-    int32_t lanes_per_row;  /* lanes of a wavefront that share one CSR row: 2, 4, 8, 16 or 32 */
-    int32_t vec;            /* CSR entries a lane loads at once: 4 or 8 (one 16/32-byte load of
-                               indices and one of values), or 1 (four strided scalar loads) */
+    int32_t lanes_per_row;  /* lanes of a wavefront that share one row: 2, 4, 8, 16 or 32 for CSR;
+                               2, 4 or 8 for BANDED */
+    int32_t vec;            /* CSR: entries a lane loads at once: 4 or 8 (one 16/32-byte load of
+                               indices and one of values), or 1 (four strided scalar loads);
+                               BANDED: entries per chunk, 4 or 8 */
     int32_t xcd_remap;      /* 1: consecutive row blocks go to the same accelerator die */
     int32_t user_set;       /* rsolve_get_spmv_shape: 1 if set by rsolve_set_spmv_shape */
+    int32_t format;         /* RSOLVE_SPMV_CSR or RSOLVE_SPMV_BANDED */
+    int32_t reserved;       /* must be 0 */
     double  us;             /* rsolve_tune_spmv: mean time of one product, microseconds */
 } rsolve_spmv_shape;
 
 /*
  * Time the Arnoldi product w = A D^{-1} v of this sequence (the kernel of section 3, in the
- * sequence's precision: float32 values for FP32_IR, else float64) for every shape: lanes per row
- * {2, 4, 8, 16, 32} x entries per lane {1, 4, 8} x block order {plain, XCD-aware}, `reps` timed
- * launches each (HIP events) after one warm-up launch, on the sequence's own stream and buffers.
- * Writes up to `cap` results in ascending time to `out` (host) and the number of candidates to
- * *count; does not change the sequence's shape.  A's pattern is checked first (E_INVALID if
- * corrupt).  Synchronous.  Errors: E_INVALID, E_DEVICE.
+ * sequence's precision: float32 values for FP32_IR, else float64) for every shape: CSR with
+ * lanes per row {2, 4, 8, 16, 32} x entries per lane {1, 4, 8}, and, when the pattern fits it,
+ * BANDED with lanes {2, 4, 8} x chunk {4, 8}; each with block order {plain, XCD-aware}.  `reps`
+ * timed launches each (HIP events) after one warm-up launch, on the sequence's own stream and
+ * buffers.  Writes up to `cap` results in ascending time to `out` (host) and the number of
+ * candidates to *count; does not change the sequence's shape.  A's pattern is checked first
+ * (E_INVALID if corrupt).  Synchronous.  Errors: E_INVALID, E_DEVICE.
  */
 int rsolve_tune_spmv(rsolve_seq* s, const rsolve_csr* A, int32_t reps, rsolve_spmv_shape* out, int32_t cap,
                      int32_t* count);
 
-/* Use `shape` (lanes_per_row, vec, xcd_remap; the other fields are ignored) for this sequence's
- * Arnoldi products from now on.  E_INVALID for a value outside the sets above. */
+/* Use `shape` (format, lanes_per_row, vec, xcd_remap; user_set and us are ignored) for this
+ * sequence's Arnoldi products from now on.  E_INVALID for a value outside the sets above; a
+ * solve with BANDED on a pattern that does not fit it fails with E_INVALID. */
 int rsolve_set_spmv_shape(rsolve_seq* s, const rsolve_spmv_shape* shape);
 
-/* The shape in use (chosen from the mean row length unless set). */
+/* The shape in use.  Unless set, it is chosen when a pattern is checked: BANDED with 8-entry
+ * chunks and 4 lanes per row when the pattern fits it and has 12 or more entries per row on
+ * average, else CSR with 4 entries per lane and lanes from the mean row length. */
 int rsolve_get_spmv_shape(rsolve_seq* s, rsolve_spmv_shape* shape);
 
 /* Destroy the handle.  Does not free the workspace (the caller owns it). */

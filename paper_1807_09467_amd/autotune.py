@@ -1,8 +1,8 @@
 """SpMV shape autotuner with a JSON cache.
 
 On first use for a (device, precision, n, nnz) the sequence's Arnoldi product is timed for
-every shape the library offers (rsolve_tune_spmv: lanes per row x entries per lane x block
-order, HIP events on the sequence's own buffers) and the fastest is stored; later sequences of
+every shape the library offers (rsolve_tune_spmv: storage format x lanes per row x entries per
+lane x block order, HIP events on the sequence's own buffers) and the fastest is stored; later sequences of
 the same size reuse it without timing.  The kernel work and its timing run in the library;
 this module only keys, stores and applies the result.
 """
@@ -46,17 +46,17 @@ def tune_sequence(seq, row_ptr, col_idx, val, cache_path=DEFAULT_CACHE, reps=20,
     table = _load(cache_path) if cache_path else {}
     if key in table and not retune:
         sh = table[key]
-        seq.set_spmv_shape(sh["lanes_per_row"], sh["vec"], sh["xcd_remap"])
+        seq.set_spmv_shape(sh["lanes_per_row"], sh["vec"], sh["xcd_remap"], sh.get("format", "csr"))
         return sh, "cache", []
     t0 = time.perf_counter()
     res = seq.tune_spmv(row_ptr, col_idx, val, reps=reps)
     best = dict(res[0])
     best["tuned_in_s"] = time.perf_counter() - t0
     default = seq.spmv_shape()
-    match = [r for r in res if (r["lanes_per_row"], r["vec"], r["xcd_remap"]) ==
-             (default["lanes_per_row"], default["vec"], default["xcd_remap"])]
+    fields = ("format", "lanes_per_row", "vec", "xcd_remap")
+    match = [r for r in res if all(r[f] == default[f] for f in fields)]
     best["default_us"] = match[0]["us"] if match else None
-    seq.set_spmv_shape(best["lanes_per_row"], best["vec"], best["xcd_remap"])
+    seq.set_spmv_shape(best["lanes_per_row"], best["vec"], best["xcd_remap"], best["format"])
     if cache_path:
         table = _load(cache_path)
         table[key] = best

@@ -11,6 +11,7 @@ constexpr int MMAX = 128;        // largest restart length
 constexpr int KMAX = 64;         // largest recycle dimension
 constexpr int SMAX = 64;         // largest snapshot ring
 constexpr int BLOCK = 256;       // threads per block of the streaming kernels
+constexpr int BP_MAX_OFFSET = 32767;   // largest |col - row| of the banded padded format
 constexpr int NBLK_MAX = 2048;   // largest grid of the split-n reductions
 constexpr int TSQR_PANEL = 256;  // rows per Householder panel
 constexpr int64_t GRAM_PARTIAL = 256LL * KMAX * KMAX;  // doubles of a Gram partial buffer

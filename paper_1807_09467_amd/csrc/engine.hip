@@ -142,7 +142,15 @@ struct rsolve_seq {
     float* w32[2] = {nullptr, nullptr};
     int nblk = 1, gblk = 1, lpr = 8, cus = 256;
     int svec = 4, sremap = 0;      // Arnoldi SpMV shape (entries per lane, XCD-aware block order)
-    bool shape_set = false;        // lpr / svec / sremap chosen by the caller (rsolve_set_spmv_shape)
+    int sfmt = RSOLVE_SPMV_CSR;    // Arnoldi SpMV storage (CSR or banded padded)
+    bool shape_set = false;        // lpr / svec / sremap / sfmt chosen by the caller (rsolve_set_spmv_shape)
+    // banded padded copy of the matrix for the Arnoldi product (RSOLVE_SPMV_BANDED)
+    int32_t* bp_p = nullptr;       // chunk offsets, n + 1
+    int16_t* bp_off = nullptr;     // column offsets col - row, bp_cap
+    void* bp_val = nullptr;        // values (float in FP32_IR mode, else double), bp_cap
+    int64_t bp_cap = 0;            // 0: the format is not available for this size
+    bool band_ok = false;          // the current pattern fits the 16-bit offsets
+    int bp_e = 0, bp_l = 0;        // chunk size and lanes the copy is laid out for (0: not built)
     const int32_t* pat_rp = nullptr;
     const int32_t* pat_ci = nullptr;
     int64_t pat_nnz = -1;
@@ -167,13 +175,15 @@ struct rsolve_seq {
     int64_t pcnt[NPK][NVAR];
     // captured Arnoldi chunks: one graph per chunk, keyed by everything its kernels bake in
     struct GraphKey {
-        int j0, j1, k, ir, lpr, vec, remap, dg, allowed;
+        int j0, j1, k, ir, lpr, vec, remap, fmt, dg, allowed;
         const void* rp;
         const void* ci;
+        const void* off;
         const void* vals;
         bool operator<(const GraphKey& o) const {
-            return std::tie(j0, j1, k, ir, lpr, vec, remap, dg, allowed, rp, ci, vals) <
-                   std::tie(o.j0, o.j1, o.k, o.ir, o.lpr, o.vec, o.remap, o.dg, o.allowed, o.rp, o.ci, o.vals);
+            return std::tie(j0, j1, k, ir, lpr, vec, remap, fmt, dg, allowed, rp, ci, off, vals) <
+                   std::tie(o.j0, o.j1, o.k, o.ir, o.lpr, o.vec, o.remap, o.fmt, o.dg, o.allowed, o.rp, o.ci, o.off,
+                            o.vals);
         }
     };
     bool graphs_on = false;
@@ -215,6 +225,13 @@ size_t layout(rsolve_seq* s, const rsolve_config& c, int64_t n, int64_t nnz_max,
     double* dinv = jac ? cv.take<double>((size_t)ld) : nullptr;
     double* vals = (jac && !ir) ? cv.take<double>((size_t)nnz_max) : nullptr;
     float* vals32 = ir ? cv.take<float>((size_t)nnz_max) : nullptr;
+    // the banded copy holds every row padded to whole chunks of at most 8 entries
+    const int64_t bp_cap = (nnz_max + 7 * n < (int64_t)INT32_MAX) ? align_up(nnz_max + 7 * n, 64) : 0;
+    int32_t* bp_p = bp_cap ? cv.take<int32_t>((size_t)n + 1) : nullptr;
+    int16_t* bp_off = bp_cap ? cv.take<int16_t>((size_t)bp_cap) : nullptr;
+    void* bp_val = bp_cap ? (ir ? static_cast<void*>(cv.take<float>((size_t)bp_cap))
+                                : static_cast<void*>(cv.take<double>((size_t)bp_cap)))
+                          : nullptr;
     double* partial = cv.take<double>((size_t)NBLK_MAX * (MMAX + 2 * KMAX + 1));
     double* gpart = cv.take<double>((size_t)GRAM_PARTIAL);
     int64_t tsq_rows = 0, tsq_ld = 0;
@@ -247,6 +264,10 @@ size_t layout(rsolve_seq* s, const rsolve_config& c, int64_t n, int64_t nnz_max,
         s->vals32 = vals32;
         s->partial = partial;
         s->gpart = gpart;
+        s->bp_p = bp_p;
+        s->bp_off = bp_off;
+        s->bp_val = bp_val;
+        s->bp_cap = bp_cap;
         s->tsq[0] = t0;
         s->tsq[1] = t1;
         s->tsq_ld = tsq_ld;
@@ -264,7 +285,7 @@ int validate_pattern(rsolve_seq* s, const rsolve_csr* A) {
     HIP_TRY(hipMemsetAsync(s->err, 0, sizeof(int32_t) * 8, stm));
     launch_validate(n, A->nnz, A->row_ptr, A->col_idx, s->diag_pos, s->err, stm);
     HIP_TRY(hipGetLastError());
-    HIP_TRY(hipMemcpyAsync(s->herr, s->err, sizeof(int32_t) * 4, hipMemcpyDeviceToHost, stm));
+    HIP_TRY(hipMemcpyAsync(s->herr, s->err, sizeof(int32_t) * 5, hipMemcpyDeviceToHost, stm));
     HIP_TRY(hipStreamSynchronize(stm));
     if (s->herr[0] || s->herr[1] || s->herr[2] || s->herr[3]) {
         set_err("corrupt CSR: row_ptr=%d col_range=%d col_order=%d no_diagonal=%d", s->herr[0], s->herr[1],
@@ -275,8 +296,74 @@ int validate_pattern(rsolve_seq* s, const rsolve_csr* A) {
     s->pat_ci = A->col_idx;
     s->pat_nnz = A->nnz;
     s->pat_ok = true;
-    if (!s->shape_set) s->lpr = pick_lpr(n, A->nnz);
+    s->band_ok = s->bp_cap > 0 && s->herr[4] == 0;
+    s->bp_e = s->bp_l = 0;   // the banded copy (if used) is laid out again for this pattern
+    if (!s->shape_set) {
+        // banded padded format with 8-entry chunks and 4 lanes per row for finite-element rows of
+        // about a dozen entries or more; CSR otherwise
+        if (s->band_ok && (double)A->nnz >= 12.0 * (double)n) {
+            s->sfmt = RSOLVE_SPMV_BANDED;
+            s->svec = 8;
+            s->lpr = 4;
+        } else {
+            s->sfmt = RSOLVE_SPMV_CSR;
+            s->svec = 4;
+            s->lpr = pick_lpr(n, A->nnz);
+        }
+        s->sremap = 0;
+    }
     return RSOLVE_OK;
+}
+
+// The matrix operand of the Arnoldi product: CSR (the caller's pattern and a value array) or the
+// sequence's banded padded copy.
+struct SpOp {
+    int fmt;
+    const int32_t* rp;    // CSR row pointers, or the banded chunk offsets
+    const int32_t* ci;    // CSR column indices (null for the banded copy)
+    const int16_t* off;   // banded column offsets (null for CSR)
+    const void* vals;
+};
+
+// Lays the banded copy out for the current pattern and shape if needed, then writes this
+// matrix's values (times D^{-1} by column when dinv is given) into it.
+int bp_prepare(rsolve_seq* s, const rsolve_csr* A, const double* dinv, bool f32) {
+    if (!s->band_ok) {
+        set_err("the banded SpMV format needs |col - row| <= %d for every entry and room for the padding",
+                BP_MAX_OFFSET);
+        return RSOLVE_E_INVALID;
+    }
+    hipStream_t stm = s->stream;
+    if (s->bp_e != s->svec || s->bp_l != s->lpr) {
+        if (bp_setup(s->n, A->row_ptr, A->col_idx, s->svec, s->lpr, s->bp_p, s->bp_off, s->bp_val, f32, stm) != 0) {
+            set_err("invalid banded SpMV shape (entries %d, lanes %d)", s->svec, s->lpr);
+            return RSOLVE_E_INVALID;
+        }
+        s->bp_e = s->svec;
+        s->bp_l = s->lpr;
+    }
+    if (f32) launch_bp_values<float>(s->n, A->row_ptr, A->col_idx, A->val, dinv, s->bp_p, s->svec, s->lpr,
+                                     static_cast<float*>(s->bp_val), stm);
+    else launch_bp_values<double>(s->n, A->row_ptr, A->col_idx, A->val, dinv, s->bp_p, s->svec, s->lpr,
+                                  static_cast<double*>(s->bp_val), stm);
+    return RSOLVE_OK;
+}
+
+// Algorithmic bytes of one Arnoldi product (entries counted without padding), w = value width.
+double spmv_bytes(const rsolve_seq* s, double w, bool vout) {
+    const double nn = (double)s->n, nz = (double)s->nnz_cur;
+    const double idx = s->sfmt == RSOLVE_SPMV_BANDED ? 2.0 : 4.0;
+    return (w + idx) * nz + 4.0 * (nn + 1.0) + (vout ? 3.0 : 2.0) * w * nn;
+}
+
+template <typename T>
+void arnoldi_product(rsolve_seq* s, const SpOp& op, const T* win, T* vout, T* y, hipEvent_t e0, hipEvent_t e1) {
+    if (op.fmt == RSOLVE_SPMV_BANDED)
+        launch_spmv_bp<T>(s->svec, s->lpr, s->sremap, s->n, op.rp, op.off, static_cast<const T*>(op.vals), win, vout,
+                          y, s->ctl, s->stream, e0, e1);
+    else
+        launch_spmv_arnoldi<T>(s->lpr, s->svec, s->sremap, s->n, op.rp, op.ci, static_cast<const T*>(op.vals), win,
+                               vout, y, s->ctl, s->stream, e0, e1);
 }
 
 // The executable graph of one Arnoldi chunk (kernel launches only, captured on the sequence's
@@ -372,8 +459,7 @@ void prof_collect(rsolve_seq* s, int steps) {
 
 // One Arnoldi step j of the current cycle on storage type T.
 template <typename T>
-void arnoldi_step(rsolve_seq* s, int j, const int32_t* rp, const int32_t* ci, const T* vals, T* V, T* const* wbuf,
-                  const T* Wt, const T* Zt, int k) {
+void arnoldi_step(rsolve_seq* s, int j, const SpOp& op, T* V, T* const* wbuf, const T* Wt, const T* Zt, int k) {
     hipStream_t st = s->stream;
     const int64_t ld = s->ld;
     T* win = wbuf[j & 1];
@@ -381,8 +467,8 @@ void arnoldi_step(rsolve_seq* s, int j, const int32_t* rp, const int32_t* ci, co
     T* vj = V + (int64_t)j * ld;
     const double w = sizeof(T), nn = (double)s->n;
     {
-        ProfEv pe(s, RSOLVE_PROF_SPMV, j, 0, (w + 4.0) * (double)s->nnz_cur + 4.0 * (nn + 1.0) + 3.0 * w * nn);
-        launch_spmv_arnoldi<T>(s->lpr, s->svec, s->sremap, s->n, rp, ci, vals, win, vj, wout, s->ctl, st, pe.e0,
+        ProfEv pe(s, RSOLVE_PROF_SPMV, j, 0, spmv_bytes(s, w, true));
+        arnoldi_product<T>(s, op, win, vj, wout, pe.e0,
                                pe.e1);
     }
     const int nv = j + 1;
@@ -417,8 +503,8 @@ void arnoldi_step(rsolve_seq* s, int j, const int32_t* rp, const int32_t* ci, co
 // (skipped on the closing step j = allowed), the sweep over [V_j, W, A W, u] with u and z, the
 // reduction that completes column j-1, and the update sweep writing v_j and the next candidate.
 template <typename T>
-void dcgs2_step(rsolve_seq* s, int j, int allowed, const int32_t* rp, const int32_t* ci, const T* vals, T* V,
-                T* const* wbuf, const T* Wt, const T* Zt, int k) {
+void dcgs2_step(rsolve_seq* s, int j, int allowed, const SpOp& op, T* V, T* const* wbuf, const T* Wt, const T* Zt,
+                int k) {
     hipStream_t st = s->stream;
     const int64_t ld = s->ld;
     T* u = wbuf[0];
@@ -426,9 +512,8 @@ void dcgs2_step(rsolve_seq* s, int j, int allowed, const int32_t* rp, const int3
     const bool has_z = j < allowed;
     const double w = sizeof(T), nn = (double)s->n;
     if (has_z) {
-        ProfEv pe(s, RSOLVE_PROF_SPMV, j, 0, (w + 4.0) * (double)s->nnz_cur + 4.0 * (nn + 1.0) + 2.0 * w * nn);
-        launch_spmv_arnoldi<T>(s->lpr, s->svec, s->sremap, s->n, rp, ci, vals, u, nullptr, z, s->ctl, st, pe.e0,
-                               pe.e1);
+        ProfEv pe(s, RSOLVE_PROF_SPMV, j, 0, spmv_bytes(s, w, false));
+        arnoldi_product<T>(s, op, u, nullptr, z, pe.e0, pe.e1);
     }
     const int ncol = j + 2 * k + 1;
     const int cpw = ncol > 64 ? 8 : 4;   // as the sweep's launcher chooses
@@ -604,12 +689,15 @@ int rsolve_profile_read(rsolve_seq* s, rsolve_prof_entry* out, int32_t cap, int3
 
 int rsolve_set_spmv_shape(rsolve_seq* s, const rsolve_spmv_shape* shape) {
     if (!s || !shape) return RSOLVE_E_INVALID;
-    const int l = shape->lanes_per_row, v = shape->vec;
-    if ((l != 2 && l != 4 && l != 8 && l != 16 && l != 32) || (v != 1 && v != 4 && v != 8) ||
-        (shape->xcd_remap != 0 && shape->xcd_remap != 1)) {
-        set_err("invalid SpMV shape (lanes %d, vec %d, remap %d)", l, v, shape->xcd_remap);
+    const int l = shape->lanes_per_row, v = shape->vec, f = shape->format;
+    const bool csr_ok = f == RSOLVE_SPMV_CSR && (l == 2 || l == 4 || l == 8 || l == 16 || l == 32) &&
+                        (v == 1 || v == 4 || v == 8);
+    const bool bp_ok = f == RSOLVE_SPMV_BANDED && (l == 2 || l == 4 || l == 8) && (v == 4 || v == 8);
+    if (!(csr_ok || bp_ok) || (shape->xcd_remap != 0 && shape->xcd_remap != 1) || shape->reserved != 0) {
+        set_err("invalid SpMV shape (format %d, lanes %d, vec %d, remap %d)", f, l, v, shape->xcd_remap);
         return RSOLVE_E_INVALID;
     }
+    s->sfmt = f;
     s->lpr = l;
     s->svec = v;
     s->sremap = shape->xcd_remap;
@@ -619,11 +707,7 @@ int rsolve_set_spmv_shape(rsolve_seq* s, const rsolve_spmv_shape* shape) {
 
 int rsolve_get_spmv_shape(rsolve_seq* s, rsolve_spmv_shape* shape) {
     if (!s || !shape) return RSOLVE_E_INVALID;
-    shape->lanes_per_row = s->lpr;
-    shape->vec = s->svec;
-    shape->xcd_remap = s->sremap;
-    shape->user_set = s->shape_set ? 1 : 0;
-    shape->us = 0.0;
+    *shape = rsolve_spmv_shape{s->lpr, s->svec, s->sremap, s->shape_set ? 1 : 0, s->sfmt, 0, 0.0};
     return RSOLVE_OK;
 }
 
@@ -639,7 +723,7 @@ int rsolve_tune_spmv(rsolve_seq* s, const rsolve_csr* A, int32_t reps, rsolve_sp
     HIP_TRY(hipSetDevice(s->device));
     hipStream_t stm = s->stream;
     // the candidates read A's indices: check the pattern first, as a solve would (this also
-    // picks the default lanes per row, unless the caller set a shape)
+    // picks the default shape, unless the caller set one)
     const int vrc = validate_pattern(s, A);
     if (vrc != RSOLVE_OK) return vrc;
     s->pat_ok = false;     // the next solve checks again (the caller did not promise the pattern)
@@ -655,28 +739,59 @@ int rsolve_tune_spmv(rsolve_seq* s, const rsolve_csr* A, int32_t reps, rsolve_sp
         return RSOLVE_E_DEVICE;
     }
     std::vector<rsolve_spmv_shape> res;
-    const int lanes[] = {2, 4, 8, 16, 32}, vecs[] = {1, 4, 8};
     hipError_t err = hipSuccess;
-    for (int l : lanes)
-        for (int v : vecs)
-            for (int rm = 0; rm < 2 && err == hipSuccess; ++rm) {
-                auto run = [&] {
-                    if (ir)
-                        launch_spmv_arnoldi<float>(l, v, rm, n, A->row_ptr, A->col_idx, s->vals32, s->w32[0], s->V32,
-                                                   s->w32[1], s->ctl, stm);
-                    else
-                        launch_spmv_arnoldi<double>(l, v, rm, n, A->row_ptr, A->col_idx, A->val, s->wb[0], s->V,
-                                                    s->wb[1], s->ctl, stm);
-                };
-                run();   // warm-up
-                err = hipEventRecord(e0, stm);
-                for (int r = 0; r < reps && err == hipSuccess; ++r) run();
-                if (err == hipSuccess) err = hipEventRecord(e1, stm);
-                if (err == hipSuccess) err = hipEventSynchronize(e1);
-                float ms = 0.f;
-                if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
-                if (err == hipSuccess) err = hipGetLastError();
-                res.push_back(rsolve_spmv_shape{l, v, rm, 0, 1e3 * (double)ms / reps});
+    auto time_it = [&](auto&& run, rsolve_spmv_shape sh) {
+        if (err != hipSuccess) return;
+        run();   // warm-up
+        err = hipEventRecord(e0, stm);
+        for (int r = 0; r < reps && err == hipSuccess; ++r) run();
+        if (err == hipSuccess) err = hipEventRecord(e1, stm);
+        if (err == hipSuccess) err = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+        if (err == hipSuccess) err = hipGetLastError();
+        sh.us = 1e3 * (double)ms / reps;
+        res.push_back(sh);
+    };
+    for (int l : {2, 4, 8, 16, 32})
+        for (int v : {1, 4, 8})
+            for (int rm = 0; rm < 2; ++rm)
+                time_it(
+                    [&] {
+                        if (ir)
+                            launch_spmv_arnoldi<float>(l, v, rm, n, A->row_ptr, A->col_idx, s->vals32, s->w32[0],
+                                                       s->V32, s->w32[1], s->ctl, stm);
+                        else
+                            launch_spmv_arnoldi<double>(l, v, rm, n, A->row_ptr, A->col_idx, A->val, s->wb[0], s->V,
+                                                        s->wb[1], s->ctl, stm);
+                    },
+                    rsolve_spmv_shape{l, v, rm, 0, RSOLVE_SPMV_CSR, 0, 0.0});
+    if (s->band_ok)
+        for (int l : {2, 4, 8})
+            for (int v : {4, 8}) {
+                // lay the copy out for this shape and fill it with A's values
+                if (err == hipSuccess && bp_setup(n, A->row_ptr, A->col_idx, v, l, s->bp_p, s->bp_off, s->bp_val, ir,
+                                                  stm) == 0) {
+                    s->bp_e = v;
+                    s->bp_l = l;
+                    if (ir) launch_bp_values<float>(n, A->row_ptr, A->col_idx, A->val, nullptr, s->bp_p, v, l,
+                                                    static_cast<float*>(s->bp_val), stm);
+                    else launch_bp_values<double>(n, A->row_ptr, A->col_idx, A->val, nullptr, s->bp_p, v, l,
+                                                  static_cast<double*>(s->bp_val), stm);
+                }
+                for (int rm = 0; rm < 2; ++rm)
+                    time_it(
+                        [&] {
+                            if (ir)
+                                launch_spmv_bp<float>(v, l, rm, n, s->bp_p, s->bp_off,
+                                                      static_cast<const float*>(s->bp_val), s->w32[0], s->V32,
+                                                      s->w32[1], s->ctl, stm);
+                            else
+                                launch_spmv_bp<double>(v, l, rm, n, s->bp_p, s->bp_off,
+                                                       static_cast<const double*>(s->bp_val), s->wb[0], s->V,
+                                                       s->wb[1], s->ctl, stm);
+                        },
+                        rsolve_spmv_shape{l, v, rm, 0, RSOLVE_SPMV_BANDED, 0, 0.0});
             }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -767,16 +882,21 @@ int rsolve_solve(rsolve_seq* s, const rsolve_csr* A, const double* b, const doub
     launch_finish_norm(s->partial, s->nblk, s->ctl, 1, stm);
 
     // a1: Jacobi scaling A D^{-1} (and the FP32 copy in mixed mode)
-    const double* kv64 = A->val;
-    if (jac) {
-        launch_diag_inv(n, s->diag_pos, A->val, s->dinv, stm);
-        if (ir) launch_scale_values(A->nnz, A->col_idx, A->val, s->dinv, nullptr, s->vals32, stm);
-        else {
-            launch_scale_values(A->nnz, A->col_idx, A->val, s->dinv, s->vals, nullptr, stm);
-            kv64 = s->vals;
-        }
+    // into the Arnoldi product's operand: the banded copy, or CSR values (the caller's FP64
+    // values when neither scaling nor conversion is needed)
+    if (jac) launch_diag_inv(n, s->diag_pos, A->val, s->dinv, stm);
+    const double* dv = jac ? s->dinv : nullptr;
+    SpOp op{RSOLVE_SPMV_CSR, A->row_ptr, A->col_idx, nullptr, A->val};
+    if (s->sfmt == RSOLVE_SPMV_BANDED) {
+        const int brc = bp_prepare(s, A, dv, ir);
+        if (brc) return brc;
+        op = SpOp{RSOLVE_SPMV_BANDED, s->bp_p, nullptr, s->bp_off, s->bp_val};
     } else if (ir) {
-        launch_scale_values(A->nnz, A->col_idx, A->val, nullptr, nullptr, s->vals32, stm);
+        launch_scale_values(A->nnz, A->col_idx, A->val, dv, nullptr, s->vals32, stm);
+        op.vals = s->vals32;
+    } else if (jac) {
+        launch_scale_values(A->nnz, A->col_idx, A->val, dv, s->vals, nullptr, stm);
+        op.vals = s->vals;
     }
 
     // a2: recycle setup A W, E = W^T A W, LU(E)
@@ -866,21 +986,18 @@ int rsolve_solve(rsolve_seq* s, const rsolve_csr* A, const double* b, const doub
             auto enqueue = [&] {
                 for (int j = j0; j < j1; ++j) {
                     if (dg) {
-                        if (ir) dcgs2_step<float>(s, j, max_steps, A->row_ptr, A->col_idx, s->vals32, s->V32, s->w32,
-                                                  W32, Z32, k);
-                        else dcgs2_step<double>(s, j, max_steps, A->row_ptr, A->col_idx, kv64, s->V, s->wb, s->W,
-                                                s->Z, k);
+                        if (ir) dcgs2_step<float>(s, j, max_steps, op, s->V32, s->w32, W32, Z32, k);
+                        else dcgs2_step<double>(s, j, max_steps, op, s->V, s->wb, s->W, s->Z, k);
                     } else {
-                        if (ir) arnoldi_step<float>(s, j, A->row_ptr, A->col_idx, s->vals32, s->V32, s->w32, W32, Z32, k);
-                        else arnoldi_step<double>(s, j, A->row_ptr, A->col_idx, kv64, s->V, s->wb, s->W, s->Z, k);
+                        if (ir) arnoldi_step<float>(s, j, op, s->V32, s->w32, W32, Z32, k);
+                        else arnoldi_step<double>(s, j, op, s->V, s->wb, s->W, s->Z, k);
                     }
                 }
             };
             if (s->graphs_on && !s->prof_on) {
-                const rsolve_seq::GraphKey key{j0, j1, k, ir ? 1 : 0, s->lpr, s->svec, s->sremap, dg ? 1 : 0,
-                                               dg ? max_steps : 0, A->row_ptr, A->col_idx,
-                                               ir ? static_cast<const void*>(s->vals32)
-                                                  : static_cast<const void*>(kv64)};
+                const rsolve_seq::GraphKey key{j0,      j1,         k,         ir ? 1 : 0, s->lpr, s->svec, s->sremap,
+                                               op.fmt,  dg ? 1 : 0, dg ? max_steps : 0,  op.rp,  op.ci,   op.off,
+                                               op.vals};
                 hipGraphExec_t ge = nullptr;
                 rc = chunk_graph(s, key, enqueue, &ge);
                 if (rc) return rc;

@@ -28,17 +28,19 @@ __global__ __launch_bounds__(BLOCK) void k_validate(int64_t n, int64_t nnz, cons
     }
     int32_t d = -1;
     int64_t prev = -1;
-    bool bad_col = false, bad_order = false;
+    bool bad_col = false, bad_order = false, wide = false;
     for (int64_t k = a; k < b; ++k) {
         const int64_t c = ci[k];
         if (c < 0 || c >= n) bad_col = true;
         if (c <= prev) bad_order = true;
         if (c == i) d = (int32_t)k;
+        if (c - i > BP_MAX_OFFSET || i - c > BP_MAX_OFFSET) wide = true;
         prev = c;
     }
     if (bad_col) err[1] = 1;
     if (bad_order) err[2] = 1;
     if (d < 0) err[3] = 1;
+    if (wide) err[4] = 1;   // not an error: the banded format cannot hold this pattern
     diag_pos[i] = d;
 }
 
@@ -136,6 +138,138 @@ __global__ __launch_bounds__(BLOCK) void k_spmv_arnoldi(int64_t n, const int32_t
         acc = (vec == 8)   ? csr_row_part_vec<T, LPR, 8>(ci, val, win, rp[row], rp[row + 1], sub)
               : (vec == 4) ? csr_row_part_vec<T, LPR, 4>(ci, val, win, rp[row], rp[row + 1], sub)
                            : csr_row_part<T, LPR>(ci, val, win, rp[row], rp[row + 1], sub);
+    acc = group_sum<LPR>(acc);
+    if (active && sub == 0) {
+        y[row] = (T)(s * acc);
+        if (vout) vout[row] = (T)(s * to_d(win[row]));
+    }
+}
+
+// ---- Banded padded CSR for the Arnoldi product ----------------------------------------------
+// Row r owns the chunks [p[r], p[r+1]) of E entries each: its entries, then zeros up to a whole
+// chunk.  Columns are kept as 16-bit offsets col - r, so a finite-element row of E entries costs
+// E (w + 2) bytes instead of E (w + 4).  The LPR lanes of a row take the chunks p[r] + sub,
+// p[r] + sub + LPR, ...; inside each round of LPR chunks the row's entries are dealt round-robin
+// over the lanes that hold a chunk of it, so at every step the lanes of a row read neighbouring
+// entries and gather neighbouring columns of x.  Padding entries have offset 0 and value 0.
+
+// Position of entry kk (0 <= kk < E LP) of a row whose chunks start at c0 (LP chunks).
+__device__ __forceinline__ int64_t bp_pos(int64_t c0, int LP, int kk, int E, int LPR) {
+    const int R = E * LPR;
+    const int it = kk / R, w = kk - it * R;
+    const int g = min(LPR, LP - LPR * it);
+    return (c0 + (int64_t)LPR * it + w % g) * E + w / g;
+}
+
+// p[i] = sum_{r < i} ceil(len_r / E), i = 0..n: one block walks the rows in tiles of 4096.
+__global__ __launch_bounds__(1024) void k_bp_scan(int64_t n, const int32_t* __restrict__ rp, int E,
+                                                  int32_t* __restrict__ p) {
+    __shared__ int wtot[1024 / WAVE];
+    const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
+    int carry = 0;
+    for (int64_t base = 0; base < n; base += 4 * 1024) {
+        const int64_t i0 = base + 4 * (int64_t)threadIdx.x;
+        int c[4], loc = 0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t i = i0 + u;
+            c[u] = i < n ? (rp[i + 1] - rp[i] + E - 1) / E : 0;
+            loc += c[u];
+        }
+        int inc = loc;
+        for (int o = 1; o < WAVE; o <<= 1) {
+            const int t = __shfl_up(inc, o, WAVE);
+            if (lane >= o) inc += t;
+        }
+        if (lane == WAVE - 1) wtot[wv] = inc;
+        __syncthreads();
+        int before = 0, tile = 0;
+        for (int w = 0; w < 1024 / WAVE; ++w) {
+            const int t = wtot[w];
+            if (w < wv) before += t;
+            tile += t;
+        }
+        int ex = carry + before + inc - loc;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (i0 + u < n) p[i0 + u] = ex;
+            ex += c[u];
+        }
+        carry += tile;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) p[n] = carry;
+}
+
+// Offsets of every entry and zero values at the padding (once per pattern): thread per row.
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_bp_pack(int64_t n, const int32_t* __restrict__ rp,
+                                                   const int32_t* __restrict__ ci, const int32_t* __restrict__ p,
+                                                   int E, int LPR, int16_t* __restrict__ off, T* __restrict__ val) {
+    const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (i >= n) return;
+    const int a = rp[i], L = rp[i + 1] - a;
+    const int c0 = p[i], LP = p[i + 1] - c0;
+    for (int kk = 0; kk < LP * E; ++kk) {
+        const int64_t q = bp_pos(c0, LP, kk, E, LPR);
+        if (kk < L) {
+            off[q] = (int16_t)(ci[a + kk] - i);
+        } else {
+            off[q] = 0;
+            val[q] = (T)0;
+        }
+    }
+}
+
+// The values of one matrix (times D^{-1} by column when dinv is given) into their positions:
+// 8 lanes per row.
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_bp_values(int64_t n, const int32_t* __restrict__ rp,
+                                                     const int32_t* __restrict__ ci, const double* __restrict__ val,
+                                                     const double* __restrict__ dinv, const int32_t* __restrict__ p,
+                                                     int E, int LPR, T* __restrict__ out) {
+    const int64_t gt = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    const int64_t i = gt / 8;
+    const int sub = (int)(gt % 8);
+    if (i >= n) return;
+    const int a = rp[i], L = rp[i + 1] - a;
+    const int c0 = p[i], LP = p[i + 1] - c0;
+    for (int kk = sub; kk < L; kk += 8) {
+        double v = val[a + kk];
+        if (dinv) v *= dinv[ci[a + kk]];
+        out[bp_pos(c0, LP, kk, E, LPR)] = (T)v;
+    }
+}
+
+// y = s A win, vout = s win (vout may be null), s = ctl->inv_h; float64 accumulation.
+template <typename T, int E, int LPR>
+__global__ __launch_bounds__(BLOCK) void k_spmv_bp(int64_t n, const int32_t* __restrict__ p,
+                                                   const int16_t* __restrict__ off, const T* __restrict__ val,
+                                                   const T* __restrict__ win, T* __restrict__ vout,
+                                                   T* __restrict__ y, const Ctl* __restrict__ ctl, int remap) {
+    if (ctl->done) return;
+    const double s = ctl->inv_h;
+    const unsigned lb = remap ? xcd_block(blockIdx.x, gridDim.x) : blockIdx.x;
+    const int64_t gt = (int64_t)lb * BLOCK + threadIdx.x;
+    const int64_t row = gt / LPR;
+    const int sub = (int)(gt % LPR);
+    double acc = 0.0;
+    const bool active = row < n;
+    if (active) {
+        const int a = p[row], e = p[row + 1];
+        const T* xr = win + row;
+        for (int q = a + sub; q < e; q += LPR) {
+            int16_t c[E];
+            T v[E];
+            __builtin_memcpy(c, __builtin_assume_aligned(off + (int64_t)q * E, 2 * E), sizeof(c));
+            __builtin_memcpy(v, __builtin_assume_aligned(val + (int64_t)q * E, 16), sizeof(v));
+            double pr[E];
+#pragma unroll
+            for (int t = 0; t < E; ++t) pr[t] = to_d(v[t]) * to_d(xr[c[t]]);
+#pragma unroll
+            for (int t = 0; t < E; ++t) acc += pr[t];
+        }
+    }
     acc = group_sum<LPR>(acc);
     if (active && sub == 0) {
         y[row] = (T)(s * acc);
@@ -252,6 +386,47 @@ template void launch_spmv_arnoldi<double>(int, int, int, int64_t, const int32_t*
 template void launch_spmv_arnoldi<float>(int, int, int, int64_t, const int32_t*, const int32_t*, const float*,
                                          const float*, float*, float*, const Ctl*, hipStream_t, hipEvent_t,
                                          hipEvent_t);
+
+int bp_setup(int64_t n, const int32_t* rp, const int32_t* ci, int E, int LPR, int32_t* p, int16_t* off, void* val,
+             bool f32, hipStream_t st) {
+    if ((E != 4 && E != 8) || (LPR != 2 && LPR != 4 && LPR != 8)) return -1;
+    k_bp_scan<<<1, 1024, 0, st>>>(n, rp, E, p);
+    if (f32) k_bp_pack<float><<<grid_for(n), BLOCK, 0, st>>>(n, rp, ci, p, E, LPR, off, static_cast<float*>(val));
+    else k_bp_pack<double><<<grid_for(n), BLOCK, 0, st>>>(n, rp, ci, p, E, LPR, off, static_cast<double*>(val));
+    return 0;
+}
+
+template <typename T>
+void launch_bp_values(int64_t n, const int32_t* rp, const int32_t* ci, const double* val, const double* dinv,
+                      const int32_t* p, int E, int LPR, T* out, hipStream_t st) {
+    k_bp_values<T><<<grid_for(n * 8), BLOCK, 0, st>>>(n, rp, ci, val, dinv, p, E, LPR, out);
+}
+template void launch_bp_values<double>(int64_t, const int32_t*, const int32_t*, const double*, const double*,
+                                       const int32_t*, int, int, double*, hipStream_t);
+template void launch_bp_values<float>(int64_t, const int32_t*, const int32_t*, const double*, const double*,
+                                      const int32_t*, int, int, float*, hipStream_t);
+
+template <typename T>
+void launch_spmv_bp(int E, int LPR, int remap, int64_t n, const int32_t* p, const int16_t* off, const T* val,
+                    const T* win, T* vout, T* y, const Ctl* ctl, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+#define RS_BP(EE, L)                                                                                             \
+    hipExtLaunchKernelGGL(k_spmv_bp<T, EE, L>, dim3(grid_for(n * L)), dim3(BLOCK), 0, st, ev0, ev1, 0, n, p, off, \
+                          val, win, vout, y, ctl, remap)
+    if (E == 8) {
+        if (LPR == 2) RS_BP(8, 2);
+        else if (LPR == 4) RS_BP(8, 4);
+        else RS_BP(8, 8);
+    } else {
+        if (LPR == 2) RS_BP(4, 2);
+        else if (LPR == 4) RS_BP(4, 4);
+        else RS_BP(4, 8);
+    }
+#undef RS_BP
+}
+template void launch_spmv_bp<double>(int, int, int, int64_t, const int32_t*, const int16_t*, const double*,
+                                     const double*, double*, double*, const Ctl*, hipStream_t, hipEvent_t, hipEvent_t);
+template void launch_spmv_bp<float>(int, int, int, int64_t, const int32_t*, const int16_t*, const float*,
+                                    const float*, float*, float*, const Ctl*, hipStream_t, hipEvent_t, hipEvent_t);
 
 void launch_residual(int lpr, int64_t n, const int32_t* rp, const int32_t* ci, const double* val, const double* x,
                      const double* b, double* r, hipStream_t st) {

@@ -12,6 +12,20 @@ namespace rs {
 // ---- sparse (k_sparse.hip) ----
 // Pattern validation: err[0..3] receive nonzero on (row_ptr range, column range, unsorted or
 // duplicate columns, missing diagonal); diag_pos[i] = CSR index of A_ii.
+// Banded padded CSR for the Arnoldi product (rows in chunks of E entries, 16-bit column offsets
+// col - row, entries dealt round-robin over the LPR lanes of a row in every round of chunks).
+// bp_setup: chunk offsets p (n + 1), offsets of every entry and zeros at the padding; returns -1
+// for an unsupported (E, LPR).  Requires |col - row| <= BP_MAX_OFFSET for every entry.
+int bp_setup(int64_t n, const int32_t* rp, const int32_t* ci, int E, int LPR, int32_t* p, int16_t* off, void* val,
+             bool f32, hipStream_t st);
+template <typename T>
+void launch_bp_values(int64_t n, const int32_t* rp, const int32_t* ci, const double* val, const double* dinv,
+                      const int32_t* p, int E, int LPR, T* out, hipStream_t st);
+template <typename T>
+void launch_spmv_bp(int E, int LPR, int remap, int64_t n, const int32_t* p, const int16_t* off, const T* val,
+                    const T* win, T* vout, T* y, const Ctl* ctl, hipStream_t st, hipEvent_t ev0 = nullptr,
+                    hipEvent_t ev1 = nullptr);
+
 void launch_validate(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* ci, int32_t* diag_pos,
                      int32_t* err, hipStream_t st);
 void launch_diag_inv(int64_t n, const int32_t* diag_pos, const double* val, double* dinv, hipStream_t st);

@@ -79,12 +79,16 @@ class ProfEntry(ctypes.Structure):
                 ("bytes", c_double)]
 
 
+SPMV_FORMATS = {0: "csr", 1: "banded"}
+
+
 class SpmvShape(ctypes.Structure):
     _fields_ = [("lanes_per_row", c_int32), ("vec", c_int32), ("xcd_remap", c_int32), ("user_set", c_int32),
-                ("us", c_double)]
+                ("format", c_int32), ("reserved", c_int32), ("us", c_double)]
 
     def as_dict(self):
-        return {"lanes_per_row": self.lanes_per_row, "vec": self.vec, "xcd_remap": self.xcd_remap, "us": self.us}
+        return {"format": SPMV_FORMATS.get(self.format, self.format), "lanes_per_row": self.lanes_per_row,
+                "vec": self.vec, "xcd_remap": self.xcd_remap, "us": self.us}
 
 
 class BatchSolveItem(ctypes.Structure):
@@ -285,8 +289,11 @@ class Sequence:
             _check(self.lib.rsolve_tune_spmv(self.handle, byref(A), int(reps), arr, cap, byref(cnt)))
         return [arr[i].as_dict() for i in range(min(cnt.value, cap))]
 
-    def set_spmv_shape(self, lanes_per_row, vec, xcd_remap=0):
-        _check(self.lib.rsolve_set_spmv_shape(self.handle, byref(SpmvShape(lanes_per_row, vec, xcd_remap, 0, 0.0))))
+    def set_spmv_shape(self, lanes_per_row, vec, xcd_remap=0, format="csr"):
+        """format: "csr" or "banded" (rsolve.h RSOLVE_SPMV_*)."""
+        fmt = {v: k for k, v in SPMV_FORMATS.items()}.get(format, format)
+        _check(self.lib.rsolve_set_spmv_shape(self.handle,
+                                              byref(SpmvShape(lanes_per_row, vec, xcd_remap, 0, fmt, 0, 0.0))))
 
     def spmv_shape(self):
         sh = SpmvShape()
