@@ -438,7 +438,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--inner-tol", type=float, default=None,
                     help="override the FP32 cycle reduction factor of the mixed-precision workload")
-    ap.add_argument("--ortho", choices=["cgs2", "dcgs2"], default="cgs2",
+    ap.add_argument("--ortho", choices=["cgs2", "dcgs2"], default="dcgs2",
                     help="Arnoldi orthogonalisation of the multi-kernel solver (both runs): classical "
                          "Gram-Schmidt twice, or the same with the second pass delayed into the next step")
     ap.add_argument("--graphs", action="store_true",
@@ -479,8 +479,7 @@ def main():
         cfg["inner_tol"] = args.inner_tol
         desc = desc + f", inner_tol {args.inner_tol:g}"
     cfg["ortho"] = args.ortho
-    if args.ortho != "cgs2":
-        desc = desc + f", Arnoldi {args.ortho}"
+    desc = desc + (", Arnoldi CGS2 with delayed reorthogonalisation" if args.ortho == "dcgs2" else ", Arnoldi CGS2")
     prob = getattr(WL, pname)
     nsteps = args.warmup + args.steps
     asm, gasm, u0, systems = generate(prob, nsteps, dev)

@@ -588,24 +588,39 @@ __global__ __launch_bounds__(1024) void k_dots2(int64_t npad, int64_t ld, const 
 
 // One block: reduce the sweep, complete and rotate column j-1, prepare step j's update.
 // has_z = 0 on the closing step of a cycle (no product was taken): only column j-1 completes.
+// The loads of the control block are issued together at the start, and the sums over the
+// Hessenberg matrix and F are split over the wavefronts, so the block waits for memory a few
+// times rather than once per term.
 __global__ __launch_bounds__(RED_T) void k_dcgs2_reduce(const double* __restrict__ partial, int nblk, int j, int k,
                                                         int has_z, Ctl* __restrict__ ctl) {
     if (ctl->done) return;
     constexpr int LDH = MMAX + 1;
     constexpr int LDR = MMAX + 1;
+    constexpr int NW = RED_T / WAVE;
     __shared__ double sums[2 * (MMAX + 2 * KMAX + 1)];
-    __shared__ double red[RED_T / WAVE];
+    __shared__ double red[NW];
     __shared__ double Es[KMAX * KMAX];
     __shared__ double cws[KMAX];
     __shared__ double wz[KMAX];
     __shared__ double Qz[MMAX + 1];
     __shared__ double hcol[MMAX + 2];
+    __shared__ double css[MMAX], sns[MMAX];
+    constexpr int NH = 8, NF = NW - 1 - NH;   // wavefronts summing H h, and h^T F
+    __shared__ double pH[NH][MMAX + 1];   // per-wavefront partial sums of H h
+    __shared__ double pF[NF][KMAX];       // ... of h^T F (row j of F before scaling)
+    static_assert(NW * MMAX <= KMAX * KMAX, "partial sums of F cws reuse the LU factors' space");
+    double(*pQ)[MMAX] = reinterpret_cast<double(*)[MMAX]>(Es);   // ... of F cws, once the LU solve is done
     __shared__ double scal[4];
     __shared__ int stop;
     const int tid = threadIdx.x;
     const int wv = tid / WAVE, lane = tid & (WAVE - 1);
     const int ncol = j + 2 * k + 1;
+    const int jc = j - 1;   // the column completed here (none when j = 0)
     for (int t = tid; t < k * k; t += RED_T) Es[t] = ctl->E[t];
+    for (int t = tid; t < jc; t += RED_T) {
+        css[t] = ctl->cs[t];
+        sns[t] = ctl->sn[t];
+    }
     reduce_columns(partial, nblk, 2 * ncol, sums, red);
     // sums[2 c] = col_c . u, sums[2 c + 1] = col_c . z; columns: V (0..j-1), W, A W, u
     const double* su = sums;
@@ -628,13 +643,14 @@ __global__ __launch_bounds__(RED_T) void k_dcgs2_reduce(const double* __restrict
                 cn += h * h;
             }
             cn = wave_sum(cn) + nu * nu;
+            if (lane == 0) hcol[j] = nu;
+            __builtin_amdgcn_wave_barrier();
+            for (int l = lane; l <= j; l += WAVE) ctl->Hs[l + LDH * jc] = hcol[l];
             if (lane == 0) {
-                hcol[j] = nu;
-                const int jc = j - 1;
-                for (int l = 0; l <= j; ++l) ctl->Hs[l + LDH * jc] = hcol[l];
                 double a = hcol[0];
+#pragma unroll 8
                 for (int l = 0; l < jc; ++l) {
-                    const double c = ctl->cs[l], sn = ctl->sn[l], b = hcol[l + 1];
+                    const double c = css[l], sn = sns[l], b = hcol[l + 1];
                     ctl->R[l + LDR * jc] = c * a + sn * b;
                     a = -sn * a + c * b;
                 }
@@ -663,6 +679,28 @@ __global__ __launch_bounds__(RED_T) void k_dcgs2_reduce(const double* __restrict
                 }
             }
         }
+    } else if (wv <= NH) {
+        // waves 1..NH: partial sums of (H h)_i = sum_{l >= i-1} H[i, l] h_l over the columns
+        // l < j - 1 kept in the control block (column j - 1 is hcol, added below)
+        const int w = wv - 1;
+        double ph0 = 0.0, ph1 = 0.0;
+        for (int l = w; l < j - 1; l += NH) {
+            const double h = su[2 * l];
+            if (lane <= l + 1) ph0 += ctl->Hs[lane + LDH * l] * h;
+            if (lane + WAVE <= l + 1) ph1 += ctl->Hs[lane + WAVE + LDH * l] * h;
+        }
+        pH[w][lane] = ph0;
+        if (lane + WAVE <= MMAX) pH[w][lane + WAVE] = ph1;
+        // rows from 2 WAVE on take no column kept in the control block (those columns end at row
+        // j - 1 < 2 WAVE)
+        for (int i = 2 * WAVE + lane; i <= MMAX; i += WAVE) pH[w][i] = 0.0;
+    } else {
+        // the other waves: partial sums of (h^T F)_c = sum_l h_l F[l, c]
+        const int w = wv - 1 - NH;
+        double pf = 0.0;
+        if (lane < k)
+            for (int l = w; l < j; l += NF) pf += su[2 * l] * ctl->F[l * KMAX + lane];
+        pF[w][lane] = pf;
     }
     __syncthreads();
     if (stop || !has_z) return;
@@ -675,36 +713,49 @@ __global__ __launch_bounds__(RED_T) void k_dcgs2_reduce(const double* __restrict
         wave_lu_solve(ctl, k, wz, cws, Es);
     }
     __syncthreads();
-    // F row j, V_j^T (P z), u^T (P z)
+    // partial sums of (F cws)_l over groups of recycle columns: wavefront w takes c = w, w + NW, ...
+    for (int l = lane; l < j; l += WAVE) {
+        double q = 0.0;
+        for (int c = wv; c < k; c += NW) q += ctl->F[l * KMAX + c] * cws[c];
+        pQ[wv][l] = q;
+    }
+    // F row j and cw
     for (int c = tid; c < k; c += RED_T) {
-        double f = su[2 * (j + k + c)];           // u . (A W)_c
-        for (int l = 0; l < j; ++l) f -= su[2 * l] * ctl->F[l * KMAX + c];
-        ctl->F[j * KMAX + c] = f * inv;
+        double f = 0.0;
+        for (int w = 0; w < NF; ++w) f += pF[w][c];
+        ctl->F[j * KMAX + c] = (su[2 * (j + k + c)] - f) * inv;   // u . (A W)_c - h^T F[:, c]
         ctl->cw[c] = cws[c];
     }
+    __syncthreads();
+    // V_j^T (P z) and u^T (P z)
     for (int l = tid; l < j; l += RED_T) {
-        double q = su[2 * l + 1];                  // v_l . z
-        for (int c = 0; c < k; ++c) q -= ctl->F[l * KMAX + c] * cws[c];
-        Qz[l] = q;
+        double q = 0.0;
+        for (int w = 0; w < NW; ++w) q += pQ[w][l];
+        Qz[l] = su[2 * l + 1] - q;   // v_l . z - (F cws)_l
     }
-    if (tid == 0) {
-        double uz = su[2 * (j + 2 * k) + 1];       // u . z
-        for (int c = 0; c < k; ++c) uz -= su[2 * (j + k + c)] * cws[c];
-        scal[1] = uz;
+    if (wv == NW - 1) {
+        double uz = 0.0;
+        for (int c = lane; c < k; c += WAVE) uz += su[2 * (j + k + c)] * cws[c];
+        uz = wave_sum(uz);
+        if (lane == 0) scal[1] = su[2 * (j + 2 * k) + 1] - uz;   // u . z - (u^T A W) cws
     }
     __syncthreads();
-    if (tid == 0) {
-        double q = scal[1];
-        for (int l = 0; l < j; ++l) q -= su[2 * l] * Qz[l];
-        Qz[j] = q * inv;                            // v_j . (P z)
-        ctl->inv_nu = inv;
+    if (wv == 0) {
+        double q = 0.0;
+        for (int l = lane; l < j; l += WAVE) q += su[2 * l] * Qz[l];
+        q = wave_sum(q);
+        if (lane == 0) {
+            Qz[j] = (scal[1] - q) * inv;   // v_j . (P z)
+            ctl->inv_nu = inv;
+        }
     }
     __syncthreads();
     // first-pass coefficients g of column j and the update coefficients d = H h / nu + g, with
     // h = V_j^T u the second-pass coefficients of v_j and H the unrotated Hessenberg (j+1 x j)
     for (int i = tid; i <= j; i += RED_T) {
         double hh = 0.0;
-        for (int l = (i > 0 ? i - 1 : 0); l < j; ++l) hh += ctl->Hs[i + LDH * l] * su[2 * l];
+        for (int w = 0; w < NH; ++w) hh += pH[w][i];
+        if (j >= 1) hh += hcol[i] * su[2 * (j - 1)];   // column j - 1 (zero below row j)
         const double g = (Qz[i] - hh) * inv;
         ctl->hp[i] = g;
         ctl->dq[i] = hh * inv + g;
@@ -712,7 +763,7 @@ __global__ __launch_bounds__(RED_T) void k_dcgs2_reduce(const double* __restrict
     for (int l = tid; l < j; l += RED_T) ctl->hr[l] = su[2 * l];
 }
 
-// v_j = (u - V_j hr) / nu; u <- (z - (A W) cw) / nu - V_j dq[0..j) - v_j dq[j]   (row per thread)
+// v_j = (u - V hr) / nu; u <- (z - (A W) cw) / nu - V dq[0..j) - v_j dq[j]   (VEC rows per thread)
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_dcgs2_update(int64_t npad, T* __restrict__ V, int64_t ld, int j,
                                                         const T* __restrict__ Z, int k, T* __restrict__ u,

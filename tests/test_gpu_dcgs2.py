@@ -109,3 +109,30 @@ def test_dcgs2_profiling(gpu_ctx):
     assert names == {"spmv_arnoldi", "dots2", "dcgs2_update"}, names
     assert all(e["launches"] > 0 and e["ms"] > 0 for e in prof)
     seq.close()
+
+
+def _check_slow_tail(out, tol):
+    """Bars for a solve whose last cycle converges slowly (a few percent per step near the
+    tolerance), where rounding moves the stopping step: the true residual meets tol, the step
+    count is within 3 of the oracle's, and the solutions differ by at most what two solutions
+    that both meet tol can differ by (2 kappa_1 tol)."""
+    for r in out:
+        assert r["status"] == 0 and r["st"]["converged"] == 1, r["step"]
+        assert r["res"] <= tol * (1 + 1e-6), (r["step"], r["res"])
+        assert abs(r["st"]["iterations"] - r["ores"].iterations) <= 3, (
+            r["step"], r["st"]["iterations"], r["ores"].iterations)
+        assert r["st"]["k_eff"] == r["ores"].k_eff
+        kappa = np.linalg.cond(r["A"].toarray(), 1)
+        assert r["rel"] <= max(1e-9, 2 * kappa * tol), (r["step"], r["rel"], kappa)
+
+
+@pytest.mark.parametrize("ortho", ["cgs2", "dcgs2"])
+def test_restart_at_the_maximum(gpu_ctx, ortho):
+    """GMRES(128), the largest restart: full 128-step cycles (about 270 steps per plain solve), so
+    the Hessenberg matrix and the sweeps reach their largest sizes; plain and recycled."""
+    hard = WL.Problem(p=3, N=16, eps=1e-4, dt=0.1, beta="rotating")
+    out = run_pair(gpu_ctx, hard, 2, 1e-10, restart_m=128, method="plain", ortho=ortho)
+    _check_slow_tail(out, 1e-10)
+    assert out[0]["st"]["iterations"] > 256 and out[0]["st"]["cycles"] >= 3
+    out = run_pair(gpu_ctx, hard, 3, 1e-10, restart_m=128, recycle_k=16, snapshots_s=20, ortho=ortho)
+    _check_slow_tail(out, 1e-10)
