@@ -134,6 +134,9 @@ struct rsolve_seq {
     int32_t* herr = nullptr;
     int32_t* diag_pos = nullptr;
     double *V = nullptr, *W = nullptr, *Z = nullptr, *X = nullptr, *xw = nullptr, *dinv = nullptr;
+    double* Wr = nullptr;          // W row-major (row r at Wr + r ldr), for Z = A W
+    int ldr = 0;                   // recycle_k rounded up to 16
+    bool wr_ok = false;            // Wr holds the current W
     double* wb[2] = {nullptr, nullptr};
     double *vals = nullptr, *partial = nullptr, *gpart = nullptr;
     double* tsq[2] = {nullptr, nullptr};
@@ -200,6 +203,10 @@ struct rsolve_seq {
 
 namespace {
 
+// The split-n reductions' partial sums (also the scratch of the banded layout's prefix sums).
+constexpr int64_t PARTIAL_DOUBLES = (int64_t)NBLK_MAX * (MMAX + 2 * KMAX + 1);
+constexpr int64_t PARTIAL_INTS = 2 * PARTIAL_DOUBLES;
+
 // Lays the sequence's buffers out in the workspace; returns the bytes used.
 size_t layout(rsolve_seq* s, const rsolve_config& c, int64_t n, int64_t nnz_max, char* base) {
     Carver cv{base};
@@ -214,6 +221,8 @@ size_t layout(rsolve_seq* s, const rsolve_config& c, int64_t n, int64_t nnz_max,
     float* V32 = ir ? cv.take<float>((size_t)(m + 1) * ld) : nullptr;
     double* W = k ? cv.take<double>((size_t)k * ld) : nullptr;
     double* Z = k ? cv.take<double>((size_t)k * ld) : nullptr;
+    const int ldr = (k + 15) / 16 * 16;
+    double* Wr = k ? cv.take<double>((size_t)ldr * ld) : nullptr;
     float* W32 = (k && ir) ? cv.take<float>((size_t)k * ld) : nullptr;
     float* Z32 = (k && ir) ? cv.take<float>((size_t)k * ld) : nullptr;
     double* X = (k && sn) ? cv.take<double>((size_t)sn * ld) : nullptr;
@@ -232,7 +241,7 @@ size_t layout(rsolve_seq* s, const rsolve_config& c, int64_t n, int64_t nnz_max,
     void* bp_val = bp_cap ? (ir ? static_cast<void*>(cv.take<float>((size_t)bp_cap))
                                 : static_cast<void*>(cv.take<double>((size_t)bp_cap)))
                           : nullptr;
-    double* partial = cv.take<double>((size_t)NBLK_MAX * (MMAX + 2 * KMAX + 1));
+    double* partial = cv.take<double>((size_t)PARTIAL_DOUBLES);
     double* gpart = cv.take<double>((size_t)GRAM_PARTIAL);
     int64_t tsq_rows = 0, tsq_ld = 0;
     double *t0 = nullptr, *t1 = nullptr;
@@ -250,6 +259,8 @@ size_t layout(rsolve_seq* s, const rsolve_config& c, int64_t n, int64_t nnz_max,
         s->V = V;
         s->V32 = V32;
         s->W = W;
+        s->Wr = Wr;
+        s->ldr = ldr;
         s->Z = Z;
         s->W32 = W32;
         s->Z32 = Z32;
@@ -335,7 +346,8 @@ int bp_prepare(rsolve_seq* s, const rsolve_csr* A, const double* dinv, bool f32)
     }
     hipStream_t stm = s->stream;
     if (s->bp_e != s->svec || s->bp_l != s->lpr) {
-        if (bp_setup(s->n, A->row_ptr, A->col_idx, s->svec, s->lpr, s->bp_p, s->bp_off, s->bp_val, f32, stm) != 0) {
+        if (bp_setup(s->n, A->row_ptr, A->col_idx, s->svec, s->lpr, s->bp_p, s->bp_off, s->bp_val, f32,
+                     reinterpret_cast<int32_t*>(s->partial), PARTIAL_INTS, stm) != 0) {
             set_err("invalid banded SpMV shape (entries %d, lanes %d)", s->svec, s->lpr);
             return RSOLVE_E_INVALID;
         }
@@ -518,7 +530,7 @@ void dcgs2_step(rsolve_seq* s, int j, int allowed, const SpOp& op, T* V, T* cons
     const int ncol = j + 2 * k + 1;
     const int cpw = ncol > 64 ? 8 : 4;   // as the sweep's launcher chooses
     const int nb1 = std::min(cols_grid(ld, s->cus, std::min(16, (ncol + cpw - 1) / cpw), 32, 2 * ncol),
-                             NBLK_MAX * (MMAX + 2 * KMAX + 1) / (2 * ncol));   // partials fit their buffer
+                             (int)(PARTIAL_DOUBLES / (2 * ncol)));   // partials fit their buffer
     {
         ProfEv pe(s, RSOLVE_PROF_DOTS, has_z ? j : MMAX, var_of(ncol), (ncol + 1.0) * w * nn);
         launch_dots2<T>(ld, ld, V, j, Wt, Zt, k, u, has_z ? z : u, s->partial, nb1, s->ctl, st, pe.e0, pe.e1);
@@ -771,7 +783,7 @@ int rsolve_tune_spmv(rsolve_seq* s, const rsolve_csr* A, int32_t reps, rsolve_sp
             for (int v : {4, 8}) {
                 // lay the copy out for this shape and fill it with A's values
                 if (err == hipSuccess && bp_setup(n, A->row_ptr, A->col_idx, v, l, s->bp_p, s->bp_off, s->bp_val, ir,
-                                                  stm) == 0) {
+                                                  reinterpret_cast<int32_t*>(s->partial), PARTIAL_INTS, stm) == 0) {
                     s->bp_e = v;
                     s->bp_l = l;
                     if (ir) launch_bp_values<float>(n, A->row_ptr, A->col_idx, A->val, nullptr, s->bp_p, v, l,
@@ -903,7 +915,11 @@ int rsolve_solve(rsolve_seq* s, const rsolve_csr* A, const double* b, const doub
     int k = (c.method != RSOLVE_PLAIN) ? s->k_w : 0;
     uint32_t flags = 0;
     if (k > 0) {
-        launch_spmm(s->lpr, n, A->row_ptr, A->col_idx, A->val, s->W, ld, k, s->Z, stm);
+        if (!s->wr_ok) {   // W came from the one-block update, which keeps no row-major copy
+            launch_to_rows(n, s->W, ld, k, s->Wr, s->ldr, stm);
+            s->wr_ok = true;
+        }
+        launch_spmm_rows(s->lpr, n, A->row_ptr, A->col_idx, A->val, s->Wr, s->ldr, k, s->Z, ld, stm);
         const int gb = launch_gram_tn(ld, s->W, ld, k, s->Z, ld, k, s->gpart, s->gblk, stm);
         launch_gram_reduce(s->gpart, gb, k * k, ctl_red(s->ctl), stm);
         launch_small_lu(ctl_red(s->ctl), k, s->ctl, stm);
@@ -1112,7 +1128,8 @@ int rsolve_update_recycle(rsolve_seq* s, const double* x) {
         const int gb = launch_gram_tn(ld, s->W, ld, keff, s->W, ld, keff, s->gpart, s->gblk, stm);
         launch_gram_reduce(s->gpart, gb, keff * keff, ctl_red(s->ctl), stm);
         launch_cholesky(keff, s->ctl, stm);
-        launch_trsm_rows(ld, s->W, ld, keff, s->ctl, stm);
+        launch_trsm_rows(ld, s->W, ld, keff, s->ctl, stm, s->Wr, s->ldr);
+        s->wr_ok = true;
         if (s->W32) launch_to_f32(keff * ld, s->W, s->W32, stm);
         HIP_TRY(hipGetLastError());
         rc = read_head(s);
@@ -1282,6 +1299,7 @@ int rsolve_update_recycle_batch(rsolve_batch_update_item* items, int32_t count, 
             const rsolve_config& c = s->cfg;
             SmallUpd& U = *s->hupd;
             memset(&U, 0, sizeof(U));
+            s->wr_ok = false;   // this update writes W only
             U.n = s->n;
             U.ld = s->ld;
             U.src = it.x ? it.x : s->xw;

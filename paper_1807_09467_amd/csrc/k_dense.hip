@@ -381,7 +381,7 @@ __global__ __launch_bounds__(WAVE) void k_cholesky(int k, Ctl* __restrict__ ctl)
 // register array shifts down after each step.
 template <int K>
 __global__ __launch_bounds__(BLOCK) void k_trsm_rows(int64_t npad, double* __restrict__ W, int64_t ldw, int k,
-                                                     const Ctl* __restrict__ ctl) {
+                                                     const Ctl* __restrict__ ctl, double* __restrict__ Wr, int ldr) {
     __shared__ double Ls[K * K];
     for (int t = threadIdx.x; t < k * k; t += BLOCK) Ls[(t / k) * K + (t % k)] = ctl->L[(t / k) * KMAX + (t % k)];
     __syncthreads();
@@ -393,6 +393,7 @@ __global__ __launch_bounds__(BLOCK) void k_trsm_rows(int64_t npad, double* __res
     for (int j = 0; j < k; ++j) {
         const double xj = w[0] / Ls[j * K + j];
         W[(int64_t)j * ldw + r] = xj;
+        if (Wr) Wr[r * ldr + j] = xj;
 #pragma unroll
         for (int i = 1; i < K; ++i)
             if (j + i < k) w[i] -= Ls[(j + i) * K + j] * xj;
@@ -450,12 +451,13 @@ void launch_form_w(int64_t n, int64_t npad, const double* X, int64_t ldx, int c,
 
 void launch_cholesky(int k, Ctl* ctl, hipStream_t st) { k_cholesky<<<1, WAVE, 0, st>>>(k, ctl); }
 
-void launch_trsm_rows(int64_t npad, double* W, int64_t ldw, int k, const Ctl* ctl, hipStream_t st) {
+void launch_trsm_rows(int64_t npad, double* W, int64_t ldw, int k, const Ctl* ctl, hipStream_t st, double* Wr,
+                      int ldr) {
     const unsigned g = (unsigned)((npad + BLOCK - 1) / BLOCK);
-    if (k <= 8) k_trsm_rows<8><<<g, BLOCK, 0, st>>>(npad, W, ldw, k, ctl);
-    else if (k <= 16) k_trsm_rows<16><<<g, BLOCK, 0, st>>>(npad, W, ldw, k, ctl);
-    else if (k <= 32) k_trsm_rows<32><<<g, BLOCK, 0, st>>>(npad, W, ldw, k, ctl);
-    else k_trsm_rows<64><<<g, BLOCK, 0, st>>>(npad, W, ldw, k, ctl);
+    if (k <= 8) k_trsm_rows<8><<<g, BLOCK, 0, st>>>(npad, W, ldw, k, ctl, Wr, ldr);
+    else if (k <= 16) k_trsm_rows<16><<<g, BLOCK, 0, st>>>(npad, W, ldw, k, ctl, Wr, ldr);
+    else if (k <= 32) k_trsm_rows<32><<<g, BLOCK, 0, st>>>(npad, W, ldw, k, ctl, Wr, ldr);
+    else k_trsm_rows<64><<<g, BLOCK, 0, st>>>(npad, W, ldw, k, ctl, Wr, ldr);
 }
 
 }  // namespace rs

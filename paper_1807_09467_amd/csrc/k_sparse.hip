@@ -8,6 +8,7 @@
 #include <cstdlib>
 
 #include "kernels.hpp"
+#include "spmv_banded.hpp"
 
 namespace rs {
 
@@ -145,72 +146,86 @@ __global__ __launch_bounds__(BLOCK) void k_spmv_arnoldi(int64_t n, const int32_t
     }
 }
 
-// ---- Banded padded CSR for the Arnoldi product ----------------------------------------------
-// Row r owns the chunks [p[r], p[r+1]) of E entries each: its entries, then zeros up to a whole
-// chunk.  Columns are kept as 16-bit offsets col - r, so a finite-element row of E entries costs
-// E (w + 2) bytes instead of E (w + 4).  The LPR lanes of a row take the chunks p[r] + sub,
-// p[r] + sub + LPR, ...; inside each round of LPR chunks the row's entries are dealt round-robin
-// over the lanes that hold a chunk of it, so at every step the lanes of a row read neighbouring
-// entries and gather neighbouring columns of x.  Padding entries have offset 0 and value 0.
+// p[i] = sum_{r < i} ceil(len_r / E), i = 0..n, in three launches: tile-local exclusive sums
+// and tile totals (tiles of BP_TILE rows, 4 per thread), an exclusive scan of the totals by one
+// block, and the tile offsets added back.
+constexpr int BP_TILE = 4 * 1024;
 
-// Position of entry kk (0 <= kk < E LP) of a row whose chunks start at c0 (LP chunks).
-__device__ __forceinline__ int64_t bp_pos(int64_t c0, int LP, int kk, int E, int LPR) {
-    const int R = E * LPR;
-    const int it = kk / R, w = kk - it * R;
-    const int g = min(LPR, LP - LPR * it);
-    return (c0 + (int64_t)LPR * it + w % g) * E + w / g;
+// Exclusive scan of v over a 1024-thread block; *total gets the block's sum.
+__device__ __forceinline__ int block_exclusive_scan(int v, int* wtot, int* total) {
+    const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
+    int inc = v;
+    for (int o = 1; o < WAVE; o <<= 1) {
+        const int t = __shfl_up(inc, o, WAVE);
+        if (lane >= o) inc += t;
+    }
+    if (lane == WAVE - 1) wtot[wv] = inc;
+    __syncthreads();
+    int before = 0, all = 0;
+    for (int w = 0; w < 1024 / WAVE; ++w) {
+        const int t = wtot[w];
+        if (w < wv) before += t;
+        all += t;
+    }
+    __syncthreads();   // wtot may be reused by the caller
+    *total = all;
+    return before + inc - v;
 }
 
-// p[i] = sum_{r < i} ceil(len_r / E), i = 0..n: one block walks the rows in tiles of 4096.
-__global__ __launch_bounds__(1024) void k_bp_scan(int64_t n, const int32_t* __restrict__ rp, int E,
-                                                  int32_t* __restrict__ p) {
+__global__ __launch_bounds__(1024) void k_bp_tiles(int64_t n, const int32_t* __restrict__ rp, int E,
+                                                   int32_t* __restrict__ p, int32_t* __restrict__ tsum) {
     __shared__ int wtot[1024 / WAVE];
-    const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
+    const int64_t i0 = (int64_t)blockIdx.x * BP_TILE + 4 * (int64_t)threadIdx.x;
+    int c[4], loc = 0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int64_t i = i0 + u;
+        c[u] = i < n ? (rp[i + 1] - rp[i] + E - 1) / E : 0;
+        loc += c[u];
+    }
+    int total = 0;
+    int ex = block_exclusive_scan(loc, wtot, &total);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        if (i0 + u < n) p[i0 + u] = ex;
+        ex += c[u];
+    }
+    if (threadIdx.x == 0) tsum[blockIdx.x] = total;
+}
+
+// In place: tsum[t] <- sum_{t' < t} tsum[t'] for t < nt, and p[n] = the grand total.
+__global__ __launch_bounds__(1024) void k_bp_tile_offsets(int64_t n, int nt, int32_t* __restrict__ tsum,
+                                                          int32_t* __restrict__ p) {
+    __shared__ int wtot[1024 / WAVE];
     int carry = 0;
-    for (int64_t base = 0; base < n; base += 4 * 1024) {
-        const int64_t i0 = base + 4 * (int64_t)threadIdx.x;
-        int c[4], loc = 0;
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int64_t i = i0 + u;
-            c[u] = i < n ? (rp[i + 1] - rp[i] + E - 1) / E : 0;
-            loc += c[u];
-        }
-        int inc = loc;
-        for (int o = 1; o < WAVE; o <<= 1) {
-            const int t = __shfl_up(inc, o, WAVE);
-            if (lane >= o) inc += t;
-        }
-        if (lane == WAVE - 1) wtot[wv] = inc;
-        __syncthreads();
-        int before = 0, tile = 0;
-        for (int w = 0; w < 1024 / WAVE; ++w) {
-            const int t = wtot[w];
-            if (w < wv) before += t;
-            tile += t;
-        }
-        int ex = carry + before + inc - loc;
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            if (i0 + u < n) p[i0 + u] = ex;
-            ex += c[u];
-        }
-        carry += tile;
-        __syncthreads();
+    for (int t0 = 0; t0 < nt; t0 += 1024) {
+        const int t = t0 + (int)threadIdx.x;
+        const int v = t < nt ? tsum[t] : 0;
+        int total = 0;
+        const int ex = block_exclusive_scan(v, wtot, &total);
+        if (t < nt) tsum[t] = carry + ex;
+        carry += total;
     }
     if (threadIdx.x == 0) p[n] = carry;
 }
 
-// Offsets of every entry and zero values at the padding (once per pattern): thread per row.
+__global__ __launch_bounds__(BLOCK) void k_bp_add(int64_t n, const int32_t* __restrict__ tsum, int32_t* __restrict__ p) {
+    const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (i < n) p[i] += tsum[i / BP_TILE];
+}
+
+// Offsets of every entry and zero values at the padding (once per pattern): 8 lanes per row.
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_bp_pack(int64_t n, const int32_t* __restrict__ rp,
                                                    const int32_t* __restrict__ ci, const int32_t* __restrict__ p,
                                                    int E, int LPR, int16_t* __restrict__ off, T* __restrict__ val) {
-    const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    const int64_t gt = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    const int64_t i = gt / 8;
+    const int sub = (int)(gt % 8);
     if (i >= n) return;
     const int a = rp[i], L = rp[i + 1] - a;
     const int c0 = p[i], LP = p[i + 1] - c0;
-    for (int kk = 0; kk < LP * E; ++kk) {
+    for (int kk = sub; kk < LP * E; kk += 8) {
         const int64_t q = bp_pos(c0, LP, kk, E, LPR);
         if (kk < L) {
             off[q] = (int16_t)(ci[a + kk] - i);
@@ -238,42 +253,6 @@ __global__ __launch_bounds__(BLOCK) void k_bp_values(int64_t n, const int32_t* _
         double v = val[a + kk];
         if (dinv) v *= dinv[ci[a + kk]];
         out[bp_pos(c0, LP, kk, E, LPR)] = (T)v;
-    }
-}
-
-// y = s A win, vout = s win (vout may be null), s = ctl->inv_h; float64 accumulation.
-template <typename T, int E, int LPR>
-__global__ __launch_bounds__(BLOCK) void k_spmv_bp(int64_t n, const int32_t* __restrict__ p,
-                                                   const int16_t* __restrict__ off, const T* __restrict__ val,
-                                                   const T* __restrict__ win, T* __restrict__ vout,
-                                                   T* __restrict__ y, const Ctl* __restrict__ ctl, int remap) {
-    if (ctl->done) return;
-    const double s = ctl->inv_h;
-    const unsigned lb = remap ? xcd_block(blockIdx.x, gridDim.x) : blockIdx.x;
-    const int64_t gt = (int64_t)lb * BLOCK + threadIdx.x;
-    const int64_t row = gt / LPR;
-    const int sub = (int)(gt % LPR);
-    double acc = 0.0;
-    const bool active = row < n;
-    if (active) {
-        const int a = p[row], e = p[row + 1];
-        const T* xr = win + row;
-        for (int q = a + sub; q < e; q += LPR) {
-            int16_t c[E];
-            T v[E];
-            __builtin_memcpy(c, __builtin_assume_aligned(off + (int64_t)q * E, 2 * E), sizeof(c));
-            __builtin_memcpy(v, __builtin_assume_aligned(val + (int64_t)q * E, 16), sizeof(v));
-            double pr[E];
-#pragma unroll
-            for (int t = 0; t < E; ++t) pr[t] = to_d(v[t]) * to_d(xr[c[t]]);
-#pragma unroll
-            for (int t = 0; t < E; ++t) acc += pr[t];
-        }
-    }
-    acc = group_sum<LPR>(acc);
-    if (active && sub == 0) {
-        y[row] = (T)(s * acc);
-        if (vout) vout[row] = (T)(s * to_d(win[row]));
     }
 }
 
@@ -338,6 +317,49 @@ __global__ __launch_bounds__(BLOCK) void k_spmm(int64_t n, const int32_t* __rest
     }
 }
 
+// Z[:, c0 + c] = A W[:, c0 + c], c < kc <= 16, with W given row-major (Wr[row * ldr + col],
+// ldr a multiple of 16): each entry of A reads the 16 coefficients of its column as one 128-byte
+// line, and neighbouring rows reuse those lines from the cache.
+template <int LPR>
+__global__ __launch_bounds__(BLOCK) void k_spmm_rows(int64_t n, const int32_t* __restrict__ rp,
+                                                     const int32_t* __restrict__ ci, const double* __restrict__ val,
+                                                     const double* __restrict__ Wr, int ldr, int c0, int kc,
+                                                     double* __restrict__ Z, int64_t ld) {
+    const int64_t gt = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    const int64_t row = gt / LPR;
+    const int sub = (int)(gt % LPR);
+    double acc[16];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) acc[c] = 0.0;
+    const bool active = row < n;
+    if (active) {
+        const int a = rp[row], e = rp[row + 1];
+        for (int j = a + sub; j < e; j += LPR) {
+            const double v = val[j];
+            const double* w = Wr + (int64_t)ci[j] * ldr + c0;
+            double wv[16];
+            __builtin_memcpy(wv, __builtin_assume_aligned(w, 128), sizeof(wv));
+#pragma unroll
+            for (int c = 0; c < 16; ++c) acc[c] += v * wv[c];
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 16; ++c) acc[c] = group_sum<LPR>(acc[c]);
+    if (active && sub == 0) {
+#pragma unroll
+        for (int c = 0; c < 16; ++c)
+            if (c < kc) Z[(int64_t)(c0 + c) * ld + row] = acc[c];
+    }
+}
+
+// Wr[r * ldr + c] = W[c * ld + r] for r < n, c < k.
+__global__ __launch_bounds__(BLOCK) void k_to_rows(int64_t n, const double* __restrict__ W, int64_t ld, int k,
+                                                   double* __restrict__ Wr, int ldr) {
+    const int64_t r = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (r >= n) return;
+    for (int c = 0; c < k; ++c) Wr[r * ldr + c] = W[(int64_t)c * ld + r];
+}
+
 __global__ __launch_bounds__(BLOCK) void k_to_f32(int64_t count, const double* __restrict__ in,
                                                   float* __restrict__ out) {
     const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
@@ -387,12 +409,18 @@ template void launch_spmv_arnoldi<float>(int, int, int, int64_t, const int32_t*,
                                          const float*, float*, float*, const Ctl*, hipStream_t, hipEvent_t,
                                          hipEvent_t);
 
+int64_t bp_scratch_ints(int64_t n) { return (n + BP_TILE - 1) / BP_TILE; }
+
 int bp_setup(int64_t n, const int32_t* rp, const int32_t* ci, int E, int LPR, int32_t* p, int16_t* off, void* val,
-             bool f32, hipStream_t st) {
-    if ((E != 4 && E != 8) || (LPR != 2 && LPR != 4 && LPR != 8)) return -1;
-    k_bp_scan<<<1, 1024, 0, st>>>(n, rp, E, p);
-    if (f32) k_bp_pack<float><<<grid_for(n), BLOCK, 0, st>>>(n, rp, ci, p, E, LPR, off, static_cast<float*>(val));
-    else k_bp_pack<double><<<grid_for(n), BLOCK, 0, st>>>(n, rp, ci, p, E, LPR, off, static_cast<double*>(val));
+             bool f32, int32_t* scratch, int64_t scratch_ints, hipStream_t st) {
+    if ((E != 4 && E != 8) || (LPR != 2 && LPR != 4 && LPR != 8) || n < 1) return -1;
+    const int64_t nt = bp_scratch_ints(n);
+    if (nt > scratch_ints || nt > INT32_MAX) return -1;
+    k_bp_tiles<<<(unsigned)nt, 1024, 0, st>>>(n, rp, E, p, scratch);
+    k_bp_tile_offsets<<<1, 1024, 0, st>>>(n, (int)nt, scratch, p);
+    k_bp_add<<<grid_for(n), BLOCK, 0, st>>>(n, scratch, p);
+    if (f32) k_bp_pack<float><<<grid_for(n * 8), BLOCK, 0, st>>>(n, rp, ci, p, E, LPR, off, static_cast<float*>(val));
+    else k_bp_pack<double><<<grid_for(n * 8), BLOCK, 0, st>>>(n, rp, ci, p, E, LPR, off, static_cast<double*>(val));
     return 0;
 }
 
@@ -406,23 +434,6 @@ template void launch_bp_values<double>(int64_t, const int32_t*, const int32_t*, 
 template void launch_bp_values<float>(int64_t, const int32_t*, const int32_t*, const double*, const double*,
                                       const int32_t*, int, int, float*, hipStream_t);
 
-template <typename T>
-void launch_spmv_bp(int E, int LPR, int remap, int64_t n, const int32_t* p, const int16_t* off, const T* val,
-                    const T* win, T* vout, T* y, const Ctl* ctl, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
-#define RS_BP(EE, L)                                                                                             \
-    hipExtLaunchKernelGGL(k_spmv_bp<T, EE, L>, dim3(grid_for(n * L)), dim3(BLOCK), 0, st, ev0, ev1, 0, n, p, off, \
-                          val, win, vout, y, ctl, remap)
-    if (E == 8) {
-        if (LPR == 2) RS_BP(8, 2);
-        else if (LPR == 4) RS_BP(8, 4);
-        else RS_BP(8, 8);
-    } else {
-        if (LPR == 2) RS_BP(4, 2);
-        else if (LPR == 4) RS_BP(4, 4);
-        else RS_BP(4, 8);
-    }
-#undef RS_BP
-}
 template void launch_spmv_bp<double>(int, int, int, int64_t, const int32_t*, const int16_t*, const double*,
                                      const double*, double*, double*, const Ctl*, hipStream_t, hipEvent_t, hipEvent_t);
 template void launch_spmv_bp<float>(int, int, int, int64_t, const int32_t*, const int16_t*, const float*,
@@ -459,6 +470,20 @@ void launch_spmm(int lpr, int64_t n, const int32_t* rp, const int32_t* ci, const
 #undef RS_CALL
         }
     }
+}
+
+void launch_spmm_rows(int lpr, int64_t n, const int32_t* rp, const int32_t* ci, const double* val, const double* Wr,
+                      int ldr, int k, double* Z, int64_t ld, hipStream_t st) {
+    for (int c0 = 0; c0 < k; c0 += 16) {
+        const int kc = (k - c0) < 16 ? (k - c0) : 16;
+#define RS_CALL(L) k_spmm_rows<L><<<grid_for(n * L), BLOCK, 0, st>>>(n, rp, ci, val, Wr, ldr, c0, kc, Z, ld)
+        RS_LPR_DISPATCH(lpr, RS_CALL)
+#undef RS_CALL
+    }
+}
+
+void launch_to_rows(int64_t n, const double* W, int64_t ld, int k, double* Wr, int ldr, hipStream_t st) {
+    k_to_rows<<<grid_for(n), BLOCK, 0, st>>>(n, W, ld, k, Wr, ldr);
 }
 
 void launch_to_f32(int64_t count, const double* in, float* out, hipStream_t st) {

@@ -15,9 +15,11 @@ namespace rs {
 // Banded padded CSR for the Arnoldi product (rows in chunks of E entries, 16-bit column offsets
 // col - row, entries dealt round-robin over the LPR lanes of a row in every round of chunks).
 // bp_setup: chunk offsets p (n + 1), offsets of every entry and zeros at the padding; returns -1
-// for an unsupported (E, LPR).  Requires |col - row| <= BP_MAX_OFFSET for every entry.
+// for an unsupported (E, LPR) or a scratch buffer (int32, device) shorter than
+// bp_scratch_ints(n).  Requires |col - row| <= BP_MAX_OFFSET for every entry.
+int64_t bp_scratch_ints(int64_t n);
 int bp_setup(int64_t n, const int32_t* rp, const int32_t* ci, int E, int LPR, int32_t* p, int16_t* off, void* val,
-             bool f32, hipStream_t st);
+             bool f32, int32_t* scratch, int64_t scratch_ints, hipStream_t st);
 template <typename T>
 void launch_bp_values(int64_t n, const int32_t* rp, const int32_t* ci, const double* val, const double* dinv,
                       const int32_t* p, int E, int LPR, T* out, hipStream_t st);
@@ -130,7 +132,15 @@ void launch_form_w(int64_t n, int64_t npad, const double* X, int64_t ldx, int c,
 // ctl->L = chol(G) for G = ctl->red (k x k column-major)
 void launch_cholesky(int k, Ctl* ctl, hipStream_t st);
 // W[r, :k] <- L^{-1} W[r, :k]^T (rows < npad)
-void launch_trsm_rows(int64_t npad, double* W, int64_t ldw, int k, const Ctl* ctl, hipStream_t st);
+// W <- W L^{-T} row by row; also writes the result row-major to Wr (row r at Wr + r ldr) when
+// Wr is not null.
+void launch_trsm_rows(int64_t npad, double* W, int64_t ldw, int k, const Ctl* ctl, hipStream_t st,
+                      double* Wr = nullptr, int ldr = 0);
+// Z = A W for W kept row-major (ldr a multiple of 16, 128-byte aligned rows); Z column-major (ld).
+void launch_spmm_rows(int lpr, int64_t n, const int32_t* rp, const int32_t* ci, const double* val, const double* Wr,
+                      int ldr, int k, double* Z, int64_t ld, hipStream_t st);
+// Wr (row-major, ldr) = W (column-major, ld), n rows, k columns.
+void launch_to_rows(int64_t n, const double* W, int64_t ld, int k, double* Wr, int ldr, hipStream_t st);
 
 // ---- one-block persistent path for small systems (k_small.hip) ----
 constexpr int SMALL_MMAX = 64;     // restart limit of the one-block solver
