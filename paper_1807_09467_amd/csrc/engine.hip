@@ -246,7 +246,7 @@ size_t layout(rsolve_seq* s, const rsolve_config& c, int64_t n, int64_t nnz_max,
     int64_t tsq_rows = 0, tsq_ld = 0;
     double *t0 = nullptr, *t1 = nullptr;
     if (k && sn) {
-        tsq_rows = ((n + TSQR_PANEL - 1) / TSQR_PANEL) * sn;
+        tsq_rows = ((n + TSQR_MIN_PANEL - 1) / TSQR_MIN_PANEL) * sn;
         tsq_ld = pad64(tsq_rows);
         t0 = cv.take<double>((size_t)tsq_ld * sn);
         t1 = cv.take<double>((size_t)tsq_ld * sn);
@@ -1098,7 +1098,8 @@ int rsolve_update_recycle(rsolve_seq* s, const double* x) {
     int lvl = 0;
     const double* R = nullptr;
     for (;;) {
-        const int P = (int)((rows + TSQR_PANEL - 1) / TSQR_PANEL);
+        const int pr = tsqr_panel_rows(cc);
+        const int P = (int)((rows + pr - 1) / pr);
         double* out = s->tsq[lvl & 1];
         launch_tsqr_level(rows, M, ldm, cc, out, s->tsq_ld, P, stm);
         R = out;
@@ -1397,7 +1398,7 @@ size_t kws_layout(int64_t n, int cols, char* base, KWs* o) {
     Carver cv{base};
     Ctl* ctl = cv.take<Ctl>(1);
     double* gp = cv.take<double>((size_t)GRAM_PARTIAL);
-    const int64_t rows = ((n + TSQR_PANEL - 1) / TSQR_PANEL) * std::max(cols, 1);
+    const int64_t rows = ((n + TSQR_MIN_PANEL - 1) / TSQR_MIN_PANEL) * std::max(cols, 1);
     const int64_t tld = pad64(rows);
     double* t0 = cv.take<double>((size_t)tld * std::max(cols, 1));
     double* t1 = cv.take<double>((size_t)tld * std::max(cols, 1));
@@ -1447,7 +1448,8 @@ int rsolve_snapshot_svd(int64_t n, const double* X, int64_t ldx, int32_t c, int3
     const double* R = nullptr;
     int lvl = 0;
     for (;;) {
-        const int P = (int)((rows + TSQR_PANEL - 1) / TSQR_PANEL);
+        const int pr = tsqr_panel_rows(c);
+        const int P = (int)((rows + pr - 1) / pr);
         double* out = (lvl & 1) ? w.t1 : w.t0;
         launch_tsqr_level(rows, M, ldm, c, out, w.tld, P, st);
         R = out;

@@ -285,6 +285,95 @@ __global__ __launch_bounds__(TSQR_PANEL) void k_tsqr_level(int64_t rows, const d
 }
 
 // ---------------------------------------------------------------------------
+// One TSQR level with one wavefront per panel of 64 RPL rows (lane l holds rows l, l + 64, ...),
+// for c <= C <= 32.  No block barriers: for column CC the squared norm below the diagonal and the
+// reflection's dot products all come from one transposed wavefront reduction of a[CC] a[j]
+// (rows below CC, columns j >= CC), and the diagonal row is broadcast through LDS with the
+// sums.  The column loop is unrolled at compile time, so iteration CC touches only columns
+// CC..C-1.  Output as k_tsqr_level: the c x c R factor of panel p in rows [p c, p c + c) of S.
+// ---------------------------------------------------------------------------
+constexpr int pow2ceil(int x) {
+    int p = 1;
+    while (p < x) p *= 2;
+    return p;
+}
+
+template <int C, int RPL, int CC>
+__device__ __forceinline__ void tsqr_wave_column(double (&a)[RPL][C], int lane, int c, double* __restrict__ S,
+                                                 int64_t lds, int64_t orow, double* rowb, double* sigb) {
+    if constexpr (CC < C) {
+        constexpr int NV = C - CC;          // columns CC..C-1
+        constexpr int NT = pow2ceil(NV);    // values of the transposed reduction
+        constexpr int OWN = WAVE / NT;      // column j's sum ends in lane j OWN
+        if (CC < c) {
+            double p[NT];
+#pragma unroll
+            for (int j = 0; j < NT; ++j) p[j] = 0.0;
+#pragma unroll
+            for (int q = 0; q < RPL; ++q) {
+                const double x = (lane + WAVE * q > CC) ? a[q][CC] : 0.0;
+#pragma unroll
+                for (int j = 0; j < NV; ++j) p[j] += x * a[q][CC + j];
+            }
+            wave_tr_reduce<NT>(p);
+            if ((lane & (OWN - 1)) == 0 && lane / OWN < NV) sigb[lane / OWN] = p[0];
+            if (lane == CC) {
+#pragma unroll
+                for (int j = 0; j < NV; ++j) rowb[j] = a[0][CC + j];
+            }
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0): the LDS writes above have landed
+            __builtin_amdgcn_wave_barrier();
+            const double alpha = rowb[0];
+            const double nrm2 = alpha * alpha + sigb[0];
+            if (nrm2 > 0.0) {   // uniform; a zero column needs no reflection
+                const double nrm = sqrt(nrm2);
+                const double beta = (alpha >= 0.0) ? -nrm : nrm;
+                const double tau = (beta - alpha) / beta;
+                const double inv = 1.0 / (alpha - beta);
+                // d_j = v^T a_j with v = (1, a_{CC+1..}[CC] / (alpha - beta))
+                double d[NV];
+#pragma unroll
+                for (int j = 1; j < NV; ++j) d[j] = rowb[j] + sigb[j] * inv;
+#pragma unroll
+                for (int q = 0; q < RPL; ++q) {
+                    const int t = lane + WAVE * q;
+                    const double v = (t > CC) ? a[q][CC] * inv : ((t == CC) ? 1.0 : 0.0);
+                    const double tv = tau * v;
+#pragma unroll
+                    for (int j = 1; j < NV; ++j) a[q][CC + j] -= tv * d[j];
+                    if (t == CC) a[q][CC] = beta;
+                    else if (t > CC) a[q][CC] = 0.0;
+                }
+            }
+            __builtin_amdgcn_wave_barrier();   // the reads above precede the next column's writes
+            if (lane < c) S[(int64_t)CC * lds + orow] = (lane <= CC) ? a[0][CC] : 0.0;
+        }
+        tsqr_wave_column<C, RPL, CC + 1>(a, lane, c, S, lds, orow, rowb, sigb);
+    }
+}
+
+template <int C, int RPL>
+__global__ __launch_bounds__(256) void k_tsqr_wave(int64_t rows, const double* __restrict__ M, int64_t ldm, int c,
+                                                   double* __restrict__ S, int64_t lds) {
+    __shared__ __attribute__((aligned(16))) double bufs[256 / WAVE][2][C];
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int wv = threadIdx.x / WAVE;
+    const int64_t panel = (int64_t)blockIdx.x * (256 / WAVE) + wv;
+    const int64_t r0 = panel * WAVE * RPL;
+    if (r0 >= rows) return;   // a wavefront past the last panel: nothing to factor or write
+    double a[RPL][C];
+#pragma unroll
+    for (int q = 0; q < RPL; ++q)
+#pragma unroll
+        for (int j = 0; j < C; ++j) {
+            const int64_t row = r0 + lane + WAVE * q;
+            a[q][j] = (row < rows && j < c) ? M[(int64_t)j * ldm + row] : 0.0;
+        }
+    tsqr_wave_column<C, RPL, 0>(a, lane, c, S, lds, panel * c + lane, bufs[wv][0], bufs[wv][1]);
+}
+
+// ---------------------------------------------------------------------------
 // One-sided Jacobi SVD of R (c x c <= 64) in one block: columns are rotated in
 // pairs (round-robin ordering, 8 threads per pair) until all pairs are
 // numerically orthogonal; the rotations accumulate in V, so R V = U Sigma.
@@ -428,11 +517,14 @@ void launch_gram_reduce(const double* partial, int nblk, int pq, double* dst, hi
 
 void launch_small_lu(const double* src, int k, Ctl* ctl, hipStream_t st) { k_small_lu<<<1, WAVE, 0, st>>>(src, k, ctl); }
 
+int tsqr_panel_rows(int c) { return c <= 8 ? 512 : (c <= 16 ? 256 : (c <= 32 ? 128 : TSQR_PANEL)); }
+
 void launch_tsqr_level(int64_t rows, const double* M, int64_t ldm, int c, double* S, int64_t lds, int npanels,
                        hipStream_t st) {
-    if (c <= 8) k_tsqr_level<8><<<npanels, TSQR_PANEL, 0, st>>>(rows, M, ldm, c, S, lds);
-    else if (c <= 16) k_tsqr_level<16><<<npanels, TSQR_PANEL, 0, st>>>(rows, M, ldm, c, S, lds);
-    else if (c <= 32) k_tsqr_level<32><<<npanels, TSQR_PANEL, 0, st>>>(rows, M, ldm, c, S, lds);
+    const unsigned wb = (unsigned)((npanels + 3) / 4);   // four one-wavefront panels per block
+    if (c <= 8) k_tsqr_wave<8, 8><<<wb, 256, 0, st>>>(rows, M, ldm, c, S, lds);
+    else if (c <= 16) k_tsqr_wave<16, 4><<<wb, 256, 0, st>>>(rows, M, ldm, c, S, lds);
+    else if (c <= 32) k_tsqr_wave<32, 2><<<wb, 256, 0, st>>>(rows, M, ldm, c, S, lds);
     else k_tsqr_level<64><<<npanels, TSQR_PANEL, 0, st>>>(rows, M, ldm, c, S, lds);
 }
 

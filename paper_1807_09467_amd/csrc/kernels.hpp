@@ -120,7 +120,10 @@ int launch_gram_tn(int64_t n, const double* A, int64_t lda, int p, const double*
 void launch_gram_reduce(const double* partial, int nblk, int pq, double* dst, hipStream_t st);
 // LU with partial pivoting of E (k x k, column-major in src) into ctl->E/piv, ctl->cond1
 void launch_small_lu(const double* src, int k, Ctl* ctl, hipStream_t st);
-// one TSQR level: panels of TSQR_PANEL rows of M (rows x c) -> stacked R factors S ((P*c) x c, ld_s)
+// one TSQR level: panels of tsqr_panel_rows(c) rows of M (rows x c) -> stacked R factors S
+// ((P*c) x c, ld_s), P = ceil(rows / tsqr_panel_rows(c)) = npanels
+constexpr int TSQR_MIN_PANEL = 128;   // the smallest panel of any c (sizes the level buffers)
+int tsqr_panel_rows(int c);
 void launch_tsqr_level(int64_t rows, const double* M, int64_t ldm, int c, double* S, int64_t lds, int npanels,
                        hipStream_t st);
 // one-sided Jacobi SVD of the c x c matrix R (column-major, ld); writes ctl->sigma, ctl->rank,

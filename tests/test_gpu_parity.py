@@ -78,7 +78,9 @@ def test_gram_tn_mfma(gpu_ctx, n, p, q):
     assert np.all(np.abs(C - ref) <= bound), np.abs(C - ref).max()
 
 
-@pytest.mark.parametrize("n,c,k", [(50, 4, 3), (1089, 10, 5), (4000, 20, 10), (70001, 32, 16), (300, 64, 64)])
+@pytest.mark.parametrize("n,c,k", [(50, 4, 3), (1089, 10, 5), (4000, 20, 10), (70001, 32, 16), (300, 64, 64),
+                                   (513, 8, 8), (257, 16, 4), (129, 32, 32), (128, 32, 16), (40000, 17, 9),
+                                   (12345, 64, 20)])
 def test_snapshot_svd_against_lapack(gpu_ctx, n, c, k):
     from paper_1807_09467_amd import rsolve
     rng = np.random.default_rng(c)
@@ -97,7 +99,8 @@ def test_snapshot_svd_against_lapack(gpu_ctx, n, c, k):
     # subspace of the leading keff singular vectors (principal angles), gap-scaled
     Uk = np.linalg.svd(X, full_matrices=False)[0][:, :keff]
     cosines = np.linalg.svd(Uk.T @ Wn, compute_uv=False)
-    gap = (s_ref[keff - 1] - s_ref[keff]) / s_ref[0] if keff < c else 1.0
+    # gap to the rest of the spectrum; with keff = c the rest is the null space (singular value 0)
+    gap = (s_ref[keff - 1] - (s_ref[keff] if keff < c else 0.0)) / s_ref[0]
     assert 1.0 - cosines.min() <= max(1e-24 / gap ** 2, 1e-14) * 100
 
 
