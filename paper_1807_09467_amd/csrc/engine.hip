@@ -923,7 +923,7 @@ int rsolve_solve(rsolve_seq* s, const rsolve_csr* A, const double* b, const doub
             launch_to_rows(n, s->W, ld, k, s->Wr, s->ldr, stm);
             s->wr_ok = true;
         }
-        launch_spmm_rows(s->lpr, n, A->row_ptr, A->col_idx, A->val, s->Wr, s->ldr, k, s->Z, ld, stm);
+        launch_spmm_rows(n, A->row_ptr, A->col_idx, A->val, s->Wr, s->ldr, k, s->Z, ld, stm);
         const int gb = launch_gram_tn(ld, s->W, ld, k, s->Z, ld, k, s->gpart, s->gblk, stm);
         launch_gram_reduce(s->gpart, gb, k * k, ctl_red(s->ctl), stm);
         launch_small_lu(ctl_red(s->ctl), k, s->ctl, stm);

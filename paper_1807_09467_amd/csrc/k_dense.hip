@@ -47,21 +47,38 @@ __global__ __launch_bounds__(BLOCK) void k_gram_tn(int64_t n, const double* __re
 #pragma unroll
         for (int b = 0; b < TQ; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
     const int64_t nslab = (n + R - 1) / R;
-    for (int64_t sl = blockIdx.x; sl < nslab; sl += nblk) {
+    // the next slab's operands are loaded into registers while the current one is multiplied
+    constexpr int NA = TP * 16 * R / BLOCK, NB = TQ * 16 * R / BLOCK;
+    double pa[NA], pb[NB];
+    auto fetch = [&](int64_t sl) {
         const int64_t r0 = sl * R;
 #pragma unroll
-        for (int t0 = 0; t0 < TP * 16 * R; t0 += BLOCK) {
-            const int t = t0 + threadIdx.x, c = t / R, r = t % R;
+        for (int u = 0; u < NA; ++u) {
+            const int t = u * BLOCK + threadIdx.x, c = t / R, r = t % R;
             const int64_t row = r0 + r;
-            As[c * RS + r] = (c < p && row < n) ? A[(int64_t)c * lda + row] : 0.0;
+            pa[u] = (sl < nslab && c < p && row < n) ? A[(int64_t)c * lda + row] : 0.0;
         }
 #pragma unroll
-        for (int t0 = 0; t0 < TQ * 16 * R; t0 += BLOCK) {
-            const int t = t0 + threadIdx.x, c = t / R, r = t % R;
+        for (int u = 0; u < NB; ++u) {
+            const int t = u * BLOCK + threadIdx.x, c = t / R, r = t % R;
             const int64_t row = r0 + r;
-            Bs[c * RS + r] = (c < q && row < n) ? B[(int64_t)c * ldb + row] : 0.0;
+            pb[u] = (sl < nslab && c < q && row < n) ? B[(int64_t)c * ldb + row] : 0.0;
+        }
+    };
+    fetch(blockIdx.x);
+    for (int64_t sl = blockIdx.x; sl < nslab; sl += nblk) {
+#pragma unroll
+        for (int u = 0; u < NA; ++u) {
+            const int t = u * BLOCK + threadIdx.x;
+            As[(t / R) * RS + t % R] = pa[u];
+        }
+#pragma unroll
+        for (int u = 0; u < NB; ++u) {
+            const int t = u * BLOCK + threadIdx.x;
+            Bs[(t / R) * RS + t % R] = pb[u];
         }
         __syncthreads();
+        fetch(sl + nblk);
 #pragma unroll
         for (int g = 0; g < RW / 4; ++g) {
             const int rr = wv * RW + g * 4 + lk;
@@ -476,19 +493,31 @@ __global__ __launch_bounds__(BLOCK) void k_trsm_rows(int64_t npad, double* __res
     __syncthreads();
     const int64_t r = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
     if (r >= npad) return;
+    // forward substitution with compile-time register indices (columns j >= k stay zero)
     double w[K];
 #pragma unroll
     for (int j = 0; j < K; ++j) w[j] = (j < k) ? W[(int64_t)j * ldw + r] : 0.0;
-    for (int j = 0; j < k; ++j) {
-        const double xj = w[0] / Ls[j * K + j];
-        W[(int64_t)j * ldw + r] = xj;
-        if (Wr) Wr[r * ldr + j] = xj;
 #pragma unroll
-        for (int i = 1; i < K; ++i)
-            if (j + i < k) w[i] -= Ls[(j + i) * K + j] * xj;
+    for (int j = 0; j < K; ++j) {
+        if (j < k) {
+            w[j] /= Ls[j * K + j];
 #pragma unroll
-        for (int i = 0; i + 1 < K; ++i) w[i] = w[i + 1];
-        w[K - 1] = 0.0;
+            for (int i = j + 1; i < K; ++i)
+                if (i < k) w[i] -= Ls[i * K + j] * w[j];
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < K; ++j)
+        if (j < k) W[(int64_t)j * ldw + r] = w[j];
+    if (Wr) {
+        // the row-major copy: this row's ldr-wide slot, written as 16-byte stores (zeros past k)
+        double* dst = Wr + r * ldr;
+#pragma unroll
+        for (int j = 0; j < K; j += 2)
+            if (j < ldr) {
+                double pr[2] = {j < k ? w[j] : 0.0, j + 1 < k ? w[j + 1] : 0.0};
+                __builtin_memcpy(__builtin_assume_aligned(dst + j, 16), pr, sizeof(pr));
+            }
     }
 }
 

@@ -49,9 +49,6 @@ void launch_residual(int lpr, int64_t n, const int32_t* rp, const int32_t* ci, c
 // y = A x (float64)
 void launch_spmv(int lpr, int64_t n, const int32_t* rp, const int32_t* ci, const double* val, const double* x,
                  double* y, hipStream_t st);
-// Z[:, c] = A W[:, c] for c < k (float64)
-void launch_spmm(int lpr, int64_t n, const int32_t* rp, const int32_t* ci, const double* val, const double* W,
-                 int64_t ld, int k, double* Z, hipStream_t st);
 // elementwise float64 -> float32 (count entries)
 void launch_to_f32(int64_t count, const double* in, float* out, hipStream_t st);
 
@@ -140,8 +137,8 @@ void launch_cholesky(int k, Ctl* ctl, hipStream_t st);
 void launch_trsm_rows(int64_t npad, double* W, int64_t ldw, int k, const Ctl* ctl, hipStream_t st,
                       double* Wr = nullptr, int ldr = 0);
 // Z = A W for W kept row-major (ldr a multiple of 16, 128-byte aligned rows); Z column-major (ld).
-void launch_spmm_rows(int lpr, int64_t n, const int32_t* rp, const int32_t* ci, const double* val, const double* Wr,
-                      int ldr, int k, double* Z, int64_t ld, hipStream_t st);
+void launch_spmm_rows(int64_t n, const int32_t* rp, const int32_t* ci, const double* val, const double* Wr, int ldr,
+                      int k, double* Z, int64_t ld, hipStream_t st);
 // Wr (row-major, ldr) = W (column-major, ld), n rows, k columns.
 void launch_to_rows(int64_t n, const double* W, int64_t ld, int k, double* Wr, int ldr, hipStream_t st);
 
