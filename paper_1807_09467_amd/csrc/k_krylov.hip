@@ -46,7 +46,7 @@ constexpr int RED_T = 1024;   // threads of the one-block reductions
 
 // sums[c] = sum over b of partial[c * nblk + b] for c < ncol, by every thread of a RED_T block:
 // each column gets a group of G threads (the largest power of two with G ncol <= RED_T, at most
-// nblk rounded up), each thread sums a lane-strided share with four accumulators, the group
+// nblk rounded up), each thread sums a lane-strided share with sixteen accumulators, the group
 // combines by butterfly within a wavefront and, for groups wider than one, over LDS in wave
 // order.  All loads of a thread are independent, so the block keeps RED_T of them in flight.
 // red: LDS scratch of RED_T / WAVE doubles.  Fixed order for given (nblk, ncol).  Ends with a
@@ -59,19 +59,27 @@ __device__ void reduce_columns(const double* __restrict__ partial, int nblk, int
     const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
     for (int c0 = 0; c0 < ncol; c0 += RED_T / G) {
         const int c = c0 + threadIdx.x / G;
-        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        // sixteen independent loads per round, so a thread waits for memory about nblk / (16 G)
+        // times rather than once per four loads
+        double a[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) a[u] = 0.0;
         if (c < ncol) {
             const double* src = partial + (int64_t)c * nblk;
             int b = sub;
-            for (; b + 3 * G < nblk; b += 4 * G) {
-                a0 += src[b];
-                a1 += src[b + G];
-                a2 += src[b + 2 * G];
-                a3 += src[b + 3 * G];
+            for (; b + 15 * G < nblk; b += 16 * G) {
+#pragma unroll
+                for (int u = 0; u < 16; ++u) a[u] += src[b + u * G];
             }
-            for (; b < nblk; b += G) a0 += src[b];
+#pragma unroll
+            for (int u = 0; u < 16; ++u)
+                if (b + u * G < nblk) a[u] += src[b + u * G];
         }
-        double v = (a0 + a1) + (a2 + a3);
+#pragma unroll
+        for (int w = 8; w > 0; w >>= 1)
+#pragma unroll
+            for (int u = 0; u < w; ++u) a[u] += a[u + w];
+        double v = a[0];
         for (int o = gw / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
         if (G > WAVE) {
             if (lane == 0) red[wv] = v;
