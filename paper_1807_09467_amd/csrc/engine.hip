@@ -534,7 +534,7 @@ void dcgs2_step(rsolve_seq* s, int j, int allowed, const SpOp& op, T* V, T* cons
     const int nw = std::min(16, (ncol + (ncol > 64 ? 7 : 3)) / (ncol > 64 ? 8 : 4));   // as the launcher
     const int64_t per_cu = nw >= 8 ? 2 : 32 / nw;
     const int64_t tiles = std::max<int64_t>(1, ld / (WAVE * (16 / (int64_t)sizeof(T))));
-    const int nb1 = (int)std::min<int64_t>({per_cu * s->cus, tiles, PARTIAL_DOUBLES / (2 * ncol), (int64_t)NBLK_MAX});
+    const int nb1 = (int)std::min<int64_t>({per_cu * s->cus, tiles, PARTIAL_DOUBLES / (2 * ncol) - 1, (int64_t)NBLK_MAX});
     {
         ProfEv pe(s, RSOLVE_PROF_DOTS, has_z ? j : MMAX, var_of(ncol), (ncol + 1.0) * w * nn);
         launch_dots2<T>(ld, ld, V, j, Wt, Zt, k, u, has_z ? z : u, s->partial, nb1, s->ctl, st, pe.e0, pe.e1);

@@ -594,19 +594,43 @@ __global__ __launch_bounds__(1024) void k_dots2(int64_t npad, int64_t ld, const 
     }
 }
 
+// sums[e] = sum over b of partial[e * nblk + b], e < nent: one wavefront per entry, eight loads
+// in flight per lane, fixed order.  Spreads the cross-block reduction of a sweep over many
+// compute units (one block reading every partial waits on remote caches for most of them).
+__global__ __launch_bounds__(1024) void k_colsum(const double* __restrict__ partial, int nblk, int nent,
+                                                 double* __restrict__ sums, const Ctl* __restrict__ ctl) {
+    if (ctl->done) return;
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int e = blockIdx.x * (1024 / WAVE) + threadIdx.x / WAVE;
+    if (e >= nent) return;
+    const double* src = partial + (int64_t)e * nblk;
+    double a[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) a[u] = 0.0;
+    int b = lane;
+    for (; b + 7 * WAVE < nblk; b += 8 * WAVE) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) a[u] += src[b + u * WAVE];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+        if (b + u * WAVE < nblk) a[u] += src[b + u * WAVE];
+    const double v = wave_sum(((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7])));
+    if (lane == 0) sums[e] = v;
+}
+
 // One block: reduce the sweep, complete and rotate column j-1, prepare step j's update.
 // has_z = 0 on the closing step of a cycle (no product was taken): only column j-1 completes.
 // The loads of the control block are issued together at the start, and the sums over the
 // Hessenberg matrix and F are split over the wavefronts, so the block waits for memory a few
 // times rather than once per term.
-__global__ __launch_bounds__(RED_T) void k_dcgs2_reduce(const double* __restrict__ partial, int nblk, int j, int k,
-                                                        int has_z, Ctl* __restrict__ ctl) {
+__global__ __launch_bounds__(RED_T) void k_dcgs2_reduce(const double* __restrict__ dsum, int j, int k, int has_z,
+                                                        Ctl* __restrict__ ctl) {
     if (ctl->done) return;
     constexpr int LDH = MMAX + 1;
     constexpr int LDR = MMAX + 1;
     constexpr int NW = RED_T / WAVE;
     __shared__ double sums[2 * (MMAX + 2 * KMAX + 1)];
-    __shared__ double red[NW];
     __shared__ double Es[KMAX * KMAX];
     __shared__ double cws[KMAX];
     __shared__ double wz[KMAX];
@@ -629,7 +653,8 @@ __global__ __launch_bounds__(RED_T) void k_dcgs2_reduce(const double* __restrict
         css[t] = ctl->cs[t];
         sns[t] = ctl->sn[t];
     }
-    reduce_columns(partial, nblk, 2 * ncol, sums, red);
+    for (int t = tid; t < 2 * ncol; t += RED_T) sums[t] = dsum[t];
+    __syncthreads();
     // sums[2 c] = col_c . u, sums[2 c + 1] = col_c . z; columns: V (0..j-1), W, A W, u
     const double* su = sums;
     if (wv == 0) {
@@ -692,6 +717,7 @@ __global__ __launch_bounds__(RED_T) void k_dcgs2_reduce(const double* __restrict
         // l < j - 1 kept in the control block (column j - 1 is hcol, added below)
         const int w = wv - 1;
         double ph0 = 0.0, ph1 = 0.0;
+#pragma unroll 4
         for (int l = w; l < j - 1; l += NH) {
             const double h = su[2 * l];
             if (lane <= l + 1) ph0 += ctl->Hs[lane + LDH * l] * h;
@@ -706,8 +732,10 @@ __global__ __launch_bounds__(RED_T) void k_dcgs2_reduce(const double* __restrict
         // the other waves: partial sums of (h^T F)_c = sum_l h_l F[l, c]
         const int w = wv - 1 - NH;
         double pf = 0.0;
-        if (lane < k)
+        if (lane < k) {
+#pragma unroll 4
             for (int l = w; l < j; l += NF) pf += su[2 * l] * ctl->F[l * KMAX + lane];
+        }
         pF[w][lane] = pf;
     }
     __syncthreads();
@@ -724,6 +752,7 @@ __global__ __launch_bounds__(RED_T) void k_dcgs2_reduce(const double* __restrict
     // partial sums of (F cws)_l over groups of recycle columns: wavefront w takes c = w, w + NW, ...
     for (int l = lane; l < j; l += WAVE) {
         double q = 0.0;
+#pragma unroll 4
         for (int c = wv; c < k; c += NW) q += ctl->F[l * KMAX + c] * cws[c];
         pQ[wv][l] = q;
     }
@@ -943,8 +972,12 @@ template void launch_dots2<float>(int64_t, int64_t, const float*, int, const flo
                                   const float*, const float*, double*, int, Ctl*, hipStream_t, hipEvent_t,
                                   hipEvent_t);
 
-void launch_dcgs2_reduce(const double* partial, int nblk, int j, int k, bool has_z, Ctl* ctl, hipStream_t st) {
-    k_dcgs2_reduce<<<1, RED_T, 0, st>>>(partial, nblk, j, k, has_z ? 1 : 0, ctl);
+void launch_dcgs2_reduce(double* partial, int nblk, int j, int k, bool has_z, Ctl* ctl, hipStream_t st) {
+    // the column sums go right after the partials
+    const int nent = 2 * (j + 2 * k + 1);
+    double* dsum = partial + (int64_t)nent * nblk;
+    k_colsum<<<(nent + 15) / 16, 1024, 0, st>>>(partial, nblk, nent, dsum, ctl);
+    k_dcgs2_reduce<<<1, RED_T, 0, st>>>(dsum, j, k, has_z ? 1 : 0, ctl);
 }
 
 template <typename T>

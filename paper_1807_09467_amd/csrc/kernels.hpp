@@ -88,7 +88,9 @@ template <typename T>
 void launch_dots2(int64_t npad, int64_t ld, const T* V, int nq, const T* W, const T* Z, int k, const T* u,
                   const T* z, double* partial, int nblk, Ctl* ctl, hipStream_t st, hipEvent_t ev0 = nullptr,
                   hipEvent_t ev1 = nullptr);
-void launch_dcgs2_reduce(const double* partial, int nblk, int j, int k, bool has_z, Ctl* ctl, hipStream_t st);
+// the sweep's column sums (written after the partials: partial needs 2 ncol (nblk + 1) doubles),
+// then the one-block reduction of the delayed scheme
+void launch_dcgs2_reduce(double* partial, int nblk, int j, int k, bool has_z, Ctl* ctl, hipStream_t st);
 template <typename T>
 void launch_dcgs2_update(int64_t npad, T* V, int64_t ld, int j, const T* Z, int k, T* u, const T* z, int nblk,
                          const Ctl* ctl, hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
