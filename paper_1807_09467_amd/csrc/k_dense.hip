@@ -390,6 +390,83 @@ __global__ __launch_bounds__(256) void k_tsqr_wave(int64_t rows, const double* _
     tsqr_wave_column<C, RPL, 0>(a, lane, c, S, lds, panel * c + lane, bufs[wv][0], bufs[wv][1]);
 }
 
+// The same factorisation with a runtime column loop (the register arrays shift by one column per
+// step, so every index stays a compile-time constant): a few kilobytes of code instead of tens,
+// for the levels with few panels, where one wavefront's instruction fetches, not arithmetic, set
+// the time.
+template <int C, int RPL>
+__global__ __launch_bounds__(256) void k_tsqr_wave_loop(int64_t rows, const double* __restrict__ M, int64_t ldm,
+                                                        int c, double* __restrict__ S, int64_t lds) {
+    __shared__ __attribute__((aligned(16))) double bufs[256 / WAVE][2][C];
+    constexpr int OWN = WAVE / C;
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int wv = threadIdx.x / WAVE;
+    const int64_t panel = (int64_t)blockIdx.x * (256 / WAVE) + wv;
+    const int64_t r0 = panel * WAVE * RPL;
+    if (r0 >= rows) return;
+    double* rowb = bufs[wv][0];
+    double* sigb = bufs[wv][1];
+    double a[RPL][C];
+#pragma unroll
+    for (int q = 0; q < RPL; ++q)
+#pragma unroll
+        for (int j = 0; j < C; ++j) {
+            const int64_t row = r0 + lane + WAVE * q;
+            a[q][j] = (row < rows && j < c) ? M[(int64_t)j * ldm + row] : 0.0;
+        }
+    const int64_t orow = panel * c + lane;
+    for (int cc = 0; cc < c; ++cc) {
+        // a[q][0] is column cc; a[q][j] column cc + j
+        double p[C];
+#pragma unroll
+        for (int j = 0; j < C; ++j) p[j] = 0.0;
+#pragma unroll
+        for (int q = 0; q < RPL; ++q) {
+            const double x = (lane + WAVE * q > cc) ? a[q][0] : 0.0;
+#pragma unroll
+            for (int j = 0; j < C; ++j) p[j] += x * a[q][j];
+        }
+        wave_tr_reduce<C>(p);
+        if ((lane & (OWN - 1)) == 0) sigb[lane / OWN] = p[0];
+        if (lane == cc) {
+#pragma unroll
+            for (int j = 0; j < C; ++j) rowb[j] = a[0][j];
+        }
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0)
+        __builtin_amdgcn_wave_barrier();
+        const double alpha = rowb[0];
+        const double nrm2 = alpha * alpha + sigb[0];
+        if (nrm2 > 0.0) {
+            const double nrm = sqrt(nrm2);
+            const double beta = (alpha >= 0.0) ? -nrm : nrm;
+            const double tau = (beta - alpha) / beta;
+            const double inv = 1.0 / (alpha - beta);
+            double d[C];
+#pragma unroll
+            for (int j = 1; j < C; ++j) d[j] = rowb[j] + sigb[j] * inv;
+#pragma unroll
+            for (int q = 0; q < RPL; ++q) {
+                const int t = lane + WAVE * q;
+                const double v = (t > cc) ? a[q][0] * inv : ((t == cc) ? 1.0 : 0.0);
+                const double tv = tau * v;
+#pragma unroll
+                for (int j = 1; j < C; ++j) a[q][j] -= tv * d[j];
+                if (t == cc) a[q][0] = beta;
+                else if (t > cc) a[q][0] = 0.0;
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+        if (lane < c) S[(int64_t)cc * lds + orow] = (lane <= cc) ? a[0][0] : 0.0;
+#pragma unroll
+        for (int q = 0; q < RPL; ++q) {
+#pragma unroll
+            for (int j = 0; j + 1 < C; ++j) a[q][j] = a[q][j + 1];
+            a[q][C - 1] = 0.0;
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // One-sided Jacobi SVD of R (c x c <= 64) in one block: columns are rotated in
 // pairs (round-robin ordering, 8 threads per pair) until all pairs are
@@ -551,10 +628,21 @@ int tsqr_panel_rows(int c) { return c <= 8 ? 512 : (c <= 16 ? 256 : (c <= 32 ? 1
 void launch_tsqr_level(int64_t rows, const double* M, int64_t ldm, int c, double* S, int64_t lds, int npanels,
                        hipStream_t st) {
     const unsigned wb = (unsigned)((npanels + 3) / 4);   // four one-wavefront panels per block
-    if (c <= 8) k_tsqr_wave<8, 8><<<wb, 256, 0, st>>>(rows, M, ldm, c, S, lds);
-    else if (c <= 16) k_tsqr_wave<16, 4><<<wb, 256, 0, st>>>(rows, M, ldm, c, S, lds);
-    else if (c <= 32) k_tsqr_wave<32, 2><<<wb, 256, 0, st>>>(rows, M, ldm, c, S, lds);
-    else k_tsqr_level<64><<<npanels, TSQR_PANEL, 0, st>>>(rows, M, ldm, c, S, lds);
+    // many panels: the unrolled kernel (its code is shared by the waves of a compute unit); few:
+    // the compact one
+    const bool many = npanels >= 1024;
+    if (c <= 8) {
+        if (many) k_tsqr_wave<8, 8><<<wb, 256, 0, st>>>(rows, M, ldm, c, S, lds);
+        else k_tsqr_wave_loop<8, 8><<<wb, 256, 0, st>>>(rows, M, ldm, c, S, lds);
+    } else if (c <= 16) {
+        if (many) k_tsqr_wave<16, 4><<<wb, 256, 0, st>>>(rows, M, ldm, c, S, lds);
+        else k_tsqr_wave_loop<16, 4><<<wb, 256, 0, st>>>(rows, M, ldm, c, S, lds);
+    } else if (c <= 32) {
+        if (many) k_tsqr_wave<32, 2><<<wb, 256, 0, st>>>(rows, M, ldm, c, S, lds);
+        else k_tsqr_wave_loop<32, 2><<<wb, 256, 0, st>>>(rows, M, ldm, c, S, lds);
+    } else {
+        k_tsqr_level<64><<<npanels, TSQR_PANEL, 0, st>>>(rows, M, ldm, c, S, lds);
+    }
 }
 
 void launch_jacobi_svd(const double* R, int64_t ld, int c, int k, int64_t n, Ctl* ctl, hipStream_t st) {
