@@ -329,8 +329,8 @@ def bench_serving(args):
     log(f"generator set-up (patterns, GPU assemblers) {t_setup:.1f}s for {len(cache.base)} (degree, mesh) pairs")
     pool = int(args.pool_gb * 2 ** 30)
     mixed_cfg = dict(restart_m=30, recycle_k=10, snapshots_s=20, svd_interval=1, precond="jacobi",
-                     precision="fp32_ir", inner_tol=1e-5)
-    plain_cfg = dict(restart_m=30, precond="jacobi", method="plain", precision="fp64")
+                     precision="fp32_ir", inner_tol=1e-5, ortho=args.ortho)
+    plain_cfg = dict(restart_m=30, precond="jacobi", method="plain", precision="fp64", ortho=args.ortho)
     runs = {}
     for name, cfg in (("recycled_mixed", mixed_cfg), ("plain_fp64", plain_cfg)):
         if warm:
@@ -354,7 +354,9 @@ def bench_serving(args):
         "vs_baseline": None,
         "dtype": "f32+f64",
         "data": "synthetic",
-        "config": {"workload": SERVE_WORKLOADS["c5"], "sequences": len(specs), "solves": m["solves"],
+        "config": {"workload": SERVE_WORKLOADS["c5"] + ("; Arnoldi CGS2 with delayed reorthogonalisation on the "
+                                                         "multi-kernel path" if args.ortho == "dcgs2" else ""),
+                   "sequences": len(specs), "solves": m["solves"],
                    "pool_gib": args.pool_gb, "large_workers": args.workers, "parallelism": "single GPU"},
         "latency_ms": m["latency_ms"],
         "recycled_mixed": m,
