@@ -20,6 +20,11 @@ convection-diffusion problems using singular value decomposition"):
 * Krylov operator P A and initial vector r0 = P r0 (Table 1, rows
   "augmented oblique" and "deflated oblique"; with the projected guess the two
   rows start from the same vector, eq. (equivalence_oblique)).
+* The orthogonal projector P_o = I - W W^T in its place (Table 1, rows
+  "augmented orthogonal" and "deflated orthogonal"; section 3.3, the first
+  projector choice): operator P_o A, initial vector r0 (augmented) or P_o r0
+  (deflated).  GMRES then minimises the projected residual ||P_o r||; the
+  cycle-end correction below makes W^T r = 0, after which P_o r = r.
 * Recycle space = leading left singular vectors of the last s solutions,
   recomputed every ell solves (section 5.2, Algorithm 1, eqs. (best_rank_s),
   (opt_svd)).
@@ -45,7 +50,8 @@ from typing import List, Optional
 import numpy as np
 import scipy.linalg
 
-PLAIN, AUG_OBLIQUE, DEFL_OBLIQUE = 0, 1, 2
+PLAIN, AUG_OBLIQUE, DEFL_OBLIQUE, AUG_ORTHO, DEFL_ORTHO = 0, 1, 2, 3, 4
+ORTHO_METHODS = (AUG_ORTHO, DEFL_ORTHO)
 PRECOND_NONE, PRECOND_JACOBI = 0, 1
 
 FLAG_RECYCLE_DROPPED = 1
@@ -111,6 +117,11 @@ def recycle_setup(A, W: np.ndarray):
 def oblique_project(W, Z, E, v):
     """P v = v - A W E^{-1} W^T v  (section 3.2, the deflation projector M_D)."""
     return v - Z @ np.linalg.solve(E, W.T @ v)
+
+
+def orthogonal_project(W, v):
+    """P_o v = v - W W^T v  (section 3.3, the orthogonal projector onto the complement of span(W))."""
+    return v - W @ (W.T @ v)
 
 
 def projection_correction(W, Z, E, x, r):
@@ -243,10 +254,12 @@ def solve(A, b: np.ndarray, x0: Optional[np.ndarray], tol: float, cfg: Config,
     if use_w:
         x, r = projection_correction(W, Z, E, x, r)
 
+    ortho = cfg.method in ORTHO_METHODS
+
     def op(v):
         w = A @ (dinv * v)
         if use_w:
-            w = oblique_project(W, Z, E, w)
+            w = orthogonal_project(W, w) if ortho else oblique_project(W, Z, E, w)
         return w
 
     stop_abs = tol * bnorm
@@ -262,7 +275,9 @@ def solve(A, b: np.ndarray, x0: Optional[np.ndarray], tol: float, cfg: Config,
             return Result(x, its, cycles, k_eff, True, flags, rnorm / bnorm, hist, implicit)
         if its >= cfg.max_iters:
             return Result(x, its, cycles, k_eff, False, flags, rnorm / bnorm, hist, implicit)
-        cyc = arnoldi_cycle(op, r, cfg.restart_m, stop_abs, cfg.max_iters - its)
+        # deflated orthogonal: the Krylov initial vector is P_o r (equal to r once W^T r = 0)
+        r_start = orthogonal_project(W, r) if (use_w and cfg.method == DEFL_ORTHO) else r
+        cyc = arnoldi_cycle(op, r_start, cfg.restart_m, stop_abs, cfg.max_iters - its)
         cycles += 1
         its += cyc.steps
         implicit += [v / bnorm for v in cyc.implicit]

@@ -305,6 +305,84 @@ def test_max_iters_not_converged():
     assert res.rel_res_true > 1e-12
 
 
+# -- orthogonal projector variants (Table 1 rows 1 and 4) and the smallest modes -------
+
+
+@pytest.mark.parametrize("method", [O.AUG_ORTHO, O.DEFL_ORTHO])
+def test_orthogonal_variant_minimises_projected_residual(method):
+    """Inside the solve, each step's implicit residual equals the brute-force minimum of
+    ||(I - W W^T)(r0 - A D^{-1} K z)|| over the Krylov space of the operator (I - W W^T) A D^{-1}
+    started from the projected-guess residual (Table 1, orthogonal rows; section 3.3)."""
+    A, b, _ = c1_system(step=4)
+    n = b.size
+    dinv = O.jacobi_inverse(A)
+    W = orthonormal(n, 3, 11)
+    # the guess: x0 = W (W^T A W)^{-1} W^T b, by dense algebra
+    Wd = W
+    E = Wd.T @ (A @ Wd)
+    x0 = Wd @ np.linalg.solve(E, Wd.T @ b)
+    r0 = b - A @ x0
+    Pmat = np.eye(n) - Wd @ Wd.T
+    op_ref = lambda v: Pmat @ (A @ (dinv * v))
+    res = O.solve(A, b, None, 1e-30, O.Config(restart_m=10, method=method, precond=O.PRECOND_JACOBI,
+                                                 max_iters=10), W)
+    bnorm = np.linalg.norm(b)
+    for j in range(1, 11):
+        ref = krylov_min_residual(op_ref, Pmat @ r0, j)
+        assert abs(res.implicit_history[j - 1] * bnorm - ref) <= 1e-9 * np.linalg.norm(r0) + 1e-8 * ref, j
+
+
+def test_orthogonal_equals_oblique_on_invariant_subspace():
+    """For symmetric A and W spanning an invariant subspace, A W = W L, so E = L and the oblique
+    projector I - A W E^{-1} W^T reduces to I - W W^T: the two methods give the same iterates."""
+    n = 60
+    rng = np.random.default_rng(4)
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    lam = np.linspace(1.0, 30.0, n)
+    A = sp.csr_matrix((Q * lam) @ Q.T)
+    W = Q[:, :5]
+    b = rng.standard_normal(n)
+    cfg = dict(restart_m=8, max_iters=200)
+    ro = O.solve(A, b, None, 1e-12, O.Config(method=O.AUG_ORTHO, **cfg), W)
+    rb = O.solve(A, b, None, 1e-12, O.Config(method=O.AUG_OBLIQUE, **cfg), W)
+    assert ro.iterations == rb.iterations
+    assert np.linalg.norm(ro.x - rb.x) <= 1e-10 * np.linalg.norm(rb.x)
+    # and on a nonsymmetric matrix the two differ (the variant is not silently the oblique one)
+    An, bn = rand_system(60, 5)
+    Wn = orthonormal(60, 5, 6)
+    r1 = O.solve(An, bn, None, 1e-12, O.Config(method=O.AUG_ORTHO, restart_m=8, max_iters=3), Wn)
+    r2 = O.solve(An, bn, None, 1e-12, O.Config(method=O.AUG_OBLIQUE, restart_m=8, max_iters=3), Wn)
+    assert np.linalg.norm(r1.x - r2.x) > 1e-6 * np.linalg.norm(r2.x)
+
+
+def test_orthogonal_solves_a_sequence_to_tolerance():
+    """The orthogonal variants converge on the generator sequence to the explicit tolerance, with
+    W^T r = 0 after every cycle's correction (so the projected and true residuals coincide)."""
+    asm, systems, _ = WL.march(WL.C1, 8, 1)
+    for method in (O.AUG_ORTHO, O.DEFL_ORTHO):
+        cfg = O.Config(restart_m=30, recycle_k=5, snapshots_s=10, method=method)
+        results, st = O.run_sequence([asm.csr(v) for v, _ in systems], [b for _, b in systems], 1e-10, cfg)
+        assert st.W.shape[1] == 5
+        for (v, b), r in zip(systems, results):
+            assert r.converged and np.linalg.norm(b - asm.csr(v) @ r.x) <= 1e-10 * np.linalg.norm(b) * (1 + 1e-6)
+
+
+def test_svd_basis_smallest_modes():
+    """select smallest: W spans the left singular vectors of the k smallest singular values above
+    the rank cut (Algorithm 1 with the trailing modes), on a matrix built from known factors."""
+    rng = np.random.default_rng(8)
+    n, c, k = 500, 12, 4
+    U, _ = np.linalg.qr(rng.standard_normal((n, c)))
+    Vt, _ = np.linalg.qr(rng.standard_normal((c, c)))
+    sig = 10.0 ** (-0.5 * np.arange(c))
+    sig[-2:] = 0.0                                   # rank 10
+    X = (U * sig) @ Vt.T
+    W, s, rank = O.svd_basis(X, k, smallest=True)
+    assert rank == 10 and W.shape[1] == k
+    cos = np.linalg.svd(U[:, rank - k:rank].T @ W, compute_uv=False)
+    assert cos.min() >= 1 - 1e-10
+
+
 # -- planted mistakes: each plausible error in the oracle is caught by a pin ----------
 
 
@@ -315,6 +393,8 @@ def _pins_pass():
         test_projection_guess_exact_when_solution_in_span()
         test_implicit_residual_is_krylov_minimum(True)
         test_correction_leaves_residual_orthogonal_to_W()
+        test_orthogonal_variant_minimises_projected_residual(O.AUG_ORTHO)
+        test_orthogonal_equals_oblique_on_invariant_subspace()
     except AssertionError:
         return False
     return True
@@ -326,9 +406,13 @@ def test_pins_pass_on_unmodified_oracle():
 
 @pytest.mark.parametrize("mutation", ["projector_uses_W", "guess_transposed_E", "givens_sign",
                                       "update_without_preconditioner", "operator_perturbed",
-                                      "correction_sign"])
+                                      "correction_sign", "ortho_projector_missing", "ortho_projector_half"])
 def test_planted_mistakes_are_caught(monkeypatch, mutation):
-    if mutation == "projector_uses_W":
+    if mutation == "ortho_projector_missing":
+        monkeypatch.setattr(O, "orthogonal_project", lambda W, v: v)
+    elif mutation == "ortho_projector_half":
+        monkeypatch.setattr(O, "orthogonal_project", lambda W, v: v - 0.5 * W @ (W.T @ v))
+    elif mutation == "projector_uses_W":
         monkeypatch.setattr(O, "oblique_project", lambda W, Z, E, v: v - W @ np.linalg.solve(E, W.T @ v))
     elif mutation == "guess_transposed_E":
         def bad(W, Z, E, x, r):
