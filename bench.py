@@ -440,6 +440,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--inner-tol", type=float, default=None,
                     help="override the FP32 cycle reduction factor of the mixed-precision workload")
+    ap.add_argument("--method", choices=["aug_oblique", "defl_oblique", "aug_ortho", "defl_ortho"], default=None,
+                    help="projector of the recycled run (default: the workload's, augmented oblique)")
+    ap.add_argument("--select", choices=["largest", "smallest"], default=None,
+                    help="singular modes kept in the recycle space (default: largest, Algorithm 1)")
     ap.add_argument("--ortho", choices=["cgs2", "dcgs2"], default="dcgs2",
                     help="Arnoldi orthogonalisation of the multi-kernel solver (both runs): classical "
                          "Gram-Schmidt twice, or the same with the second pass delayed into the next step")
@@ -482,6 +486,12 @@ def main():
         desc = desc + f", inner_tol {args.inner_tol:g}"
     cfg["ortho"] = args.ortho
     desc = desc + (", Arnoldi CGS2 with delayed reorthogonalisation" if args.ortho == "dcgs2" else ", Arnoldi CGS2")
+    if args.method:
+        cfg["method"] = args.method
+        desc = desc + f", projector {args.method}"
+    if args.select:
+        cfg["select"] = args.select
+        desc = desc + f", {args.select} singular modes"
     prob = getattr(WL, pname)
     nsteps = args.warmup + args.steps
     asm, gasm, u0, systems = generate(prob, nsteps, dev)

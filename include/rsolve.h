@@ -61,11 +61,18 @@ extern "C" {
 #define RSOLVE_AUG_OBLIQUE    1   /* Table 1, augmented oblique */
 #define RSOLVE_DEFL_OBLIQUE   2   /* Table 1, deflated oblique (same iteration under right
                                      preconditioning with the projected initial guess) */
+#define RSOLVE_AUG_ORTHO      3   /* Table 1, augmented orthogonal: Krylov operator (I - W W^T) A D^{-1};
+                                     GMRES minimises the projected residual, the cycle-end correction
+                                     x += W E^{-1} W^T r makes W^T r = 0 (multi-kernel path only) */
+#define RSOLVE_DEFL_ORTHO     4   /* Table 1, deflated orthogonal: also the initial vector projected
+                                     (the same iteration once the projected guess leaves W^T r = 0) */
 #define RSOLVE_PRECOND_NONE   0
 #define RSOLVE_PRECOND_JACOBI 1   /* right Jacobi: operator P A D^{-1}, x = x0 + D^{-1} V y */
 #define RSOLVE_FP64           0   /* everything in float64 */
 #define RSOLVE_FP32_IR        1   /* float32 Arnoldi cycles inside float64 iterative refinement */
 #define RSOLVE_SELECT_LARGEST 0   /* W = leading left singular vectors (Algorithm 1) */
+#define RSOLVE_SELECT_SMALLEST 1  /* W = left singular vectors of the k smallest singular values above
+                                     the numerical rank cut (section 5.2, the other choice) */
 #define RSOLVE_ORTHO_CGS2     0   /* classical Gram-Schmidt applied twice: three basis sweeps per step */
 #define RSOLVE_ORTHO_DCGS2    1   /* the same Arnoldi process with the second pass of each basis vector
                                      merged into the next step: two basis sweeps per step, the
@@ -92,11 +99,11 @@ typedef struct {
     int32_t recycle_k;     /* recycle dimension k, 0..RSOLVE_MAX_RECYCLE (0 = plain) */
     int32_t snapshots_s;   /* snapshot ring size s, k <= s <= RSOLVE_MAX_SNAPSHOTS (0 if k = 0) */
     int32_t svd_interval;  /* ell >= 1: recompute W every ell updates (Algorithm 1) */
-    int32_t method;        /* RSOLVE_PLAIN / RSOLVE_AUG_OBLIQUE / RSOLVE_DEFL_OBLIQUE */
+    int32_t method;        /* RSOLVE_PLAIN / _AUG_OBLIQUE / _DEFL_OBLIQUE / _AUG_ORTHO / _DEFL_ORTHO */
     int32_t precond;       /* RSOLVE_PRECOND_NONE / RSOLVE_PRECOND_JACOBI */
     int32_t precision;     /* RSOLVE_FP64 / RSOLVE_FP32_IR */
     int32_t max_iters;     /* cap on Arnoldi steps per solve (>= 1) */
-    int32_t select;        /* RSOLVE_SELECT_LARGEST */
+    int32_t select;        /* RSOLVE_SELECT_LARGEST / RSOLVE_SELECT_SMALLEST */
     int32_t ortho;         /* RSOLVE_ORTHO_CGS2 (0) / RSOLVE_ORTHO_DCGS2 (1): Arnoldi orthogonalisation
                               of the multi-kernel path (the one-block path always uses CGS2) */
     double  inner_tol;     /* FP32_IR only: an FP32 cycle stops once its residual estimate has
@@ -188,8 +195,9 @@ int rsolve_get_recycle(rsolve_seq* s, int32_t* k_eff, int32_t* rank, double* sig
 
 /* ---- batched solves of many sequences in one launch ---- */
 
-/* One-block limits: an item whose sequence is FP64 with restart_m, recycle_k (and, for the
- * update, snapshots_s <= restart_m + 1) within these limits and n <= RSOLVE_SMALL_MAX_N runs
+/* One-block limits: an item whose sequence is FP64 with an oblique (or no) projector, restart_m,
+ * recycle_k (and, for the update, snapshots_s <= restart_m + 1) within these limits and
+ * n <= RSOLVE_SMALL_MAX_N runs
  * as one workgroup of a shared persistent launch; any other item runs through the
  * multi-kernel path of rsolve_solve / rsolve_update_recycle, one after the other, while that
  * launch is in flight. */

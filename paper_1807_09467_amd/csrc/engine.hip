@@ -73,11 +73,11 @@ int cfg_check(const rsolve_config* c) {
     if (c->snapshots_s < 0 || c->snapshots_s > RSOLVE_MAX_SNAPSHOTS) return RSOLVE_E_INVALID;
     if (c->recycle_k > 0 && c->snapshots_s < c->recycle_k) return RSOLVE_E_INVALID;
     if (c->svd_interval < 1) return RSOLVE_E_INVALID;
-    if (c->method < RSOLVE_PLAIN || c->method > RSOLVE_DEFL_OBLIQUE) return RSOLVE_E_INVALID;
+    if (c->method < RSOLVE_PLAIN || c->method > RSOLVE_DEFL_ORTHO) return RSOLVE_E_INVALID;
     if (c->precond != RSOLVE_PRECOND_NONE && c->precond != RSOLVE_PRECOND_JACOBI) return RSOLVE_E_INVALID;
     if (c->precision != RSOLVE_FP64 && c->precision != RSOLVE_FP32_IR) return RSOLVE_E_INVALID;
     if (c->max_iters < 1) return RSOLVE_E_INVALID;
-    if (c->select != RSOLVE_SELECT_LARGEST) return RSOLVE_E_INVALID;
+    if (c->select != RSOLVE_SELECT_LARGEST && c->select != RSOLVE_SELECT_SMALLEST) return RSOLVE_E_INVALID;
     if (c->ortho != RSOLVE_ORTHO_CGS2 && c->ortho != RSOLVE_ORTHO_DCGS2) return RSOLVE_E_INVALID;
     if (c->precision == RSOLVE_FP32_IR && !(c->inner_tol > 0.0 && c->inner_tol < 1.0)) return RSOLVE_E_INVALID;
     return RSOLVE_OK;
@@ -471,7 +471,10 @@ void prof_collect(rsolve_seq* s, int steps) {
 
 // One Arnoldi step j of the current cycle on storage type T.
 template <typename T>
-void arnoldi_step(rsolve_seq* s, int j, const SpOp& op, T* V, T* const* wbuf, const T* Wt, const T* Zt, int k) {
+void arnoldi_step(rsolve_seq* s, int j, const SpOp& op, T* V, T* const* wbuf, const T* Wt, const T* Zt, int k,
+                  bool orth) {
+    // the orthogonal projector I - W W^T takes W where the oblique one takes A W
+    const T* Pt = orth ? Wt : Zt;
     hipStream_t st = s->stream;
     const int64_t ld = s->ld;
     T* win = wbuf[j & 1];
@@ -487,11 +490,11 @@ void arnoldi_step(rsolve_seq* s, int j, const SpOp& op, T* V, T* const* wbuf, co
     const int ntot = k > 0 ? nv + 2 * k : nv;
     const int nb1 = cols_grid(ld, s->cus, std::min(16, (ntot + 7) / 8), 32, ntot);
     if (k > 0) {
-        const T* bases[3] = {V, Wt, Zt};
+        const T* bases[3] = {V, Wt, Pt};
         const T* vecs[3] = {wout, wout, vj};
         const int counts[3] = {nv, k, k};
         ProfEv pe(s, RSOLVE_PROF_DOTS, j, var_of(ntot), (nv + 2.0 * k + 1.0) * w * nn);
-        launch_dots<T>(ld, ld, bases, vecs, counts, 3, s->partial, nb1, s->ctl, st, nv, k, pe.e0, pe.e1);
+        launch_dots<T>(ld, ld, bases, vecs, counts, 3, s->partial, nb1, s->ctl, st, nv, k, pe.e0, pe.e1, orth);
     } else {
         const T* bases[1] = {V};
         const T* vecs[1] = {wout};
@@ -502,7 +505,7 @@ void arnoldi_step(rsolve_seq* s, int j, const SpOp& op, T* V, T* const* wbuf, co
     const int nb2 = cols_grid(ld, s->cus, (nv + 7) / 8, 16, nv);
     {
         ProfEv pe(s, RSOLVE_PROF_UPDATE_DOTS, j, var_of(nv), (nv + k + 2.0) * w * nn);
-        launch_update_dots<T>(ld, V, ld, nv, Zt, k, wout, ctl_h1(s->ctl), ctl_cw(s->ctl), s->partial, nb2, s->ctl, st,
+        launch_update_dots<T>(ld, V, ld, nv, Pt, k, wout, ctl_h1(s->ctl), ctl_cw(s->ctl), s->partial, nb2, s->ctl, st,
                               pe.e0, pe.e1);
     }
     {
@@ -516,7 +519,9 @@ void arnoldi_step(rsolve_seq* s, int j, const SpOp& op, T* V, T* const* wbuf, co
 // reduction that completes column j-1, and the update sweep writing v_j and the next candidate.
 template <typename T>
 void dcgs2_step(rsolve_seq* s, int j, int allowed, const SpOp& op, T* V, T* const* wbuf, const T* Wt, const T* Zt,
-                int k) {
+                int k, bool orth) {
+    // the orthogonal projector I - W W^T needs no A W columns in the sweep and takes W in the update
+    const int kz = orth ? 0 : k;
     hipStream_t st = s->stream;
     const int64_t ld = s->ld;
     T* u = wbuf[0];
@@ -527,7 +532,7 @@ void dcgs2_step(rsolve_seq* s, int j, int allowed, const SpOp& op, T* V, T* cons
         ProfEv pe(s, RSOLVE_PROF_SPMV, j, 0, spmv_bytes(s, w, false));
         arnoldi_product<T>(s, op, u, nullptr, z, pe.e0, pe.e1);
     }
-    const int ncol = j + 2 * k + 1;
+    const int ncol = j + k + kz + 1;
     // two blocks per compute unit once a block has 8 or more wavefronts (measured on Q3 for 34..83
     // columns: one block per unit leaves the wide sweeps a third slower, three or four are slower
     // too), about 32 wavefronts per unit for narrower sweeps; the partials within their buffer
@@ -537,12 +542,12 @@ void dcgs2_step(rsolve_seq* s, int j, int allowed, const SpOp& op, T* V, T* cons
     const int nb1 = (int)std::min<int64_t>({per_cu * s->cus, tiles, PARTIAL_DOUBLES / (2 * ncol) - 1, (int64_t)NBLK_MAX});
     {
         ProfEv pe(s, RSOLVE_PROF_DOTS, has_z ? j : MMAX, var_of(ncol), (ncol + 1.0) * w * nn);
-        launch_dots2<T>(ld, ld, V, j, Wt, Zt, k, u, has_z ? z : u, s->partial, nb1, s->ctl, st, pe.e0, pe.e1);
+        launch_dots2<T>(ld, ld, V, j, Wt, Zt, k, kz, u, has_z ? z : u, s->partial, nb1, s->ctl, st, pe.e0, pe.e1);
     }
-    launch_dcgs2_reduce(s->partial, nb1, j, k, has_z, s->ctl, st);
+    launch_dcgs2_reduce(s->partial, nb1, j, k, kz, orth, has_z, s->ctl, st);
     if (has_z) {
         ProfEv pe(s, RSOLVE_PROF_UPDATE_DOTS, j, var_of(j + 1), (j + k + 4.0) * w * nn);
-        launch_dcgs2_update<T>(ld, V, ld, j, Zt, k, u, z, s->nblk, s->ctl, st, pe.e0, pe.e1);
+        launch_dcgs2_update<T>(ld, V, ld, j, orth ? Wt : Zt, k, u, z, s->nblk, s->ctl, st, pe.e0, pe.e1);
     }
 }
 
@@ -573,8 +578,9 @@ static_assert(SMALL_MMAX == RSOLVE_SMALL_MAX_RESTART && SMALL_KMAX == RSOLVE_SMA
 
 bool small_solve_ok(const rsolve_seq* s) {
     const rsolve_config& c = s->cfg;
+    // the one-block solve implements the oblique projector only
     return c.precision == RSOLVE_FP64 && c.restart_m <= SMALL_MMAX && c.recycle_k <= SMALL_KMAX &&
-           s->n <= RSOLVE_SMALL_MAX_N;
+           s->n <= RSOLVE_SMALL_MAX_N && c.method != RSOLVE_AUG_ORTHO && c.method != RSOLVE_DEFL_ORTHO;
 }
 
 bool small_update_ok(const rsolve_seq* s) {
@@ -988,6 +994,7 @@ int rsolve_solve(rsolve_seq* s, const rsolve_csr* A, const double* b, const doub
         const int max_steps = std::min(m, c.max_iters - its);
         const double cyc_stop = ir ? std::max(c.inner_tol * rnorm, stop_abs) : stop_abs;
         const bool dg = c.ortho == RSOLVE_ORTHO_DCGS2;
+        const bool orth = c.method == RSOLVE_AUG_ORTHO || c.method == RSOLVE_DEFL_ORTHO;
         launch_cycle_init(s->ctl, max_steps, cyc_stop, stm, dg);
         if (ir) launch_to_f32(ld, s->wb[0], s->w32[0], stm);
         // Enqueue the cycle in chunks; after chunk c the done flag is copied to pinned memory, and
@@ -1006,18 +1013,18 @@ int rsolve_solve(rsolve_seq* s, const rsolve_csr* A, const double* b, const doub
             auto enqueue = [&] {
                 for (int j = j0; j < j1; ++j) {
                     if (dg) {
-                        if (ir) dcgs2_step<float>(s, j, max_steps, op, s->V32, s->w32, W32, Z32, k);
-                        else dcgs2_step<double>(s, j, max_steps, op, s->V, s->wb, s->W, s->Z, k);
+                        if (ir) dcgs2_step<float>(s, j, max_steps, op, s->V32, s->w32, W32, Z32, k, orth);
+                        else dcgs2_step<double>(s, j, max_steps, op, s->V, s->wb, s->W, s->Z, k, orth);
                     } else {
-                        if (ir) arnoldi_step<float>(s, j, op, s->V32, s->w32, W32, Z32, k);
-                        else arnoldi_step<double>(s, j, op, s->V, s->wb, s->W, s->Z, k);
+                        if (ir) arnoldi_step<float>(s, j, op, s->V32, s->w32, W32, Z32, k, orth);
+                        else arnoldi_step<double>(s, j, op, s->V, s->wb, s->W, s->Z, k, orth);
                     }
                 }
             };
             if (s->graphs_on && !s->prof_on) {
                 const rsolve_seq::GraphKey key{j0,      j1,         k,         ir ? 1 : 0, s->lpr, s->svec, s->sremap,
-                                               op.fmt,  dg ? 1 : 0, dg ? max_steps : 0,  op.rp,  op.ci,   op.off,
-                                               op.vals};
+                                               op.fmt,  (dg ? 1 : 0) | (orth ? 2 : 0), dg ? max_steps : 0, op.rp, op.ci,
+                                               op.off,  op.vals};
                 hipGraphExec_t ge = nullptr;
                 rc = chunk_graph(s, key, enqueue, &ge);
                 if (rc) return rc;
@@ -1114,7 +1121,7 @@ int rsolve_update_recycle(rsolve_seq* s, const double* x) {
         ++lvl;
     }
     HIP_TRY(hipMemsetAsync(s->ctl, 0, CTL_HEAD, stm));
-    launch_jacobi_svd(R, s->tsq_ld, cc, c.recycle_k, n, s->ctl, stm);
+    launch_jacobi_svd(R, s->tsq_ld, cc, c.recycle_k, n, s->ctl, stm, c.select == RSOLVE_SELECT_SMALLEST);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipMemcpyAsync(s->hsig, ctl_sigma(s->ctl), sizeof(double) * cc, hipMemcpyDeviceToHost, stm));
     int rc = read_head(s);
@@ -1315,6 +1322,7 @@ int rsolve_update_recycle_batch(rsolve_batch_update_item* items, int32_t count, 
             U.c = (int32_t)std::min<int64_t>(s->count + 1, c.snapshots_s);
             U.k = c.recycle_k;
             U.svd = ((s->count + 1) % c.svd_interval == 0) ? 1 : 0;
+            U.smallest = c.select == RSOLVE_SELECT_SMALLEST ? 1 : 0;
             U.status = RSOLVE_E_DEVICE;
             batch.job[q] = s->hupd;
         }

@@ -473,7 +473,7 @@ __global__ __launch_bounds__(256) void k_tsqr_wave_loop(int64_t rows, const doub
 // numerically orthogonal; the rotations accumulate in V, so R V = U Sigma.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(BLOCK) void k_jacobi_svd(const double* __restrict__ R, int64_t ld, int c, int k,
-                                                      int64_t n, Ctl* __restrict__ ctl) {
+                                                      int64_t n, Ctl* __restrict__ ctl, int smallest) {
     constexpr int LDC = SMAX + 1;
     __shared__ double Ac[(SMAX + 1) * LDC];   // column j at Ac[j * LDC + i]
     __shared__ double Vc[(SMAX + 1) * LDC];
@@ -493,9 +493,10 @@ __global__ __launch_bounds__(BLOCK) void k_jacobi_svd(const double* __restrict__
     const double s1 = (c > 0) ? sig[order[0]] : 0.0;
     const int keff = rank < k ? rank : k;
     for (int i = tid; i < c; i += BLOCK) ctl->sigma[i] = sig[order[i]];
+    const int first = smallest ? rank - keff : 0;   // the modes kept: order[first .. first + keff)
     for (int t = tid; t < c * keff; t += BLOCK) {
         const int i = t / keff, j = t % keff;
-        ctl->T[i * KMAX + j] = Vc[order[j] * LDC + i] / sig[order[j]];
+        ctl->T[i * KMAX + j] = Vc[order[first + j] * LDC + i] / sig[order[first + j]];
     }
     if (tid == 0) {
         ctl->rank = rank;
@@ -645,8 +646,9 @@ void launch_tsqr_level(int64_t rows, const double* M, int64_t ldm, int c, double
     }
 }
 
-void launch_jacobi_svd(const double* R, int64_t ld, int c, int k, int64_t n, Ctl* ctl, hipStream_t st) {
-    k_jacobi_svd<<<1, BLOCK, 0, st>>>(R, ld, c, k, n, ctl);
+void launch_jacobi_svd(const double* R, int64_t ld, int c, int k, int64_t n, Ctl* ctl, hipStream_t st,
+                       bool smallest) {
+    k_jacobi_svd<<<1, BLOCK, 0, st>>>(R, ld, c, k, n, ctl, smallest ? 1 : 0);
 }
 
 void launch_form_w(int64_t n, int64_t npad, const double* X, int64_t ldx, int c, int k, const Ctl* ctl, double* W,

@@ -133,8 +133,9 @@ __global__ __launch_bounds__(RED_T) void k_reduce(const double* __restrict__ par
 // Pass-1 coefficients of step j (nv = j + 1 basis vectors) with the oblique projector folded in:
 // sums = [V^T w0 | W^T w0 | Z^T v_j]; F[j, :] = v_j^T Z; cw = E^{-1} W^T w0;
 // h1 = V^T (w0 - Z cw) = V^T w0 - F cw.  Run by one block of any size (>= 1 wavefront).
+// orth: the orthogonal projector I - W W^T (the third group then holds W^T v_j, and cw = W^T w0).
 __device__ void pass1_coefficients(const double* __restrict__ partial, int nblk, int nv, int k, Ctl* __restrict__ ctl,
-                                   double* sums, double* Es, double* cws, double* red) {
+                                   double* sums, double* Es, double* cws, double* red, int orth = 0) {
     const int wv = threadIdx.x / WAVE;
     const int ncol = nv + 2 * k;
     for (int t = threadIdx.x; t < k * k; t += blockDim.x) Es[t] = ctl->E[t];
@@ -143,7 +144,11 @@ __device__ void pass1_coefficients(const double* __restrict__ partial, int nblk,
         for (int i = threadIdx.x; i < nv; i += blockDim.x) ctl->h1[i] = sums[i];
         return;
     }
-    if (wv == 0) wave_lu_solve(ctl, k, sums + nv, cws, Es);
+    if (orth) {
+        for (int c = threadIdx.x; c < k; c += blockDim.x) cws[c] = sums[nv + c];
+    } else if (wv == 0) {
+        wave_lu_solve(ctl, k, sums + nv, cws, Es);
+    }
     __syncthreads();
     for (int c = threadIdx.x; c < k; c += blockDim.x) {
         ctl->F[(nv - 1) * KMAX + c] = sums[nv + k + c];
@@ -165,13 +170,13 @@ __device__ void pass1_coefficients(const double* __restrict__ partial, int nblk,
 }
 
 __global__ __launch_bounds__(RED_T) void k_reduce_pass1(const double* __restrict__ partial, int nblk, int nv, int k,
-                                                        Ctl* __restrict__ ctl) {
+                                                        int orth, Ctl* __restrict__ ctl) {
     if (ctl->done) return;
     __shared__ double sums[MMAX + 2 * KMAX];
     __shared__ double Es[KMAX * KMAX];
     __shared__ double cws[KMAX];
     __shared__ double red[RED_T / WAVE];
-    pass1_coefficients(partial, nblk, nv, k, ctl, sums, Es, cws, red);
+    pass1_coefficients(partial, nblk, nv, k, ctl, sums, Es, cws, red, orth);
 }
 
 // Sweep of dot products: wavefront w of the block owns columns [w CPW, w CPW + CPW) of the
@@ -543,7 +548,7 @@ __global__ __launch_bounds__(BLOCK) void k_copy_pad(int64_t n, int64_t npad, con
 // wavefront, 64-row tiles): partial[(2c + e) nblk + b], e = 0 for u, 1 for z.
 template <typename T, int CPW>
 __global__ __launch_bounds__(1024) void k_dots2(int64_t npad, int64_t ld, const T* __restrict__ V, int nq,
-                                                const T* __restrict__ W, const T* __restrict__ Z, int k,
+                                                const T* __restrict__ W, const T* __restrict__ Z, int k, int kz,
                                                 const T* __restrict__ u, const T* __restrict__ z, int c_begin,
                                                 int c_end, double* __restrict__ partial, int nblk,
                                                 const Ctl* __restrict__ ctl) {
@@ -556,7 +561,7 @@ __global__ __launch_bounds__(1024) void k_dots2(int64_t npad, int64_t ld, const 
     for (int s = 0; s < CPW; ++s) {
         int c = c0 + s < c_end ? c0 + s : (c0 < c_end ? c0 : c_begin);
         col[s] = c < nq ? V + (int64_t)c * ld
-                        : (c < nq + k ? W + (int64_t)(c - nq) * ld : (c < nq + 2 * k ? Z + (int64_t)(c - nq - k) * ld : u));
+                        : (c < nq + k ? W + (int64_t)(c - nq) * ld : (c < nq + k + kz ? Z + (int64_t)(c - nq - k) * ld : u));
     }
     // 16-byte loads: VEC consecutive rows per lane (npad is a multiple of 64)
     constexpr int VEC = 16 / sizeof(T);
@@ -624,8 +629,8 @@ __global__ __launch_bounds__(1024) void k_colsum(const double* __restrict__ part
 // The loads of the control block are issued together at the start, and the sums over the
 // Hessenberg matrix and F are split over the wavefronts, so the block waits for memory a few
 // times rather than once per term.
-__global__ __launch_bounds__(RED_T) void k_dcgs2_reduce(const double* __restrict__ dsum, int j, int k, int has_z,
-                                                        Ctl* __restrict__ ctl) {
+__global__ __launch_bounds__(RED_T) void k_dcgs2_reduce(const double* __restrict__ dsum, int j, int k, int kz,
+                                                        int orth, int has_z, Ctl* __restrict__ ctl) {
     if (ctl->done) return;
     constexpr int LDH = MMAX + 1;
     constexpr int LDR = MMAX + 1;
@@ -646,7 +651,11 @@ __global__ __launch_bounds__(RED_T) void k_dcgs2_reduce(const double* __restrict
     __shared__ int stop;
     const int tid = threadIdx.x;
     const int wv = tid / WAVE, lane = tid & (WAVE - 1);
-    const int ncol = j + 2 * k + 1;
+    const int ncol = j + k + kz + 1;
+    // sweep columns: V (0..j-1), W (j..j+k-1), A W (kz = k columns, oblique projector only), u;
+    // pz = first column of the projector's image (A W for the oblique projector, W for the
+    // orthogonal one), cu = the column of u
+    const int pz = orth ? j : j + k, cu = j + k + kz;
     const int jc = j - 1;   // the column completed here (none when j = 0)
     for (int t = tid; t < k * k; t += RED_T) Es[t] = ctl->E[t];
     for (int t = tid; t < jc; t += RED_T) {
@@ -661,7 +670,7 @@ __global__ __launch_bounds__(RED_T) void k_dcgs2_reduce(const double* __restrict
         double hh = 0.0;
         for (int l = lane; l < j; l += WAVE) hh += su[2 * l] * su[2 * l];
         hh = wave_sum(hh);
-        const double uu = su[2 * (j + 2 * k)];
+        const double uu = su[2 * cu];
         const double nu = (j == 0) ? ctl->beta : sqrt(fmax(uu - hh, 0.0));
         if (lane == 0) {
             scal[0] = nu;
@@ -742,11 +751,15 @@ __global__ __launch_bounds__(RED_T) void k_dcgs2_reduce(const double* __restrict
     if (stop || !has_z) return;
     const double nu = scal[0];
     const double inv = 1.0 / nu;
-    // c = E^{-1} W^T z (the oblique projector's coefficients for z)
+    // the projector's coefficients for z: c = E^{-1} W^T z (oblique) or W^T z (orthogonal)
     if (k > 0 && wv == 0) {
         if (lane < k) wz[lane] = su[2 * (j + lane) + 1];   // W^T z, contiguous for the solve
         __builtin_amdgcn_wave_barrier();
-        wave_lu_solve(ctl, k, wz, cws, Es);
+        if (orth) {
+            if (lane < k) cws[lane] = wz[lane];
+        } else {
+            wave_lu_solve(ctl, k, wz, cws, Es);
+        }
     }
     __syncthreads();
     // partial sums of (F cws)_l over groups of recycle columns: wavefront w takes c = w, w + NW, ...
@@ -760,7 +773,7 @@ __global__ __launch_bounds__(RED_T) void k_dcgs2_reduce(const double* __restrict
     for (int c = tid; c < k; c += RED_T) {
         double f = 0.0;
         for (int w = 0; w < NF; ++w) f += pF[w][c];
-        ctl->F[j * KMAX + c] = (su[2 * (j + k + c)] - f) * inv;   // u . (A W)_c - h^T F[:, c]
+        ctl->F[j * KMAX + c] = (su[2 * (pz + c)] - f) * inv;   // u . (A W or W)_c - h^T F[:, c]
         ctl->cw[c] = cws[c];
     }
     __syncthreads();
@@ -772,9 +785,9 @@ __global__ __launch_bounds__(RED_T) void k_dcgs2_reduce(const double* __restrict
     }
     if (wv == NW - 1) {
         double uz = 0.0;
-        for (int c = lane; c < k; c += WAVE) uz += su[2 * (j + k + c)] * cws[c];
+        for (int c = lane; c < k; c += WAVE) uz += su[2 * (pz + c)] * cws[c];
         uz = wave_sum(uz);
-        if (lane == 0) scal[1] = su[2 * (j + 2 * k) + 1] - uz;   // u . z - (u^T A W) cws
+        if (lane == 0) scal[1] = su[2 * cu + 1] - uz;   // u . z - (u^T A W or u^T W) cws
     }
     __syncthreads();
     if (wv == 0) {
@@ -863,7 +876,7 @@ __global__ __launch_bounds__(BLOCK) void k_dcgs2_update(int64_t npad, T* __restr
 template <typename T>
 void launch_dots(int64_t npad, int64_t ld, const T* const* bases, const T* const* vecs, const int* counts,
                  int ngroups, double* partial, int nblk, Ctl* ctl, hipStream_t st, int pass1_nv, int pass1_k,
-                 hipEvent_t ev0, hipEvent_t ev1) {
+                 hipEvent_t ev0, hipEvent_t ev1, bool pass1_orth) {
     constexpr int CPW = 8;
     int ntot = 0;
     for (int q = 0; q < ngroups; ++q) ntot += counts[q];
@@ -892,12 +905,12 @@ void launch_dots(int64_t npad, int64_t ld, const T* const* bases, const T* const
                               last ? ev1 : nullptr, 0, npad, ld, g, partial + (int64_t)a * nblk, nblk,
                               static_cast<const Ctl*>(ctl));
     }
-    if (pass1_nv > 0) k_reduce_pass1<<<1, RED_T, 0, st>>>(partial, nblk, pass1_nv, pass1_k, ctl);
+    if (pass1_nv > 0) k_reduce_pass1<<<1, RED_T, 0, st>>>(partial, nblk, pass1_nv, pass1_k, pass1_orth ? 1 : 0, ctl);
 }
 template void launch_dots<double>(int64_t, int64_t, const double* const*, const double* const*, const int*, int,
-                                  double*, int, Ctl*, hipStream_t, int, int, hipEvent_t, hipEvent_t);
+                                  double*, int, Ctl*, hipStream_t, int, int, hipEvent_t, hipEvent_t, bool);
 template void launch_dots<float>(int64_t, int64_t, const float* const*, const float* const*, const int*, int,
-                                 double*, int, Ctl*, hipStream_t, int, int, hipEvent_t, hipEvent_t);
+                                 double*, int, Ctl*, hipStream_t, int, int, hipEvent_t, hipEvent_t, bool);
 
 void launch_reduce(const double* partial, int nblk, int ncol, double* dst, Ctl* ctl, int nv, int nw, bool lu_solve,
                    bool check_done, hipStream_t st) {
@@ -943,9 +956,9 @@ void launch_cycle_init(Ctl* ctl, int max_steps, double stop_abs, hipStream_t st,
 }
 
 template <typename T>
-void launch_dots2(int64_t npad, int64_t ld, const T* V, int nq, const T* W, const T* Z, int k, const T* u,
+void launch_dots2(int64_t npad, int64_t ld, const T* V, int nq, const T* W, const T* Z, int k, int kz, const T* u,
                   const T* z, double* partial, int nblk, Ctl* ctl, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
-    const int ncol = nq + 2 * k + 1;
+    const int ncol = nq + k + kz + 1;
     // four columns per wavefront up to 64 columns, eight up to 128; at most 16 wavefronts per
     // launch, and u, z are read again by each further launch
     const int cpw = ncol > 64 ? 8 : 4;
@@ -957,27 +970,28 @@ void launch_dots2(int64_t npad, int64_t ld, const T* V, int nq, const T* W, cons
         const bool first = a == 0, last = b == ncol;
         if (cpw == 8)
             hipExtLaunchKernelGGL(k_dots2<T, 8>, dim3(nblk), dim3(nw * WAVE), 0, st, first ? ev0 : nullptr,
-                                  last ? ev1 : nullptr, 0, npad, ld, V, nq, W, Z, k, u, z, a, b, partial, nblk,
+                                  last ? ev1 : nullptr, 0, npad, ld, V, nq, W, Z, k, kz, u, z, a, b, partial, nblk,
                                   static_cast<const Ctl*>(ctl));
         else
             hipExtLaunchKernelGGL(k_dots2<T, 4>, dim3(nblk), dim3(nw * WAVE), 0, st, first ? ev0 : nullptr,
-                                  last ? ev1 : nullptr, 0, npad, ld, V, nq, W, Z, k, u, z, a, b, partial, nblk,
+                                  last ? ev1 : nullptr, 0, npad, ld, V, nq, W, Z, k, kz, u, z, a, b, partial, nblk,
                                   static_cast<const Ctl*>(ctl));
     }
 }
-template void launch_dots2<double>(int64_t, int64_t, const double*, int, const double*, const double*, int,
+template void launch_dots2<double>(int64_t, int64_t, const double*, int, const double*, const double*, int, int,
                                    const double*, const double*, double*, int, Ctl*, hipStream_t, hipEvent_t,
                                    hipEvent_t);
-template void launch_dots2<float>(int64_t, int64_t, const float*, int, const float*, const float*, int,
+template void launch_dots2<float>(int64_t, int64_t, const float*, int, const float*, const float*, int, int,
                                   const float*, const float*, double*, int, Ctl*, hipStream_t, hipEvent_t,
                                   hipEvent_t);
 
-void launch_dcgs2_reduce(double* partial, int nblk, int j, int k, bool has_z, Ctl* ctl, hipStream_t st) {
+void launch_dcgs2_reduce(double* partial, int nblk, int j, int k, int kz, bool orth, bool has_z, Ctl* ctl,
+                         hipStream_t st) {
     // the column sums go right after the partials
-    const int nent = 2 * (j + 2 * k + 1);
+    const int nent = 2 * (j + k + kz + 1);
     double* dsum = partial + (int64_t)nent * nblk;
     k_colsum<<<(nent + 15) / 16, 1024, 0, st>>>(partial, nblk, nent, dsum, ctl);
-    k_dcgs2_reduce<<<1, RED_T, 0, st>>>(dsum, j, k, has_z ? 1 : 0, ctl);
+    k_dcgs2_reduce<<<1, RED_T, 0, st>>>(dsum, j, k, kz, orth ? 1 : 0, has_z ? 1 : 0, ctl);
 }
 
 template <typename T>

@@ -583,8 +583,9 @@ __global__ __launch_bounds__(TB) void k_small_update(SmallUpdBatch batch) {
     const int keff = isfinite(s1) ? (rank < J.k ? rank : J.k) : 0;
     // W = Q [U_R[:, :keff]; 0]: U_R in the top c rows, then the reflectors in reverse order
     double* W = J.W;
+    const int first = J.smallest ? rank - keff : 0;   // the modes kept: order[first .. first + keff)
     for (int q = 0; q < keff; ++q) {
-        const int col = L.order[q];
+        const int col = L.order[first + q];
         const double inv = 1.0 / L.sig[col];
         for (int64_t i = threadIdx.x; i < ld; i += TB)
             W[(int64_t)q * ld + i] = (i < c && i < n) ? L.Ac[col * LDC + i] * inv : 0.0;

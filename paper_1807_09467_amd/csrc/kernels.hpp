@@ -60,7 +60,7 @@ void launch_to_f32(int64_t count, const double* in, float* out, hipStream_t st);
 template <typename T>
 void launch_dots(int64_t npad, int64_t ld, const T* const* bases, const T* const* vecs, const int* counts,
                  int ngroups, double* partial, int nblk, Ctl* ctl, hipStream_t st, int pass1_nv = 0,
-                 int pass1_k = 0, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+                 int pass1_k = 0, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr, bool pass1_orth = false);
 // fixed-order sum of the partials into dst[0..ncol); if lu_solve, also ctl->cw = E^{-1} dst[nv..nv+nw)
 void launch_reduce(const double* partial, int nblk, int ncol, double* dst, Ctl* ctl, int nv, int nw,
                    bool lu_solve, bool check_done, hipStream_t st);
@@ -85,12 +85,13 @@ void launch_cycle_init(Ctl* ctl, int max_steps, double stop_abs, hipStream_t st,
 // with u and z; the one-block reduction (completes and rotates column j-1, sets done, prepares
 // step j; has_z = false on the closing step); the update sweep (v_j and the next candidate u).
 template <typename T>
-void launch_dots2(int64_t npad, int64_t ld, const T* V, int nq, const T* W, const T* Z, int k, const T* u,
+void launch_dots2(int64_t npad, int64_t ld, const T* V, int nq, const T* W, const T* Z, int k, int kz, const T* u,
                   const T* z, double* partial, int nblk, Ctl* ctl, hipStream_t st, hipEvent_t ev0 = nullptr,
                   hipEvent_t ev1 = nullptr);
 // the sweep's column sums (written after the partials: partial needs 2 ncol (nblk + 1) doubles),
 // then the one-block reduction of the delayed scheme
-void launch_dcgs2_reduce(double* partial, int nblk, int j, int k, bool has_z, Ctl* ctl, hipStream_t st);
+void launch_dcgs2_reduce(double* partial, int nblk, int j, int k, int kz, bool orth, bool has_z, Ctl* ctl,
+                         hipStream_t st);
 template <typename T>
 void launch_dcgs2_update(int64_t npad, T* V, int64_t ld, int j, const T* Z, int k, T* u, const T* z, int nblk,
                          const Ctl* ctl, hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
@@ -126,8 +127,10 @@ int tsqr_panel_rows(int c);
 void launch_tsqr_level(int64_t rows, const double* M, int64_t ldm, int c, double* S, int64_t lds, int npanels,
                        hipStream_t st);
 // one-sided Jacobi SVD of the c x c matrix R (column-major, ld); writes ctl->sigma, ctl->rank,
-// ctl->k_eff = min(k, rank), ctl->T = V_k Sigma_k^{-1}
-void launch_jacobi_svd(const double* R, int64_t ld, int c, int k, int64_t n, Ctl* ctl, hipStream_t st);
+// ctl->k_eff = min(k, rank), ctl->T = V_k Sigma_k^{-1} (the k_eff leading modes, or with smallest the
+// k_eff trailing ones above the rank cut)
+void launch_jacobi_svd(const double* R, int64_t ld, int c, int k, int64_t n, Ctl* ctl, hipStream_t st,
+                       bool smallest = false);
 // W[:, :k] = X[:, :c] T (T from ctl); rows >= n get zero
 void launch_form_w(int64_t n, int64_t npad, const double* X, int64_t ldx, int c, int k, const Ctl* ctl,
                    double* W, int64_t ldw, hipStream_t st);
@@ -190,7 +193,7 @@ struct SmallUpd {
     double* W;          // output basis (k_eff columns of ld)
     int32_t slot, c, k, svd;
     // results
-    int32_t status, rank, k_eff, pad0;
+    int32_t status, rank, k_eff, smallest;   // smallest: keep the trailing modes above the rank cut
     double sigma[SMALL_SMAX];
 };
 

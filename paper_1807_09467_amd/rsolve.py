@@ -17,7 +17,8 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "librsolve.s
 OK, NOT_CONVERGED = 0, 1
 E_INVALID, E_NONFINITE, E_WORKSPACE, E_DEVICE, E_STATE, E_BUDGET = -1, -2, -3, -4, -5, -6
 
-PLAIN, AUG_OBLIQUE, DEFL_OBLIQUE = 0, 1, 2
+PLAIN, AUG_OBLIQUE, DEFL_OBLIQUE, AUG_ORTHO, DEFL_ORTHO = 0, 1, 2, 3, 4
+SELECT_LARGEST, SELECT_SMALLEST = 0, 1
 PRECOND_NONE, PRECOND_JACOBI = 0, 1
 FP64, FP32_IR = 0, 1
 SAME_PATTERN = 1
@@ -26,7 +27,9 @@ FLAG_RECYCLE_DROPPED = 1
 FLAG_BREAKDOWN_LUCKY = 2
 FLAG_NONFINITE = 4
 
-_METHODS = {"plain": PLAIN, "aug_oblique": AUG_OBLIQUE, "defl_oblique": DEFL_OBLIQUE}
+_METHODS = {"plain": PLAIN, "aug_oblique": AUG_OBLIQUE, "defl_oblique": DEFL_OBLIQUE, "aug_ortho": AUG_ORTHO,
+            "defl_ortho": DEFL_ORTHO}
+_SELECTS = {"largest": SELECT_LARGEST, "smallest": SELECT_SMALLEST}
 _PRECONDS = {"none": PRECOND_NONE, "jacobi": PRECOND_JACOBI}
 _PRECISIONS = {"fp64": FP64, "fp32_ir": FP32_IR}
 
@@ -179,9 +182,9 @@ _ORTHOS = {"cgs2": 0, "dcgs2": 1}
 
 
 def make_config(restart_m=30, recycle_k=0, snapshots_s=0, svd_interval=1, method="aug_oblique", precond="none",
-                precision="fp64", max_iters=10000, inner_tol=1e-5, ortho="cgs2") -> Config:
+                precision="fp64", max_iters=10000, inner_tol=1e-5, ortho="cgs2", select="largest") -> Config:
     return Config(restart_m, recycle_k, snapshots_s, svd_interval, _METHODS[method], _PRECONDS[precond],
-                  _PRECISIONS[precision], max_iters, 0, _ORTHOS[ortho], float(inner_tol))
+                  _PRECISIONS[precision], max_iters, _SELECTS[select], _ORTHOS[ortho], float(inner_tol))
 
 
 def workspace_bytes(cfg: Config, n: int, nnz_max: int) -> int:

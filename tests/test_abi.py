@@ -153,6 +153,19 @@ def test_invalid_configs_rejected(lib, bad):
     assert rc == rsolve.E_INVALID and not h.value
 
 
+def test_method_and_select_values(lib):
+    """Methods 0..4 (plain, oblique and orthogonal rows of Table 1) and both mode selections are
+    accepted; values outside are refused."""
+    for m in ("plain", "aug_oblique", "defl_oblique", "aug_ortho", "defl_ortho"):
+        for sel in ("largest", "smallest"):
+            assert rsolve.workspace_bytes(rsolve.make_config(restart_m=30, recycle_k=4, snapshots_s=6, method=m,
+                                                             select=sel), 100, 500) > 0
+    for field, v in (("method", 5), ("method", -1), ("select", 2)):
+        cfg = rsolve.make_config(restart_m=30)
+        setattr(cfg, field, v)
+        assert rsolve.workspace_bytes(cfg, 100, 500) == 0
+
+
 def test_ortho_field(lib):
     """The orthogonalisation scheme is 0 (CGS2) or 1 (delayed); anything else is refused."""
     ok = rsolve.make_config(restart_m=30, ortho="dcgs2")

@@ -26,9 +26,10 @@ def run_pair(dev, prob, steps, tol, seed=0, precision="fp64", oracle_tol=None, *
     seq = rsolve.Sequence(pat.n, pat.nnz, device=dev, precision=precision, **kw)
     ocfg = O.Config(restart_m=kw.get("restart_m", 30), recycle_k=kw.get("recycle_k", 0),
                     snapshots_s=kw.get("snapshots_s", 0), svd_interval=kw.get("svd_interval", 1),
-                    method={"plain": O.PLAIN, "aug_oblique": O.AUG_OBLIQUE, "defl_oblique": O.DEFL_OBLIQUE}[
-                        kw.get("method", "aug_oblique")],
-                    precond=O.PRECOND_JACOBI if kw.get("precond") == "jacobi" else O.PRECOND_NONE)
+                    method={"plain": O.PLAIN, "aug_oblique": O.AUG_OBLIQUE, "defl_oblique": O.DEFL_OBLIQUE,
+                            "aug_ortho": O.AUG_ORTHO, "defl_ortho": O.DEFL_ORTHO}[kw.get("method", "aug_oblique")],
+                    precond=O.PRECOND_JACOBI if kw.get("precond") == "jacobi" else O.PRECOND_NONE,
+                    select_smallest=kw.get("select") == "smallest")
     ost = O.RecycleState(pat.n, ocfg)
     import torch
     xg_prev = torch.zeros(pat.n, dtype=torch.float64, device=dev)
