@@ -25,6 +25,11 @@ convection-diffusion problems using singular value decomposition"):
   projector choice): operator P_o A, initial vector r0 (augmented) or P_o r0
   (deflated).  GMRES then minimises the projected residual ||P_o r||; the
   cycle-end correction below makes W^T r = 0, after which P_o r = r.
+* Initial-guess-only strategies (section 4): the Galerkin projection guess
+  onto span(W) followed by plain GMRES (section 4.2, eqs. (projection_guess),
+  (projection_t_s), (iteration_projection)), and Lagrange extrapolation of
+  order 2, 3 or 4 from the most recent solutions (section 4.1, eqs. (ext2),
+  (ext3), (ext4)) followed by plain GMRES.
 * Recycle space = leading left singular vectors of the last s solutions,
   recomputed every ell solves (section 5.2, Algorithm 1, eqs. (best_rank_s),
   (opt_svd)).
@@ -51,7 +56,10 @@ import numpy as np
 import scipy.linalg
 
 PLAIN, AUG_OBLIQUE, DEFL_OBLIQUE, AUG_ORTHO, DEFL_ORTHO = 0, 1, 2, 3, 4
+GUESS_PROJECT, GUESS_EXTRAP2, GUESS_EXTRAP3, GUESS_EXTRAP4 = 5, 6, 7, 8
 ORTHO_METHODS = (AUG_ORTHO, DEFL_ORTHO)
+EXTRAP_ORDER = {GUESS_EXTRAP2: 2, GUESS_EXTRAP3: 3, GUESS_EXTRAP4: 4}
+GUESS_ONLY_METHODS = (GUESS_PROJECT, GUESS_EXTRAP2, GUESS_EXTRAP3, GUESS_EXTRAP4)
 PRECOND_NONE, PRECOND_JACOBI = 0, 1
 
 FLAG_RECYCLE_DROPPED = 1
@@ -117,6 +125,23 @@ def recycle_setup(A, W: np.ndarray):
 def oblique_project(W, Z, E, v):
     """P v = v - A W E^{-1} W^T v  (section 3.2, the deflation projector M_D)."""
     return v - Z @ np.linalg.solve(E, W.T @ v)
+
+
+def extrapolation_weights(order: int):
+    """Weights of x_{i-1}, ..., x_{i-order} in the Lagrange extrapolation to the next equispaced
+    time (section 4.1): the interpolating polynomial through the last `order` solutions, taken one
+    step ahead, is sum_j (-1)^(j+1) C(order, j) x_{i-j} (eqs. (ext2): 2, -1; (ext3): 3, -3, 1;
+    (ext4): 4, -6, 4, -1)."""
+    from math import comb
+    return [(-1) ** (j + 1) * comb(order, j) for j in range(1, order + 1)]
+
+
+def extrapolate(history: List[np.ndarray], order: int) -> np.ndarray:
+    """The extrapolated guess from the most recent solutions (history[-1] = x_{i-1}); with fewer
+    than `order` solutions the highest order they allow."""
+    q = min(order, len(history))
+    wts = extrapolation_weights(q)
+    return sum(w * history[-1 - j] for j, w in enumerate(wts))
 
 
 def orthogonal_project(W, v):
@@ -224,11 +249,13 @@ def arnoldi_cycle(op, r0: np.ndarray, m: int, stop_abs: float, max_steps: int) -
 
 
 def solve(A, b: np.ndarray, x0: Optional[np.ndarray], tol: float, cfg: Config,
-          W: Optional[np.ndarray] = None) -> Result:
+          W: Optional[np.ndarray] = None, history: Optional[List[np.ndarray]] = None) -> Result:
     """Solve A x = b to ||b - A x||_2 <= tol ||b||_2 with recycled GMRES(m).
 
     A: scipy CSR matrix (used only for A @ v and its diagonal).  W: recycle
-    basis (n x k_eff, orthonormal columns) or None.
+    basis (n x k_eff, orthonormal columns) or None.  history: previous solutions,
+    most recent last (the extrapolation methods' input; x0 is used while it is
+    empty).
     """
     b = np.asarray(b, dtype=np.float64)
     n = b.size
@@ -250,15 +277,20 @@ def solve(A, b: np.ndarray, x0: Optional[np.ndarray], tol: float, cfg: Config,
         else:
             k_eff = W.shape[1]
     x = np.zeros(n) if x0 is None else np.array(x0, dtype=np.float64)
+    if cfg.method in EXTRAP_ORDER and history:
+        x = extrapolate(history, EXTRAP_ORDER[cfg.method])
     r = b - A @ x
     if use_w:
         x, r = projection_correction(W, Z, E, x, r)
+    # guess-only projection: span(W) enters the initial guess alone; the Krylov part is plain GMRES
+    guess_only = cfg.method in GUESS_ONLY_METHODS
+    use_w_krylov = use_w and not guess_only
 
     ortho = cfg.method in ORTHO_METHODS
 
     def op(v):
         w = A @ (dinv * v)
-        if use_w:
+        if use_w_krylov:
             w = orthogonal_project(W, w) if ortho else oblique_project(W, Z, E, w)
         return w
 
@@ -276,7 +308,7 @@ def solve(A, b: np.ndarray, x0: Optional[np.ndarray], tol: float, cfg: Config,
         if its >= cfg.max_iters:
             return Result(x, its, cycles, k_eff, False, flags, rnorm / bnorm, hist, implicit)
         # deflated orthogonal: the Krylov initial vector is P_o r (equal to r once W^T r = 0)
-        r_start = orthogonal_project(W, r) if (use_w and cfg.method == DEFL_ORTHO) else r
+        r_start = orthogonal_project(W, r) if (use_w_krylov and cfg.method == DEFL_ORTHO) else r
         cyc = arnoldi_cycle(op, r_start, cfg.restart_m, stop_abs, cfg.max_iters - its)
         cycles += 1
         its += cyc.steps
@@ -287,7 +319,7 @@ def solve(A, b: np.ndarray, x0: Optional[np.ndarray], tol: float, cfg: Config,
         y = scipy.linalg.solve_triangular(cyc.R[:j, :j], cyc.g[:j], lower=False)
         x = krylov_update(x, dinv, cyc.V[:, :j], y)
         r = b - A @ x
-        if use_w:
+        if use_w_krylov:
             x, r = projection_correction(W, Z, E, x, r)
         rnorm = float(np.linalg.norm(r))
         hist.append(rnorm / bnorm)
@@ -333,15 +365,19 @@ class RecycleState:
         self.rank = 0
 
     def update(self, x: np.ndarray):
-        """Store x among the s most recent solutions; every ell solves recompute W."""
+        """Store x among the s most recent solutions; every ell solves recompute W (the
+        extrapolation methods keep the ring only)."""
         s = self.cfg.snapshots_s
-        if s <= 0 or self.cfg.recycle_k <= 0:
+        extrap = self.cfg.method in EXTRAP_ORDER
+        if s <= 0 or (self.cfg.recycle_k <= 0 and not extrap):
             self.count += 1
             return
         self.ring.append(np.array(x, dtype=np.float64))
         if len(self.ring) > s:
             self.ring.pop(0)
         self.count += 1
+        if extrap:
+            return
         if self.count % max(1, self.cfg.svd_interval) == 0:
             X = np.stack(self.ring, axis=1)
             self.W, self.sigma, self.rank = svd_basis(X, self.cfg.recycle_k, self.cfg.select_smallest)
@@ -354,7 +390,7 @@ def run_sequence(A_list, b_list, tol: float, cfg: Config, x_init=None):
     x_prev = np.zeros(n) if x_init is None else x_init
     results = []
     for A, b in zip(A_list, b_list):
-        res = solve(A, b, x_prev, tol, cfg, st.W)
+        res = solve(A, b, x_prev, tol, cfg, st.W, st.ring)
         results.append(res)
         st.update(res.x)
         x_prev = res.x

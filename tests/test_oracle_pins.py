@@ -383,6 +383,125 @@ def test_svd_basis_smallest_modes():
     assert cos.min() >= 1 - 1e-10
 
 
+# -- initial-guess strategies (section 4) ----------------------------------------------
+
+
+def test_extrapolation_weights_are_the_printed_ones():
+    """Eqs. (ext2), (ext3), (ext4) print the coefficients of the linear, quadratic and cubic
+    extrapolations."""
+    assert O.extrapolation_weights(2) == [2, -1]
+    assert O.extrapolation_weights(3) == [3, -3, 1]
+    assert O.extrapolation_weights(4) == [4, -6, 4, -1]
+    assert O.extrapolation_weights(1) == [1]
+
+
+def _poly_history(deg, count, n=40, seed=0):
+    """x(t) = sum_{d<=deg} c_d t^d at t = 0..count (the last one is the value to predict)."""
+    rng = np.random.default_rng(seed)
+    C = rng.standard_normal((deg + 1, n))
+    return [sum(C[d] * float(t) ** d for d in range(deg + 1)) for t in range(count + 1)]
+
+
+@pytest.mark.parametrize("order", [2, 3, 4])
+def test_extrapolation_exact_for_polynomials_in_time(order):
+    """Lagrange extrapolation through `order` equispaced points reproduces every polynomial of
+    degree < order (section 4.1); one degree more it does not."""
+    xs = _poly_history(order - 1, 6)
+    pred = O.extrapolate(xs[:-1], order)
+    assert np.linalg.norm(pred - xs[-1]) <= 1e-10 * np.linalg.norm(xs[-1])
+    xs = _poly_history(order, 6, seed=1)
+    pred = O.extrapolate(xs[:-1], order)
+    assert np.linalg.norm(pred - xs[-1]) > 1e-3 * np.linalg.norm(xs[-1])
+
+
+@pytest.mark.parametrize("order", [2, 3, 4])
+def test_extrapolated_guess_then_no_iteration_on_polynomial_sequence(order):
+    """A fixed matrix and solutions polynomial in the step index (degree order-1): from exact
+    previous solutions the guess is the solution and GMRES takes no step; along a solved
+    sequence (previous solutions exact to the tolerance only) the guess is off by the propagated
+    solve errors, so a step or two remain; the guess itself is the closed-form extrapolation."""
+    A, _ = rand_system(40, 11)
+    xs = _poly_history(order - 1, 9, n=40, seed=2)
+    method = {2: O.GUESS_EXTRAP2, 3: O.GUESS_EXTRAP3, 4: O.GUESS_EXTRAP4}[order]
+    cfg = O.Config(restart_m=20, snapshots_s=order, method=method)
+    for i in range(order, 10):
+        res = O.solve(A, A @ xs[i], None, 1e-10, cfg, None, xs[i - order:i])
+        assert res.converged and res.iterations == 0, (i, res.iterations)
+        assert np.linalg.norm(res.x - xs[i]) <= 1e-9 * np.linalg.norm(xs[i])
+    results, st = O.run_sequence([A] * 10, [A @ x for x in xs], 1e-10, cfg)
+    first = results[1].iterations
+    assert first > 4
+    for i, res in enumerate(results):
+        assert res.converged
+        if i >= order:
+            assert res.iterations <= 2, (i, res.iterations)
+    assert len(st.ring) == order and st.W.shape[1] == 0
+    # with max_iters = 0 the returned iterate is the guess: the printed combination of the history
+    hist = [np.array(x) for x in _poly_history(order, 5, n=40, seed=3)[:-1]]
+    cfg0 = O.Config(restart_m=20, snapshots_s=order, method=method, max_iters=0)
+    res = O.solve(A, A @ hist[0], None, 1e-10, cfg0, None, hist)
+    want = {2: 2 * hist[-1] - hist[-2],
+            3: 3 * hist[-1] - 3 * hist[-2] + hist[-3],
+            4: 4 * hist[-1] - 6 * hist[-2] + 4 * hist[-3] - hist[-4]}[order]
+    assert np.allclose(res.x, want, rtol=0, atol=1e-12 * np.abs(want).max())
+
+
+def test_projection_guess_satisfies_the_galerkin_conditions():
+    """Eq. (projection_guess): x0 lies in span(W) and its residual is orthogonal to W; the two
+    conditions fix x0 (max_iters = 0 returns the guess itself)."""
+    A, b = rand_system(60, 21)
+    W = orthonormal(60, 5, 22)
+    cfg = O.Config(restart_m=20, recycle_k=5, snapshots_s=5, method=O.GUESS_PROJECT, max_iters=0)
+    res = O.solve(A, b, None, 1e-10, cfg, W)
+    x = res.x
+    assert np.linalg.norm(x - W @ (W.T @ x)) <= 1e-13 * np.linalg.norm(x)
+    assert np.abs(W.T @ (b - A @ x)).max() <= 1e-12 * np.linalg.norm(b)
+    assert np.linalg.norm(x) > 0.0
+
+
+def test_projection_guess_then_plain_gmres():
+    """Eq. (iteration_projection): after the guess the Krylov iteration is the unmodified one: its
+    implicit residuals are the brute-force minima over K_j(A D^-1, r0) of the plain operator."""
+    A, b, _ = c1_system(step=4)
+    n = b.size
+    W = orthonormal(n, 4, 23)
+    dinv = O.jacobi_inverse(A)
+    cfg0 = O.Config(restart_m=8, recycle_k=4, snapshots_s=4, method=O.GUESS_PROJECT,
+                    precond=O.PRECOND_JACOBI, max_iters=0)
+    xg = O.solve(A, b, None, 0.0, cfg0, W).x
+    r0 = b - A @ xg
+    cfg = O.Config(restart_m=8, recycle_k=4, snapshots_s=4, method=O.GUESS_PROJECT,
+                   precond=O.PRECOND_JACOBI, max_iters=8)
+    res = O.solve(A, b, None, 0.0, cfg, W)
+    bn = np.linalg.norm(b)
+    op = lambda v: A @ (dinv * v)
+    for j in range(1, 9):
+        ref = krylov_min_residual(op, r0, j)
+        assert abs(res.implicit_history[j - 1] * bn - ref) <= 1e-9 * np.linalg.norm(r0) + 1e-8 * ref
+
+
+def test_projection_beats_extrapolation_off_polynomial_trajectory():
+    """Solutions in a fixed two-dimensional space with non-polynomial coefficients: once W spans
+    it (after two solves) the projection guess is exact up to the previous solves' tolerance (a
+    step or two remain), while linear extrapolation leaves a residual that needs a full solve;
+    with exact previous solutions the projection guess is the solution."""
+    A, _ = rand_system(50, 31)
+    U = orthonormal(50, 2, 32)
+    xs = [U @ np.array([np.cos(0.7 * i), np.sin(1.3 * i) + 2.0]) for i in range(8)]
+    bs = [A @ x for x in xs]
+    proj, _ = O.run_sequence([A] * 8, bs, 1e-10,
+                             O.Config(restart_m=20, recycle_k=2, snapshots_s=2, method=O.GUESS_PROJECT))
+    ext, _ = O.run_sequence([A] * 8, bs, 1e-10,
+                            O.Config(restart_m=20, snapshots_s=2, method=O.GUESS_EXTRAP2))
+    assert all(r.iterations <= 2 for r in proj[2:])
+    assert all(r.iterations >= proj[0].iterations // 2 for r in ext[2:])
+    W = np.linalg.qr(np.column_stack(xs[:2]))[0]
+    cfg = O.Config(restart_m=20, recycle_k=2, snapshots_s=2, method=O.GUESS_PROJECT)
+    for i in range(2, 8):
+        res = O.solve(A, bs[i], None, 1e-10, cfg, W)
+        assert res.iterations == 0 and np.linalg.norm(res.x - xs[i]) <= 1e-9 * np.linalg.norm(xs[i])
+
+
 # -- planted mistakes: each plausible error in the oracle is caught by a pin ----------
 
 
@@ -395,6 +514,9 @@ def _pins_pass():
         test_correction_leaves_residual_orthogonal_to_W()
         test_orthogonal_variant_minimises_projected_residual(O.AUG_ORTHO)
         test_orthogonal_equals_oblique_on_invariant_subspace()
+        test_extrapolated_guess_then_no_iteration_on_polynomial_sequence(3)
+        test_projection_guess_satisfies_the_galerkin_conditions()
+        test_projection_guess_then_plain_gmres()
     except AssertionError:
         return False
     return True
@@ -406,8 +528,19 @@ def test_pins_pass_on_unmodified_oracle():
 
 @pytest.mark.parametrize("mutation", ["projector_uses_W", "guess_transposed_E", "givens_sign",
                                       "update_without_preconditioner", "operator_perturbed",
-                                      "correction_sign", "ortho_projector_missing", "ortho_projector_half"])
+                                      "correction_sign", "ortho_projector_missing", "ortho_projector_half",
+                                      "extrap_weights_reversed", "extrap_off_by_one",
+                                      "guess_only_projects_krylov"])
 def test_planted_mistakes_are_caught(monkeypatch, mutation):
+    if mutation == "extrap_weights_reversed":
+        orig_w = O.extrapolation_weights
+        monkeypatch.setattr(O, "extrapolation_weights", lambda q: orig_w(q)[::-1])
+    elif mutation == "extrap_off_by_one":
+        monkeypatch.setattr(O, "extrapolate",
+                            lambda h, q: sum(w * h[-2 - j] if len(h) > j + 1 else w * h[0]
+                                             for j, w in enumerate(O.extrapolation_weights(min(q, len(h))))))
+    elif mutation == "guess_only_projects_krylov":
+        monkeypatch.setattr(O, "GUESS_ONLY_METHODS", ())
     if mutation == "ortho_projector_missing":
         monkeypatch.setattr(O, "orthogonal_project", lambda W, v: v)
     elif mutation == "ortho_projector_half":
