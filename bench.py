@@ -407,6 +407,37 @@ def summarize(r, steps):
     }
 
 
+def bench_guess_table(args, gasm, u0, systems, tol, cfg, desc, dev):
+    """Extrapolation against projection initial guesses (section 4, the comparison of Table 2): for
+    s = 2, 3, 4, extrapolation of order s from the last s solutions and the projection guess onto
+    the span of the last s solutions (recycle space of k = s singular vectors, which spans them),
+    each followed by plain GMRES; average and standard deviation of the Arnoldi steps per solve
+    over the timed steps, and the solve rate.  One JSON line."""
+    rows = []
+    for sdim in (2, 3, 4):
+        row = {"s": sdim}
+        for tag, over in (("ext", dict(method=f"guess_extrap{sdim}", recycle_k=0, snapshots_s=sdim)),
+                          ("proj", dict(method="guess_project", recycle_k=sdim, snapshots_s=sdim))):
+            c = dict(cfg)
+            c.update(over)
+            r = run_solver(gasm, u0, systems, args.warmup, args.steps, tol, c, dev, label=f"{tag} s={sdim}",
+                           graphs=args.graphs)
+            its = np.array(r["its"], dtype=float)
+            row[f"{tag}_av"] = float(its.mean())
+            row[f"{tag}_dev"] = float(its.std())
+            row[f"{tag}_solves_per_s"] = args.steps / r["elapsed"]
+            row[f"{tag}_max_rel_residual"] = float(np.max(r["rel"]))
+            del r
+        rows.append(row)
+        log(f"s={sdim}: ext {row['ext_av']:.2f} +- {row['ext_dev']:.2f} its, proj {row['proj_av']:.2f} +- "
+            f"{row['proj_dev']:.2f} its")
+    out = {"metric": "arnoldi_steps_per_solve", "unit": "steps", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "higher_is_better": False, "data": "synthetic",
+           "config": {"workload": args.workload, "description": desc + ", initial-guess comparison"},
+           "rows": rows}
+    print(json.dumps(out), flush=True)
+
+
 def cpu_baseline(prob, asm_host, tol):
     """Oracle (plain FP64 GMRES(50), right Jacobi) on time step 1 of the same sequence, host cores."""
     from threadpoolctl import threadpool_info
@@ -440,8 +471,13 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--inner-tol", type=float, default=None,
                     help="override the FP32 cycle reduction factor of the mixed-precision workload")
-    ap.add_argument("--method", choices=["aug_oblique", "defl_oblique", "aug_ortho", "defl_ortho"], default=None,
-                    help="projector of the recycled run (default: the workload's, augmented oblique)")
+    ap.add_argument("--method", choices=["aug_oblique", "defl_oblique", "aug_ortho", "defl_ortho", "guess_project",
+                                         "guess_extrap2", "guess_extrap3", "guess_extrap4"], default=None,
+                    help="method of the recycled run (default: the workload's, augmented oblique); the "
+                         "extrapolation guesses keep a ring of `order` solutions and no recycle space")
+    ap.add_argument("--guess-table", action="store_true",
+                    help="instead of the headline line: extrapolation of order s against the projection guess "
+                         "onto the s previous solutions (k = s), s = 2, 3, 4, on the workload's sequence")
     ap.add_argument("--select", choices=["largest", "smallest"], default=None,
                     help="singular modes kept in the recycle space (default: largest, Algorithm 1)")
     ap.add_argument("--ortho", choices=["cgs2", "dcgs2"], default="dcgs2",
@@ -488,7 +524,9 @@ def main():
     desc = desc + (", Arnoldi CGS2 with delayed reorthogonalisation" if args.ortho == "dcgs2" else ", Arnoldi CGS2")
     if args.method:
         cfg["method"] = args.method
-        desc = desc + f", projector {args.method}"
+        desc = desc + f", method {args.method}"
+        if args.method.startswith("guess_extrap"):
+            cfg["recycle_k"], cfg["snapshots_s"] = 0, int(args.method[-1])
     if args.select:
         cfg["select"] = args.select
         desc = desc + f", {args.select} singular modes"
@@ -496,6 +534,8 @@ def main():
     nsteps = args.warmup + args.steps
     asm, gasm, u0, systems = generate(prob, nsteps, dev)
 
+    if args.guess_table:
+        return bench_guess_table(args, gasm, u0, systems, tol, cfg, desc, dev)
     kinds = None if args.profile_kinds == "all" else [k for k in args.profile_kinds.split(",") if k]
     main_run = run_solver(gasm, u0, systems, args.warmup, args.steps, tol, cfg, dev, profile=not args.no_profile,
                           label="recycled", graphs=args.graphs, profile_kinds=kinds)

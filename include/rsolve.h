@@ -66,6 +66,18 @@ extern "C" {
                                      x += W E^{-1} W^T r makes W^T r = 0 (multi-kernel path only) */
 #define RSOLVE_DEFL_ORTHO     4   /* Table 1, deflated orthogonal: also the initial vector projected
                                      (the same iteration once the projected guess leaves W^T r = 0) */
+#define RSOLVE_GUESS_PROJECT  5   /* section 4.2: the projection guess x0 + W E^{-1} W^T (b - A x0) onto
+                                     the recycle space, then GMRES(m) with the unmodified operator
+                                     A D^{-1} and no cycle-end correction (eq. (iteration_projection)) */
+#define RSOLVE_GUESS_EXTRAP2  6   /* section 4.1, eq. (ext2): x0 = 2 x_{i-1} - x_{i-2} from the ring of
+                                     previous solutions, then plain GMRES(m) */
+#define RSOLVE_GUESS_EXTRAP3  7   /* eq. (ext3): x0 = 3 x_{i-1} - 3 x_{i-2} + x_{i-3} */
+#define RSOLVE_GUESS_EXTRAP4  8   /* eq. (ext4): x0 = 4 x_{i-1} - 6 x_{i-2} + 4 x_{i-3} - x_{i-4}.
+                                     The extrapolation methods keep the ring only (recycle_k = 0,
+                                     snapshots_s >= the order, no SVD); with fewer stored solutions
+                                     than the order the highest order they allow is used (the last
+                                     solution alone once one is stored), and x0 is used only while
+                                     the ring is empty.  None of 5..8 runs on the one-block path. */
 #define RSOLVE_PRECOND_NONE   0
 #define RSOLVE_PRECOND_JACOBI 1   /* right Jacobi: operator P A D^{-1}, x = x0 + D^{-1} V y */
 #define RSOLVE_FP64           0   /* everything in float64 */
@@ -97,9 +109,11 @@ typedef struct rsolve_seq rsolve_seq;
 typedef struct {
     int32_t restart_m;     /* GMRES restart length m, 1..RSOLVE_MAX_RESTART */
     int32_t recycle_k;     /* recycle dimension k, 0..RSOLVE_MAX_RECYCLE (0 = plain) */
-    int32_t snapshots_s;   /* snapshot ring size s, k <= s <= RSOLVE_MAX_SNAPSHOTS (0 if k = 0) */
+    int32_t snapshots_s;   /* snapshot ring size s, k <= s <= RSOLVE_MAX_SNAPSHOTS (0 if k = 0);
+                              for RSOLVE_GUESS_EXTRAPq: q <= s (the ring of previous solutions) */
     int32_t svd_interval;  /* ell >= 1: recompute W every ell updates (Algorithm 1) */
-    int32_t method;        /* RSOLVE_PLAIN / _AUG_OBLIQUE / _DEFL_OBLIQUE / _AUG_ORTHO / _DEFL_ORTHO */
+    int32_t method;        /* RSOLVE_PLAIN / _AUG_OBLIQUE / _DEFL_OBLIQUE / _AUG_ORTHO / _DEFL_ORTHO /
+                              _GUESS_PROJECT / _GUESS_EXTRAP2 / _GUESS_EXTRAP3 / _GUESS_EXTRAP4 */
     int32_t precond;       /* RSOLVE_PRECOND_NONE / RSOLVE_PRECOND_JACOBI */
     int32_t precision;     /* RSOLVE_FP64 / RSOLVE_FP32_IR */
     int32_t max_iters;     /* cap on Arnoldi steps per solve (>= 1) */
@@ -162,7 +176,9 @@ int rsolve_create_sequence(const rsolve_config* cfg, int64_t n, int64_t nnz_max,
  * section 6.1; the check is an explicit FP64 residual).  x0 may be NULL
  * (zero start) and x may alias x0.  The initial guess is
  * x0 + W E^{-1} W^T (b - A x0) when the sequence holds a recycle basis; with
- * x0 = NULL this is the projection guess W E^{-1} W^T b of section 4.2.
+ * x0 = NULL this is the projection guess W E^{-1} W^T b of section 4.2.  For
+ * the extrapolation methods the guess is the extrapolation of the stored
+ * solutions (x0 only while none is stored).
  * Synchronous: returns after x and *st are final.  A's buffers need only stay
  * valid for the duration of the call.  b = 0 gives x = 0 and 0 iterations.
  * Returns OK, NOT_CONVERGED (x = last iterate), E_INVALID (bad pointers, n
@@ -177,7 +193,9 @@ int rsolve_solve(rsolve_seq* s, const rsolve_csr* A, const double* b, const doub
  * solutions; when the number of stored solutions is a multiple of
  * svd_interval, replace W by the min(k, numerical rank) leading left singular
  * vectors of the ring (numerical rank: sigma_i > sigma_1 * max(n, c) * 2^-52
- * with c the number of stored columns).  Synchronous.  Errors: E_STATE (x =
+ * with c the number of stored columns).  The extrapolation methods only store
+ * x (no SVD; W stays empty; a non-finite x surfaces in the next solve).
+ * Synchronous.  Errors: E_STATE (x =
  * NULL before any solve), E_INVALID, E_NONFINITE (non-finite snapshot),
  * E_DEVICE.
  */
@@ -195,9 +213,9 @@ int rsolve_get_recycle(rsolve_seq* s, int32_t* k_eff, int32_t* rank, double* sig
 
 /* ---- batched solves of many sequences in one launch ---- */
 
-/* One-block limits: an item whose sequence is FP64 with an oblique (or no) projector, restart_m,
- * recycle_k (and, for the update, snapshots_s <= restart_m + 1) within these limits and
- * n <= RSOLVE_SMALL_MAX_N runs
+/* One-block limits: an item whose sequence is FP64 with method RSOLVE_PLAIN, _AUG_OBLIQUE or
+ * _DEFL_OBLIQUE, restart_m, recycle_k (and, for the update, snapshots_s <= restart_m + 1)
+ * within these limits and n <= RSOLVE_SMALL_MAX_N runs
  * as one workgroup of a shared persistent launch; any other item runs through the
  * multi-kernel path of rsolve_solve / rsolve_update_recycle, one after the other, while that
  * launch is in flight. */

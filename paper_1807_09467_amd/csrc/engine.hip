@@ -66,6 +66,11 @@ struct Carver {
 
 constexpr size_t CTL_HEAD = offsetof(Ctl, g);   // fields the host reads after a sync
 
+// Order of the extrapolated initial guess (eqs. (ext2)-(ext4)), 0 for the other methods.
+int extrap_order(int method) {
+    return (method >= RSOLVE_GUESS_EXTRAP2 && method <= RSOLVE_GUESS_EXTRAP4) ? method - RSOLVE_GUESS_EXTRAP2 + 2 : 0;
+}
+
 int cfg_check(const rsolve_config* c) {
     if (!c) return RSOLVE_E_INVALID;
     if (c->restart_m < 1 || c->restart_m > RSOLVE_MAX_RESTART) return RSOLVE_E_INVALID;
@@ -73,7 +78,10 @@ int cfg_check(const rsolve_config* c) {
     if (c->snapshots_s < 0 || c->snapshots_s > RSOLVE_MAX_SNAPSHOTS) return RSOLVE_E_INVALID;
     if (c->recycle_k > 0 && c->snapshots_s < c->recycle_k) return RSOLVE_E_INVALID;
     if (c->svd_interval < 1) return RSOLVE_E_INVALID;
-    if (c->method < RSOLVE_PLAIN || c->method > RSOLVE_DEFL_ORTHO) return RSOLVE_E_INVALID;
+    if (c->method < RSOLVE_PLAIN || c->method > RSOLVE_GUESS_EXTRAP4) return RSOLVE_E_INVALID;
+    // the extrapolation methods keep a ring of at least `order` solutions and no recycle space
+    if (extrap_order(c->method) && (c->recycle_k != 0 || c->snapshots_s < extrap_order(c->method)))
+        return RSOLVE_E_INVALID;
     if (c->precond != RSOLVE_PRECOND_NONE && c->precond != RSOLVE_PRECOND_JACOBI) return RSOLVE_E_INVALID;
     if (c->precision != RSOLVE_FP64 && c->precision != RSOLVE_FP32_IR) return RSOLVE_E_INVALID;
     if (c->max_iters < 1) return RSOLVE_E_INVALID;
@@ -225,7 +233,7 @@ size_t layout(rsolve_seq* s, const rsolve_config& c, int64_t n, int64_t nnz_max,
     double* Wr = k ? cv.take<double>((size_t)ldr * ld) : nullptr;
     float* W32 = (k && ir) ? cv.take<float>((size_t)k * ld) : nullptr;
     float* Z32 = (k && ir) ? cv.take<float>((size_t)k * ld) : nullptr;
-    double* X = (k && sn) ? cv.take<double>((size_t)sn * ld) : nullptr;
+    double* X = ((k || extrap_order(c.method)) && sn) ? cv.take<double>((size_t)sn * ld) : nullptr;
     double* wb0 = cv.take<double>((size_t)ld);
     double* wb1 = cv.take<double>((size_t)ld);
     float* w320 = ir ? cv.take<float>((size_t)ld) : nullptr;
@@ -578,15 +586,15 @@ static_assert(SMALL_MMAX == RSOLVE_SMALL_MAX_RESTART && SMALL_KMAX == RSOLVE_SMA
 
 bool small_solve_ok(const rsolve_seq* s) {
     const rsolve_config& c = s->cfg;
-    // the one-block solve implements the oblique projector only
+    // the one-block solve implements the oblique projector (or none) only
     return c.precision == RSOLVE_FP64 && c.restart_m <= SMALL_MMAX && c.recycle_k <= SMALL_KMAX &&
-           s->n <= RSOLVE_SMALL_MAX_N && c.method != RSOLVE_AUG_ORTHO && c.method != RSOLVE_DEFL_ORTHO;
+           s->n <= RSOLVE_SMALL_MAX_N && c.method <= RSOLVE_DEFL_OBLIQUE;
 }
 
 bool small_update_ok(const rsolve_seq* s) {
     const rsolve_config& c = s->cfg;
     return c.precision == RSOLVE_FP64 && c.snapshots_s <= SMALL_SMAX && c.snapshots_s <= c.restart_m + 1 &&
-           s->n >= c.snapshots_s && s->n <= RSOLVE_SMALL_MAX_N;
+           s->n >= c.snapshots_s && s->n <= RSOLVE_SMALL_MAX_N && extrap_order(c.method) == 0;
 }
 
 // Argument checks shared with rsolve_solve; returns RSOLVE_OK or E_INVALID (message set).
@@ -922,7 +930,7 @@ int rsolve_solve(rsolve_seq* s, const rsolve_csr* A, const double* b, const doub
     }
 
     // a2: recycle setup A W, E = W^T A W, LU(E)
-    int k = (c.method != RSOLVE_PLAIN) ? s->k_w : 0;
+    int k = (c.method != RSOLVE_PLAIN) ? s->k_w : 0;   // always 0 for the extrapolation methods
     uint32_t flags = 0;
     if (k > 0) {
         if (!s->wr_ok) {   // W came from the one-block update, which keeps no row-major copy
@@ -935,8 +943,24 @@ int rsolve_solve(rsolve_seq* s, const rsolve_csr* A, const double* b, const doub
         launch_small_lu(ctl_red(s->ctl), k, s->ctl, stm);
         if (ir) launch_to_f32(k * ld, s->Z, s->Z32, stm);
     }
-    // a3: r = b - A x0
-    launch_copy_pad(n, ld, x0, s->xw, stm);
+    // a3: r = b - A x0, x0 the caller's or (extrapolation methods, once solutions are stored) the
+    // extrapolation of the most recent ones: order min(q, stored), weights (-1)^{j+1} C(order, j)
+    const int q_ext = extrap_order(c.method);
+    const int stored = (int)std::min<int64_t>(s->count, c.snapshots_s);
+    if (q_ext && stored > 0) {
+        Extrap e{};
+        e.q = std::min(q_ext, stored);
+        int64_t binom = 1;
+        for (int j = 0; j < e.q; ++j) {
+            binom = binom * (e.q - j) / (j + 1);   // C(q, j + 1)
+            const int64_t slot = (s->count - 1 - j) % c.snapshots_s;
+            e.x[j] = s->X + slot * ld;
+            e.w[j] = (j % 2 == 0) ? (double)binom : -(double)binom;
+        }
+        launch_extrapolate(n, ld, e, s->xw, stm);
+    } else {
+        launch_copy_pad(n, ld, x0, s->xw, stm);
+    }
     HIP_TRY(hipGetLastError());
     int rc = read_head(s);
     if (rc) return rc;
@@ -963,6 +987,8 @@ int rsolve_solve(rsolve_seq* s, const rsolve_csr* A, const double* b, const doub
     }
     residual_and_correct(s, A, b, k);
     HIP_TRY(hipGetLastError());
+    // the projection-guess method uses W for the guess only: plain Krylov cycles (kry = 0)
+    const int kry = (c.method == RSOLVE_GUESS_PROJECT) ? 0 : k;
     const double stop_abs = tol * bnorm;
     const double t_setup = ms_since(t0);
 
@@ -1013,16 +1039,16 @@ int rsolve_solve(rsolve_seq* s, const rsolve_csr* A, const double* b, const doub
             auto enqueue = [&] {
                 for (int j = j0; j < j1; ++j) {
                     if (dg) {
-                        if (ir) dcgs2_step<float>(s, j, max_steps, op, s->V32, s->w32, W32, Z32, k, orth);
-                        else dcgs2_step<double>(s, j, max_steps, op, s->V, s->wb, s->W, s->Z, k, orth);
+                        if (ir) dcgs2_step<float>(s, j, max_steps, op, s->V32, s->w32, W32, Z32, kry, orth);
+                        else dcgs2_step<double>(s, j, max_steps, op, s->V, s->wb, s->W, s->Z, kry, orth);
                     } else {
-                        if (ir) arnoldi_step<float>(s, j, op, s->V32, s->w32, W32, Z32, k, orth);
-                        else arnoldi_step<double>(s, j, op, s->V, s->wb, s->W, s->Z, k, orth);
+                        if (ir) arnoldi_step<float>(s, j, op, s->V32, s->w32, W32, Z32, kry, orth);
+                        else arnoldi_step<double>(s, j, op, s->V, s->wb, s->W, s->Z, kry, orth);
                     }
                 }
             };
             if (s->graphs_on && !s->prof_on) {
-                const rsolve_seq::GraphKey key{j0,      j1,         k,         ir ? 1 : 0, s->lpr, s->svec, s->sremap,
+                const rsolve_seq::GraphKey key{j0,      j1,         kry,       ir ? 1 : 0, s->lpr, s->svec, s->sremap,
                                                op.fmt,  (dg ? 1 : 0) | (orth ? 2 : 0), dg ? max_steps : 0, op.rp, op.ci,
                                                op.off,  op.vals};
                 hipGraphExec_t ge = nullptr;
@@ -1042,7 +1068,7 @@ int rsolve_solve(rsolve_seq* s, const rsolve_csr* A, const double* b, const doub
         launch_cycle_solve(s->ctl, stm);
         if (ir) launch_x_update<float>(n, s->V32, ld, jac ? s->dinv : nullptr, s->xw, s->ctl, stm);
         else launch_x_update<double>(n, s->V, ld, jac ? s->dinv : nullptr, s->xw, s->ctl, stm);
-        residual_and_correct(s, A, b, k);
+        residual_and_correct(s, A, b, kry);
         HIP_TRY(hipGetLastError());
         rc = read_head(s);
         if (rc) return rc;
@@ -1088,7 +1114,8 @@ int rsolve_update_recycle(rsolve_seq* s, const double* x) {
         src = s->xw;
     }
     const rsolve_config& c = s->cfg;
-    if (c.recycle_k == 0 || c.snapshots_s == 0) {
+    const bool extrap = extrap_order(c.method) != 0;
+    if ((c.recycle_k == 0 && !extrap) || c.snapshots_s == 0) {
         s->count++;
         return RSOLVE_OK;
     }
@@ -1098,7 +1125,7 @@ int rsolve_update_recycle(rsolve_seq* s, const double* x) {
     const int slot = (int)(s->count % c.snapshots_s);
     HIP_TRY(hipMemcpyAsync(s->X + (int64_t)slot * ld, src, sizeof(double) * n, hipMemcpyDeviceToDevice, stm));
     s->count++;
-    if (s->count % c.svd_interval != 0) {
+    if (extrap || s->count % c.svd_interval != 0) {   // the extrapolation methods keep the ring only
         HIP_TRY(hipStreamSynchronize(stm));
         return RSOLVE_OK;
     }
@@ -1292,7 +1319,7 @@ int rsolve_update_recycle_batch(rsolve_batch_update_item* items, int32_t count, 
             continue;
         }
         const rsolve_config& c = s->cfg;
-        if (c.recycle_k == 0 || c.snapshots_s == 0) {
+        if ((c.recycle_k == 0 && extrap_order(c.method) == 0) || c.snapshots_s == 0) {
             s->count++;
             it.status = RSOLVE_OK;
             continue;

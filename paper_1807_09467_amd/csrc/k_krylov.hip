@@ -533,6 +533,19 @@ __global__ __launch_bounds__(BLOCK) void k_copy_pad(int64_t n, int64_t npad, con
     if (i < npad) out[i] = (in && i < n) ? in[i] : 0.0;
 }
 
+// out = sum_{j<q} w_j x_j over the first n entries, zero up to npad: the extrapolated initial
+// guess from the most recent solutions (section 4.1, eqs. (ext2)-(ext4)); one pass over the q
+// inputs and the output.
+__global__ __launch_bounds__(BLOCK) void k_extrapolate(int64_t n, int64_t npad, Extrap e, double* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (i >= npad) return;
+    double acc = 0.0;
+    if (i < n) {
+        for (int j = 0; j < e.q; ++j) acc += e.w[j] * e.x[j][i];
+    }
+    out[i] = acc;
+}
+
 // ---------------------------------------------------------------------------
 // Arnoldi with delayed reorthogonalisation (two sweeps per step).  Step j holds the candidate
 // u for basis vector j, orthogonalised once against V_j = [v_0 .. v_{j-1}] and not normalised,
@@ -1032,6 +1045,10 @@ void launch_norm2(int64_t n, const double* v, double* partial, int nblk, hipStre
 
 void launch_copy_pad(int64_t n, int64_t npad, const double* in, double* out, hipStream_t st) {
     k_copy_pad<<<(unsigned)((npad + BLOCK - 1) / BLOCK), BLOCK, 0, st>>>(n, npad, in, out);
+}
+
+void launch_extrapolate(int64_t n, int64_t npad, const Extrap& e, double* out, hipStream_t st) {
+    k_extrapolate<<<(unsigned)((npad + BLOCK - 1) / BLOCK), BLOCK, 0, st>>>(n, npad, e, out);
 }
 
 }  // namespace rs

@@ -110,6 +110,13 @@ void launch_finish_norm(const double* partial, int nblk, Ctl* ctl, int which, hi
 void launch_norm2(int64_t n, const double* v, double* partial, int nblk, hipStream_t st);
 // out[i] = in[i] for i < n, 0 for n <= i < npad
 void launch_copy_pad(int64_t n, int64_t npad, const double* in, double* out, hipStream_t st);
+// out[i] = sum_{j<q} w[j] x[j][i] for i < n, 0 for n <= i < npad (1 <= q <= 4)
+struct Extrap {
+    const double* x[4];
+    double w[4];
+    int q;
+};
+void launch_extrapolate(int64_t n, int64_t npad, const Extrap& e, double* out, hipStream_t st);
 
 // ---- dense (k_dense.hip) ----
 // partial[e * nblk + b] = block b's share of (A^T B)[e] (MFMA f64, e = i + p j); rows >= n read

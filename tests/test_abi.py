@@ -154,16 +154,30 @@ def test_invalid_configs_rejected(lib, bad):
 
 
 def test_method_and_select_values(lib):
-    """Methods 0..4 (plain, oblique and orthogonal rows of Table 1) and both mode selections are
-    accepted; values outside are refused."""
-    for m in ("plain", "aug_oblique", "defl_oblique", "aug_ortho", "defl_ortho"):
+    """Methods 0..5 (plain, oblique and orthogonal rows of Table 1, projection guess) and both mode
+    selections are accepted; values outside are refused."""
+    for m in ("plain", "aug_oblique", "defl_oblique", "aug_ortho", "defl_ortho", "guess_project"):
         for sel in ("largest", "smallest"):
             assert rsolve.workspace_bytes(rsolve.make_config(restart_m=30, recycle_k=4, snapshots_s=6, method=m,
                                                              select=sel), 100, 500) > 0
-    for field, v in (("method", 5), ("method", -1), ("select", 2)):
+    for field, v in (("method", 9), ("method", -1), ("select", 2)):
         cfg = rsolve.make_config(restart_m=30)
         setattr(cfg, field, v)
         assert rsolve.workspace_bytes(cfg, 100, 500) == 0
+
+
+@pytest.mark.parametrize("order", [2, 3, 4])
+def test_extrapolation_configs(lib, order):
+    """Extrapolation of order q (eqs. (ext2)-(ext4)) needs a ring of at least q solutions and no
+    recycle space; its workspace holds the ring (s vectors) and grows with s."""
+    m = "guess_extrap%d" % order
+    ok = rsolve.workspace_bytes(rsolve.make_config(restart_m=30, snapshots_s=order, method=m), 1000, 5000)
+    big = rsolve.workspace_bytes(rsolve.make_config(restart_m=30, snapshots_s=order + 4, method=m), 1000, 5000)
+    plain = rsolve.workspace_bytes(rsolve.make_config(restart_m=30, method="plain"), 1000, 5000)
+    assert ok > plain and big - ok >= 4 * 1000 * 8
+    assert rsolve.workspace_bytes(rsolve.make_config(restart_m=30, snapshots_s=order - 1, method=m), 1000, 5000) == 0
+    assert rsolve.workspace_bytes(rsolve.make_config(restart_m=30, recycle_k=2, snapshots_s=order + 2, method=m),
+                                  1000, 5000) == 0
 
 
 def test_ortho_field(lib):

@@ -27,7 +27,9 @@ def run_pair(dev, prob, steps, tol, seed=0, precision="fp64", oracle_tol=None, *
     ocfg = O.Config(restart_m=kw.get("restart_m", 30), recycle_k=kw.get("recycle_k", 0),
                     snapshots_s=kw.get("snapshots_s", 0), svd_interval=kw.get("svd_interval", 1),
                     method={"plain": O.PLAIN, "aug_oblique": O.AUG_OBLIQUE, "defl_oblique": O.DEFL_OBLIQUE,
-                            "aug_ortho": O.AUG_ORTHO, "defl_ortho": O.DEFL_ORTHO}[kw.get("method", "aug_oblique")],
+                            "aug_ortho": O.AUG_ORTHO, "defl_ortho": O.DEFL_ORTHO, "guess_project": O.GUESS_PROJECT,
+                            "guess_extrap2": O.GUESS_EXTRAP2, "guess_extrap3": O.GUESS_EXTRAP3,
+                            "guess_extrap4": O.GUESS_EXTRAP4}[kw.get("method", "aug_oblique")],
                     precond=O.PRECOND_JACOBI if kw.get("precond") == "jacobi" else O.PRECOND_NONE,
                     select_smallest=kw.get("select") == "smallest")
     ost = O.RecycleState(pat.n, ocfg)
@@ -39,7 +41,7 @@ def run_pair(dev, prob, steps, tol, seed=0, precision="fp64", oracle_tol=None, *
         A = asm.csr(vals)
         x, st, status = seq.solve(rp, ci, _t(vals, dev), _t(b, dev), x0=xg_prev, tol=tol, same_pattern=i > 0)
         seq.update()
-        ores = O.solve(A, b, xo_prev, oracle_tol or tol, ocfg, ost.W)
+        ores = O.solve(A, b, xo_prev, oracle_tol or tol, ocfg, ost.W, ost.ring)
         ost.update(ores.x)
         xg = x.cpu().numpy()
         out.append(dict(step=i, status=status, st=st, ores=ores, xg=xg, A=A, b=b,
