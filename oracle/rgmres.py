@@ -25,6 +25,14 @@ convection-diffusion problems using singular value decomposition"):
   projector choice): operator P_o A, initial vector r0 (augmented) or P_o r0
   (deflated).  GMRES then minimises the projected residual ||P_o r||; the
   cycle-end correction below makes W^T r = 0, after which P_o r = r.
+* The least-squares projector P_LS = I - A W (W^T A^T A W)^{-1} W^T A^T in
+  its place (Table 1, rows "augmented LS" and "deflated LS"; section 3.3, the
+  third projector choice): operator P_LS A, initial vector r0 (augmented) or
+  P_LS r0 (deflated; the inner iteration of GCRO).  P_LS is the orthogonal
+  projector onto the complement of range(A W), so GMRES minimises ||P_LS r||,
+  and the cycle-end correction is the least-squares one,
+  x += W c, r <- r - A W c with c = argmin ||r - A W c||, after which
+  P_LS r = r: the true residual is the minimised one.
 * Initial-guess-only strategies (section 4): the Galerkin projection guess
   onto span(W) followed by plain GMRES (section 4.2, eqs. (projection_guess),
   (projection_t_s), (iteration_projection)), and Lagrange extrapolation of
@@ -57,7 +65,10 @@ import scipy.linalg
 
 PLAIN, AUG_OBLIQUE, DEFL_OBLIQUE, AUG_ORTHO, DEFL_ORTHO = 0, 1, 2, 3, 4
 GUESS_PROJECT, GUESS_EXTRAP2, GUESS_EXTRAP3, GUESS_EXTRAP4 = 5, 6, 7, 8
+AUG_LS, DEFL_LS = 9, 10
 ORTHO_METHODS = (AUG_ORTHO, DEFL_ORTHO)
+LS_METHODS = (AUG_LS, DEFL_LS)
+PROJECTED_START_METHODS = (DEFL_ORTHO, DEFL_LS)   # deflated rows: Krylov initial vector P r
 EXTRAP_ORDER = {GUESS_EXTRAP2: 2, GUESS_EXTRAP3: 3, GUESS_EXTRAP4: 4}
 GUESS_ONLY_METHODS = (GUESS_PROJECT, GUESS_EXTRAP2, GUESS_EXTRAP3, GUESS_EXTRAP4)
 PRECOND_NONE, PRECOND_JACOBI = 0, 1
@@ -147,6 +158,25 @@ def extrapolate(history: List[np.ndarray], order: int) -> np.ndarray:
 def orthogonal_project(W, v):
     """P_o v = v - W W^T v  (section 3.3, the orthogonal projector onto the complement of span(W))."""
     return v - W @ (W.T @ v)
+
+
+def ls_coefficients(Z, v):
+    """c = argmin ||v - Z c||_2 = (Z^T Z)^{-1} Z^T v, with Z = A W (section 3.3, the third
+    projector choice), by a library least-squares solve."""
+    return np.linalg.lstsq(Z, v, rcond=None)[0]
+
+
+def ls_project(Z, v):
+    """P_LS v = v - A W (W^T A^T A W)^{-1} W^T A^T v: v minus its orthogonal projection onto
+    range(A W) (section 3.3, the third projector; Table 1 LS rows)."""
+    return v - Z @ ls_coefficients(Z, v)
+
+
+def ls_correction(W, Z, x, r):
+    """x <- x + W c, r <- r - A W c with c the least-squares coefficients of r on A W: the
+    minimal-residual correction in span(W), after which (A W)^T r = 0."""
+    c = ls_coefficients(Z, r)
+    return x + W @ c, r - Z @ c
 
 
 def projection_correction(W, Z, E, x, r):
@@ -287,12 +317,20 @@ def solve(A, b: np.ndarray, x0: Optional[np.ndarray], tol: float, cfg: Config,
     use_w_krylov = use_w and not guess_only
 
     ortho = cfg.method in ORTHO_METHODS
+    lsq = cfg.method in LS_METHODS
 
     def op(v):
         w = A @ (dinv * v)
         if use_w_krylov:
-            w = orthogonal_project(W, w) if ortho else oblique_project(W, Z, E, w)
+            if lsq:
+                w = ls_project(Z, w)
+            else:
+                w = orthogonal_project(W, w) if ortho else oblique_project(W, Z, E, w)
         return w
+
+    def correct(x, r):
+        # cycle-end correction in span(W): least squares for the LS rows, Galerkin otherwise
+        return ls_correction(W, Z, x, r) if lsq else projection_correction(W, Z, E, x, r)
 
     stop_abs = tol * bnorm
     its = 0
@@ -307,8 +345,11 @@ def solve(A, b: np.ndarray, x0: Optional[np.ndarray], tol: float, cfg: Config,
             return Result(x, its, cycles, k_eff, True, flags, rnorm / bnorm, hist, implicit)
         if its >= cfg.max_iters:
             return Result(x, its, cycles, k_eff, False, flags, rnorm / bnorm, hist, implicit)
-        # deflated orthogonal: the Krylov initial vector is P_o r (equal to r once W^T r = 0)
-        r_start = orthogonal_project(W, r) if (use_w_krylov and cfg.method == DEFL_ORTHO) else r
+        # deflated rows: the Krylov initial vector is the projected residual (P_o r equals r once
+        # W^T r = 0; P_LS r equals r once (A W)^T r = 0, i.e. after the first cycle's correction)
+        r_start = r
+        if use_w_krylov and cfg.method in PROJECTED_START_METHODS:
+            r_start = ls_project(Z, r) if lsq else orthogonal_project(W, r)
         cyc = arnoldi_cycle(op, r_start, cfg.restart_m, stop_abs, cfg.max_iters - its)
         cycles += 1
         its += cyc.steps
@@ -320,7 +361,7 @@ def solve(A, b: np.ndarray, x0: Optional[np.ndarray], tol: float, cfg: Config,
         x = krylov_update(x, dinv, cyc.V[:, :j], y)
         r = b - A @ x
         if use_w_krylov:
-            x, r = projection_correction(W, Z, E, x, r)
+            x, r = correct(x, r)
         rnorm = float(np.linalg.norm(r))
         hist.append(rnorm / bnorm)
         if not np.isfinite(rnorm):

@@ -502,6 +502,132 @@ def test_projection_beats_extrapolation_off_polynomial_trajectory():
         assert res.iterations == 0 and np.linalg.norm(res.x - xs[i]) <= 1e-9 * np.linalg.norm(xs[i])
 
 
+# -- least-squares projector rows (Table 1 rows 3 and 6) -------------------------------
+
+
+def _galerkin_guess(A, W, b):
+    """x0 = W (W^T A W)^{-1} W^T b (eq. (projection_t_s)) by dense algebra, and its residual."""
+    E = W.T @ (A @ W)
+    x0 = W @ np.linalg.solve(E, W.T @ b)
+    return x0, b - A @ x0
+
+
+def _krylov_basis(op, r0, j):
+    """Orthonormal basis of K_j(op, r0) from the normalised power sequence and a library QR."""
+    K = np.empty((r0.size, j))
+    v = r0 / np.linalg.norm(r0)
+    for i in range(j):
+        K[:, i] = v
+        v = op(v)
+        v = v / np.linalg.norm(v)
+    return np.linalg.qr(K)[0]
+
+
+def _ls_case():
+    A, b, _ = c1_system(step=4)
+    n = b.size
+    dinv = O.jacobi_inverse(A)
+    W = orthonormal(n, 3, 12)
+    AW = np.asarray(A @ W)
+    Qz = np.linalg.qr(AW)[0]
+    Pm = np.eye(n) - Qz @ Qz.T          # orthogonal projector onto range(A W)^perp, by a dense QR
+    x0, r0 = _galerkin_guess(A, W, b)
+    return A, b, dinv, W, AW, Pm, r0
+
+
+def test_deflated_ls_is_minimal_residual_over_the_sum_space():
+    """Deflated LS (Table 1 row 6, the inner iteration of GCRO): after j steps the implicit
+    residual, and the true residual of the returned iterate after the least-squares correction,
+    equal the brute-force minimum of ||r0 - A W c - A D^{-1} K z|| over c and over z in
+    K_j(P A D^{-1}, P r0), with P built from a dense QR of A W and r0 the residual of the
+    projection guess; the final residual is orthogonal to A W."""
+    A, b, dinv, W, AW, Pm, r0 = _ls_case()
+    op_ref = lambda v: Pm @ (A @ (dinv * v))
+    bnorm = np.linalg.norm(b)
+    for j in (1, 3, 6, 10):
+        res = O.solve(A, b, None, 1e-30, O.Config(restart_m=10, method=O.DEFL_LS, precond=O.PRECOND_JACOBI,
+                                                     max_iters=j), W)
+        K = _krylov_basis(op_ref, Pm @ r0, j)
+        M = np.column_stack([AW, A @ (dinv[:, None] * K)])
+        c, *_ = np.linalg.lstsq(M, r0, rcond=None)
+        ref = np.linalg.norm(r0 - M @ c)
+        rfin = b - A @ res.x
+        assert res.iterations == j and res.k_eff == 3
+        assert abs(res.implicit_history[j - 1] * bnorm - ref) <= 1e-9 * np.linalg.norm(r0), j
+        assert abs(np.linalg.norm(rfin) - ref) <= 1e-9 * np.linalg.norm(r0), j
+        assert np.linalg.norm(AW.T @ rfin) <= 1e-10 * np.linalg.norm(AW) * np.linalg.norm(r0), j
+
+
+def test_augmented_ls_minimises_from_the_unprojected_residual():
+    """Augmented LS (Table 1 row 3): the Krylov space K_j(P A D^{-1}, r0) starts from the
+    unprojected residual, so the implicit residual is the brute-force minimum of
+    ||r0 - P A D^{-1} K z|| and never falls below ||(I - P) r0|| (why the paper saw this row fail
+    to converge); after the least-squares correction the true residual is the minimum of
+    ||r0 - A W c - A D^{-1} K z|| over the same space, and the two differ by exactly that floor."""
+    A, b, dinv, W, AW, Pm, r0 = _ls_case()
+    op_ref = lambda v: Pm @ (A @ (dinv * v))
+    bnorm = np.linalg.norm(b)
+    floor = np.linalg.norm(r0 - Pm @ r0)
+    assert floor > 1e-3 * np.linalg.norm(r0)          # the case is not degenerate
+    for j in (2, 5, 9):
+        res = O.solve(A, b, None, 1e-30, O.Config(restart_m=10, method=O.AUG_LS, precond=O.PRECOND_JACOBI,
+                                                     max_iters=j), W)
+        imp = res.implicit_history[j - 1] * bnorm
+        assert abs(imp - krylov_min_residual(op_ref, r0, j)) <= 1e-9 * np.linalg.norm(r0), j
+        assert imp >= floor * (1 - 1e-12)
+        K = _krylov_basis(op_ref, r0, j)
+        M = np.column_stack([AW, A @ (dinv[:, None] * K)])
+        c, *_ = np.linalg.lstsq(M, r0, rcond=None)
+        ref = np.linalg.norm(r0 - M @ c)
+        fin = np.linalg.norm(b - A @ res.x)
+        assert abs(fin - ref) <= 1e-9 * np.linalg.norm(r0), j
+        assert abs(imp ** 2 - floor ** 2 - fin ** 2) <= 1e-8 * np.linalg.norm(r0) ** 2, j
+
+
+def test_ls_rows_equal_oblique_on_invariant_subspace():
+    """If A W = W L (W spans an invariant subspace of a nonsymmetric A), range(A W) = range(W) and
+    the least-squares, orthogonal and oblique projectors coincide, as do the least-squares and
+    Galerkin corrections: all rows give the same iterates.  On a generic matrix they differ."""
+    n, k = 60, 5
+    rng = np.random.default_rng(21)
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    T = np.triu(rng.standard_normal((n, n)), 1) * 0.3 + np.diag(np.linspace(2.0, 20.0, n))
+    T[k:, :k] = 0.0                                  # block upper triangular: span(Q[:, :k]) invariant
+    A = sp.csr_matrix(Q @ T @ Q.T)
+    W = Q[:, :k]
+    b = rng.standard_normal(n)
+    cfg = dict(restart_m=8, max_iters=300)
+    ref = O.solve(A, b, None, 1e-12, O.Config(method=O.AUG_OBLIQUE, **cfg), W)
+    for m in (O.AUG_LS, O.DEFL_LS):
+        r = O.solve(A, b, None, 1e-12, O.Config(method=m, **cfg), W)
+        assert r.converged and r.iterations == ref.iterations, (m, r.iterations, ref.iterations)
+        assert np.linalg.norm(r.x - ref.x) <= 1e-10 * np.linalg.norm(ref.x)
+    An, bn = rand_system(60, 5)
+    Wn = orthonormal(60, 5, 6)
+    xs = [O.solve(An, bn, None, 1e-12, O.Config(method=m, restart_m=8, max_iters=3), Wn).x
+          for m in (O.AUG_OBLIQUE, O.AUG_LS, O.DEFL_LS)]
+    assert np.linalg.norm(xs[1] - xs[0]) > 1e-6 * np.linalg.norm(xs[0])
+    assert np.linalg.norm(xs[2] - xs[1]) > 1e-6 * np.linalg.norm(xs[0])
+
+
+def test_ls_rows_solve_a_sequence_to_tolerance():
+    """Both LS rows converge on the generator sequence with the SVD recycle space (augmented LS
+    through a restart: its first cycle's estimate is floored, the correction then removes the
+    floor), and deflated LS takes no more Arnoldi steps than plain GMRES on any system."""
+    asm, systems, _ = WL.march(WL.C1, 8, 1)
+    As = [asm.csr(v) for v, _ in systems]
+    bs = [b for _, b in systems]
+    plain, _ = O.run_sequence(As, bs, 1e-10, O.Config(restart_m=30, method=O.PLAIN))
+    for method in (O.AUG_LS, O.DEFL_LS):
+        cfg = O.Config(restart_m=30, recycle_k=5, snapshots_s=10, method=method)
+        results, st = O.run_sequence(As, bs, 1e-10, cfg)
+        assert st.W.shape[1] == 5
+        for A, b, r, p in zip(As, bs, results, plain):
+            assert r.converged and np.linalg.norm(b - A @ r.x) <= 1e-10 * np.linalg.norm(b) * (1 + 1e-6)
+            if method == O.DEFL_LS:
+                assert r.iterations <= p.iterations
+
+
 # -- planted mistakes: each plausible error in the oracle is caught by a pin ----------
 
 
@@ -517,6 +643,8 @@ def _pins_pass():
         test_extrapolated_guess_then_no_iteration_on_polynomial_sequence(3)
         test_projection_guess_satisfies_the_galerkin_conditions()
         test_projection_guess_then_plain_gmres()
+        test_deflated_ls_is_minimal_residual_over_the_sum_space()
+        test_augmented_ls_minimises_from_the_unprojected_residual()
     except AssertionError:
         return False
     return True
@@ -530,7 +658,9 @@ def test_pins_pass_on_unmodified_oracle():
                                       "update_without_preconditioner", "operator_perturbed",
                                       "correction_sign", "ortho_projector_missing", "ortho_projector_half",
                                       "extrap_weights_reversed", "extrap_off_by_one",
-                                      "guess_only_projects_krylov"])
+                                      "guess_only_projects_krylov", "ls_projector_missing",
+                                      "ls_correction_galerkin", "ls_coefficients_unnormalised",
+                                      "ls_deflated_start_unprojected"])
 def test_planted_mistakes_are_caught(monkeypatch, mutation):
     if mutation == "extrap_weights_reversed":
         orig_w = O.extrapolation_weights
@@ -541,6 +671,15 @@ def test_planted_mistakes_are_caught(monkeypatch, mutation):
                                              for j, w in enumerate(O.extrapolation_weights(min(q, len(h))))))
     elif mutation == "guess_only_projects_krylov":
         monkeypatch.setattr(O, "GUESS_ONLY_METHODS", ())
+    elif mutation == "ls_projector_missing":
+        monkeypatch.setattr(O, "ls_project", lambda Z, v: v)
+    elif mutation == "ls_correction_galerkin":
+        monkeypatch.setattr(O, "ls_correction",
+                            lambda W, Z, x, r: O.projection_correction(W, Z, W.T @ Z, x, r))
+    elif mutation == "ls_coefficients_unnormalised":
+        monkeypatch.setattr(O, "ls_coefficients", lambda Z, v: Z.T @ v)
+    elif mutation == "ls_deflated_start_unprojected":
+        monkeypatch.setattr(O, "PROJECTED_START_METHODS", (O.DEFL_ORTHO,))
     if mutation == "ortho_projector_missing":
         monkeypatch.setattr(O, "orthogonal_project", lambda W, v: v)
     elif mutation == "ortho_projector_half":
