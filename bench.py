@@ -472,7 +472,8 @@ def main():
     ap.add_argument("--inner-tol", type=float, default=None,
                     help="override the FP32 cycle reduction factor of the mixed-precision workload")
     ap.add_argument("--method", choices=["aug_oblique", "defl_oblique", "aug_ortho", "defl_ortho", "guess_project",
-                                         "guess_extrap2", "guess_extrap3", "guess_extrap4"], default=None,
+                                         "guess_extrap2", "guess_extrap3", "guess_extrap4", "aug_ls", "defl_ls"],
+                    default=None,
                     help="method of the recycled run (default: the workload's, augmented oblique); the "
                          "extrapolation guesses keep a ring of `order` solutions and no recycle space")
     ap.add_argument("--guess-table", action="store_true",

@@ -78,6 +78,16 @@ extern "C" {
                                      than the order the highest order they allow is used (the last
                                      solution alone once one is stored), and x0 is used only while
                                      the ring is empty.  None of 5..8 runs on the one-block path. */
+#define RSOLVE_AUG_LS         9   /* Table 1, augmented LS (section 3.3, the third projector): Krylov
+                                     operator P_LS A D^{-1} with P_LS = I - A W (W^T A^T A W)^{-1} W^T A^T,
+                                     the orthogonal projector onto the complement of range(A W); the
+                                     Krylov initial vector is r itself.  Projected guess as for the
+                                     oblique rows; every cycle ends with the least-squares correction
+                                     x += W c, r -= A W c, c = (W^T A^T A W)^{-1} W^T A^T r, after which
+                                     the true residual is the minimised one (multi-kernel path only) */
+#define RSOLVE_DEFL_LS       10   /* Table 1, deflated LS: the Krylov initial vector is P_LS r (the inner
+                                     iteration of GCRO); applied as a least-squares correction of x
+                                     and r before the first cycle, which leaves the same iterates */
 #define RSOLVE_PRECOND_NONE   0
 #define RSOLVE_PRECOND_JACOBI 1   /* right Jacobi: operator P A D^{-1}, x = x0 + D^{-1} V y */
 #define RSOLVE_FP64           0   /* everything in float64 */
@@ -113,7 +123,8 @@ typedef struct {
                               for RSOLVE_GUESS_EXTRAPq: q <= s (the ring of previous solutions) */
     int32_t svd_interval;  /* ell >= 1: recompute W every ell updates (Algorithm 1) */
     int32_t method;        /* RSOLVE_PLAIN / _AUG_OBLIQUE / _DEFL_OBLIQUE / _AUG_ORTHO / _DEFL_ORTHO /
-                              _GUESS_PROJECT / _GUESS_EXTRAP2 / _GUESS_EXTRAP3 / _GUESS_EXTRAP4 */
+                              _GUESS_PROJECT / _GUESS_EXTRAP2 / _GUESS_EXTRAP3 / _GUESS_EXTRAP4 /
+                              _AUG_LS / _DEFL_LS */
     int32_t precond;       /* RSOLVE_PRECOND_NONE / RSOLVE_PRECOND_JACOBI */
     int32_t precision;     /* RSOLVE_FP64 / RSOLVE_FP32_IR */
     int32_t max_iters;     /* cap on Arnoldi steps per solve (>= 1) */

@@ -78,7 +78,7 @@ int cfg_check(const rsolve_config* c) {
     if (c->snapshots_s < 0 || c->snapshots_s > RSOLVE_MAX_SNAPSHOTS) return RSOLVE_E_INVALID;
     if (c->recycle_k > 0 && c->snapshots_s < c->recycle_k) return RSOLVE_E_INVALID;
     if (c->svd_interval < 1) return RSOLVE_E_INVALID;
-    if (c->method < RSOLVE_PLAIN || c->method > RSOLVE_GUESS_EXTRAP4) return RSOLVE_E_INVALID;
+    if (c->method < RSOLVE_PLAIN || c->method > RSOLVE_DEFL_LS) return RSOLVE_E_INVALID;
     // the extrapolation methods keep a ring of at least `order` solutions and no recycle space
     if (extrap_order(c->method) && (c->recycle_k != 0 || c->snapshots_s < extrap_order(c->method)))
         return RSOLVE_E_INVALID;
@@ -525,11 +525,13 @@ void arnoldi_step(rsolve_seq* s, int j, const SpOp& op, T* V, T* const* wbuf, co
 // One step j of a cycle with delayed reorthogonalisation (RSOLVE_ORTHO_DCGS2): z = A D^{-1} u
 // (skipped on the closing step j = allowed), the sweep over [V_j, W, A W, u] with u and z, the
 // reduction that completes column j-1, and the update sweep writing v_j and the next candidate.
+// ls: the least-squares projector, called with Wt = Zt = A W; the sweep then reads A W once (its
+// dots with z give the projector's right-hand side, those with u the row of F).
 template <typename T>
 void dcgs2_step(rsolve_seq* s, int j, int allowed, const SpOp& op, T* V, T* const* wbuf, const T* Wt, const T* Zt,
-                int k, bool orth) {
+                int k, bool orth, bool ls) {
     // the orthogonal projector I - W W^T needs no A W columns in the sweep and takes W in the update
-    const int kz = orth ? 0 : k;
+    const int kz = (orth || ls) ? 0 : k;
     hipStream_t st = s->stream;
     const int64_t ld = s->ld;
     T* u = wbuf[0];
@@ -559,13 +561,14 @@ void dcgs2_step(rsolve_seq* s, int j, int allowed, const SpOp& op, T* V, T* cons
     }
 }
 
-// r (wb[0]) = b - A xw, then the span(W) correction x += W E^{-1} W^T r, r -= A W E^{-1} W^T r
-// (section 4.2, eq. (projection_t_s)), then ctl->rnorm = ||r||.
-void residual_and_correct(rsolve_seq* s, const rsolve_csr* A, const double* b, int k) {
+// The span(W) correction of r (wb[0]) and x: c = M^{-1} Q^T r, x += W c, r -= A W c, then
+// ctl->rnorm = ||r||.  Q = W with M = E = W^T A W (the projection guess and the Galerkin
+// correction, section 4.2, eq. (projection_t_s)); Q = A W with M = (A W)^T A W (the least-squares
+// correction); M's LU factors are those in the control block.
+void correct(rsolve_seq* s, const double* Q, int k) {
     hipStream_t st = s->stream;
-    launch_residual(s->lpr, s->n, A->row_ptr, A->col_idx, A->val, s->xw, b, s->wb[0], st);
     if (k > 0) {
-        const double* bases[1] = {s->W};
+        const double* bases[1] = {Q};
         const double* vecs[1] = {s->wb[0]};
         const int counts[1] = {k};
         const int nb = cols_grid(s->ld, s->cus, (k + 7) / 8, 32, k);
@@ -574,6 +577,12 @@ void residual_and_correct(rsolve_seq* s, const rsolve_csr* A, const double* b, i
     }
     launch_correct(s->ld, s->W, s->Z, s->ld, k, s->xw, s->wb[0], s->ctl, s->partial, s->nblk, st);
     launch_finish_norm(s->partial, s->nblk, s->ctl, 0, st);
+}
+
+// r (wb[0]) = b - A xw, then the span(W) correction with dot basis Q (see correct).
+void residual_and_correct(rsolve_seq* s, const rsolve_csr* A, const double* b, int k, const double* Q) {
+    launch_residual(s->lpr, s->n, A->row_ptr, A->col_idx, A->val, s->xw, b, s->wb[0], s->stream);
+    correct(s, Q, k);
 }
 
 double ms_since(std::chrono::steady_clock::time_point t0) {
@@ -985,10 +994,21 @@ int rsolve_solve(rsolve_seq* s, const rsolve_csr* A, const double* b, const doub
         k = 0;
         flags |= RSOLVE_FLAG_RECYCLE_DROPPED;
     }
-    residual_and_correct(s, A, b, k);
+    residual_and_correct(s, A, b, k, s->W);
     HIP_TRY(hipGetLastError());
     // the projection-guess method uses W for the guess only: plain Krylov cycles (kry = 0)
-    const int kry = (c.method == RSOLVE_GUESS_PROJECT) ? 0 : k;
+    int kry = (c.method == RSOLVE_GUESS_PROJECT) ? 0 : k;
+    // least-squares projector: once the guess has used E, the control block's factors become
+    // those of (A W)^T A W (symmetric positive definite for A W of full rank), which the Arnoldi
+    // reductions and the cycle-end correction then apply, with A W in the place of W in the dots
+    const bool ls = c.method == RSOLVE_AUG_LS || c.method == RSOLVE_DEFL_LS;
+    if (ls && kry > 0) {
+        const int gb = launch_gram_tn(ld, s->Z, ld, kry, s->Z, ld, kry, s->gpart, s->gblk, stm);
+        launch_gram_reduce(s->gpart, gb, kry * kry, ctl_red(s->ctl), stm);
+        launch_small_lu(ctl_red(s->ctl), kry, s->ctl, stm);
+        HIP_TRY(hipGetLastError());
+    }
+    const double* Qd = ls ? s->Z : s->W;   // dot basis of the cycle-end correction
     const double stop_abs = tol * bnorm;
     const double t_setup = ms_since(t0);
 
@@ -1017,10 +1037,25 @@ int rsolve_solve(rsolve_seq* s, const rsolve_csr* A, const double* b, const doub
             status = RSOLVE_NOT_CONVERGED;
             break;
         }
+        if (cycles == 0 && ls && kry > 0) {
+            if (s->hctl->lu_fail) {   // (A W)^T A W numerically singular: plain cycles from here
+                kry = 0;
+                flags |= RSOLVE_FLAG_RECYCLE_DROPPED;
+            } else if (c.method == RSOLVE_DEFL_LS) {
+                // deflated LS: the Krylov initial vector P_LS r, taken as the least-squares
+                // correction of x and r (the final residual, hence x, is the same as projecting
+                // only the initial vector, since P_LS is idempotent)
+                correct(s, s->Z, kry);
+                HIP_TRY(hipGetLastError());
+            }
+        }
         const int max_steps = std::min(m, c.max_iters - its);
         const double cyc_stop = ir ? std::max(c.inner_tol * rnorm, stop_abs) : stop_abs;
         const bool dg = c.ortho == RSOLVE_ORTHO_DCGS2;
         const bool orth = c.method == RSOLVE_AUG_ORTHO || c.method == RSOLVE_DEFL_ORTHO;
+        // the least-squares projector takes A W where the oblique one takes W (dots) as well
+        const double* Wd = ls ? s->Z : s->W;
+        const float* Wf = ls ? Z32 : W32;
         launch_cycle_init(s->ctl, max_steps, cyc_stop, stm, dg);
         if (ir) launch_to_f32(ld, s->wb[0], s->w32[0], stm);
         // Enqueue the cycle in chunks; after chunk c the done flag is copied to pinned memory, and
@@ -1039,17 +1074,18 @@ int rsolve_solve(rsolve_seq* s, const rsolve_csr* A, const double* b, const doub
             auto enqueue = [&] {
                 for (int j = j0; j < j1; ++j) {
                     if (dg) {
-                        if (ir) dcgs2_step<float>(s, j, max_steps, op, s->V32, s->w32, W32, Z32, kry, orth);
-                        else dcgs2_step<double>(s, j, max_steps, op, s->V, s->wb, s->W, s->Z, kry, orth);
+                        if (ir) dcgs2_step<float>(s, j, max_steps, op, s->V32, s->w32, Wf, Z32, kry, orth, ls);
+                        else dcgs2_step<double>(s, j, max_steps, op, s->V, s->wb, Wd, s->Z, kry, orth, ls);
                     } else {
-                        if (ir) arnoldi_step<float>(s, j, op, s->V32, s->w32, W32, Z32, kry, orth);
-                        else arnoldi_step<double>(s, j, op, s->V, s->wb, s->W, s->Z, kry, orth);
+                        if (ir) arnoldi_step<float>(s, j, op, s->V32, s->w32, Wf, Z32, kry, orth);
+                        else arnoldi_step<double>(s, j, op, s->V, s->wb, Wd, s->Z, kry, orth);
                     }
                 }
             };
             if (s->graphs_on && !s->prof_on) {
                 const rsolve_seq::GraphKey key{j0,      j1,         kry,       ir ? 1 : 0, s->lpr, s->svec, s->sremap,
-                                               op.fmt,  (dg ? 1 : 0) | (orth ? 2 : 0), dg ? max_steps : 0, op.rp, op.ci,
+                                               op.fmt,  (dg ? 1 : 0) | (orth ? 2 : 0) | (ls ? 4 : 0),
+                                               dg ? max_steps : 0, op.rp, op.ci,
                                                op.off,  op.vals};
                 hipGraphExec_t ge = nullptr;
                 rc = chunk_graph(s, key, enqueue, &ge);
@@ -1068,7 +1104,7 @@ int rsolve_solve(rsolve_seq* s, const rsolve_csr* A, const double* b, const doub
         launch_cycle_solve(s->ctl, stm);
         if (ir) launch_x_update<float>(n, s->V32, ld, jac ? s->dinv : nullptr, s->xw, s->ctl, stm);
         else launch_x_update<double>(n, s->V, ld, jac ? s->dinv : nullptr, s->xw, s->ctl, stm);
-        residual_and_correct(s, A, b, kry);
+        residual_and_correct(s, A, b, kry, Qd);
         HIP_TRY(hipGetLastError());
         rc = read_head(s);
         if (rc) return rc;

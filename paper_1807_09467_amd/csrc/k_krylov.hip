@@ -666,9 +666,10 @@ __global__ __launch_bounds__(RED_T) void k_dcgs2_reduce(const double* __restrict
     const int wv = tid / WAVE, lane = tid & (WAVE - 1);
     const int ncol = j + k + kz + 1;
     // sweep columns: V (0..j-1), W (j..j+k-1), A W (kz = k columns, oblique projector only), u;
-    // pz = first column of the projector's image (A W for the oblique projector, W for the
-    // orthogonal one), cu = the column of u
-    const int pz = orth ? j : j + k, cu = j + k + kz;
+    // pz = first column of the projector's image (A W for the oblique projector; the W slot when
+    // the sweep has no A W columns: W for the orthogonal projector, and for the least-squares one,
+    // whose caller puts A W in the W slot), cu = the column of u
+    const int pz = (kz == 0) ? j : j + k, cu = j + k + kz;
     const int jc = j - 1;   // the column completed here (none when j = 0)
     for (int t = tid; t < k * k; t += RED_T) Es[t] = ctl->E[t];
     for (int t = tid; t < jc; t += RED_T) {

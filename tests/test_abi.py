@@ -154,13 +154,14 @@ def test_invalid_configs_rejected(lib, bad):
 
 
 def test_method_and_select_values(lib):
-    """Methods 0..5 (plain, oblique and orthogonal rows of Table 1, projection guess) and both mode
-    selections are accepted; values outside are refused."""
-    for m in ("plain", "aug_oblique", "defl_oblique", "aug_ortho", "defl_ortho", "guess_project"):
+    """Methods 0..5, 9 and 10 (plain, the oblique, orthogonal and least-squares rows of Table 1,
+    projection guess) and both mode selections are accepted; values outside are refused."""
+    for m in ("plain", "aug_oblique", "defl_oblique", "aug_ortho", "defl_ortho", "guess_project", "aug_ls",
+              "defl_ls"):
         for sel in ("largest", "smallest"):
             assert rsolve.workspace_bytes(rsolve.make_config(restart_m=30, recycle_k=4, snapshots_s=6, method=m,
                                                              select=sel), 100, 500) > 0
-    for field, v in (("method", 9), ("method", -1), ("select", 2)):
+    for field, v in (("method", 11), ("method", -1), ("select", 2)):
         cfg = rsolve.make_config(restart_m=30)
         setattr(cfg, field, v)
         assert rsolve.workspace_bytes(cfg, 100, 500) == 0

@@ -29,7 +29,8 @@ def run_pair(dev, prob, steps, tol, seed=0, precision="fp64", oracle_tol=None, *
                     method={"plain": O.PLAIN, "aug_oblique": O.AUG_OBLIQUE, "defl_oblique": O.DEFL_OBLIQUE,
                             "aug_ortho": O.AUG_ORTHO, "defl_ortho": O.DEFL_ORTHO, "guess_project": O.GUESS_PROJECT,
                             "guess_extrap2": O.GUESS_EXTRAP2, "guess_extrap3": O.GUESS_EXTRAP3,
-                            "guess_extrap4": O.GUESS_EXTRAP4}[kw.get("method", "aug_oblique")],
+                            "guess_extrap4": O.GUESS_EXTRAP4, "aug_ls": O.AUG_LS,
+                            "defl_ls": O.DEFL_LS}[kw.get("method", "aug_oblique")],
                     precond=O.PRECOND_JACOBI if kw.get("precond") == "jacobi" else O.PRECOND_NONE,
                     select_smallest=kw.get("select") == "smallest")
     ost = O.RecycleState(pat.n, ocfg)
