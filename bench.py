@@ -67,6 +67,15 @@ SERVE_WORKLOADS = {
 }
 
 
+# the paper's own experiments (section 6.1, Tables 2-4): vortex field, random low-mode forcing, zero
+# initial value, dt = 0.5, tol 1e-8; right Jacobi stands in for the paper's SSOR
+PAPER_WORKLOADS = {
+    # name: (description, generator problem; a dict is keyed by nu)
+    "paper_q1": ("first-order elements on a 64x64 grid (n=4225, nnz=35225)", "PAPER_Q1"),
+    "paper_sem23": ("2x2 Legendre spectral elements of order 23 (n=2209, nnz=1117433, 506 per row)", "PAPER_SEM23"),
+}
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -101,8 +110,94 @@ def generate(prob, nsteps, dev):
     return asm, gasm, u0, systems
 
 
+class HostSystems:
+    """The pattern of a host-assembled sequence on the device (what run_solver needs of an assembler)."""
+
+    def __init__(self, asm, dev):
+        import torch
+        self.asm = asm
+        self.row_ptr = torch.from_numpy(asm.pat.row_ptr).to(dev)
+        self.col_idx = torch.from_numpy(asm.pat.col_idx).to(dev)
+
+
+def generate_host(prob, nsteps, dev, seed=0):
+    """Systems of the paper's experiments, assembled on the host (vortex field, forcing drawn per step);
+    the trajectory is advanced by the GPU solver (plain FP64 GMRES(50), right Jacobi, tol 1e-12) and the
+    systems are kept resident on the device."""
+    import torch
+
+    from paper_1807_09467_amd import rsolve
+    from paper_1807_09467_amd import workload as WL
+    t0 = time.time()
+    asm = WL.Assembler(prob)
+    hs = HostSystems(asm, dev)
+    pat = asm.pat
+    coeffs = WL.forcing_coefficients(seed, nsteps) if prob.forcing else [None] * nsteps
+    traj = rsolve.Sequence(pat.n, pat.nnz, device=dev, restart_m=50, method="plain", precond="jacobi")
+    u = WL.initial_condition(prob, seed)
+    u0 = torch.from_numpy(u).to(dev)
+    ud = u0
+    systems = []
+    for i in range(nsteps):
+        vals, b = asm.system(u, coeffs[i])
+        vt, bt = torch.from_numpy(vals).to(dev), torch.from_numpy(b).to(dev)
+        systems.append((vt, bt))
+        x, st, status = traj.solve(hs.row_ptr, hs.col_idx, vt, bt, x0=ud, tol=1e-12, same_pattern=i > 0)
+        if status != 0:
+            raise RuntimeError(f"trajectory solve failed at step {i}: {status}")
+        ud = x.clone()
+        u = ud.cpu().numpy()
+        if (i + 1) % 100 == 0 or i + 1 == nsteps:
+            log(f"generated step {i + 1}/{nsteps} ({st['iterations']} its), {time.time() - t0:.1f}s")
+    traj.close()
+    torch.cuda.synchronize()
+    return asm, hs, u0, systems
+
+
+def bench_paper_table(args, dev):
+    """The paper's timing protocol (Tables 3 and 4) on its own workload: no recycling against a recycle
+    space of dimension 20 taken from the SVD of the last L solutions every L steps, L = 20, 40, 60, 80,
+    for the augmented orthogonal row (the paper's timed method) and the augmented oblique row; GMRES(30),
+    tol 1e-8, every step timed. With --guess-table, Table 2's comparison of extrapolation and projection
+    guesses instead. One JSON line."""
+    from paper_1807_09467_amd import workload as WL
+    desc, pname = PAPER_WORKLOADS[args.workload]
+    prob = getattr(WL, pname)
+    prob = prob[args.nu] if isinstance(prob, dict) else prob
+    nsteps = args.table_steps
+    tol = 1e-8
+    desc = (f"paper experiment (section 6.1): {desc}, nu={prob.eps:g}, dt={prob.dt:g}, vortex field, random "
+            f"low-mode forcing, zero start, {nsteps} steps, GMRES(30) right Jacobi (stand-in for SSOR), tol 1e-8, "
+            f"Arnoldi {args.ortho}")
+    asm, hs, u0, systems = generate_host(prob, nsteps, dev)
+    base = dict(restart_m=30, precond="jacobi", precision="fp64", ortho=args.ortho)
+    if args.guess_table:
+        a = argparse.Namespace(**vars(args))
+        a.warmup, a.steps = 0, nsteps
+        return bench_guess_table(a, hs, u0, systems, tol, base, desc, dev)
+    runs = [("no aug", dict(method="plain"))]
+    for L in (20, 40, 60, 80):
+        for meth in ("aug_ortho", "aug_oblique"):
+            runs.append((f"{meth} {L}", dict(method=meth, recycle_k=20, snapshots_s=L, svd_interval=L)))
+    rows = []
+    for label, over in runs:
+        c = dict(base)
+        c.update(over)
+        r = run_solver(hs, u0, systems, 0, nsteps, tol, c, dev, label=label, quiet=True)
+        its = np.array(r["its"], dtype=float)
+        rows.append({"method": label, "avg_iterations": float(its.mean()), "dev": float(its.std()),
+                     "avg_cycles": float(np.mean(r["cycles"])), "solver_wall_s": r["elapsed"],
+                     "solves_per_s": nsteps / r["elapsed"], "max_rel_residual": float(np.max(r["rel"]))})
+        log(f"{label}: {its.mean():.2f} +- {its.std():.2f} its, {r['elapsed']:.2f} s")
+        del r
+    out = {"metric": "solver wall time over the sequence", "unit": "s", "n_gpus": 1, "steps": nsteps,
+           "warmup": 0, "higher_is_better": False, "data": "synthetic",
+           "config": {"workload": args.workload, "description": desc}, "rows": rows}
+    print(json.dumps(out), flush=True)
+
+
 def run_solver(gasm, u0, systems, warmup, steps, tol, cfg, dev, profile=False, label="", graphs=False,
-               profile_kinds=None):
+               profile_kinds=None, quiet=False):
     """One pass over the sequence: warmup untimed solves, then `steps` timed solve+update steps."""
     import torch
 
@@ -139,8 +234,9 @@ def run_solver(gasm, u0, systems, warmup, steps, tol, cfg, dev, profile=False, l
             rel.append(st["rel_res_true"])
         xs.append(x)
         x_prev = x
-        log(f"{label} step {i + 1}/{warmup + steps}: {st['iterations']} its, {st['cycles']} cycles, "
-            f"k_eff {st['k_eff']}, {1e3 * (t1 - t0):.2f} ms")
+        if not quiet or (i + 1) % 100 == 0:
+            log(f"{label} step {i + 1}/{warmup + steps}: {st['iterations']} its, {st['cycles']} cycles, "
+                f"k_eff {st['k_eff']}, {1e3 * (t1 - t0):.2f} ms")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
     prof = seq.profile_read() if profile else []
@@ -463,10 +559,14 @@ def main():
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="c4",
-                    choices=sorted(WORKLOADS) + sorted(BATCH_WORKLOADS) + sorted(SERVE_WORKLOADS))
+                    choices=sorted(WORKLOADS) + sorted(BATCH_WORKLOADS) + sorted(SERVE_WORKLOADS)
+                    + sorted(PAPER_WORKLOADS))
     ap.add_argument("--sequences", type=int, default=512, help="serving workload: sequences to replay")
     ap.add_argument("--pool-gb", type=float, default=96.0, help="serving workload: the server's HBM pool")
     ap.add_argument("--workers", type=int, default=4, help="serving workload: large-sequence worker streams")
+    ap.add_argument("--nu", type=float, default=1e-2, choices=[1e-1, 1e-2, 1e-3],
+                    help="paper workloads: the diffusion coefficient of the first-order case")
+    ap.add_argument("--table-steps", type=int, default=1000, help="paper workloads: time steps of the sequence")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain FP64 comparison run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--inner-tol", type=float, default=None,
@@ -510,6 +610,8 @@ def main():
     if args.workload in SERVE_WORKLOADS:
         return bench_serving(args)
     dev = torch.device("cuda:0")
+    if args.workload in PAPER_WORKLOADS:
+        return bench_paper_table(args, dev)
     if args.calib_copy:
         src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
         dst = torch.empty_like(src)

@@ -44,7 +44,20 @@ class Problem:
     """One PDE / mesh / time-step setting.
 
     beta: 'const' uses beta_const everywhere; 'rotating' uses
-    beta = 2 pi (-(y - 1/2), x - 1/2) (a rigid rotation about the centre).
+    beta = 2 pi (-(y - 1/2), x - 1/2) (a rigid rotation about the centre);
+    'vortex' uses beta = (-sin(pi x) cos(pi y), cos(pi x) sin(pi y)), the
+    field of the paper's experiments (section 6.1).
+
+    forcing: add the load (v, f) of the paper's random low-mode forcing
+    (section 6.1): f = (C/2) sum_{j=1}^{16} c_j exp(-j^2/20) sin(2 j pi x)
+    sin(2 j pi y) with C = 0.1, c_1 = 1 and c_2..c_16 drawn uniformly from
+    [-1, 1] at every step (seeded; see forcing_coefficients).  Since v lies in
+    the discrete space, (v, P f) = (v, f) for the L2 projection P of the paper.
+
+    u0: 'bump' (a seeded Gaussian bump) or 'zero' (the paper's zero initial value).
+
+    nodes: support points of the 1-D Lagrange basis, 'equispaced' or 'gll'
+    (Gauss-Lobatto-Legendre, the support points of Legendre spectral elements).
     """
 
     p: int
@@ -53,6 +66,9 @@ class Problem:
     dt: float
     beta: str = "const"
     beta_const: tuple = (1.0, 0.5)
+    forcing: bool = False
+    u0: str = "bump"
+    nodes: str = "equispaced"
 
     @property
     def n1(self) -> int:
@@ -73,18 +89,45 @@ C3 = Problem(p=3, N=512, eps=1e-4, dt=5e-3, beta="rotating")
 C2_SMALL = Problem(p=2, N=32, eps=1e-3, dt=5e-3, beta="const")
 C3_SMALL = Problem(p=3, N=16, eps=1e-4, dt=5e-3, beta="rotating")
 
+# The paper's own experiments (section 6.1): vortex field, random low-mode
+# forcing, zero initial value, dt = 0.5; first-order elements on a 64 x 64 grid
+# for nu = 1e-1, 1e-2, 1e-3, and a 2 x 2 grid of order-23 Legendre spectral
+# elements (section 6.3) for nu = 1e-2.
+PAPER_Q1 = {nu: Problem(p=1, N=64, eps=nu, dt=0.5, beta="vortex", forcing=True, u0="zero")
+            for nu in (1e-1, 1e-2, 1e-3)}
+PAPER_SEM23 = Problem(p=23, N=2, eps=1e-2, dt=0.5, beta="vortex", forcing=True, u0="zero", nodes="gll")
+# reduced spectral-element shape for the CPU oracle (same family, lower order)
+PAPER_SEM8 = Problem(p=8, N=2, eps=1e-2, dt=0.5, beta="vortex", forcing=True, u0="zero", nodes="gll")
+
+FORCING_MODES = 16
+FORCING_C = 0.1
+
 
 # ---------------------------------------------------------------------------
 # 1-D Lagrange basis and quadrature
 # ---------------------------------------------------------------------------
 
 
-def lagrange_1d(p: int, x: np.ndarray):
-    """Values and derivatives of the p+1 equispaced Lagrange polynomials on [0, 1].
+def support_points(p: int, kind: str = "equispaced") -> np.ndarray:
+    """The p+1 support points on [0, 1]: equispaced, or Gauss-Lobatto-Legendre (the end
+    points and the roots of the derivative of the Legendre polynomial of degree p)."""
+    if kind == "equispaced":
+        return np.linspace(0.0, 1.0, p + 1)
+    if kind == "gll":
+        if p == 1:
+            return np.array([0.0, 1.0])
+        inner = np.sort(np.polynomial.legendre.Legendre.basis(p).deriv().roots().real)
+        return 0.5 * (np.concatenate([[-1.0], inner, [1.0]]) + 1.0)
+    raise ValueError(kind)
+
+
+def lagrange_1d(p: int, x: np.ndarray, kind: str = "equispaced"):
+    """Values and derivatives of the p+1 Lagrange polynomials on [0, 1] with the support
+    points of `support_points(p, kind)`.
 
     Returns (V, D) with V[q, a] = phi_a(x_q), D[q, a] = phi_a'(x_q).
     """
-    nodes = np.linspace(0.0, 1.0, p + 1)
+    nodes = support_points(p, kind)
     x = np.asarray(x, dtype=np.float64)
     V = np.ones((x.size, p + 1))
     D = np.zeros((x.size, p + 1))
@@ -136,10 +179,10 @@ class ElementTables:
     stiff_ref: np.ndarray   # (nl, nl) integral grad phi_i . grad phi_j
 
 
-def element_tables(p: int) -> ElementTables:
+def element_tables(p: int, kind: str = "equispaced") -> ElementTables:
     nq1 = p + 2
     xq, wq = gauss_01(nq1)
-    V, D = lagrange_1d(p, xq)
+    V, D = lagrange_1d(p, xq, kind)
     nl = (p + 1) ** 2
     nq = nq1 * nq1
     qx = np.tile(np.arange(nq1), nq1)
@@ -257,7 +300,7 @@ class Assembler:
     def __init__(self, prob: Problem, pattern: Optional[Pattern] = None):
         self.prob = prob
         self.pat = pattern if pattern is not None else build_pattern(prob)
-        self.tab = element_tables(prob.p)
+        self.tab = element_tables(prob.p, prob.nodes)
         h = 1.0 / prob.N
         self.h = h
         t = self.tab
@@ -265,10 +308,12 @@ class Assembler:
         # static element matrix: M/dt + eps K  (the same on every element of a uniform mesh)
         self.static_e = (mass_e / prob.dt + prob.eps * t.stiff_ref).ravel()
         self.mass_e = mass_e.ravel()
-        # B_x[q, i*nl + j] = phi_i(q) dphi_j/dxi(q)
+        # B_x[q, i*nl + j] = phi_i(q) dphi_j/dxi(q) (low orders; high orders contract per element)
         nl = t.nl
-        self.Bx = (t.phi[:, :, None] * t.dxi[:, None, :]).reshape(t.nq, nl * nl)
-        self.By = (t.phi[:, :, None] * t.deta[:, None, :]).reshape(t.nq, nl * nl)
+        self._tensor_b = t.nq * nl * nl <= (1 << 22)
+        if self._tensor_b:
+            self.Bx = (t.phi[:, :, None] * t.dxi[:, None, :]).reshape(t.nq, nl * nl)
+            self.By = (t.phi[:, :, None] * t.deta[:, None, :]).reshape(t.nq, nl * nl)
         pat = self.pat
         keep = pat.emap >= 0
         self._keep = keep
@@ -281,12 +326,18 @@ class Assembler:
         if prob.beta == "const":
             bx, by = prob.beta_const
             return float(bx), float(by)
+        x, y = self.quad_points()
         if prob.beta == "rotating":
-            org = self.pat.elem_origin
-            x = org[:, 0:1] + self.h * t.xi[None, :]
-            y = org[:, 1:2] + self.h * t.eta[None, :]
             return -2.0 * math.pi * (y - 0.5), 2.0 * math.pi * (x - 0.5)
+        if prob.beta == "vortex":
+            return (-np.sin(math.pi * x) * np.cos(math.pi * y), np.cos(math.pi * x) * np.sin(math.pi * y))
         raise ValueError(prob.beta)
+
+    def quad_points(self):
+        """Physical x, y of every (element, quadrature point)."""
+        t = self.tab
+        org = self.pat.elem_origin
+        return org[:, 0:1] + self.h * t.xi[None, :], org[:, 1:2] + self.h * t.eta[None, :]
 
     def element_values(self, u_prev: np.ndarray) -> np.ndarray:
         """(E, nl*nl) element matrices of A(u_prev)."""
@@ -297,8 +348,13 @@ class Assembler:
         scale = self.h * t.w[None, :] * Uq         # dx = h^2 dxi, grad = grad_ref / h
         ax = scale * bx
         ay = scale * by
-        vals = ax @ self.Bx
-        vals += ay @ self.By
+        if self._tensor_b:
+            vals = ax @ self.Bx
+            vals += ay @ self.By
+        else:
+            # (E, nl, nq) @ (nq, nl): sum_q phi_i(q) (ax dphi_j/dxi + ay dphi_j/deta)(q)
+            phit = t.phi.T[None, :, :]
+            vals = ((phit * ax[:, None, :]) @ t.dxi + (phit * ay[:, None, :]) @ t.deta).reshape(len(U), -1)
         vals += self.static_e[None, :]
         return vals
 
@@ -321,13 +377,37 @@ class Assembler:
             self._mass_vals = vals
         return self._mass_vals
 
-    def rhs(self, u_prev: np.ndarray) -> np.ndarray:
-        """b(u_prev) = M u_prev / dt on interior rows, 0 on the boundary."""
+    def forcing_modes(self) -> np.ndarray:
+        """(16, n) loads L_j[i] = integral of phi_i sin(2 j pi x) sin(2 j pi y), j = 1..16,
+        by the element quadrature; boundary entries zero."""
+        if getattr(self, "_fmodes", None) is None:
+            t, pat = self.tab, self.pat
+            x, y = self.quad_points()
+            L = np.zeros((FORCING_MODES, pat.n))
+            wq = (self.h * self.h) * t.w[None, :]
+            for j in range(1, FORCING_MODES + 1):
+                fq = np.sin(2 * j * math.pi * x) * np.sin(2 * j * math.pi * y) * wq   # (E, nq)
+                L[j - 1] = np.bincount(pat.elem_nodes.ravel(), weights=(fq @ t.phi).ravel(), minlength=pat.n)
+            L[:, pat.boundary] = 0.0
+            self._fmodes = L
+        return self._fmodes
+
+    def forcing_load(self, coeffs: np.ndarray) -> np.ndarray:
+        """(v, f) for one step's coefficients c_1..c_16 (section 6.1)."""
+        j = np.arange(1, FORCING_MODES + 1)
+        a = 0.5 * FORCING_C * np.asarray(coeffs, dtype=np.float64) * np.exp(-(j * j) / 20.0)
+        return a @ self.forcing_modes()
+
+    def rhs(self, u_prev: np.ndarray, coeffs: Optional[np.ndarray] = None) -> np.ndarray:
+        """b(u_prev) = M u_prev / dt (+ the forcing load of `coeffs`) on interior rows, 0 on
+        the boundary."""
         import scipy.sparse as sp
         pat = self.pat
         if getattr(self, "_mass_csr", None) is None:
             self._mass_csr = sp.csr_matrix((self.mass_values(), pat.col_idx, pat.row_ptr), shape=(pat.n, pat.n))
         b = (self._mass_csr @ u_prev) / self.prob.dt
+        if coeffs is not None:
+            b += self.forcing_load(coeffs)
         b[pat.boundary] = 0.0
         return b
 
@@ -336,13 +416,25 @@ class Assembler:
         pat = self.pat
         return sp.csr_matrix((vals, pat.col_idx, pat.row_ptr), shape=(pat.n, pat.n))
 
-    def system(self, u_prev: np.ndarray):
-        """(vals, b) of step i given u^{i-1}."""
-        return self.matrix_values(u_prev), self.rhs(u_prev)
+    def system(self, u_prev: np.ndarray, coeffs: Optional[np.ndarray] = None):
+        """(vals, b) of step i given u^{i-1} (and step i's forcing coefficients)."""
+        return self.matrix_values(u_prev), self.rhs(u_prev, coeffs)
+
+
+def forcing_coefficients(seed: int, steps: int) -> np.ndarray:
+    """(steps, 16) forcing coefficients: c_1 = 1, c_2..c_16 ~ U[-1, 1] drawn afresh at every
+    step from one seeded stream (section 6.1)."""
+    rng = np.random.default_rng([seed, 6101])
+    c = np.ones((steps, FORCING_MODES))
+    c[:, 1:] = rng.uniform(-1.0, 1.0, size=(steps, FORCING_MODES - 1))
+    return c
 
 
 def initial_condition(prob: Problem, seed: int, pattern: Optional[Pattern] = None) -> np.ndarray:
-    """Gaussian bump of amplitude 1 and width 0.1, centre ~ U[0.25, 0.75]^2, zero on the boundary."""
+    """Gaussian bump of amplitude 1 and width 0.1, centre ~ U[0.25, 0.75]^2, zero on the
+    boundary; or zero everywhere for u0 = 'zero'."""
+    if prob.u0 == "zero":
+        return np.zeros(prob.n)
     rng = np.random.default_rng(seed)
     c = rng.uniform(0.25, 0.75, size=2)
     n1 = prob.n1
@@ -378,9 +470,10 @@ def march(prob: Problem, steps: int, seed: int,
     asm = asm if asm is not None else Assembler(prob)
     adv = advance if advance is not None else direct_solver(asm)
     u = initial_condition(prob, seed, asm.pat)
+    coeffs = forcing_coefficients(seed, steps) if prob.forcing else [None] * steps
     systems, states = [], []
-    for _ in range(steps):
-        vals, b = asm.system(u)
+    for i in range(steps):
+        vals, b = asm.system(u, coeffs[i])
         systems.append((vals, b))
         u = adv(vals, b)
         states.append(u)
@@ -428,6 +521,9 @@ class GpuAssembler:
 
     def __init__(self, asm: Assembler, device):
         import torch
+        if asm.prob.beta not in ("const", "rotating") or asm.prob.forcing:
+            raise ValueError("the device assembler builds the constant and rotating-field families without "
+                             "forcing; assemble this problem with the host Assembler")
         self.asm = asm
         self.dev = torch.device(device)
         pat, t = asm.pat, asm.tab
