@@ -147,6 +147,8 @@ struct rsolve_seq {
     bool wr_ok = false;            // Wr holds the current W
     double* wb[2] = {nullptr, nullptr};
     double *vals = nullptr, *partial = nullptr, *gpart = nullptr;
+    double* zpart = nullptr;   // per-block A W dots of the delayed scheme's update (k <= DCGS2_ZD_KMAX)
+    double* gz = nullptr;      // (A W)^T A W for them
     double* tsq[2] = {nullptr, nullptr};
     int64_t tsq_ld = 0;
     float *V32 = nullptr, *W32 = nullptr, *Z32 = nullptr, *vals32 = nullptr;
@@ -251,6 +253,8 @@ size_t layout(rsolve_seq* s, const rsolve_config& c, int64_t n, int64_t nnz_max,
                           : nullptr;
     double* partial = cv.take<double>((size_t)PARTIAL_DOUBLES);
     double* gpart = cv.take<double>((size_t)GRAM_PARTIAL);
+    double* zpart = (k > 0 && k <= DCGS2_ZD_KMAX) ? cv.take<double>((size_t)k * NBLK_MAX) : nullptr;
+    double* gz = zpart ? cv.take<double>((size_t)k * k) : nullptr;
     int64_t tsq_rows = 0, tsq_ld = 0;
     double *t0 = nullptr, *t1 = nullptr;
     if (k && sn) {
@@ -283,6 +287,8 @@ size_t layout(rsolve_seq* s, const rsolve_config& c, int64_t n, int64_t nnz_max,
         s->vals32 = vals32;
         s->partial = partial;
         s->gpart = gpart;
+        s->zpart = zpart;
+        s->gz = gz;
         s->bp_p = bp_p;
         s->bp_off = bp_off;
         s->bp_val = bp_val;
@@ -543,21 +549,27 @@ void dcgs2_step(rsolve_seq* s, int j, int allowed, const SpOp& op, T* V, T* cons
         arnoldi_product<T>(s, op, u, nullptr, z, pe.e0, pe.e1);
     }
     const int ncol = j + k + kz + 1;
+    // oblique projector, k <= DCGS2_ZD_KMAX: every update writes the dots of A W with the candidate
+    // it forms, so from step 1 on the sweep reads [V_j, W, u] and not A W (k columns fewer)
+    double* zpart = (kz > 0 && s->zpart) ? s->zpart : nullptr;
+    const int zskip = (zpart && j >= 1) ? kz : 0;
+    const int nsw = ncol - zskip;   // swept columns
     // two blocks per compute unit once a block has 8 or more wavefronts (measured on Q3 for 34..83
     // columns: one block per unit leaves the wide sweeps a third slower, three or four are slower
     // too), about 32 wavefronts per unit for narrower sweeps; the partials within their buffer
-    const int nw = std::min(16, (ncol + (ncol > 64 ? 7 : 3)) / (ncol > 64 ? 8 : 4));   // as the launcher
+    const int nw = std::min(16, (nsw + (nsw > 64 ? 7 : 3)) / (nsw > 64 ? 8 : 4));   // as the launcher
     const int64_t per_cu = nw >= 8 ? 2 : 32 / nw;
     const int64_t tiles = std::max<int64_t>(1, ld / (WAVE * (16 / (int64_t)sizeof(T))));
     const int nb1 = (int)std::min<int64_t>({per_cu * s->cus, tiles, PARTIAL_DOUBLES / (2 * ncol) - 1, (int64_t)NBLK_MAX});
     {
-        ProfEv pe(s, RSOLVE_PROF_DOTS, has_z ? j : MMAX, var_of(ncol), (ncol + 1.0) * w * nn);
-        launch_dots2<T>(ld, ld, V, j, Wt, Zt, k, kz, u, has_z ? z : u, s->partial, nb1, s->ctl, st, pe.e0, pe.e1);
+        ProfEv pe(s, RSOLVE_PROF_DOTS, has_z ? j : MMAX, var_of(nsw), (nsw + 1.0) * w * nn);
+        launch_dots2<T>(ld, ld, V, j, Wt, Zt, k, kz, zskip, u, has_z ? z : u, s->partial, nb1, s->ctl, st, pe.e0,
+                        pe.e1);
     }
-    launch_dcgs2_reduce(s->partial, nb1, j, k, kz, orth, has_z, s->ctl, st);
+    launch_dcgs2_reduce(s->partial, nb1, j, k, kz, orth, has_z, s->ctl, st, zskip ? zpart : nullptr, s->nblk, s->gz);
     if (has_z) {
         ProfEv pe(s, RSOLVE_PROF_UPDATE_DOTS, j, var_of(j + 1), (j + k + 4.0) * w * nn);
-        launch_dcgs2_update<T>(ld, V, ld, j, orth ? Wt : Zt, k, u, z, s->nblk, s->ctl, st, pe.e0, pe.e1);
+        launch_dcgs2_update<T>(ld, V, ld, j, orth ? Wt : Zt, k, u, z, s->nblk, s->ctl, st, pe.e0, pe.e1, zpart);
     }
 }
 
@@ -1006,6 +1018,14 @@ int rsolve_solve(rsolve_seq* s, const rsolve_csr* A, const double* b, const doub
         const int gb = launch_gram_tn(ld, s->Z, ld, kry, s->Z, ld, kry, s->gpart, s->gblk, stm);
         launch_gram_reduce(s->gpart, gb, kry * kry, ctl_red(s->ctl), stm);
         launch_small_lu(ctl_red(s->ctl), kry, s->ctl, stm);
+        HIP_TRY(hipGetLastError());
+    }
+    // delayed scheme with the oblique projector: G = (A W)^T A W, with which the column sums turn
+    // the update's dots of A W into (A W)^T u for the next step
+    if (!ls && kry > 0 && s->zpart && c.ortho == RSOLVE_ORTHO_DCGS2 && c.method != RSOLVE_AUG_ORTHO &&
+        c.method != RSOLVE_DEFL_ORTHO) {
+        const int gb = launch_gram_tn(ld, s->Z, ld, kry, s->Z, ld, kry, s->gpart, s->gblk, stm);
+        launch_gram_reduce(s->gpart, gb, kry * kry, s->gz, stm);
         HIP_TRY(hipGetLastError());
     }
     const double* Qd = ls ? s->Z : s->W;   // dot basis of the cycle-end correction

@@ -558,12 +558,15 @@ __global__ __launch_bounds__(BLOCK) void k_extrapolate(int64_t n, int64_t npad, 
 // ---------------------------------------------------------------------------
 
 // Sweep of the columns [V_j, W, A W, u], each dotted with u and with z (CPW columns per
-// wavefront, 64-row tiles): partial[(2c + e) nblk + b], e = 0 for u, 1 for z.
+// wavefront, 64-row tiles): partial[(2c + e) nblk + b], e = 0 for u, 1 for z.  With zskip = kz
+// the A W columns are left out of the sweep (the swept columns are [V_j, W, u], numbered
+// 0 .. nq + k) and their slots of the partials stay unwritten: the update sweep of the previous
+// step has already formed their dots with u, and the dots of A W with z are not used.
 template <typename T, int CPW>
 __global__ __launch_bounds__(1024) void k_dots2(int64_t npad, int64_t ld, const T* __restrict__ V, int nq,
                                                 const T* __restrict__ W, const T* __restrict__ Z, int k, int kz,
-                                                const T* __restrict__ u, const T* __restrict__ z, int c_begin,
-                                                int c_end, double* __restrict__ partial, int nblk,
+                                                int zskip, const T* __restrict__ u, const T* __restrict__ z,
+                                                int c_begin, int c_end, double* __restrict__ partial, int nblk,
                                                 const Ctl* __restrict__ ctl) {
     if (ctl->done) return;
     const int lane = threadIdx.x & (WAVE - 1);
@@ -573,6 +576,7 @@ __global__ __launch_bounds__(1024) void k_dots2(int64_t npad, int64_t ld, const 
 #pragma unroll
     for (int s = 0; s < CPW; ++s) {
         int c = c0 + s < c_end ? c0 + s : (c0 < c_end ? c0 : c_begin);
+        if (c >= nq + k) c += zskip;   // swept column -> slot of [V_j, W, A W, u]
         col[s] = c < nq ? V + (int64_t)c * ld
                         : (c < nq + k ? W + (int64_t)(c - nq) * ld : (c < nq + k + kz ? Z + (int64_t)(c - nq - k) * ld : u));
     }
@@ -607,7 +611,8 @@ __global__ __launch_bounds__(1024) void k_dots2(int64_t npad, int64_t ld, const 
         for (int t = 0; t < wave_tr_left<2 * CPW>(); ++t) {
             const int q = wave_tr_col<2 * CPW>(t);   // q = 2 s + e
             const int c = c0 + q / 2;
-            if (c < c_end) partial[(int64_t)(2 * c + (q & 1)) * nblk + blockIdx.x] = acc[t];
+            const int slot = c >= nq + k ? c + zskip : c;
+            if (c < c_end) partial[(int64_t)(2 * slot + (q & 1)) * nblk + blockIdx.x] = acc[t];
         }
     }
 }
@@ -615,13 +620,31 @@ __global__ __launch_bounds__(1024) void k_dots2(int64_t npad, int64_t ld, const 
 // sums[e] = sum over b of partial[e * nblk + b], e < nent: one wavefront per entry, eight loads
 // in flight per lane, fixed order.  Spreads the cross-block reduction of a sweep over many
 // compute units (one block reading every partial waits on remote caches for most of them).
+// With zpart, the entries of the kz A W columns (slots zlo .. zlo + kz - 1) come from the update
+// sweep's partials instead: their dots with u are the sum of zpart[c * nblk_z + b] minus
+// (G cw)_c / nu with the previous step's cw and nu (still in the control block) and
+// G = (A W)^T A W (gz, kz x kz row-major); their dots with z are not used and are set to zero.
 __global__ __launch_bounds__(1024) void k_colsum(const double* __restrict__ partial, int nblk, int nent,
-                                                 double* __restrict__ sums, const Ctl* __restrict__ ctl) {
+                                                 double* __restrict__ sums, const Ctl* __restrict__ ctl,
+                                                 const double* __restrict__ zpart, int nblk_z, int zlo, int kz,
+                                                 const double* __restrict__ gz) {
     if (ctl->done) return;
     const int lane = threadIdx.x & (WAVE - 1);
     const int e = blockIdx.x * (1024 / WAVE) + threadIdx.x / WAVE;
     if (e >= nent) return;
     const double* src = partial + (int64_t)e * nblk;
+    double corr = 0.0;
+    if (zpart && e >= 2 * zlo && e < 2 * (zlo + kz)) {
+        if (e & 1) {
+            if (lane == 0) sums[e] = 0.0;
+            return;
+        }
+        const int c = (e - 2 * zlo) / 2;
+        src = zpart + (int64_t)c * nblk_z;
+        nblk = nblk_z;
+        double g = lane < kz ? gz[c * kz + lane] * ctl->cw[lane] : 0.0;
+        corr = wave_sum(g) * ctl->inv_nu;
+    }
     double a[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) a[u] = 0.0;
@@ -634,7 +657,7 @@ __global__ __launch_bounds__(1024) void k_colsum(const double* __restrict__ part
     for (int u = 0; u < 8; ++u)
         if (b + u * WAVE < nblk) a[u] += src[b + u * WAVE];
     const double v = wave_sum(((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7])));
-    if (lane == 0) sums[e] = v;
+    if (lane == 0) sums[e] = v - corr;
 }
 
 // One block: reduce the sweep, complete and rotate column j-1, prepare step j's update.
@@ -885,6 +908,92 @@ __global__ __launch_bounds__(BLOCK) void k_dcgs2_update(int64_t npad, T* __restr
     }
 }
 
+// The update above for recycle dimensions k <= KZ, which also forms the per-block dots of the
+// A W columns with the new candidate u: with y = V dq + v_j dq_j and s = z / nu - y (both known
+// before the A W columns are read), u = s - (A W) cw / nu, so (A W)^T u = (A W)^T s -
+// G cw / nu with G = (A W)^T A W.  The kernel accumulates (A W)^T s while it streams A W for
+// the projector (zpart[c * nblk + b]); the column sums of the next step subtract G cw / nu.
+// The next step's sweep then need not read A W at all.
+template <typename T, int KZ>
+__global__ __launch_bounds__(BLOCK) void k_dcgs2_update_zd(int64_t npad, T* __restrict__ V, int64_t ld, int j,
+                                                           const T* __restrict__ Z, int k, T* __restrict__ u,
+                                                           const T* __restrict__ z, int nblk,
+                                                           const Ctl* __restrict__ ctl, double* __restrict__ zpart) {
+    if (ctl->done) return;
+    __shared__ double hr[MMAX], dq[MMAX + 1], cw[KMAX];
+    __shared__ double zs[BLOCK / WAVE][KZ];
+    for (int t = threadIdx.x; t < j; t += BLOCK) hr[t] = ctl->hr[t];
+    for (int t = threadIdx.x; t <= j; t += BLOCK) dq[t] = ctl->dq[t];
+    for (int t = threadIdx.x; t < k; t += BLOCK) cw[t] = ctl->cw[t];
+    const double inv = ctl->inv_nu;
+    __syncthreads();
+    T* vj = V + (int64_t)j * ld;
+    constexpr int VEC = 16 / sizeof(T);
+    double acc[KZ];
+#pragma unroll
+    for (int c = 0; c < KZ; ++c) acc[c] = 0.0;
+    const int64_t nvec = npad / VEC;
+    for (int64_t q = (int64_t)blockIdx.x * BLOCK + threadIdx.x; q < nvec; q += (int64_t)nblk * BLOCK) {
+        const int64_t i = q * VEC;
+        T t[VEC];
+        double a[VEC], b[VEC];
+        __builtin_memcpy(t, u + i, sizeof(t));
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+            a[e] = to_d(t[e]);
+            b[e] = 0.0;
+        }
+#pragma unroll 4
+        for (int l = 0; l < j; ++l) {
+            T v[VEC];
+            __builtin_memcpy(v, V + (int64_t)l * ld + i, sizeof(v));
+            const double h = hr[l], d = dq[l];
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) {
+                a[e] -= to_d(v[e]) * h;
+                b[e] += to_d(v[e]) * d;
+            }
+        }
+        T qs[VEC];
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) qs[e] = (T)(a[e] * inv);
+        __builtin_memcpy(vj + i, qs, sizeof(qs));
+        __builtin_memcpy(t, z + i, sizeof(t));
+        double zc[VEC], sv[VEC];
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+            zc[e] = to_d(t[e]);
+            sv[e] = zc[e] * inv - (b[e] + to_d(qs[e]) * dq[j]);
+        }
+#pragma unroll
+        for (int c = 0; c < KZ; ++c) {
+            if (c < k) {
+                T w[VEC];
+                __builtin_memcpy(w, Z + (int64_t)c * ld + i, sizeof(w));
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) {
+                    zc[e] -= to_d(w[e]) * cw[c];
+                    acc[c] += to_d(w[e]) * sv[e];
+                }
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) t[e] = (T)(zc[e] * inv - b[e] - to_d(qs[e]) * dq[j]);
+        __builtin_memcpy(u + i, t, sizeof(t));
+    }
+    wave_tr_reduce<KZ>(acc);
+    const int wv = threadIdx.x / WAVE;
+    if (wave_tr_owner<KZ>()) {
+#pragma unroll
+        for (int t = 0; t < wave_tr_left<KZ>(); ++t) zs[wv][wave_tr_col<KZ>(t)] = acc[t];
+    }
+    __syncthreads();
+    if (threadIdx.x < k) {
+        const int c = threadIdx.x;
+        zpart[(int64_t)c * nblk + blockIdx.x] = (zs[0][c] + zs[1][c]) + (zs[2][c] + zs[3][c]);
+    }
+}
+
 }  // namespace
 
 template <typename T>
@@ -970,9 +1079,10 @@ void launch_cycle_init(Ctl* ctl, int max_steps, double stop_abs, hipStream_t st,
 }
 
 template <typename T>
-void launch_dots2(int64_t npad, int64_t ld, const T* V, int nq, const T* W, const T* Z, int k, int kz, const T* u,
-                  const T* z, double* partial, int nblk, Ctl* ctl, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
-    const int ncol = nq + k + kz + 1;
+void launch_dots2(int64_t npad, int64_t ld, const T* V, int nq, const T* W, const T* Z, int k, int kz, int zskip,
+                  const T* u, const T* z, double* partial, int nblk, Ctl* ctl, hipStream_t st, hipEvent_t ev0,
+                  hipEvent_t ev1) {
+    const int ncol = nq + k + kz + 1 - zskip;   // swept columns
     // four columns per wavefront up to 64 columns, eight up to 128; at most 16 wavefronts per
     // launch, and u, z are read again by each further launch
     const int cpw = ncol > 64 ? 8 : 4;
@@ -984,40 +1094,48 @@ void launch_dots2(int64_t npad, int64_t ld, const T* V, int nq, const T* W, cons
         const bool first = a == 0, last = b == ncol;
         if (cpw == 8)
             hipExtLaunchKernelGGL(k_dots2<T, 8>, dim3(nblk), dim3(nw * WAVE), 0, st, first ? ev0 : nullptr,
-                                  last ? ev1 : nullptr, 0, npad, ld, V, nq, W, Z, k, kz, u, z, a, b, partial, nblk,
-                                  static_cast<const Ctl*>(ctl));
+                                  last ? ev1 : nullptr, 0, npad, ld, V, nq, W, Z, k, kz, zskip, u, z, a, b, partial,
+                                  nblk, static_cast<const Ctl*>(ctl));
         else
             hipExtLaunchKernelGGL(k_dots2<T, 4>, dim3(nblk), dim3(nw * WAVE), 0, st, first ? ev0 : nullptr,
-                                  last ? ev1 : nullptr, 0, npad, ld, V, nq, W, Z, k, kz, u, z, a, b, partial, nblk,
-                                  static_cast<const Ctl*>(ctl));
+                                  last ? ev1 : nullptr, 0, npad, ld, V, nq, W, Z, k, kz, zskip, u, z, a, b, partial,
+                                  nblk, static_cast<const Ctl*>(ctl));
     }
 }
-template void launch_dots2<double>(int64_t, int64_t, const double*, int, const double*, const double*, int, int,
+template void launch_dots2<double>(int64_t, int64_t, const double*, int, const double*, const double*, int, int, int,
                                    const double*, const double*, double*, int, Ctl*, hipStream_t, hipEvent_t,
                                    hipEvent_t);
-template void launch_dots2<float>(int64_t, int64_t, const float*, int, const float*, const float*, int, int,
+template void launch_dots2<float>(int64_t, int64_t, const float*, int, const float*, const float*, int, int, int,
                                   const float*, const float*, double*, int, Ctl*, hipStream_t, hipEvent_t,
                                   hipEvent_t);
 
 void launch_dcgs2_reduce(double* partial, int nblk, int j, int k, int kz, bool orth, bool has_z, Ctl* ctl,
-                         hipStream_t st) {
+                         hipStream_t st, const double* zpart, int nblk_z, const double* gz) {
     // the column sums go right after the partials
     const int nent = 2 * (j + k + kz + 1);
     double* dsum = partial + (int64_t)nent * nblk;
-    k_colsum<<<(nent + 15) / 16, 1024, 0, st>>>(partial, nblk, nent, dsum, ctl);
+    k_colsum<<<(nent + 15) / 16, 1024, 0, st>>>(partial, nblk, nent, dsum, ctl, zpart, nblk_z, j + k, kz, gz);
     k_dcgs2_reduce<<<1, RED_T, 0, st>>>(dsum, j, k, kz, orth ? 1 : 0, has_z ? 1 : 0, ctl);
 }
 
 template <typename T>
 void launch_dcgs2_update(int64_t npad, T* V, int64_t ld, int j, const T* Z, int k, T* u, const T* z, int nblk,
-                         const Ctl* ctl, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
-    hipExtLaunchKernelGGL(k_dcgs2_update<T>, dim3(nblk), dim3(BLOCK), 0, st, ev0, ev1, 0, npad, V, ld, j, Z, k, u, z,
-                          nblk, ctl);
+                         const Ctl* ctl, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1, double* zpart) {
+    if (zpart && k <= 8)
+        hipExtLaunchKernelGGL(k_dcgs2_update_zd<T, 8>, dim3(nblk), dim3(BLOCK), 0, st, ev0, ev1, 0, npad, V, ld, j, Z,
+                              k, u, z, nblk, ctl, zpart);
+    else if (zpart && k <= DCGS2_ZD_KMAX)
+        hipExtLaunchKernelGGL(k_dcgs2_update_zd<T, DCGS2_ZD_KMAX>, dim3(nblk), dim3(BLOCK), 0, st, ev0, ev1, 0, npad,
+                              V, ld, j, Z, k, u, z, nblk, ctl, zpart);
+    else
+        hipExtLaunchKernelGGL(k_dcgs2_update<T>, dim3(nblk), dim3(BLOCK), 0, st, ev0, ev1, 0, npad, V, ld, j, Z, k, u,
+                              z, nblk, ctl);
 }
 template void launch_dcgs2_update<double>(int64_t, double*, int64_t, int, const double*, int, double*,
-                                          const double*, int, const Ctl*, hipStream_t, hipEvent_t, hipEvent_t);
+                                          const double*, int, const Ctl*, hipStream_t, hipEvent_t, hipEvent_t,
+                                          double*);
 template void launch_dcgs2_update<float>(int64_t, float*, int64_t, int, const float*, int, float*, const float*, int,
-                                         const Ctl*, hipStream_t, hipEvent_t, hipEvent_t);
+                                         const Ctl*, hipStream_t, hipEvent_t, hipEvent_t, double*);
 
 void launch_cycle_solve(Ctl* ctl, hipStream_t st) { k_cycle_solve<<<1, WAVE, 0, st>>>(ctl); }
 

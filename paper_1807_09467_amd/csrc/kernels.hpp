@@ -84,17 +84,23 @@ void launch_cycle_init(Ctl* ctl, int max_steps, double stop_abs, hipStream_t st,
 // Delayed reorthogonalisation, step j: the sweep over [V_j (nq = j columns), W, A W, u] dotted
 // with u and z; the one-block reduction (completes and rotates column j-1, sets done, prepares
 // step j; has_z = false on the closing step); the update sweep (v_j and the next candidate u).
+// zskip = kz leaves the A W columns out (their dots with u come from the previous update).
 template <typename T>
-void launch_dots2(int64_t npad, int64_t ld, const T* V, int nq, const T* W, const T* Z, int k, int kz, const T* u,
-                  const T* z, double* partial, int nblk, Ctl* ctl, hipStream_t st, hipEvent_t ev0 = nullptr,
-                  hipEvent_t ev1 = nullptr);
+void launch_dots2(int64_t npad, int64_t ld, const T* V, int nq, const T* W, const T* Z, int k, int kz, int zskip,
+                  const T* u, const T* z, double* partial, int nblk, Ctl* ctl, hipStream_t st,
+                  hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 // the sweep's column sums (written after the partials: partial needs 2 ncol (nblk + 1) doubles),
-// then the one-block reduction of the delayed scheme
+// then the one-block reduction of the delayed scheme; with zpart, the A W dots with u are the sums
+// of the previous update's per-block partials (nblk_z of them per column) minus G cw / nu, with
+// G = (A W)^T A W in gz (kz x kz, row-major)
 void launch_dcgs2_reduce(double* partial, int nblk, int j, int k, int kz, bool orth, bool has_z, Ctl* ctl,
-                         hipStream_t st);
+                         hipStream_t st, const double* zpart = nullptr, int nblk_z = 0, const double* gz = nullptr);
+// with zpart (k <= DCGS2_ZD_KMAX), also the per-block dots of the k columns of Z with
+// z / nu - V dq - v_j dq_j (the new candidate u plus (A W) cw / nu): zpart[c * nblk + b]
 template <typename T>
 void launch_dcgs2_update(int64_t npad, T* V, int64_t ld, int j, const T* Z, int k, T* u, const T* z, int nblk,
-                         const Ctl* ctl, hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+                         const Ctl* ctl, hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr,
+                         double* zpart = nullptr);
 // y = R^{-1} g (ctl->steps unknowns)
 void launch_cycle_solve(Ctl* ctl, hipStream_t st);
 // x[i] += dinv[i] * sum_{c < steps} V[i, c] y[c]   (dinv nullable)
