@@ -1,0 +1,87 @@
+"""GPU parity at the full sizes the benchmark runs, in its launch configuration.
+
+* Q2 256x256 (n = 263,169, nnz = 4,159,569): recycled FP64 GMRES(30), k = 10, s = 20, right
+  Jacobi, delayed reorthogonalisation, tol 1e-10, over the first eight steps of the sequence:
+  solutions within 1e-9 of the oracle, Arnoldi steps within 2, the same k_eff, and the true
+  residual (host FP64 product) within the tolerance.
+* Q3 512x512 (n = 2,362,369, nnz = 58,789,033): the headline configuration (recycled mixed
+  precision, FP32 Arnoldi cycles inside FP64 refinement, GMRES(50), k = 16, s = 32, banded SpMV
+  with 4 lanes per row and 8-entry chunks), first two steps (the second with a recycle space):
+  the true residual within 1e-8 (a property at any size), and the solution within the
+  refinement bar of the oracle's FP64 solution to the same tolerance.  cond(A) cannot be formed
+  at this size; two solutions that both meet a 1e-8 residual differ by up to cond(A) 1e-8, and
+  the bar 1e-6 admits cond(A) up to 50 (the mixed and FP64 solutions of the benchmark differ by
+  7e-9 on this sequence).
+
+The sequence is advanced along the oracle's own solutions (A_i is assembled from the oracle's
+x_{i-1}), and both sides start each solve from that x_{i-1}: no input of the oracle comes from the
+GPU path."""
+import numpy as np
+import pytest
+
+from oracle import rgmres as O
+from paper_1807_09467_amd import workload as WL
+
+from test_gpu_parity import _t
+
+pytestmark = pytest.mark.gpu
+
+
+def _run(dev, prob, steps, tol, oracle_tol, gcfg, ocfg, shape=None):
+    import torch
+
+    from paper_1807_09467_amd import rsolve
+    asm = WL.Assembler(prob)
+    pat = asm.pat
+    rp, ci = _t(pat.row_ptr, dev), _t(pat.col_idx, dev)
+    seq = rsolve.Sequence(pat.n, pat.nnz, device=dev, **gcfg)
+    if shape:
+        seq.set_spmv_shape(*shape)
+    ost = O.RecycleState(pat.n, ocfg)
+    u = WL.initial_condition(prob, 0)
+    out = []
+    for i in range(steps):
+        vals, b = asm.system(u)
+        A = asm.csr(vals)
+        print(f"[fullsize] {prob.p} {prob.N} step {i}", flush=True)
+        x, st, status = seq.solve(rp, ci, _t(vals, dev), _t(b, dev), x0=_t(u, dev), tol=tol, same_pattern=i > 0)
+        seq.update()
+        ores = O.solve(A, b, u, oracle_tol, ocfg, ost.W, ost.ring)
+        ost.update(ores.x)
+        xg = x.cpu().numpy()
+        torch.cuda.synchronize()
+        out.append(dict(step=i, status=status, st=st, ores=ores,
+                        rel=np.linalg.norm(xg - ores.x) / np.linalg.norm(ores.x),
+                        res=np.linalg.norm(b - A @ xg) / np.linalg.norm(b)))
+        u = ores.x
+    seq.close()
+    return out
+
+
+def test_q2_full_size_recycled_fp64(gpu_ctx):
+    gcfg = dict(restart_m=30, recycle_k=10, snapshots_s=20, svd_interval=1, precond="jacobi", precision="fp64",
+                ortho="dcgs2")
+    ocfg = O.Config(restart_m=30, recycle_k=10, snapshots_s=20, svd_interval=1, method=O.AUG_OBLIQUE,
+                    precond=O.PRECOND_JACOBI)
+    out = _run(gpu_ctx, WL.C2, 8, 1e-10, 1e-10, gcfg, ocfg)
+    for r in out:
+        assert r["status"] == 0 and r["st"]["converged"] == 1, r["step"]
+        assert r["res"] <= 1e-10 * (1 + 1e-6), (r["step"], r["res"])
+        assert r["rel"] <= 1e-9, (r["step"], r["rel"])
+        assert abs(r["st"]["iterations"] - r["ores"].iterations) <= 2, (
+            r["step"], r["st"]["iterations"], r["ores"].iterations)
+        assert r["st"]["k_eff"] == r["ores"].k_eff == min(r["step"], 10)
+
+
+def test_q3_full_size_headline_mixed(gpu_ctx):
+    gcfg = dict(restart_m=50, recycle_k=16, snapshots_s=32, svd_interval=1, precond="jacobi", precision="fp32_ir",
+                inner_tol=1e-5, ortho="dcgs2")
+    ocfg = O.Config(restart_m=50, recycle_k=16, snapshots_s=32, svd_interval=1, method=O.AUG_OBLIQUE,
+                    precond=O.PRECOND_JACOBI)
+    out = _run(gpu_ctx, WL.C3, 2, 1e-8, 1e-8, gcfg, ocfg, shape=(4, 8, 0, "banded"))
+    for r in out:
+        assert r["status"] == 0 and r["st"]["converged"] == 1, r["step"]
+        assert r["res"] <= 1e-8 * (1 + 1e-6), (r["step"], r["res"])
+        assert r["ores"].converged
+        assert r["rel"] <= 1e-6, (r["step"], r["rel"])
+        assert r["st"]["k_eff"] == r["ores"].k_eff == r["step"]
