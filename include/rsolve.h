@@ -293,14 +293,17 @@ typedef struct {
 } rsolve_prof_entry;
 
 #define RSOLVE_PROF_ALL         0xF /* every kind below: (1 << RSOLVE_PROF_SPMV) | ... */
+/* sampling: time only the steps j with j % stride == stride / 2 (stride 1..256, default 1) */
+#define RSOLVE_PROF_STRIDE(stride) ((int32_t)(((stride) - 1) & 0xFF) << 8)
 
 /*
  * Per-kernel timing for this sequence: `kinds` is a bit set (bit RSOLVE_PROF_x times that
  * kernel kind, RSOLVE_PROF_ALL all of them, 0 switches timing off).  A timed Arnoldi-step
  * kernel gets two HIP events stamped by its own dispatch on the sequence's stream; durations of
  * the launches that did work are summed after each cycle.  Each timed launch costs a few
- * microseconds of host and queue work, so time only the kinds you need.  Errors: E_INVALID,
- * E_DEVICE (event creation).
+ * microseconds of host and queue work, so time only the kinds you need, or OR in
+ * RSOLVE_PROF_STRIDE(s) to time every s-th step of a cycle only (the averages stay those of
+ * the sampled launches).  Errors: E_INVALID, E_DEVICE (event creation).
  */
 int rsolve_profile_enable(rsolve_seq* s, int32_t kinds);
 

@@ -179,6 +179,7 @@ struct rsolve_seq {
     static constexpr int NPK = 4, NVAR = 4;
     bool prof_on = false;
     int prof_mask = 0;                   // bit RSOLVE_PROF_* set: that kernel kind is timed
+    int prof_stride = 1;                 // time steps j with j % prof_stride == prof_stride / 2
     hipEvent_t* pev = nullptr;           // [NPK][MMAX][2]
     int pvar[NPK][MMAX];                 // variant recorded for step j
     double pbytes[NPK][MMAX];            // algorithmic bytes of step j's launch
@@ -455,7 +456,7 @@ inline int var_of(int cols) { return cols <= 8 ? 0 : (cols <= 16 ? 1 : (cols <= 
 struct ProfEv {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     ProfEv(rsolve_seq* s, int kind, int j, int var, double bytes) {
-        if (!(s->prof_mask & (1 << kind)) || j >= MMAX) return;
+        if (!(s->prof_mask & (1 << kind)) || j >= MMAX || j % s->prof_stride != s->prof_stride / 2) return;
         s->pvar[kind][j] = var;
         s->pbytes[kind][j] = bytes;
         s->pset[kind][j] = true;
@@ -707,7 +708,9 @@ int rsolve_create_sequence(const rsolve_config* cfg, int64_t n, int64_t nnz_max,
 }
 
 int rsolve_profile_enable(rsolve_seq* s, int32_t kinds) {
-    if (!s || kinds < 0 || kinds > RSOLVE_PROF_ALL) return RSOLVE_E_INVALID;
+    if (!s || kinds < 0 || (kinds & ~(RSOLVE_PROF_ALL | 0xFF00))) return RSOLVE_E_INVALID;
+    s->prof_stride = ((kinds >> 8) & 0xFF) + 1;
+    kinds &= RSOLVE_PROF_ALL;
     if (kinds && !s->pev) {
         HIP_TRY(hipSetDevice(s->device));
         const int cnt = rsolve_seq::NPK * MMAX * 2;

@@ -317,8 +317,9 @@ class Sequence:
         _check(self.lib.rsolve_graph_counts(self.handle, byref(c), byref(l)))
         return c.value, l.value
 
-    def profile(self, on=True, kinds=None):
-        """Per-kernel event timing: kinds = iterable of names from PROF_KERNELS (default: all)."""
+    def profile(self, on=True, kinds=None, stride=1):
+        """Per-kernel event timing: kinds = iterable of names from PROF_KERNELS (default: all);
+        stride s times only every s-th step of a cycle (rsolve.h RSOLVE_PROF_STRIDE)."""
         if not on:
             mask = 0
         elif kinds is None:
@@ -328,6 +329,10 @@ class Sequence:
             mask = 0
             for k in kinds:
                 mask |= 1 << names[k]
+        if on:
+            if not 1 <= stride <= 256:
+                raise ValueError("stride must be in 1..256")
+            mask |= (stride - 1) << 8
         _check(self.lib.rsolve_profile_enable(self.handle, mask))
 
     def profile_read(self, reset=False):
