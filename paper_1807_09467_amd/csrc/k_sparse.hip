@@ -237,22 +237,41 @@ __global__ __launch_bounds__(BLOCK) void k_bp_pack(int64_t n, const int32_t* __r
 }
 
 // The values of one matrix (times D^{-1} by column when dinv is given) into their positions:
-// 8 lanes per row.
+// 8 lanes per row, each lane writing VEC consecutive positions of the row's chunks with one
+// 16-byte store (padding positions get 0), so the row's region is written whole and in order.
+// The entry at row-local position t (chunk t / E, slot t % E) is the inverse of bp_pos: with
+// it = chunk / LPR, l = chunk % LPR and g the lanes of that round, entry it E LPR + slot g + l.
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_bp_values(int64_t n, const int32_t* __restrict__ rp,
                                                      const int32_t* __restrict__ ci, const double* __restrict__ val,
                                                      const double* __restrict__ dinv, const int32_t* __restrict__ p,
                                                      int E, int LPR, T* __restrict__ out) {
-    const int64_t gt = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    const int64_t gt = (int64_t)xcd_block(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
     const int64_t i = gt / 8;
     const int sub = (int)(gt % 8);
     if (i >= n) return;
     const int a = rp[i], L = rp[i + 1] - a;
     const int c0 = p[i], LP = p[i + 1] - c0;
-    for (int kk = sub; kk < L; kk += 8) {
-        double v = val[a + kk];
-        if (dinv) v *= dinv[ci[a + kk]];
-        out[bp_pos(c0, LP, kk, E, LPR)] = (T)v;
+    constexpr int VEC = 16 / sizeof(T);   // divides E (4 or 8), so a store never leaves its chunk
+    T* dst = out + (int64_t)c0 * E;
+    const int tot = LP * E, R = E * LPR;
+    for (int t0 = sub * VEC; t0 < tot; t0 += 8 * VEC) {
+        T o[VEC];
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+            const int t = t0 + e;
+            const int chunk = t / E, slot = t - chunk * E;
+            const int it = chunk / LPR, l = chunk - it * LPR;
+            const int g = min(LPR, LP - LPR * it);
+            const int kk = it * R + slot * g + l;
+            double v = 0.0;
+            if (kk < L) {
+                v = val[a + kk];
+                if (dinv) v *= dinv[ci[a + kk]];
+            }
+            o[e] = (T)v;
+        }
+        __builtin_memcpy(dst + t0, o, sizeof(o));
     }
 }
 
@@ -294,7 +313,9 @@ __global__ __launch_bounds__(BLOCK) void k_spmm_rows(int64_t n, const int32_t* _
                                                      const int32_t* __restrict__ ci, const double* __restrict__ val,
                                                      const double* __restrict__ Wr, int ldr, int c0, int kc,
                                                      double* __restrict__ Z, int64_t ld) {
-    const int64_t gt = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    // XCD-aware rows: each XCD takes a contiguous share, so the W rows a block gathers (the columns
+    // near its rows) are fetched into that XCD's L2 once rather than once per XCD
+    const int64_t gt = (int64_t)xcd_block(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
     const int64_t row = gt / 4;
     const int sub = (int)(gt % 4);
     if (row >= n) return;
