@@ -136,3 +136,14 @@ def test_restart_at_the_maximum(gpu_ctx, ortho):
     assert out[0]["st"]["iterations"] > 256 and out[0]["st"]["cycles"] >= 3
     out = run_pair(gpu_ctx, hard, 3, 1e-10, restart_m=128, recycle_k=16, snapshots_s=20, ortho=ortho)
     _check_slow_tail(out, 1e-10)
+
+
+@pytest.mark.parametrize("ortho", ["cgs2", "dcgs2"])
+def test_maximum_recycle_dimensions(gpu_ctx, ortho):
+    """k = s = 64 (the largest recycle dimension and ring): the ring fills after 64 solves and
+    the recycle space keeps all 64 directions (the smallest singular value of the ring stays an
+    order of magnitude above the rank cut), so the sweeps carry 2 k + j columns and the small LU
+    is 64 x 64."""
+    out = run_pair(gpu_ctx, WL.C1, 68, 1e-10, restart_m=30, recycle_k=64, snapshots_s=64, ortho=ortho)
+    _check_parity(out)
+    assert [r["st"]["k_eff"] for r in out][-4:] == [64] * 4
