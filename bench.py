@@ -248,7 +248,8 @@ def run_solver(gasm, u0, systems, warmup, steps, tol, cfg, dev, profile=False, l
 
 
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_spmv_bp_f32-q3_512x512_recycled_mixed-hbm_traffic.md")
-TRAFFIC_SOURCES = ["paper_1807_09467_amd/csrc/spmv_banded.hpp", "paper_1807_09467_amd/csrc/common.hpp"]
+TRAFFIC_SOURCES = ["paper_1807_09467_amd/csrc/spmv_banded.hpp", "paper_1807_09467_amd/csrc/spmv_classes.hpp",
+                   "paper_1807_09467_amd/csrc/common.hpp"]
 
 
 def measured_traffic(kernel):

@@ -17,6 +17,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <unordered_map>
 #include <tuple>
 #include <vector>
 
@@ -164,6 +165,13 @@ struct rsolve_seq {
     int64_t bp_cap = 0;            // 0: the format is not available for this size
     bool band_ok = false;          // the current pattern fits the 16-bit offsets
     int bp_e = 0, bp_l = 0;        // chunk size and lanes the copy is laid out for (0: not built)
+    // shared offset lists of the banded copy: rows of equal offsets form a class (cls_row), each
+    // class keeps one list in cls_dict starting at chunk cls_start[c]
+    uint16_t* cls_row = nullptr;
+    int32_t* cls_start = nullptr;
+    int16_t* cls_dict = nullptr;
+    bool cls_ok = false;           // the classes describe the banded copy as laid out now
+    int ncls = 0;
     const int32_t* pat_rp = nullptr;
     const int32_t* pat_ci = nullptr;
     int64_t pat_nnz = -1;
@@ -252,6 +260,9 @@ size_t layout(rsolve_seq* s, const rsolve_config& c, int64_t n, int64_t nnz_max,
     void* bp_val = bp_cap ? (ir ? static_cast<void*>(cv.take<float>((size_t)bp_cap))
                                 : static_cast<void*>(cv.take<double>((size_t)bp_cap)))
                           : nullptr;
+    uint16_t* cls_row = bp_cap ? cv.take<uint16_t>((size_t)n) : nullptr;
+    int32_t* cls_start = bp_cap ? cv.take<int32_t>((size_t)CLS_MAX) : nullptr;
+    int16_t* cls_dict = bp_cap ? cv.take<int16_t>((size_t)CLS_DICT_CHUNKS * 8) : nullptr;
     double* partial = cv.take<double>((size_t)PARTIAL_DOUBLES);
     double* gpart = cv.take<double>((size_t)GRAM_PARTIAL);
     double* zpart = (k > 0 && k <= DCGS2_ZD_KMAX) ? cv.take<double>((size_t)k * NBLK_MAX) : nullptr;
@@ -294,6 +305,9 @@ size_t layout(rsolve_seq* s, const rsolve_config& c, int64_t n, int64_t nnz_max,
         s->bp_off = bp_off;
         s->bp_val = bp_val;
         s->bp_cap = bp_cap;
+        s->cls_row = cls_row;
+        s->cls_start = cls_start;
+        s->cls_dict = cls_dict;
         s->tsq[0] = t0;
         s->tsq[1] = t1;
         s->tsq_ld = tsq_ld;
@@ -324,6 +338,7 @@ int validate_pattern(rsolve_seq* s, const rsolve_csr* A) {
     s->pat_ok = true;
     s->band_ok = s->bp_cap > 0 && s->herr[4] == 0;
     s->bp_e = s->bp_l = 0;   // the banded copy (if used) is laid out again for this pattern
+    s->cls_ok = false;
     if (!s->shape_set) {
         // banded padded format with 8-entry chunks and 4 lanes per row for finite-element rows of
         // about a dozen entries or more; CSR otherwise
@@ -353,6 +368,63 @@ struct SpOp {
 
 // Lays the banded copy out for the current pattern and shape if needed, then writes this
 // matrix's values (times D^{-1} by column when dinv is given) into it.
+// The offset classes of the banded copy just laid out (chunk size E): the copy's chunk offsets
+// and column offsets are read back once, rows are grouped by their offset lists (hash, then an
+// exact comparison), and the row classes, class starts and lists are written to the workspace.
+// Leaves cls_ok false (no error) when the pattern has more than CLS_MAX classes or their lists
+// exceed CLS_DICT_CHUNKS chunks: the product then reads the copy's own offsets.
+int cls_build(rsolve_seq* s, int E) {
+    s->cls_ok = false;
+    if (!CLS_ON) return RSOLVE_OK;
+    hipStream_t stm = s->stream;
+    const int64_t n = s->n;
+    std::vector<int32_t> hp((size_t)n + 1);
+    HIP_TRY(hipMemcpyAsync(hp.data(), s->bp_p, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToHost, stm));
+    HIP_TRY(hipStreamSynchronize(stm));
+    const int64_t total = (int64_t)hp[n] * E;
+    std::vector<int16_t> hoff((size_t)total);
+    HIP_TRY(hipMemcpyAsync(hoff.data(), s->bp_off, sizeof(int16_t) * total, hipMemcpyDeviceToHost, stm));
+    HIP_TRY(hipStreamSynchronize(stm));
+    std::vector<uint16_t> rowc((size_t)n);
+    std::vector<int32_t> cstart, clen;
+    std::vector<int16_t> dict;
+    std::unordered_multimap<uint64_t, int> by_hash;
+    for (int64_t r = 0; r < n; ++r) {
+        const int LP = hp[r + 1] - hp[r];
+        const int16_t* sp = hoff.data() + (int64_t)hp[r] * E;
+        const int len = LP * E;
+        uint64_t h = 1469598103934665603ull ^ (uint64_t)LP;
+        for (int t = 0; t < len; ++t) h = (h ^ (uint16_t)sp[t]) * 1099511628211ull;
+        int id = -1;
+        auto range = by_hash.equal_range(h);
+        for (auto it = range.first; it != range.second; ++it) {
+            const int c = it->second;
+            if (clen[c] == LP && std::memcmp(dict.data() + (int64_t)cstart[c] * E, sp, sizeof(int16_t) * len) == 0) {
+                id = c;
+                break;
+            }
+        }
+        if (id < 0) {
+            const int64_t chunks = (int64_t)dict.size() / E;
+            if ((int)cstart.size() >= CLS_MAX || chunks + LP > CLS_DICT_CHUNKS) return RSOLVE_OK;
+            id = (int)cstart.size();
+            cstart.push_back((int32_t)chunks);
+            clen.push_back(LP);
+            dict.insert(dict.end(), sp, sp + len);
+            by_hash.emplace(h, id);
+        }
+        rowc[r] = (uint16_t)id;
+    }
+    HIP_TRY(hipMemcpyAsync(s->cls_row, rowc.data(), sizeof(uint16_t) * n, hipMemcpyHostToDevice, stm));
+    HIP_TRY(hipMemcpyAsync(s->cls_start, cstart.data(), sizeof(int32_t) * cstart.size(), hipMemcpyHostToDevice, stm));
+    if (!dict.empty())
+        HIP_TRY(hipMemcpyAsync(s->cls_dict, dict.data(), sizeof(int16_t) * dict.size(), hipMemcpyHostToDevice, stm));
+    HIP_TRY(hipStreamSynchronize(stm));   // the host vectors go out of scope
+    s->ncls = (int)cstart.size();
+    s->cls_ok = true;
+    return RSOLVE_OK;
+}
+
 int bp_prepare(rsolve_seq* s, const rsolve_csr* A, const double* dinv, bool f32) {
     if (!s->band_ok) {
         set_err("the banded SpMV format needs |col - row| <= %d for every entry and room for the padding",
@@ -368,6 +440,8 @@ int bp_prepare(rsolve_seq* s, const rsolve_csr* A, const double* dinv, bool f32)
         }
         s->bp_e = s->svec;
         s->bp_l = s->lpr;
+        const int crc = cls_build(s, s->svec);
+        if (crc) return crc;
     }
     if (f32) launch_bp_values<float>(s->n, A->row_ptr, A->col_idx, A->val, dinv, s->bp_p, s->svec, s->lpr,
                                      static_cast<float*>(s->bp_val), stm);
@@ -379,13 +453,18 @@ int bp_prepare(rsolve_seq* s, const rsolve_csr* A, const double* dinv, bool f32)
 // Algorithmic bytes of one Arnoldi product (entries counted without padding), w = value width.
 double spmv_bytes(const rsolve_seq* s, double w, bool vout) {
     const double nn = (double)s->n, nz = (double)s->nnz_cur;
+    if (s->sfmt == RSOLVE_SPMV_BANDED && s->cls_ok)   // values, chunk offsets, class numbers
+        return w * nz + 4.0 * (nn + 1.0) + 2.0 * nn + (vout ? 3.0 : 2.0) * w * nn;
     const double idx = s->sfmt == RSOLVE_SPMV_BANDED ? 2.0 : 4.0;
     return (w + idx) * nz + 4.0 * (nn + 1.0) + (vout ? 3.0 : 2.0) * w * nn;
 }
 
 template <typename T>
 void arnoldi_product(rsolve_seq* s, const SpOp& op, const T* win, T* vout, T* y, hipEvent_t e0, hipEvent_t e1) {
-    if (op.fmt == RSOLVE_SPMV_BANDED)
+    if (op.fmt == RSOLVE_SPMV_BANDED && s->cls_ok)
+        launch_spmv_bc<T>(s->svec, s->lpr, s->sremap, s->n, op.rp, s->cls_row, s->cls_start, s->cls_dict,
+                          static_cast<const T*>(op.vals), win, vout, y, s->ctl, s->stream, e0, e1);
+    else if (op.fmt == RSOLVE_SPMV_BANDED)
         launch_spmv_bp<T>(s->svec, s->lpr, s->sremap, s->n, op.rp, op.off, static_cast<const T*>(op.vals), win, vout,
                           y, s->ctl, s->stream, e0, e1);
     else
@@ -824,10 +903,12 @@ int rsolve_tune_spmv(rsolve_seq* s, const rsolve_csr* A, int32_t reps, rsolve_sp
         for (int l : {2, 4, 8})
             for (int v : {4, 8}) {
                 // lay the copy out for this shape and fill it with A's values
+                s->cls_ok = false;
                 if (err == hipSuccess && bp_setup(n, A->row_ptr, A->col_idx, v, l, s->bp_p, s->bp_off, s->bp_val, ir,
                                                   reinterpret_cast<int32_t*>(s->partial), PARTIAL_INTS, stm) == 0) {
                     s->bp_e = v;
                     s->bp_l = l;
+                    if (cls_build(s, v) != RSOLVE_OK) err = hipErrorUnknown;
                     if (ir) launch_bp_values<float>(n, A->row_ptr, A->col_idx, A->val, nullptr, s->bp_p, v, l,
                                                     static_cast<float*>(s->bp_val), stm);
                     else launch_bp_values<double>(n, A->row_ptr, A->col_idx, A->val, nullptr, s->bp_p, v, l,
@@ -836,10 +917,18 @@ int rsolve_tune_spmv(rsolve_seq* s, const rsolve_csr* A, int32_t reps, rsolve_sp
                 for (int rm = 0; rm < 2; ++rm)
                     time_it(
                         [&] {
-                            if (ir)
+                            if (ir && s->cls_ok)
+                                launch_spmv_bc<float>(v, l, rm, n, s->bp_p, s->cls_row, s->cls_start, s->cls_dict,
+                                                      static_cast<const float*>(s->bp_val), s->w32[0], s->V32,
+                                                      s->w32[1], s->ctl, stm);
+                            else if (ir)
                                 launch_spmv_bp<float>(v, l, rm, n, s->bp_p, s->bp_off,
                                                       static_cast<const float*>(s->bp_val), s->w32[0], s->V32,
                                                       s->w32[1], s->ctl, stm);
+                            else if (s->cls_ok)
+                                launch_spmv_bc<double>(v, l, rm, n, s->bp_p, s->cls_row, s->cls_start, s->cls_dict,
+                                                       static_cast<const double*>(s->bp_val), s->wb[0], s->V,
+                                                       s->wb[1], s->ctl, stm);
                             else
                                 launch_spmv_bp<double>(v, l, rm, n, s->bp_p, s->bp_off,
                                                        static_cast<const double*>(s->bp_val), s->wb[0], s->V,
@@ -1042,9 +1131,13 @@ int rsolve_solve(rsolve_seq* s, const rsolve_csr* A, const double* b, const doub
     const int m = c.restart_m;
     const float* W32 = s->W32;
     const float* Z32 = s->Z32;
+    bool head_fresh = false;   // the control block's head was read after the last enqueued work
     for (;;) {
-        rc = read_head(s);
-        if (rc) return rc;
+        if (!head_fresh) {
+            rc = read_head(s);
+            if (rc) return rc;
+        }
+        head_fresh = false;
         const double rnorm = s->hctl->rnorm;
         if (s->hctl->nonfinite || !std::isfinite(rnorm)) {
             flags |= RSOLVE_FLAG_NONFINITE;
@@ -1107,7 +1200,7 @@ int rsolve_solve(rsolve_seq* s, const rsolve_csr* A, const double* b, const doub
             };
             if (s->graphs_on && !s->prof_on) {
                 const rsolve_seq::GraphKey key{j0,      j1,         kry,       ir ? 1 : 0, s->lpr, s->svec, s->sremap,
-                                               op.fmt,  (dg ? 1 : 0) | (orth ? 2 : 0) | (ls ? 4 : 0),
+                                               op.fmt,  (dg ? 1 : 0) | (orth ? 2 : 0) | (ls ? 4 : 0) | (s->cls_ok ? 8 : 0),
                                                dg ? max_steps : 0, op.rp, op.ci,
                                                op.off,  op.vals};
                 hipGraphExec_t ge = nullptr;
@@ -1131,6 +1224,7 @@ int rsolve_solve(rsolve_seq* s, const rsolve_csr* A, const double* b, const doub
         HIP_TRY(hipGetLastError());
         rc = read_head(s);
         if (rc) return rc;
+        head_fresh = true;
         prof_collect(s, s->hctl->steps);
         its += s->hctl->steps;
         cycles += 1;

@@ -9,6 +9,7 @@
 
 #include "kernels.hpp"
 #include "spmv_banded.hpp"
+#include "spmv_classes.hpp"
 
 namespace rs {
 
@@ -323,6 +324,25 @@ __global__ __launch_bounds__(BLOCK) void k_spmm_rows(int64_t n, const int32_t* _
     const double* wb = Wr + c0 + 4 * sub;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     int j = a;
+    // eight entries at a time: their column indices and values first, then the eight W gathers
+    // together, so each round trip to memory carries eight entries rather than two
+    for (; j + 7 < e; j += 8) {
+        int c[8];
+        double v[8], w[8][4];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            c[u] = ci[j + u];
+            v[u] = val[j + u];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            __builtin_memcpy(w[u], __builtin_assume_aligned(wb + (int64_t)c[u] * ldr, 32), sizeof(w[u]));
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+#pragma unroll
+            for (int cc = 0; cc < 4; ++cc) acc[cc] += v[u] * w[u][cc];
+        }
+    }
     for (; j + 1 < e; j += 2) {
         const double v0 = val[j], v1 = val[j + 1];
         double w0[4], w1[4];
@@ -429,6 +449,12 @@ template void launch_spmv_bp<double>(int, int, int, int64_t, const int32_t*, con
                                      const double*, double*, double*, const Ctl*, hipStream_t, hipEvent_t, hipEvent_t);
 template void launch_spmv_bp<float>(int, int, int, int64_t, const int32_t*, const int16_t*, const float*,
                                     const float*, float*, float*, const Ctl*, hipStream_t, hipEvent_t, hipEvent_t);
+template void launch_spmv_bc<double>(int, int, int, int64_t, const int32_t*, const uint16_t*, const int32_t*,
+                                     const int16_t*, const double*, const double*, double*, double*, const Ctl*,
+                                     hipStream_t, hipEvent_t, hipEvent_t);
+template void launch_spmv_bc<float>(int, int, int, int64_t, const int32_t*, const uint16_t*, const int32_t*,
+                                    const int16_t*, const float*, const float*, float*, float*, const Ctl*,
+                                    hipStream_t, hipEvent_t, hipEvent_t);
 
 void launch_residual(int lpr, int64_t n, const int32_t* rp, const int32_t* ci, const double* val, const double* x,
                      const double* b, double* r, hipStream_t st) {

@@ -27,6 +27,12 @@ template <typename T>
 void launch_spmv_bp(int E, int LPR, int remap, int64_t n, const int32_t* p, const int16_t* off, const T* val,
                     const T* win, T* vout, T* y, const Ctl* ctl, hipStream_t st, hipEvent_t ev0 = nullptr,
                     hipEvent_t ev1 = nullptr);
+// the same product with the offsets of row r read from dict + cstart[cls[r]] E (rows of equal
+// offsets share one list)
+template <typename T>
+void launch_spmv_bc(int E, int LPR, int remap, int64_t n, const int32_t* p, const uint16_t* cls,
+                    const int32_t* cstart, const int16_t* dict, const T* val, const T* win, T* vout, T* y,
+                    const Ctl* ctl, hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 
 void launch_validate(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* ci, int32_t* diag_pos,
                      int32_t* err, hipStream_t st);
