@@ -247,7 +247,7 @@ def run_solver(gasm, u0, systems, warmup, steps, tol, cfg, dev, profile=False, l
     return dict(elapsed=elapsed, lat=lat, its=its, cycles=cyc, k_eff=keff, rel=rel, prof=prof, xs=xs, shape=shape)
 
 
-TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_spmv_bp_f32-q3_512x512_recycled_mixed-hbm_traffic.md")
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_spmv_bc_f32-q3_512x512_recycled_mixed-hbm_traffic.md")
 TRAFFIC_SOURCES = ["paper_1807_09467_amd/csrc/spmv_banded.hpp", "paper_1807_09467_amd/csrc/spmv_classes.hpp",
                    "paper_1807_09467_amd/csrc/common.hpp"]
 

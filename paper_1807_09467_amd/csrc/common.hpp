@@ -14,7 +14,7 @@ constexpr int BLOCK = 256;       // threads per block of the streaming kernels
 constexpr int BP_MAX_OFFSET = 32767;   // largest |col - row| of the banded padded format
 constexpr int NBLK_MAX = 2048;   // largest grid of the split-n reductions
 constexpr int DCGS2_ZD_KMAX = 16;   // largest recycle dimension whose A W dots ride in the update
-constexpr bool CLS_ON = false;         // shared offset lists for the banded product
+constexpr bool CLS_ON = true;          // shared offset lists for the banded product
 constexpr int CLS_MAX = 4096;          // most offset classes of a banded copy
 constexpr int CLS_DICT_CHUNKS = 65536; // most chunks of their shared offset lists
 constexpr int TSQR_PANEL = 256;  // rows per Householder panel
