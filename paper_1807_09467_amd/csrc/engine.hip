@@ -171,6 +171,7 @@ struct rsolve_seq {
     int32_t* cls_start = nullptr;
     int16_t* cls_dict = nullptr;
     bool cls_ok = false;           // the classes describe the banded copy as laid out now
+    bool cls_allowed = true;       // build them at all (the serving loop turns this off)
     int ncls = 0;
     const int32_t* pat_rp = nullptr;
     const int32_t* pat_ci = nullptr;
@@ -375,7 +376,7 @@ struct SpOp {
 // exceed CLS_DICT_CHUNKS chunks: the product then reads the copy's own offsets.
 int cls_build(rsolve_seq* s, int E) {
     s->cls_ok = false;
-    if (!CLS_ON) return RSOLVE_OK;
+    if (!CLS_ON || !s->cls_allowed) return RSOLVE_OK;
     hipStream_t stm = s->stream;
     const int64_t n = s->n;
     std::vector<int32_t> hp((size_t)n + 1);
@@ -719,6 +720,11 @@ int check_solve_args(const rsolve_seq* s, const rsolve_csr* A, const double* b, 
 }  // namespace
 
 void rs::seq_set_stream(rsolve_seq* s, hipStream_t st) { s->stream = st; }
+
+void rs::seq_set_offset_classes(rsolve_seq* s, bool on) {
+    s->cls_allowed = on;
+    if (!on) s->cls_ok = false;
+}
 
 extern "C" {
 

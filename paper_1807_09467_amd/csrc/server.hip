@@ -325,6 +325,9 @@ int rsolve_server_open(rsolve_server* s, const rsolve_config* cfg, int64_t n, in
     rsolve_seq* h = nullptr;
     (void)hipSetDevice(s->device);
     const int rc = rsolve_create_sequence(&c, n, nnz_max, s->admin, base, bytes, &h);
+    // served sequences run tens of steps: the per-pattern build of shared offset lists (a read-back
+    // and a host pass over the rows) costs more than the few per cent it saves per product
+    if (rc == RSOLVE_OK) rs::seq_set_offset_classes(h, false);
     std::lock_guard<std::mutex> lk(s->mu);
     SeqRec& r = s->seqs[id];
     if (rc != RSOLVE_OK) {
