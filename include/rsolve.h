@@ -337,7 +337,10 @@ int rsolve_graph_counts(rsolve_seq* s, int64_t* captures, int64_t* launches);
                                   dealt round-robin over the row's lanes.  Needs |col - row| <=
                                   32767 for every entry; built once per pattern, values copied
                                   into it once per solve; (w + 2) bytes per entry instead of
-                                  (w + 4) (w = 4 in FP32_IR mode, else 8) */
+                                  (w + 4) (w = 4 in FP32_IR mode, else 8).  Rows whose offset
+                                  lists are equal (the node classes of a structured mesh) share
+                                  one list when the pattern has at most 4096 such classes: the
+                                  product then reads w bytes per entry and 2 per row */
 
 typedef struct {
     int32_t lanes_per_row;  /* lanes of a wavefront that share one row: 2, 4, 8, 16 or 32 for CSR;
