@@ -195,6 +195,15 @@ def krylov_update(x, dinv, V, y):
     return x + dinv * (V @ y)
 
 
+def is_lucky_breakdown(h_next: float, colnorm: float) -> bool:
+    """The Krylov space has become invariant: the new Hessenberg subdiagonal entry is zero up to
+    rounding, relative to the norm of its column (scale-free, so a matrix multiplied by any
+    constant breaks down at the same step).  The minimal-residual iterate over the current space
+    is then the exact solution of the projected system (section 3: the search space stops growing
+    once it contains the solution)."""
+    return h_next <= LUCKY_REL * colnorm
+
+
 def givens(a: float, b: float):
     """Rotation (c, s) with [c s; -s c] [a; b] = [rho; 0], rho = hypot(a, b)."""
     rho = float(np.hypot(a, b))
@@ -262,7 +271,7 @@ def arnoldi_cycle(op, r0: np.ndarray, m: int, stop_abs: float, max_steps: int) -
         g[j] = c * g[j]
         implicit.append(abs(g[j + 1]))
         steps = j + 1
-        if hcol[j + 1] <= LUCKY_REL * colnorm:
+        if is_lucky_breakdown(hcol[j + 1], colnorm):
             lucky = True
             j = steps
             break

@@ -298,6 +298,59 @@ def test_singular_E_drops_recycling():
     assert res.flags & O.FLAG_RECYCLE_DROPPED and res.k_eff == 0 and res.converged
 
 
+def invariant_krylov_system(n=60, d=3, seed=11, scale=1.0):
+    """A system whose Krylov space from b is a d-dimensional invariant subspace of A:
+    A = Pi diag(B, C) Pi^T (B d x d nonsymmetric, C a random shifted sparse block, Pi a random
+    permutation that scatters the subspace over the index range) and b = Pi [b1; 0].  The exact
+    solution is Pi [B^{-1} b1; 0], and K_j(A, b) stops growing at j = d.  Products with vectors
+    supported on the subspace are exact outside it, so the Hessenberg entry that signals the
+    breakdown is zero up to rounding of the subspace's own arithmetic."""
+    rng = np.random.default_rng(seed)
+    B = rng.standard_normal((d, d)) + 3.0 * np.eye(d)
+    C, _ = rand_system(n - d, seed + 1)
+    M = sp.block_diag([sp.csr_matrix(B), C]).tocsr()
+    perm = rng.permutation(n)
+    P = sp.csr_matrix((np.ones(n), (perm, np.arange(n))), shape=(n, n))
+    A = (scale * (P @ M @ P.T)).tocsr()
+    A.sort_indices()
+    b1 = rng.standard_normal(d)
+    b = P @ np.concatenate([b1, np.zeros(n - d)])
+    xs = P @ np.concatenate([np.linalg.solve(B, b1) / scale, np.zeros(n - d)])
+    return A, b, xs
+
+
+@pytest.mark.parametrize("scale", [1.0, 1e20, 1e-20])
+def test_lucky_breakdown_exit(scale):
+    """Krylov space invariant after d steps: the cycle ends at exactly step d with the lucky
+    flag (even with the residual stop switched off), at any scale of A, and the iterate is the
+    exact solution; a generic system never raises the flag."""
+    for d in (1, 3, 5):
+        A, b, xs = invariant_krylov_system(d=d, scale=scale)
+        cyc = O.arnoldi_cycle(lambda v: A @ v, b, 20, 0.0, 20)
+        assert cyc.lucky and cyc.steps == d, (d, cyc.lucky, cyc.steps)
+        y = scipy.linalg.solve_triangular(cyc.R[:d, :d], cyc.g[:d])
+        assert np.linalg.norm(cyc.V[:, :d] @ y - xs) <= 1e-12 * np.linalg.norm(xs)
+        res = O.solve(A, b, None, 1e-12, O.Config(restart_m=20, method=O.PLAIN))
+        assert res.flags & O.FLAG_BREAKDOWN_LUCKY and res.iterations == d and res.cycles == 1, (d, res.flags)
+        assert res.converged and np.linalg.norm(res.x - xs) <= 1e-12 * np.linalg.norm(xs)
+        # nearly invariant: b leaves the subspace by 1e-11 relative, so the subdiagonal entry at
+        # step d is small (about 1e-11 to 1e-9 of its column) but far above rounding: no
+        # breakdown, and the iteration goes on to the full solution
+        c = np.random.default_rng(5).standard_normal(b.size)
+        c[b != 0] = 0.0
+        b2 = b + 1e-11 * np.linalg.norm(b) * c / np.linalg.norm(c)
+        res = O.solve(A, b2, None, 1e-12, O.Config(restart_m=20, method=O.PLAIN))
+        assert res.converged and not res.flags & O.FLAG_BREAKDOWN_LUCKY and res.iterations > d, (d, res.flags)
+        x2 = np.linalg.solve(A.toarray(), b2)
+        assert np.linalg.norm(res.x - x2) <= 1e-10 * np.linalg.norm(x2)
+    # generic systems: restarted cycles, no invariant subspace reached, no flag
+    for seed in range(4):
+        A, b = rand_system(60, seed)
+        A = (scale * A).tocsr()
+        res = O.solve(A, b, None, 1e-10, O.Config(restart_m=10, method=O.PLAIN))
+        assert res.converged and not res.flags & O.FLAG_BREAKDOWN_LUCKY, seed
+
+
 def test_max_iters_not_converged():
     A, b, _ = c1_system()
     res = O.solve(A, b, None, 1e-12, O.Config(restart_m=30, method=O.PLAIN, max_iters=3))
@@ -645,6 +698,8 @@ def _pins_pass():
         test_projection_guess_then_plain_gmres()
         test_deflated_ls_is_minimal_residual_over_the_sum_space()
         test_augmented_ls_minimises_from_the_unprojected_residual()
+        test_lucky_breakdown_exit(1e20)
+        test_lucky_breakdown_exit(1e-20)
     except AssertionError:
         return False
     return True
@@ -660,9 +715,16 @@ def test_pins_pass_on_unmodified_oracle():
                                       "extrap_weights_reversed", "extrap_off_by_one",
                                       "guess_only_projects_krylov", "ls_projector_missing",
                                       "ls_correction_galerkin", "ls_coefficients_unnormalised",
-                                      "ls_deflated_start_unprojected"])
+                                      "ls_deflated_start_unprojected", "lucky_never", "lucky_absolute",
+                                      "lucky_loose"])
 def test_planted_mistakes_are_caught(monkeypatch, mutation):
-    if mutation == "extrap_weights_reversed":
+    if mutation == "lucky_never":
+        monkeypatch.setattr(O, "is_lucky_breakdown", lambda h, c: False)
+    elif mutation == "lucky_absolute":
+        monkeypatch.setattr(O, "is_lucky_breakdown", lambda h, c: h <= O.LUCKY_REL)
+    elif mutation == "lucky_loose":
+        monkeypatch.setattr(O, "is_lucky_breakdown", lambda h, c: h <= 1e-10 * c)
+    elif mutation == "extrap_weights_reversed":
         orig_w = O.extrapolation_weights
         monkeypatch.setattr(O, "extrapolation_weights", lambda q: orig_w(q)[::-1])
     elif mutation == "extrap_off_by_one":
