@@ -1,0 +1,118 @@
+"""GPU parity on the method's degenerate cases, against the FP64 oracle on the same inputs.
+
+* Lucky breakdown: b lies in a d-dimensional invariant subspace of A, so the Krylov space stops
+  growing after d steps; every Arnoldi path (classical Gram-Schmidt twice, its delayed form, the
+  one-block batched path) must end the cycle at step d with the breakdown flag, as the oracle
+  does, and return the exact solution.
+* Singular E = W^T A W (section 5.2 notes that E may be singular; the reading drops the recycle
+  space for that solve when cond_1(E) > 1e13 or the factorisation fails): the ring holds unit
+  vectors e_0..e_{k-1} and the leading k x k block of A is zero, so E = 0; the solve must run as
+  plain GMRES with the dropped-recycling flag, on the multi-kernel and the one-block path, and
+  match the oracle.
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from oracle import rgmres as O
+
+from test_oracle_pins import invariant_krylov_system, rand_system
+
+pytestmark = pytest.mark.gpu
+
+
+def _t(a, dev):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+
+def _csr_parts(A, dev):
+    A = A.tocsr()
+    A.sort_indices()
+    return _t(A.indptr.astype(np.int32), dev), _t(A.indices.astype(np.int32), dev), _t(A.data, dev)
+
+
+@pytest.mark.parametrize("path", ["cgs2", "dcgs2", "one_block"])
+@pytest.mark.parametrize("d", [1, 3, 5])
+def test_lucky_breakdown_matches_oracle(gpu_ctx, path, d):
+    from paper_1807_09467_amd import rsolve
+    A, b, xs = invariant_krylov_system(n=200, d=d)
+    print(f"[edges] lucky path={path} d={d} n=200 nnz={A.nnz}", flush=True)
+    ores = O.solve(A, b, None, 1e-12, O.Config(restart_m=20, method=O.PLAIN))
+    assert ores.flags & O.FLAG_BREAKDOWN_LUCKY and ores.iterations == d
+    rp, ci, v = _csr_parts(A, gpu_ctx)
+    seq = rsolve.Sequence(200, A.nnz, device=gpu_ctx, restart_m=20, method="plain",
+                          ortho="dcgs2" if path == "dcgs2" else "cgs2")
+    if path == "one_block":
+        (x, st, status), = rsolve.solve_batch([dict(seq=seq, row_ptr=rp, col_idx=ci, val=v, b=_t(b, gpu_ctx),
+                                                    tol=1e-12)])
+    else:
+        x, st, status = seq.solve(rp, ci, v, _t(b, gpu_ctx), tol=1e-12)
+    seq.close()
+    assert status == 0 and st["converged"] == 1
+    assert st["flags"] & rsolve.FLAG_BREAKDOWN_LUCKY, st["flags"]
+    assert st["iterations"] == ores.iterations == d and st["cycles"] == ores.cycles == 1
+    xg = x.cpu().numpy()
+    assert np.linalg.norm(xg - ores.x) <= 1e-12 * np.linalg.norm(ores.x)
+    assert np.abs(xg - xs).max() <= 1e-12 * np.abs(xs).max()
+
+
+def _zero_leading_block(n, k, seed):
+    """A nonsingular sparse A with an explicitly stored, zero-valued leading k x k block (diagonal
+    entries kept in the pattern, as the CSR convention asks)."""
+    A, b = rand_system(n, seed, density=12.0 / n, shift=8.0)   # about 12 random entries a row around 8 I
+    A = A.tolil()
+    for i in range(k):
+        for j in range(k):
+            if A[i, j] != 0 or i == j:
+                A[i, j] = 1.0          # make the entry structural, then zero its value
+    A = A.tocsr()
+    A.sort_indices()
+    for i in range(k):
+        for p in range(A.indptr[i], A.indptr[i + 1]):
+            if A.indices[p] < k:
+                A.data[p] = 0.0
+    assert np.linalg.matrix_rank(A.toarray()) == n
+    return A, b
+
+
+@pytest.mark.parametrize("path", ["multi_kernel", "one_block"])
+@pytest.mark.parametrize("k", [1, 2])
+def test_singular_E_drops_recycle_space(gpu_ctx, path, k):
+    import torch
+    from paper_1807_09467_amd import rsolve
+    n = 300
+    A, b = _zero_leading_block(n, k, seed=7 + k)
+    print(f"[edges] singular E path={path} k={k} n={n} nnz={A.nnz}", flush=True)
+    ocfg = O.Config(restart_m=30, recycle_k=k, snapshots_s=k)
+    ost = O.RecycleState(n, ocfg)
+    seq = rsolve.Sequence(n, A.nnz, device=gpu_ctx, restart_m=30, recycle_k=k, snapshots_s=k)
+    for i in range(k):
+        e = np.zeros(n)
+        e[i] = 1.0
+        ost.update(e)
+        et = _t(e, gpu_ctx)
+        if path == "one_block":
+            assert rsolve.update_batch([seq], [et])[0] == 0
+        else:
+            seq.update(et)
+    assert ost.W.shape[1] == k and np.abs(ost.W.T @ (A @ ost.W)).max() == 0.0
+    assert seq.recycle()["k_eff"] == k
+    ores = O.solve(A, b, None, 1e-10, ocfg, ost.W)
+    assert ores.flags & O.FLAG_RECYCLE_DROPPED and ores.k_eff == 0 and ores.converged
+    rp, ci, v = _csr_parts(A, gpu_ctx)
+    if path == "one_block":
+        (x, st, status), = rsolve.solve_batch([dict(seq=seq, row_ptr=rp, col_idx=ci, val=v, b=_t(b, gpu_ctx),
+                                                    tol=1e-10)])
+    else:
+        x, st, status = seq.solve(rp, ci, v, _t(b, gpu_ctx), tol=1e-10)
+    torch.cuda.synchronize()
+    seq.close()
+    assert status == 0 and st["converged"] == 1
+    assert st["flags"] & rsolve.FLAG_RECYCLE_DROPPED and st["k_eff"] == 0, (st["flags"], st["k_eff"])
+    assert abs(st["iterations"] - ores.iterations) <= 2, (st["iterations"], ores.iterations)
+    xg = x.cpu().numpy()
+    rel = np.linalg.norm(xg - ores.x) / np.linalg.norm(ores.x)
+    print(f"[edges] rel={rel:.2e} its gpu={st['iterations']} oracle={ores.iterations}", flush=True)
+    assert rel <= 1e-9
+    assert np.linalg.norm(b - A @ xg) <= 1e-10 * np.linalg.norm(b) * (1 + 1e-6)

@@ -21,19 +21,23 @@ def _specs():
             SeqSpec(4, 0.008, 1, 64, 5e-3, 6, 15), SeqSpec(5, 0.010, 2, 32, 1e-3, 5, 16)]
 
 
-def test_serving_alone_equals_mixed_bitwise(gpu_ctx):
+@pytest.mark.parametrize("precision", ["fp64", "fp32_ir"])
+def test_serving_alone_equals_mixed_bitwise(gpu_ctx, precision):
+    """precision fp32_ir: the large sequences run FP32 Arnoldi cycles inside FP64 refinement (as
+    in the serving replay), the batched small ones stay FP64."""
     import torch
     from paper_1807_09467_amd import serve
     specs = _specs()
     cache = serve.AssemblerCache(gpu_ctx)
     keep = {s.idx for s in specs}
-    _, summ, mixed = serve.run_serving(specs, CFG, 1e-8, gpu_ctx, 4 << 30, large_workers=2, cache=cache,
+    cfg = dict(CFG, precision=precision, inner_tol=1e-4) if precision == "fp32_ir" else CFG
+    _, summ, mixed = serve.run_serving(specs, cfg, 1e-8, gpu_ctx, 4 << 30, large_workers=2, cache=cache,
                                        keep_solutions=keep)
     assert summ["all_converged"] and summ["solves"] == sum(s.steps for s in specs)
     assert 0.0 < summ["batched_fraction"] < 1.0
     for sp in specs:
         alone_spec = serve.SeqSpec(sp.idx, 0.0, sp.p, sp.N, sp.eps, sp.steps, sp.seed)
-        _, _, alone = serve.run_serving([alone_spec], CFG, 1e-8, gpu_ctx, 4 << 30, large_workers=2, cache=cache,
+        _, _, alone = serve.run_serving([alone_spec], cfg, 1e-8, gpu_ctx, 4 << 30, large_workers=2, cache=cache,
                                         keep_solutions={sp.idx})
         assert len(alone[sp.idx]) == sp.steps
         for i, (xa, xm) in enumerate(zip(alone[sp.idx], mixed[sp.idx])):
