@@ -38,6 +38,23 @@ int rsolve_gram_tn(int64_t n, const double* A, int64_t lda, int32_t p,
                    void* workspace, size_t ws_bytes, void* hip_stream);
 
 /*
+ * rsolve_gram_tn without a workspace argument, for callers that cannot allocate device memory
+ * (code under stream capture, tight serving loops, harnesses that forbid allocation).  Same
+ * arguments, result and kernels as rsolve_gram_tn; the split-n partial sums and the reduced
+ * p x q result live in a static array of RSOLVE_GRAM_NOALLOC_SCRATCH_BYTES inside the library,
+ * one per GPU, held from the first call on that GPU until the process ends.  Nothing in it must
+ * start at zero (every launch writes each slot it reads).  Calls on one GPU share that array:
+ * calls that overlap on one GPU (from several threads, or on several streams without ordering)
+ * race and give wrong results; calls on different GPUs do not interact.  Allocates nothing (no
+ * hipMalloc, no library allocator).  Synchronous.  Errors: E_INVALID (null pointer, n < 1,
+ * lda or ldb < n, p or q outside 1..RSOLVE_GRAM_NOALLOC_MAX_COLS), E_DEVICE.
+ */
+#define RSOLVE_GRAM_NOALLOC_MAX_COLS     64
+#define RSOLVE_GRAM_NOALLOC_SCRATCH_BYTES ((size_t)(256 * 64 * 64 + 64 * 64) * 8)   /* 8,421,376 */
+int rsolve_gram_tn_noalloc(int64_t n, const double* A, int64_t lda, int32_t p, const double* B, int64_t ldb,
+                           int32_t q, double* C_host, void* hip_stream);
+
+/*
  * The SVD step of Algorithm 1 (section 5.2) on an arbitrary snapshot matrix
  * X (n x c, c <= 64): R from a Householder TSQR of X, one-sided Jacobi SVD of
  * R, then W = X V_k Sigma_k^{-1} re-orthonormalised, with

@@ -17,6 +17,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <unordered_map>
 #include <tuple>
 #include <vector>
@@ -1625,6 +1626,78 @@ int rsolve_gram_tn(int64_t n, const double* A, int64_t lda, int32_t p, const dou
     launch_gram_reduce(w.gpart, gblk, p * q, ctl_red(w.ctl), st);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipMemcpyAsync(C_host, ctl_red(w.ctl), sizeof(double) * p * q, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return RSOLVE_OK;
+}
+
+}  // extern "C"
+
+// ---- the Gram product without a workspace argument ----
+namespace {
+// split-n partial sums (as many as the Gram kernel may write for any p, q <= 64), then the
+// reduced p x q result
+constexpr size_t NOALLOC_PARTIAL = (size_t)GRAM_PARTIAL;
+constexpr size_t NOALLOC_RESULT = (size_t)RSOLVE_GRAM_NOALLOC_MAX_COLS * RSOLVE_GRAM_NOALLOC_MAX_COLS;
+static_assert((NOALLOC_PARTIAL + NOALLOC_RESULT) * sizeof(double) == RSOLVE_GRAM_NOALLOC_SCRATCH_BYTES,
+              "scratch size stated in the header");
+static_assert(RSOLVE_GRAM_NOALLOC_MAX_COLS <= KMAX, "the Gram kernel's column limit");
+
+// One copy per GPU, placed by the loader.  In host code this name stands for the symbol only:
+// kernels and copies get the device address taken below.
+static __device__ __align__(256) double scratch[NOALLOC_PARTIAL + NOALLOC_RESULT];
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+
+// Device address of the current GPU's copy of `scratch`, looked up once per device (with that
+// device current) and kept.
+int scratch_address(double** out) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) {
+        set_err("device %d beyond the %d devices the static scratch table covers", dev, NOALLOC_MAX_DEVICES);
+        return RSOLVE_E_INVALID;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) {
+            set_err("hipGetSymbolAddress returned no address for the static scratch");
+            return RSOLVE_E_DEVICE;
+        }
+        g_scratch_ptr[dev] = static_cast<double*>(ptr);
+    }
+    *out = g_scratch_ptr[dev];
+    return RSOLVE_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int rsolve_gram_tn_noalloc(int64_t n, const double* A, int64_t lda, int32_t p, const double* B, int64_t ldb,
+                           int32_t q, double* C_host, void* hip_stream) {
+    g_err[0] = 0;
+    if (n < 1 || !A || !B || !C_host || lda < n || ldb < n) {
+        set_err("null pointer, n < 1 or leading dimension below n");
+        return RSOLVE_E_INVALID;
+    }
+    if (p < 1 || q < 1 || p > RSOLVE_GRAM_NOALLOC_MAX_COLS || q > RSOLVE_GRAM_NOALLOC_MAX_COLS) {
+        set_err("p = %d, q = %d: the static scratch holds products of at most %d x %d", p, q,
+                RSOLVE_GRAM_NOALLOC_MAX_COLS, RSOLVE_GRAM_NOALLOC_MAX_COLS);
+        return RSOLVE_E_INVALID;
+    }
+    double* base = nullptr;
+    const int rc = scratch_address(&base);
+    if (rc) return rc;
+    double* partial = base;
+    double* result = base + NOALLOC_PARTIAL;
+    hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+    const int gblk = launch_gram_tn(n, A, lda, p, B, ldb, q, partial, pick_gblk(n), st);
+    launch_gram_reduce(partial, gblk, p * q, result, st);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(C_host, result, sizeof(double) * p * q, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     return RSOLVE_OK;
 }

@@ -43,7 +43,7 @@ EXPORTS = [
     "rsolve_spmv", "rsolve_kernel_workspace_bytes", "rsolve_gram_tn", "rsolve_snapshot_svd",
     "rsolve_profile_enable", "rsolve_profile_read", "rsolve_solve_batch", "rsolve_update_recycle_batch",
     "rsolve_tune_spmv", "rsolve_set_spmv_shape", "rsolve_get_spmv_shape", "rsolve_enable_graphs",
-    "rsolve_graph_counts",
+    "rsolve_graph_counts", "rsolve_gram_tn_noalloc",
     # serving loop (rsolve_server.h; bound in serve.py)
     "rsolve_server_create", "rsolve_server_open", "rsolve_server_submit", "rsolve_server_poll",
     "rsolve_server_close", "rsolve_server_info_get", "rsolve_server_destroy",
@@ -148,6 +148,9 @@ def load():
     lib.rsolve_gram_tn.argtypes = [c_int64, c_void_p, c_int64, c_int32, c_void_p, c_int64, c_int32,
                                    POINTER(c_double), c_void_p, c_size_t, c_void_p]
     lib.rsolve_gram_tn.restype = c_int
+    lib.rsolve_gram_tn_noalloc.argtypes = [c_int64, c_void_p, c_int64, c_int32, c_void_p, c_int64, c_int32,
+                                           POINTER(c_double), c_void_p]
+    lib.rsolve_gram_tn_noalloc.restype = c_int
     lib.rsolve_snapshot_svd.argtypes = [c_int64, c_void_p, c_int64, c_int32, c_int32, c_void_p, c_int64,
                                         POINTER(c_double), POINTER(c_int32), POINTER(c_int32), c_void_p, c_size_t,
                                         c_void_p]
@@ -542,6 +545,29 @@ def gram_tn(A, B, stream=None):
     _check(lib.rsolve_gram_tn(n, c_void_p(A.data_ptr()), n, p, c_void_p(B.data_ptr()), n, q, C,
                               c_void_p(ws.data_ptr()), nbytes, _stream_handle(stream)))
     return np.frombuffer(C, dtype=np.float64).reshape(q, p).T.copy()
+
+
+def last_error():
+    """The library's description of the last error seen by this thread ("" if none)."""
+    return load().rsolve_last_error().decode()
+
+
+def gram_tn_noalloc(A, B, stream=None, check=True):
+    """gram_tn through rsolve_gram_tn_noalloc (no workspace: the library's static scratch).
+    Returns (C, status); C is None when the call failed."""
+    import numpy as np
+    lib = load()
+    p, n = A.shape
+    q, n2 = B.shape
+    assert n == n2
+    C = (c_double * max(p * q, 1))()
+    status = lib.rsolve_gram_tn_noalloc(n, c_void_p(A.data_ptr()), n, p, c_void_p(B.data_ptr()), n, q, C,
+                                        _stream_handle(stream))
+    if check:
+        _check(status)
+    if status != OK:
+        return None, status
+    return np.frombuffer(C, dtype=np.float64)[: p * q].reshape(q, p).T.copy(), status
 
 
 def snapshot_svd(X, k, stream=None):
