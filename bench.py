@@ -10,7 +10,11 @@ runs the recycled mixed-precision solver (float32 Arnoldi cycles inside
 float64 iterative refinement, GMRES(50), k = 16, s = 32, ell = 1, right
 Jacobi) to 1e-8 relative residual on the `steps` systems, one solve plus one
 recycle update per step.  Plain FP64 GMRES(50) with right Jacobi runs on the
-same systems as the comparison.  Prints one JSON line.
+same systems as the comparison, and two attribution legs (plain GMRES in the same
+mixed precision; the recycled method in FP64) split the speed-up between recycling
+and FP32.  The update (Algorithm 1) is timed on its own, per-kernel-class rooflines
+come from sampled HIP-event stamps, and the oracle's first time steps give the
+CPU baseline and the per-solve difference from the oracle.  Prints one JSON line.
 
 python bench.py [--steps K] [--warmup W] [--workload c4|c3|c2|c1] [--gpus 1]
 """
@@ -197,9 +201,35 @@ def bench_paper_table(args, dev):
     print(json.dumps(out), flush=True)
 
 
+class Roctx:
+    """roctx range around the timed region (a no-op unless a profiler records marker traces)."""
+
+    def __init__(self, on):
+        self.lib = None
+        if on:
+            import ctypes
+            for name in ("librocprofiler-sdk-roctx.so.1", "librocprofiler-sdk-roctx.so", "libroctx64.so"):
+                try:
+                    self.lib = ctypes.CDLL(name)
+                    break
+                except OSError:
+                    continue
+            if self.lib is None:
+                log("roctx library not found: no marker range")
+
+    def push(self, name):
+        if self.lib is not None:
+            self.lib.roctxRangePushA(name.encode())
+
+    def pop(self):
+        if self.lib is not None:
+            self.lib.roctxRangePop()
+
+
 def run_solver(gasm, u0, systems, warmup, steps, tol, cfg, dev, profile=False, label="", graphs=False,
-               profile_kinds=None, quiet=False):
-    """One pass over the sequence: warmup untimed solves, then `steps` timed solve+update steps."""
+               profile_kinds=None, quiet=False, roctx=None, profile_stride=4):
+    """One pass over the sequence: warmup untimed solves, then `steps` timed solve+update steps.
+    The recycle update (Algorithm 1) is synchronous, so the host clock around it is its duration."""
     import torch
 
     from paper_1807_09467_amd import rsolve
@@ -212,24 +242,28 @@ def run_solver(gasm, u0, systems, warmup, steps, tol, cfg, dev, profile=False, l
         f"remap {shape['xcd_remap']}: {shape['us']:.1f} us (default {shape['default_us']:.1f} us)")
     seq.graphs(graphs)
     x_prev = u0
-    lat, its, cyc, keff, rel = [], [], [], [], []
+    lat, its, cyc, keff, rel, upd = [], [], [], [], [], []
     xs = []
     t_start = None
     for i, (vals, b) in enumerate(systems[: warmup + steps]):
         if i == warmup:
             torch.cuda.synchronize()
             if profile:
-                # every fourth step: the events' own queue work stays off most steps, and the
-                # product's duration does not depend on the step
-                seq.profile(True, kinds=profile_kinds, stride=4)
+                # every fourth step by default: the events' own queue work stays off most steps, and
+                # the sampled steps cover every stage of a cycle
+                seq.profile(True, kinds=profile_kinds, stride=profile_stride)
+            if roctx is not None:
+                roctx.push(f"timed {label}")
             t_start = time.perf_counter()
         t0 = time.perf_counter()
         x, st, status = seq.solve(gasm.row_ptr, gasm.col_idx, vals, b, x0=x_prev, tol=tol, same_pattern=i > 0)
         if status != 0:
             raise RuntimeError(f"{label}: solve {i} returned {status}")
+        tu = time.perf_counter()
         seq.update()
         t1 = time.perf_counter()
         if i >= warmup:
+            upd.append((t1 - tu) * 1e3)
             lat.append((t1 - t0) * 1e3)
             its.append(st["iterations"])
             cyc.append(st["cycles"])
@@ -242,30 +276,44 @@ def run_solver(gasm, u0, systems, warmup, steps, tol, cfg, dev, profile=False, l
                 f"k_eff {st['k_eff']}, {1e3 * (t1 - t0):.2f} ms")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
+    if roctx is not None:
+        roctx.pop()
     prof = seq.profile_read() if profile else []
     seq.close()
-    return dict(elapsed=elapsed, lat=lat, its=its, cycles=cyc, k_eff=keff, rel=rel, prof=prof, xs=xs, shape=shape)
+    return dict(elapsed=elapsed, lat=lat, its=its, cycles=cyc, k_eff=keff, rel=rel, upd=upd, prof=prof, xs=xs,
+                shape=shape)
 
 
-TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_spmv_bc_f32-q3_512x512_recycled_mixed-hbm_traffic.md")
-TRAFFIC_SOURCES = ["paper_1807_09467_amd/csrc/spmv_banded.hpp", "paper_1807_09467_amd/csrc/spmv_classes.hpp",
-                   "paper_1807_09467_amd/csrc/common.hpp"]
+# rocprofv3 counter summaries of the headline run's kernels: kernel class -> (summary, the sources the
+# kernel is built from); a summary's figure counts only while those sources are unchanged
+TRAFFIC = {
+    "spmv_arnoldi": ("k_spmv_bc_f32-q3_512x512_recycled_mixed-hbm_traffic.md",
+                     ["paper_1807_09467_amd/csrc/spmv_banded.hpp", "paper_1807_09467_amd/csrc/spmv_classes.hpp",
+                      "paper_1807_09467_amd/csrc/common.hpp"]),
+    "dots2": ("k_dots2_f32-q3_512x512_recycled_mixed-hbm_traffic.md",
+              ["paper_1807_09467_amd/csrc/k_krylov.hip", "paper_1807_09467_amd/csrc/common.hpp"]),
+    "dcgs2_update": ("k_dcgs2_update_f32-q3_512x512_recycled_mixed-hbm_traffic.md",
+                     ["paper_1807_09467_amd/csrc/k_krylov.hip", "paper_1807_09467_amd/csrc/common.hpp"]),
+}
 
 
 def measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary, or None when
+    """HBM bytes per launch of `kernel` from its committed rocprofv3 counter summary, or None when
     there is none or the kernel's sources have changed since the counters were taken."""
     import hashlib
     import re
+    if kernel not in TRAFFIC:
+        return None
+    summary, sources = TRAFFIC[kernel]
     try:
-        text = open(TRAFFIC_SUMMARY).read()
+        text = open(os.path.join(ROOT, "profiles", summary)).read()
     except OSError:
         return None
     m = re.search(r"^traffic_bytes_per_launch=(\d+) kernel=(\S+) sources_sha256=([0-9a-f]{64})$", text, re.M)
     if not m or m.group(2) != kernel:
         return None
     h = hashlib.sha256()
-    for f in TRAFFIC_SOURCES:
+    for f in sources:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return float(m.group(1)) if h.hexdigest() == m.group(3) else None
@@ -497,7 +545,7 @@ def cpu_baseline_small(prob, asm_host, cfg, tol):
 
 def summarize(r, steps):
     lat = np.array(r["lat"])
-    return {
+    out = {
         "solves_per_s": steps / r["elapsed"],
         "ms_per_solve": 1e3 * r["elapsed"] / steps,
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
@@ -505,6 +553,11 @@ def summarize(r, steps):
         "avg_cycles": float(np.mean(r["cycles"])),
         "max_rel_residual": float(np.max(r["rel"])),
     }
+    if r.get("upd"):
+        # Algorithm 1 (ring push, TSQR, SVD, new W) against the whole solve + update step
+        out["update_ms"] = float(np.mean(r["upd"]))
+        out["update_share"] = float(np.sum(r["upd"]) / np.sum(r["lat"]))
+    return out
 
 
 def bench_guess_table(args, gasm, u0, systems, tol, cfg, desc, dev):
@@ -538,10 +591,11 @@ def bench_guess_table(args, gasm, u0, systems, tol, cfg, desc, dev):
     print(json.dumps(out), flush=True)
 
 
-def cpu_baseline(prob, asm_host, tol, cfg, steps=2):
-    """The oracle on the host cores: its own recycled FP64 solves of the first `steps` time steps of the
+def cpu_baseline(prob, asm_host, tol, cfg, steps=3):
+    """The oracle on the host cores: its own recycled solves of the first `steps` time steps of the
     same sequence (same restart, recycle dimension, snapshots, Jacobi and tolerance; Algorithm 1 update
-    after each), each system assembled from the oracle's previous solution (assembly not timed)."""
+    after each), each system assembled from the oracle's previous solution (assembly not timed).
+    Returns the baseline entry and the steps' systems, starting guesses and oracle solutions."""
     from threadpoolctl import threadpool_info
 
     from oracle import rgmres as O
@@ -553,7 +607,7 @@ def cpu_baseline(prob, asm_host, tol, cfg, steps=2):
     state = O.RecycleState(asm_host.pat.n, ocfg)
     threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
     u = WL.initial_condition(prob, 0)
-    dt, its, keff = 0.0, [], []
+    dt, its, keff, records = 0.0, [], [], []
     for _ in range(steps):
         vals, b = asm_host.system(u)
         A = asm_host.csr(vals)
@@ -563,13 +617,44 @@ def cpu_baseline(prob, asm_host, tol, cfg, steps=2):
         dt += time.perf_counter() - t0
         its.append(res.iterations)
         keff.append(res.k_eff)
+        records.append((vals, b, u, res.x))
         u = res.x
         log(f"oracle step {len(its)}/{steps}: {res.iterations} its, k_eff {res.k_eff}, {dt:.1f} s so far")
-    return {"value": steps / dt, "unit": "solves/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"the oracle's own recycled FP64 solves of time steps 1-{steps} of the same sequence "
-                      f"(GMRES({cfg['restart_m']}), k={cfg.get('recycle_k', 0)}, s={cfg.get('snapshots_s', 0)}, right "
-                      f"Jacobi, tol {tol:g}, Algorithm 1 update after each; {its} its, k_eff {keff}, {dt:.1f} s); "
-                      f"scipy CSR matvec on 1 thread, OpenBLAS on {threads}"}
+    entry = {"value": steps / dt, "unit": "solves/s", "cores": int(threads), "kind": "oracle",
+             "sample": f"the oracle's own recycled FP64 solves of time steps 1-{steps} of the same sequence "
+                       f"(GMRES({cfg['restart_m']}), k={cfg.get('recycle_k', 0)}, s={cfg.get('snapshots_s', 0)}, "
+                       f"right Jacobi, tol {tol:g}, Algorithm 1 update after each; {its} its, k_eff {keff}, "
+                       f"{dt:.1f} s); scipy CSR matvec on 1 thread, OpenBLAS on {threads}"}
+    return entry, records
+
+
+def gpu_vs_oracle(records, asm_host, tol, cfg, shape, dev):
+    """The timed configuration (same solver settings and SpMV shape) on the oracle's own systems, each
+    started from the oracle's previous solution: per-solve difference from the oracle's solution
+    (relative 2-norm and largest entry), both solved to the same tolerance."""
+    import torch
+
+    from paper_1807_09467_amd import rsolve
+    pat = asm_host.pat
+    rp = torch.from_numpy(pat.row_ptr).to(dev)
+    ci = torch.from_numpy(pat.col_idx).to(dev)
+    seq = rsolve.Sequence(pat.n, pat.nnz, device=dev, **cfg)
+    seq.set_spmv_shape(shape["lanes_per_row"], shape["vec"], shape["xcd_remap"], shape["format"])
+    rel, ent = [], []
+    for i, (vals, b, u, xo) in enumerate(records):
+        x, st, status = seq.solve(rp, ci, torch.from_numpy(vals).to(dev), torch.from_numpy(b).to(dev),
+                                  x0=torch.from_numpy(u).to(dev), tol=tol, same_pattern=i > 0)
+        if status != 0:
+            raise RuntimeError(f"solve of the oracle's step {i + 1} returned {status}")
+        seq.update()
+        xg = x.cpu().numpy()
+        rel.append(float(np.linalg.norm(xg - xo) / np.linalg.norm(xo)))
+        ent.append(float(np.abs(xg - xo).max() / np.abs(xo).max()))
+    seq.close()
+    return {"steps": list(range(1, len(records) + 1)), "rel": rel, "max_entry_rel": ent, "tol": tol,
+            "note": "the timed configuration on the oracle's systems (time steps assembled from the oracle's "
+                    "solutions), started from the oracle's previous solution; both stop at the same relative "
+                    "residual, so they may differ by up to cond(A) tol"}
 
 
 def main():
@@ -605,9 +690,16 @@ def main():
                          "Gram-Schmidt twice, or the same with the second pass delayed into the next step")
     ap.add_argument("--graphs", action="store_true",
                     help="replay the Arnoldi steps as captured hipGraphs (needs --no-profile to take effect)")
-    ap.add_argument("--profile-kinds", default="spmv_arnoldi",
-                    help="kernel kinds timed with HIP events in the timed run: comma list of spmv_arnoldi, dots, "
-                         "update_dots, update_norm, or 'all' (each timed kind is slowed by its event stamps)")
+    ap.add_argument("--profile-kinds", default="all",
+                    help="kernel kinds timed with HIP events (every fourth Arnoldi step) in the timed run: comma "
+                         "list of spmv_arnoldi, dots, update_dots, update_norm, or 'all'")
+    ap.add_argument("--profile-stride", type=int, default=4,
+                    help="time every s-th Arnoldi step of a cycle (1 = all, for counter runs)")
+    ap.add_argument("--no-legs", action="store_true",
+                    help="skip the attribution legs (plain GMRES in mixed precision, recycled FP64)")
+    ap.add_argument("--roctx", action="store_true",
+                    help="mark each timed region with a roctx range (for rocprofv3 --marker-trace)")
+    ap.add_argument("--oracle-steps", type=int, default=3, help="time steps the oracle solves for the CPU baseline")
     ap.add_argument("--no-profile", action="store_true",
                     help="run the timed solves without per-kernel event timing (roofline then null)")
     ap.add_argument("--calib-copy", action="store_true",
@@ -659,57 +751,83 @@ def main():
     if args.guess_table:
         return bench_guess_table(args, gasm, u0, systems, tol, cfg, desc, dev)
     kinds = None if args.profile_kinds == "all" else [k for k in args.profile_kinds.split(",") if k]
+    roctx = Roctx(args.roctx)
     main_run = run_solver(gasm, u0, systems, args.warmup, args.steps, tol, cfg, dev, profile=not args.no_profile,
-                          label="recycled", graphs=args.graphs, profile_kinds=kinds)
+                          label="recycled", graphs=args.graphs, profile_kinds=kinds, roctx=roctx,
+                          profile_stride=args.profile_stride)
     main_sum = summarize(main_run, args.steps)
+
+    def leg(over, label):
+        c = dict(cfg)
+        c.update(over)
+        r = run_solver(gasm, u0, systems, args.warmup, args.steps, tol, c, dev, label=label, graphs=args.graphs,
+                       roctx=roctx)
+        sm = summarize(r, args.steps)
+        sm["max_rel_diff_vs_recycled"] = max(float(torch.linalg.norm(a - b) / torch.linalg.norm(b))
+                                             for a, b in zip(main_run["xs"][args.warmup:], r["xs"][args.warmup:]))
+        return sm
+
     plain_sum = None
     if not args.no_plain:
-        pcfg = dict(restart_m=cfg["restart_m"], precond=cfg["precond"], method="plain", precision="fp64",
-                    ortho=args.ortho)
-        plain_run = run_solver(gasm, u0, systems, args.warmup, args.steps, tol, pcfg, dev, label="plain-fp64",
-                               graphs=args.graphs)
-        plain_sum = summarize(plain_run, args.steps)
         # the same systems, solved twice: both answers meet the tolerance, so they agree to kappa * tol
-        diffs = [float(torch.linalg.norm(a - b) / torch.linalg.norm(b))
-                 for a, b in zip(main_run["xs"][args.warmup:], plain_run["xs"][args.warmup:])]
-        plain_sum["max_rel_diff_vs_recycled"] = max(diffs)
-        del plain_run
+        plain_sum = leg(dict(method="plain", recycle_k=0, snapshots_s=0, precision="fp64"), "plain-fp64")
+    legs = {}
+    if not args.no_legs and args.workload == "c4":
+        # attribution: recycling without FP32 and FP32 without recycling, on the same systems
+        legs["plain_mixed"] = leg(dict(method="plain", recycle_k=0, snapshots_s=0), "plain-mixed")
+        legs["recycled_fp64"] = leg(dict(precision="fp64"), "recycled-fp64")
 
-    # roofline of the dominant kernel (HIP events around each launch inside the library)
+    # roofline per kernel class (HIP events around sampled launches inside the library); the dominant
+    # class is the one with the most time
     prof = main_run["prof"]
+    wsz = 4.0 if cfg.get("precision") == "fp32_ir" else 8.0
+    classes = {}
+    for e in prof:
+        c = classes.setdefault(e["kernel"], {"kernel": e["kernel"], "launches": 0, "ms": 0.0, "bytes": 0.0})
+        c["launches"] += e["launches"]
+        c["ms"] += e["ms"]
+        c["bytes"] += e["bytes"]
+    rooflines = []
+    for c in classes.values():
+        avg_us = 1e3 * c["ms"] / c["launches"]
+        alg = c["bytes"] / c["launches"]
+        achieved = alg / (avg_us * 1e-6) / 1e9
+        r = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": c["kernel"],
+             "algorithmic_bytes_per_launch": round(alg), "avg_launch_us": round(avg_us, 2),
+             "launches": c["launches"], "ms_sampled": round(c["ms"], 3)}
+        if c["kernel"] == "spmv_arnoldi":
+            # the storage format's bytes (values, chunk offsets, class numbers, x read, y written); the
+            # CSR figure (w + 4) nnz + 4 (n + 1) + 2 w n of the same product is reported beside it
+            nn, nz = float(asm.pat.n), float(asm.pat.nnz)
+            csr = (wsz + 4.0) * nz + 4.0 * (nn + 1.0) + 2.0 * wsz * nn
+            r["algorithmic_bytes"] = "w nnz + 4 (n + 1) + 2 n + 2 w n (banded copy with class offset lists)"
+            r["csr_equivalent_bytes_per_launch"] = round(csr)
+            r["csr_equivalent_gbs"] = round(csr / (avg_us * 1e-6) / 1e9, 1)
+        elif c["kernel"] in ("dots2", "dots"):
+            r["algorithmic_bytes"] = "(columns swept + 1) w n per launch (basis, recycle columns, vectors)"
+        elif c["kernel"] in ("dcgs2_update", "update_dots"):
+            r["algorithmic_bytes"] = "(j + k + 4) w n per launch (basis, A W columns, candidate in and out)"
+        tr = measured_traffic(c["kernel"]) if pname == "C3" and cfg.get("precision") == "fp32_ir" else None
+        if tr is not None:
+            r["traffic"] = tr
+            r["traffic_unit"] = "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
+            r["traffic_gbs"] = round(tr / (avg_us * 1e-6) / 1e9, 1)
+        rooflines.append(r)
+    rooflines.sort(key=lambda r: -r["ms_sampled"])
+    roofline = rooflines[0] if rooflines else None
     for e in prof:
         e["avg_us"] = 1e3 * e["ms"] / e["launches"]
         e["gb_per_s"] = e["bytes"] / (e["ms"] * 1e-3) / 1e9
-    dom = max(prof, key=lambda e: e["ms"]) if prof else None
-    roofline = None
-    if dom is not None:
-        fmt_bytes = dom["bytes"] / dom["launches"]   # what the chosen storage format must move
-        alg_bytes = fmt_bytes
-        alg_def = "the library's byte model of the kernel"
-        if dom["kernel"] == "spmv_arnoldi":
-            # the sparse product's algorithmic bytes: (w + 4) nnz + 4 (n + 1) + 2 w n (CSR values, 32-bit
-            # column indices, row pointers, x read and y written once); the banded format with 16-bit
-            # offsets moves (w + 2) nnz + ... plus its row padding
-            wsz = 4.0 if cfg.get("precision") == "fp32_ir" else 8.0
-            nn, nz = float(asm.pat.n), float(asm.pat.nnz)
-            alg_bytes = (wsz + 4.0) * nz + 4.0 * (nn + 1.0) + 2.0 * wsz * nn
-            alg_def = "(w + 4) nnz + 4 (n + 1) + 2 w n"
-        achieved = alg_bytes / (dom["avg_us"] * 1e-6) / 1e9
-        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(achieved / HBM_PEAK_GBS, 4),
-                    "traffic": measured_traffic(dom["kernel"]) if pname == "C3" and cfg.get("precision") == "fp32_ir"
-                    else None,
-                    "kernel": f"{dom['kernel']} (variant {dom['variant']})",
-                    "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE x2 + WRITE_SIZE x1)",
-                    "algorithmic_bytes_per_launch": round(alg_bytes), "algorithmic_bytes": alg_def,
-                    "format_bytes_per_launch": round(fmt_bytes),
-                    "format_frac": round(fmt_bytes / (dom["avg_us"] * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
-                    "avg_launch_us": round(dom["avg_us"], 2), "launches": dom["launches"]}
 
     cpu = None
+    err = None
     if not args.no_cpu_baseline and pname == "C3":
         log("timing the oracle on the host")
-        cpu = cpu_baseline(prob, asm, tol, cfg)
+        cpu, records = cpu_baseline(prob, asm, tol, cfg, steps=args.oracle_steps)
+        err = gpu_vs_oracle(records, asm, tol, cfg, main_run["shape"], dev)
+        log(f"GPU vs oracle on the oracle's steps: rel {err['rel']}")
+        del records
 
     vs = None
     out = {
@@ -734,12 +852,22 @@ def main():
         "avg_iterations": main_sum["avg_iterations"],
         "avg_cycles": main_sum["avg_cycles"],
         "max_rel_residual": main_sum["max_rel_residual"],
+        "update_ms": main_sum.get("update_ms"),
+        "update_share": main_sum.get("update_share"),
         "plain_fp64": plain_sum,
         "speedup_vs_plain_fp64": (main_sum["solves_per_s"] / plain_sum["solves_per_s"]) if plain_sum else None,
+        "attribution": {name: v for name, v in legs.items()} or None,
         "roofline": roofline,
+        "rooflines": rooflines,
         "kernels": [{k: (round(v, 3) if isinstance(v, float) else v) for k, v in e.items()} for e in prof],
+        "err_vs_oracle": err,
         "cpu_baseline": cpu,
     }
+    if legs and plain_sum:
+        pm, rf = legs.get("plain_mixed"), legs.get("recycled_fp64")
+        out["attribution"]["speedup_recycling_in_mixed"] = main_sum["solves_per_s"] / pm["solves_per_s"]
+        out["attribution"]["speedup_fp32_without_recycling"] = pm["solves_per_s"] / plain_sum["solves_per_s"]
+        out["attribution"]["speedup_recycling_in_fp64"] = rf["solves_per_s"] / plain_sum["solves_per_s"]
     print(json.dumps(out), flush=True)
 
 
