@@ -41,6 +41,12 @@ convection-diffusion problems using singular value decomposition"):
 * Recycle space = leading left singular vectors of the last s solutions,
   recomputed every ell solves (section 5.2, Algorithm 1, eqs. (best_rank_s),
   (opt_svd)).
+* Or, in its place, Ritz or harmonic Ritz vectors of A (section 5.1, eqs.
+  (def_Ritz_pair), (eigenvalues_hessenberg), (eigenvalues_harmonic)) with
+  respect to the search space of the solve just finished: span(W) plus the
+  x-space directions D^{-1} V of its last cycle; the k pairs of smallest
+  |theta| are kept (the small eigenvalues the deflation targets), a complex
+  pair as the real and imaginary parts of its vector.
 
 Readings where the paper is silent (each also listed in the design notes):
 * right Jacobi preconditioning D^{-1} (operator P A D^{-1}, x = x0 + D^{-1} V y),
@@ -53,7 +59,11 @@ Readings where the paper is silent (each also listed in the design notes):
   exceeds 1e13 recycling is dropped for that solve (section 5.2 notes E may
   be singular and takes no measure);
 * the snapshot ring holds the s most recent solutions; the numerical rank
-  uses sigma_i > sigma_1 * max(n, c) * eps64 and k_eff = min(k, rank).
+  uses sigma_i > sigma_1 * max(n, c) * eps64 and k_eff = min(k, rank);
+* Ritz and harmonic Ritz spaces: the search space is orthonormalised (its
+  numerical rank cut as for the ring), the k values of smallest modulus are
+  kept, a complex conjugate pair only whole (a pair that would exceed k is
+  left out), and the kept vectors are orthonormalised with the same rank cut.
 """
 from __future__ import annotations
 
@@ -72,6 +82,8 @@ PROJECTED_START_METHODS = (DEFL_ORTHO, DEFL_LS)   # deflated rows: Krylov initia
 EXTRAP_ORDER = {GUESS_EXTRAP2: 2, GUESS_EXTRAP3: 3, GUESS_EXTRAP4: 4}
 GUESS_ONLY_METHODS = (GUESS_PROJECT, GUESS_EXTRAP2, GUESS_EXTRAP3, GUESS_EXTRAP4)
 PRECOND_NONE, PRECOND_JACOBI = 0, 1
+
+SPACE_SVD, SPACE_RITZ, SPACE_HARMONIC = "svd", "ritz", "harmonic_ritz"
 
 FLAG_RECYCLE_DROPPED = 1
 FLAG_BREAKDOWN_LUCKY = 2
@@ -92,6 +104,7 @@ class Config:
     precond: int = PRECOND_NONE
     max_iters: int = 10000
     select_smallest: bool = False
+    recycle_space: str = SPACE_SVD   # SPACE_SVD (Algorithm 1), SPACE_RITZ or SPACE_HARMONIC (section 5.1)
 
 
 @dataclasses.dataclass
@@ -105,6 +118,7 @@ class Result:
     rel_res_true: float
     res_history: List[float]        # explicit ||r||/||b|| at the end of every cycle
     implicit_history: List[float]   # |g_{j+1}|/||b|| after every Arnoldi step
+    krylov_x: Optional[np.ndarray] = None   # D^{-1} V_j of the last cycle: its x-space directions
 
 
 # ---------------------------------------------------------------------------
@@ -344,6 +358,7 @@ def solve(A, b: np.ndarray, x0: Optional[np.ndarray], tol: float, cfg: Config,
     stop_abs = tol * bnorm
     its = 0
     cycles = 0
+    last_kx = None
     hist: List[float] = []
     implicit: List[float] = []
     rnorm = float(np.linalg.norm(r))
@@ -351,9 +366,9 @@ def solve(A, b: np.ndarray, x0: Optional[np.ndarray], tol: float, cfg: Config,
         return Result(x, 0, 0, k_eff, False, flags | FLAG_NONFINITE, float("nan"), [], [])
     while True:
         if rnorm <= stop_abs:
-            return Result(x, its, cycles, k_eff, True, flags, rnorm / bnorm, hist, implicit)
+            return Result(x, its, cycles, k_eff, True, flags, rnorm / bnorm, hist, implicit, last_kx)
         if its >= cfg.max_iters:
-            return Result(x, its, cycles, k_eff, False, flags, rnorm / bnorm, hist, implicit)
+            return Result(x, its, cycles, k_eff, False, flags, rnorm / bnorm, hist, implicit, last_kx)
         # deflated rows: the Krylov initial vector is the projected residual (P_o r equals r once
         # W^T r = 0; P_LS r equals r once (A W)^T r = 0, i.e. after the first cycle's correction)
         r_start = r
@@ -368,6 +383,7 @@ def solve(A, b: np.ndarray, x0: Optional[np.ndarray], tol: float, cfg: Config,
         j = cyc.steps
         y = scipy.linalg.solve_triangular(cyc.R[:j, :j], cyc.g[:j], lower=False)
         x = krylov_update(x, dinv, cyc.V[:, :j], y)
+        last_kx = krylov_directions(dinv, cyc.V[:, :j])
         r = b - A @ x
         if use_w_krylov:
             x, r = correct(x, r)
@@ -402,6 +418,83 @@ def svd_basis(X: np.ndarray, k: int, smallest: bool = False):
     return U[:, :k_eff].copy(), sig, rank
 
 
+def orthonormal_basis(U: np.ndarray) -> np.ndarray:
+    """Orthonormal basis of span(U) from its SVD, with the numerical-rank cut of the ring
+    (sigma_i > sigma_1 * max(n, c) * eps64)."""
+    n, c = U.shape
+    if c == 0:
+        return np.zeros((n, 0))
+    Q, sig, _ = np.linalg.svd(U, full_matrices=False)
+    if sig[0] == 0.0 or not np.isfinite(sig[0]):
+        return np.zeros((n, 0))
+    return Q[:, : int(np.sum(sig > sig[0] * max(n, c) * EPS64))].copy()
+
+
+def ritz_pairs(A, Q: np.ndarray, harmonic: bool):
+    """Ritz (or harmonic Ritz) pairs of A with respect to span(Q), Q with orthonormal columns:
+    theta and z with Q^T A Q z = theta z (section 5.1, eq. (eigenvalues_hessenberg); Q^T Q = I), or
+    (A Q)^T (A Q) z = theta (A Q)^T Q z (eq. (eigenvalues_harmonic)).  The vectors are y = Q z.
+    A Q is formed one column at a time with the sparse product."""
+    AQ = np.empty_like(Q)
+    for i in range(Q.shape[1]):
+        AQ[:, i] = A @ Q[:, i]
+    if harmonic:
+        theta, Z = scipy.linalg.eig(AQ.T @ AQ, AQ.T @ Q)
+    else:
+        theta, Z = scipy.linalg.eig(Q.T @ AQ)
+    return theta, Z
+
+
+def ritz_order(theta: np.ndarray):
+    """Indices of the finite values, smallest modulus first (the eigenvalues that deflation removes,
+    section 3.2; harmonic Ritz values approximate those nearest the origin, section 5.1)."""
+    return [i for i in np.argsort(np.abs(theta), kind="stable") if np.isfinite(theta[i])]
+
+
+def pair_basis(y: np.ndarray):
+    """Real vectors spanning the same space as a complex Ritz vector and its conjugate."""
+    return [y.real.copy(), y.imag.copy()]
+
+
+def krylov_directions(dinv: np.ndarray, V: np.ndarray) -> np.ndarray:
+    """The x-space directions of a cycle's Krylov basis under right preconditioning: D^{-1} V."""
+    return dinv[:, None] * V
+
+
+def ritz_basis(A, U: np.ndarray, k: int, harmonic: bool):
+    """Recycle basis from the Ritz or harmonic Ritz vectors of A over span(U) (section 5.1): the k
+    pairs of smallest |theta| (finite values only), a complex pair as the real and imaginary parts
+    of its vector and only whole, orthonormalised.  Returns (W, selected theta)."""
+    n = U.shape[0]
+    Q = orthonormal_basis(U)
+    if Q.shape[1] == 0 or k == 0:
+        return np.zeros((n, 0)), np.zeros(0, dtype=complex)
+    theta, Z = ritz_pairs(A, Q, harmonic)
+    order = ritz_order(theta)
+    cols, picked, used = [], [], set()
+    for i in order:
+        if i in used:
+            continue
+        if abs(theta[i].imag) > 0.0:
+            # the conjugate partner: the other index of equal modulus and opposite imaginary part
+            partner = min((j for j in order if j not in used and j != i),
+                          key=lambda j: abs(theta[j] - np.conj(theta[i])), default=None)
+            if len(cols) + 2 > k:
+                break
+            cols += pair_basis(Q @ Z[:, i])
+            picked += [theta[i], np.conj(theta[i])]
+            used.update({i, partner})
+        else:
+            if len(cols) + 1 > k:
+                break
+            cols.append((Q @ Z[:, i]).real)
+            picked.append(theta[i])
+            used.add(i)
+    if not cols:
+        return np.zeros((n, 0)), np.zeros(0, dtype=complex)
+    return orthonormal_basis(np.column_stack(cols)), np.array(picked)
+
+
 class RecycleState:
     """Snapshot ring and recycle basis of one sequence (section 5.2, Algorithm 1)."""
 
@@ -412,11 +505,23 @@ class RecycleState:
         self.count = 0
         self.W = np.zeros((n, 0))
         self.sigma = np.zeros(0)
+        self.theta = np.zeros(0, dtype=complex)
         self.rank = 0
 
-    def update(self, x: np.ndarray):
+    def update(self, x: np.ndarray, A=None, result: Optional[Result] = None):
         """Store x among the s most recent solutions; every ell solves recompute W (the
-        extrapolation methods keep the ring only)."""
+        extrapolation methods keep the ring only).  With a Ritz or harmonic Ritz recycle space, W
+        is instead recomputed after every solve from A and the solve's search space: the W it
+        used plus its last cycle's directions (result.krylov_x)."""
+        if self.cfg.recycle_space != SPACE_SVD:
+            self.count += 1
+            if self.cfg.recycle_k <= 0 or result is None or result.krylov_x is None:
+                return
+            U = np.column_stack([self.W, result.krylov_x])
+            self.W, self.theta = ritz_basis(A, U, self.cfg.recycle_k,
+                                            self.cfg.recycle_space == SPACE_HARMONIC)
+            self.rank = self.W.shape[1]
+            return
         s = self.cfg.snapshots_s
         extrap = self.cfg.method in EXTRAP_ORDER
         if s <= 0 or (self.cfg.recycle_k <= 0 and not extrap):
@@ -442,6 +547,6 @@ def run_sequence(A_list, b_list, tol: float, cfg: Config, x_init=None):
     for A, b in zip(A_list, b_list):
         res = solve(A, b, x_prev, tol, cfg, st.W, st.ring)
         results.append(res)
-        st.update(res.x)
+        st.update(res.x, A, res)
         x_prev = res.x
     return results, st

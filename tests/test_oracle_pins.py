@@ -681,6 +681,133 @@ def test_ls_rows_solve_a_sequence_to_tolerance():
                 assert r.iterations <= p.iterations
 
 
+# -- Ritz and harmonic Ritz recycle spaces (section 5.1) -------------------------------
+
+
+def small_eigen_system(n=64, seed=21):
+    """A = Pi [[B, K], [0, C]] Pi^T: B (4 x 4) holds the four eigenvalues of smallest modulus,
+    0.01 +- 0.02i, 0.03 and 0.05 (a rotation block and two diagonal entries), C is a shifted random
+    sparse block whose field of values stays far from the origin, K a sparse coupling (so the
+    invariant subspace of B, the columns Pi e_0..e_3, has no invariant orthogonal complement and
+    its left and right eigenvectors differ); Pi scatters it over the index range."""
+    rng = np.random.default_rng(seed)
+    B = np.array([[0.01, 0.02, 0, 0], [-0.02, 0.01, 0, 0], [0, 0, 0.03, 0], [0, 0, 0, 0.05]])
+    C, _ = rand_system(n - 4, seed + 1, density=0.08, shift=4.0)
+    K = sp.random(4, n - 4, density=0.2, random_state=rng) * 0.5
+    M = sp.bmat([[sp.csr_matrix(B), K], [None, C]]).tocsr()
+    perm = rng.permutation(n)
+    P = sp.csr_matrix((np.ones(n), (perm, np.arange(n))), shape=(n, n))
+    A = (P @ M @ P.T).tocsr()
+    A.sort_indices()
+    X_B = P.toarray()[:, :4]          # orthonormal basis of B's invariant subspace
+    return A, X_B, np.array([0.01 + 0.02j, 0.01 - 0.02j, 0.03, 0.05])
+
+
+def _max_angle_sin(X, Y):
+    """sin of the largest principal angle between span(X) and span(Y) (equal dimensions)."""
+    Qx, Qy = np.linalg.qr(X)[0], np.linalg.qr(Y)[0]
+    return float(np.linalg.norm(Qy - Qx @ (Qx.T @ Qy), 2))
+
+
+@pytest.mark.parametrize("harmonic", [False, True])
+def test_ritz_space_recovers_an_invariant_subspace(harmonic):
+    """A search space that contains an invariant subspace gives its eigenpairs exactly: the four
+    smallest (harmonic) Ritz values are B's eigenvalues, the complex pair included, and W spans
+    the subspace; with k = 3 the pair and 0.03 are kept; with k = 1 the pair does not fit and
+    nothing is kept before it."""
+    A, X_B, lam = small_eigen_system()
+    rng = np.random.default_rng(3)
+    U = np.column_stack([X_B @ rng.standard_normal((4, 4)), rng.standard_normal((64, 3))])
+    W, theta = O.ritz_basis(A, U, 4, harmonic)
+    assert W.shape[1] == 4 and np.abs(W.T @ W - np.eye(4)).max() <= 1e-13
+    assert _max_angle_sin(W, X_B) <= 1e-10
+    assert np.allclose(np.sort_complex(theta), np.sort_complex(lam), atol=1e-11)
+    W3, theta3 = O.ritz_basis(A, U, 3, harmonic)
+    assert W3.shape[1] == 3 and np.allclose(np.sort(np.abs(theta3)), np.sort(np.abs(lam[:3])), atol=1e-11)
+    assert _max_angle_sin(W3, X_B[:, :3]) <= 1e-10
+    W1, theta1 = O.ritz_basis(A, U, 1, harmonic)
+    assert W1.shape[1] == 0
+
+
+def test_harmonic_ritz_values_are_inverse_ritz_values_of_the_inverse():
+    """Eq. (harmonic_ritz_inverse): the harmonic Ritz values of A over span(U) are the reciprocals of
+    the Ritz values of A^{-1} over A span(U) (computed here with a dense inverse)."""
+    rng = np.random.default_rng(8)
+    n = 40
+    Ad = rng.standard_normal((n, n)) + 6.0 * np.eye(n)
+    A = sp.csr_matrix(Ad)
+    U = rng.standard_normal((n, 7))
+    Q = O.orthonormal_basis(U)
+    theta, _ = O.ritz_pairs(A, Q, harmonic=True)
+    P = np.linalg.qr(Ad @ Q)[0]
+    mu = np.linalg.eigvals(P.T @ np.linalg.inv(Ad) @ P)
+    assert np.allclose(np.sort_complex(theta), np.sort_complex(1.0 / mu), rtol=1e-10)
+    # and they differ from the (plain) Ritz values on the same space
+    ritz, _ = O.ritz_pairs(A, Q, harmonic=False)
+    assert not np.allclose(np.sort_complex(theta), np.sort_complex(ritz), rtol=1e-3)
+
+
+@pytest.mark.parametrize("harmonic", [False, True])
+def test_ritz_values_of_a_symmetric_matrix_lie_in_its_spectrum(harmonic):
+    """Symmetric positive definite A: (harmonic) Ritz values are real and inside [lambda_min,
+    lambda_max] (Courant-Fischer; harmonic ones are inverted Ritz values of A^{-1}), and the pairs
+    satisfy their Galerkin (Petrov-Galerkin) conditions."""
+    rng = np.random.default_rng(5)
+    n = 50
+    G = rng.standard_normal((n, n))
+    Ad = G @ G.T / n + 0.05 * np.eye(n)
+    lam = np.linalg.eigvalsh(Ad)
+    A = sp.csr_matrix(Ad)
+    Q = O.orthonormal_basis(rng.standard_normal((n, 9)))
+    theta, Z = O.ritz_pairs(A, Q, harmonic)
+    assert np.abs(theta.imag).max() <= 1e-10 * lam[-1]
+    assert theta.real.min() >= lam[0] * (1 - 1e-10) and theta.real.max() <= lam[-1] * (1 + 1e-10)
+    for i in range(theta.size):
+        y = Q @ Z[:, i]
+        res = Ad @ y - theta[i] * y
+        T = Ad @ Q if harmonic else Q
+        assert np.linalg.norm(T.T @ res) <= 1e-10 * lam[-1] * np.linalg.norm(y)
+
+
+def test_krylov_directions_carry_the_last_cycle_update():
+    """Right Jacobi, one cycle: the returned solution minus the starting guess lies in the span of
+    the cycle's x-space directions D^{-1} V (and not in the span of V itself)."""
+    A, b = rand_system(40, 12, shift=4.0)
+    A = (A + sp.diags(np.linspace(1.0, 30.0, 40))).tocsr()   # a diagonal far from constant
+    x0 = np.random.default_rng(1).standard_normal(40)
+    res = O.solve(A, b, x0, 1e-10, O.Config(restart_m=40, method=O.PLAIN, precond=O.PRECOND_JACOBI))
+    assert res.cycles == 1
+    K = res.krylov_x
+    d = res.x - x0
+    coef = np.linalg.lstsq(K, d, rcond=None)[0]
+    assert np.linalg.norm(K @ coef - d) <= 1e-10 * np.linalg.norm(d)
+    V = K / (1.0 / A.diagonal())[:, None]
+    coef = np.linalg.lstsq(V[:, : K.shape[1] - 2], d, rcond=None)[0]
+    assert np.linalg.norm(V[:, : K.shape[1] - 2] @ coef - d) > 1e-6 * np.linalg.norm(d)
+
+
+@pytest.mark.parametrize("space", [O.SPACE_RITZ, O.SPACE_HARMONIC])
+def test_ritz_recycling_deflates_small_eigenvalues(space):
+    """GMRES(20) crawls on the four small eigenvalues; recycling the (harmonic) Ritz vectors of each
+    solve's search space converges onto their invariant subspace within a few solves of the
+    sequence (the same matrix, new right-hand sides), and the later solves take a small fraction of
+    plain GMRES(20)'s steps on the same systems."""
+    A, X_B, _ = small_eigen_system()
+    rng = np.random.default_rng(9)
+    bs = [rng.standard_normal(64) for _ in range(6)]
+    plain = [O.solve(A, b, None, 1e-8, O.Config(restart_m=20, method=O.PLAIN)).iterations for b in bs]
+    cfg = O.Config(restart_m=20, recycle_k=4, method=O.AUG_OBLIQUE, recycle_space=space)
+    st = O.RecycleState(64, cfg)
+    its = []
+    for b in bs:
+        r = O.solve(A, b, None, 1e-8, cfg, st.W)
+        assert r.converged
+        st.update(r.x, A, r)
+        its.append(r.iterations)
+    assert sum(its[3:]) <= 0.25 * sum(plain[3:]), (its, plain)
+    assert st.W.shape[1] == 4 and _max_angle_sin(st.W, X_B) <= 0.05
+
+
 # -- planted mistakes: each plausible error in the oracle is caught by a pin ----------
 
 
@@ -700,6 +827,10 @@ def _pins_pass():
         test_augmented_ls_minimises_from_the_unprojected_residual()
         test_lucky_breakdown_exit(1e20)
         test_lucky_breakdown_exit(1e-20)
+        test_ritz_space_recovers_an_invariant_subspace(False)
+        test_ritz_space_recovers_an_invariant_subspace(True)
+        test_harmonic_ritz_values_are_inverse_ritz_values_of_the_inverse()
+        test_krylov_directions_carry_the_last_cycle_update()
     except AssertionError:
         return False
     return True
@@ -716,9 +847,28 @@ def test_pins_pass_on_unmodified_oracle():
                                       "guess_only_projects_krylov", "ls_projector_missing",
                                       "ls_correction_galerkin", "ls_coefficients_unnormalised",
                                       "ls_deflated_start_unprojected", "lucky_never", "lucky_absolute",
-                                      "lucky_loose"])
+                                      "lucky_loose", "ritz_largest_first", "harmonic_as_plain_ritz",
+                                      "ritz_pair_real_part_only", "ritz_left_eigenvectors",
+                                      "krylov_directions_unpreconditioned"])
 def test_planted_mistakes_are_caught(monkeypatch, mutation):
-    if mutation == "lucky_never":
+    if mutation == "ritz_largest_first":
+        orig_o = O.ritz_order
+        monkeypatch.setattr(O, "ritz_order", lambda th: orig_o(th)[::-1])
+    elif mutation == "harmonic_as_plain_ritz":
+        orig_p = O.ritz_pairs
+        monkeypatch.setattr(O, "ritz_pairs", lambda A, Q, harmonic: orig_p(A, Q, False))
+    elif mutation == "ritz_pair_real_part_only":
+        monkeypatch.setattr(O, "pair_basis", lambda y: [y.real.copy(), y.real.copy()])
+    elif mutation == "ritz_left_eigenvectors":
+        def left(A, Q, harmonic):
+            AQ = np.column_stack([A @ Q[:, i] for i in range(Q.shape[1])])
+            if harmonic:
+                return scipy.linalg.eig((AQ.T @ AQ).T, (AQ.T @ Q).T)
+            return scipy.linalg.eig((Q.T @ AQ).T)
+        monkeypatch.setattr(O, "ritz_pairs", left)
+    elif mutation == "krylov_directions_unpreconditioned":
+        monkeypatch.setattr(O, "krylov_directions", lambda dinv, V: V.copy())
+    elif mutation == "lucky_never":
         monkeypatch.setattr(O, "is_lucky_breakdown", lambda h, c: False)
     elif mutation == "lucky_absolute":
         monkeypatch.setattr(O, "is_lucky_breakdown", lambda h, c: h <= O.LUCKY_REL)
