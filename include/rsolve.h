@@ -95,6 +95,17 @@ extern "C" {
 #define RSOLVE_SELECT_LARGEST 0   /* W = leading left singular vectors (Algorithm 1) */
 #define RSOLVE_SELECT_SMALLEST 1  /* W = left singular vectors of the k smallest singular values above
                                      the numerical rank cut (section 5.2, the other choice) */
+#define RSOLVE_SELECT_RITZ     2  /* W = Ritz vectors of A (section 5.1, eqs. (def_Ritz_pair),
+                                     (eigenvalues_hessenberg)) over the search space of the last
+                                     solve, span(W) + span(D^{-1} V_j) with V_j the basis of its last
+                                     cycle: the k pairs of smallest |theta|, a complex pair as the real
+                                     and imaginary parts of its vector and only whole, orthonormalised
+                                     (rank cut as for the ring).  Prepared at the end of each solve,
+                                     installed by rsolve_update_recycle (whose x is then not stored; no
+                                     snapshot ring is kept).  Needs recycle_k >= 1 and recycle_k +
+                                     restart_m <= 64; not on the one-block path */
+#define RSOLVE_SELECT_HARMONIC 3  /* the same with harmonic Ritz vectors, (A U)^T (A U) z = theta (A U)^T U z
+                                     (eq. (eigenvalues_harmonic)) */
 #define RSOLVE_ORTHO_CGS2     0   /* classical Gram-Schmidt applied twice: three basis sweeps per step */
 #define RSOLVE_ORTHO_DCGS2    1   /* the same Arnoldi process with the second pass of each basis vector
                                      merged into the next step: two basis sweeps per step, the
@@ -119,7 +130,8 @@ typedef struct rsolve_seq rsolve_seq;
 typedef struct {
     int32_t restart_m;     /* GMRES restart length m, 1..RSOLVE_MAX_RESTART */
     int32_t recycle_k;     /* recycle dimension k, 0..RSOLVE_MAX_RECYCLE (0 = plain) */
-    int32_t snapshots_s;   /* snapshot ring size s, k <= s <= RSOLVE_MAX_SNAPSHOTS (0 if k = 0);
+    int32_t snapshots_s;   /* snapshot ring size s, k <= s <= RSOLVE_MAX_SNAPSHOTS (0 if k = 0; unused by
+                              the Ritz selections);
                               for RSOLVE_GUESS_EXTRAPq: q <= s (the ring of previous solutions) */
     int32_t svd_interval;  /* ell >= 1: recompute W every ell updates (Algorithm 1) */
     int32_t method;        /* RSOLVE_PLAIN / _AUG_OBLIQUE / _DEFL_OBLIQUE / _AUG_ORTHO / _DEFL_ORTHO /
@@ -128,7 +140,7 @@ typedef struct {
     int32_t precond;       /* RSOLVE_PRECOND_NONE / RSOLVE_PRECOND_JACOBI */
     int32_t precision;     /* RSOLVE_FP64 / RSOLVE_FP32_IR */
     int32_t max_iters;     /* cap on Arnoldi steps per solve (>= 1) */
-    int32_t select;        /* RSOLVE_SELECT_LARGEST / RSOLVE_SELECT_SMALLEST */
+    int32_t select;        /* RSOLVE_SELECT_LARGEST / _SMALLEST (SVD of the ring) / _RITZ / _HARMONIC */
     int32_t ortho;         /* RSOLVE_ORTHO_CGS2 (0) / RSOLVE_ORTHO_DCGS2 (1): Arnoldi orthogonalisation
                               of the multi-kernel path (the one-block path always uses CGS2) */
     double  inner_tol;     /* FP32_IR only: an FP32 cycle stops once its residual estimate has

@@ -73,12 +73,19 @@ int extrap_order(int method) {
     return (method >= RSOLVE_GUESS_EXTRAP2 && method <= RSOLVE_GUESS_EXTRAP4) ? method - RSOLVE_GUESS_EXTRAP2 + 2 : 0;
 }
 
+bool ritz_mode(const rsolve_config& c) {
+    return c.select == RSOLVE_SELECT_RITZ || c.select == RSOLVE_SELECT_HARMONIC;
+}
+
 int cfg_check(const rsolve_config* c) {
     if (!c) return RSOLVE_E_INVALID;
     if (c->restart_m < 1 || c->restart_m > RSOLVE_MAX_RESTART) return RSOLVE_E_INVALID;
     if (c->recycle_k < 0 || c->recycle_k > RSOLVE_MAX_RECYCLE) return RSOLVE_E_INVALID;
     if (c->snapshots_s < 0 || c->snapshots_s > RSOLVE_MAX_SNAPSHOTS) return RSOLVE_E_INVALID;
-    if (c->recycle_k > 0 && c->snapshots_s < c->recycle_k) return RSOLVE_E_INVALID;
+    const bool ritz = c->select == RSOLVE_SELECT_RITZ || c->select == RSOLVE_SELECT_HARMONIC;
+    // the Ritz spaces come from the search space [W, D^{-1} V_m] (no ring needed), at most SMAX wide
+    if (ritz && (c->recycle_k < 1 || c->recycle_k + c->restart_m > SMAX)) return RSOLVE_E_INVALID;
+    if (c->recycle_k > 0 && !ritz && c->snapshots_s < c->recycle_k) return RSOLVE_E_INVALID;
     if (c->svd_interval < 1) return RSOLVE_E_INVALID;
     if (c->method < RSOLVE_PLAIN || c->method > RSOLVE_DEFL_LS) return RSOLVE_E_INVALID;
     // the extrapolation methods keep a ring of at least `order` solutions and no recycle space
@@ -87,7 +94,7 @@ int cfg_check(const rsolve_config* c) {
     if (c->precond != RSOLVE_PRECOND_NONE && c->precond != RSOLVE_PRECOND_JACOBI) return RSOLVE_E_INVALID;
     if (c->precision != RSOLVE_FP64 && c->precision != RSOLVE_FP32_IR) return RSOLVE_E_INVALID;
     if (c->max_iters < 1) return RSOLVE_E_INVALID;
-    if (c->select != RSOLVE_SELECT_LARGEST && c->select != RSOLVE_SELECT_SMALLEST) return RSOLVE_E_INVALID;
+    if (c->select < RSOLVE_SELECT_LARGEST || c->select > RSOLVE_SELECT_HARMONIC) return RSOLVE_E_INVALID;
     if (c->ortho != RSOLVE_ORTHO_CGS2 && c->ortho != RSOLVE_ORTHO_DCGS2) return RSOLVE_E_INVALID;
     if (c->precision == RSOLVE_FP32_IR && !(c->inner_tol > 0.0 && c->inner_tol < 1.0)) return RSOLVE_E_INVALID;
     return RSOLVE_OK;
@@ -178,6 +185,15 @@ struct rsolve_seq {
     const int32_t* pat_ci = nullptr;
     int64_t pat_nnz = -1;
     bool pat_ok = false;
+    // Ritz and harmonic Ritz recycle spaces: the search space U = [W, D^{-1} V_j] of the last
+    // solve, its orthonormal basis Q and A Q, the pairs' basis before orthonormalisation, and the
+    // new W prepared at the end of the solve (A is not available to the update)
+    double *rz_u = nullptr, *rz_q = nullptr, *rz_aq = nullptr, *rz_tmp = nullptr, *rz_w = nullptr;
+    double *rz_g = nullptr, *rz_eig = nullptr;
+    int rz_k = 0;                  // columns of rz_w
+    bool rz_pending = false;       // rz_w holds the next W
+    double rz_theta[SMAX];         // |theta| of the kept pairs
+    int last_steps = 0;            // Arnoldi steps of the last cycle of the last solve
     int k_w = 0, rank = 0, nsig = 0;
     int64_t count = 0;
     double sigma[SMAX];
@@ -269,13 +285,27 @@ size_t layout(rsolve_seq* s, const rsolve_config& c, int64_t n, int64_t nnz_max,
     double* gpart = cv.take<double>((size_t)GRAM_PARTIAL);
     double* zpart = (k > 0 && k <= DCGS2_ZD_KMAX) ? cv.take<double>((size_t)k * NBLK_MAX) : nullptr;
     double* gz = zpart ? cv.take<double>((size_t)k * k) : nullptr;
+    const bool rz = ritz_mode(c) && k > 0;
+    const int rzc = rz ? k + m : 0;   // widest search space
+    double *rz_u = nullptr, *rz_q = nullptr, *rz_aq = nullptr, *rz_tmp = nullptr, *rz_w = nullptr;
+    double *rz_g = nullptr, *rz_eig = nullptr;
+    if (rz) {
+        rz_u = cv.take<double>((size_t)rzc * ld);
+        rz_q = cv.take<double>((size_t)rzc * ld);
+        rz_aq = cv.take<double>((size_t)rzc * ld);
+        rz_tmp = cv.take<double>((size_t)k * ld);
+        rz_w = cv.take<double>((size_t)k * ld);
+        rz_g = cv.take<double>((size_t)2 * SMAX * SMAX);
+        rz_eig = cv.take<double>((size_t)9 * SMAX * SMAX);
+    }
+    const int tcols = std::max(rz ? rzc : 0, (k || extrap_order(c.method)) ? sn : 0);   // TSQR width
     int64_t tsq_rows = 0, tsq_ld = 0;
     double *t0 = nullptr, *t1 = nullptr;
-    if (k && sn) {
-        tsq_rows = ((n + TSQR_MIN_PANEL - 1) / TSQR_MIN_PANEL) * sn;
+    if (k && tcols) {
+        tsq_rows = ((n + TSQR_MIN_PANEL - 1) / TSQR_MIN_PANEL) * tcols;
         tsq_ld = pad64(tsq_rows);
-        t0 = cv.take<double>((size_t)tsq_ld * sn);
-        t1 = cv.take<double>((size_t)tsq_ld * sn);
+        t0 = cv.take<double>((size_t)tsq_ld * tcols);
+        t1 = cv.take<double>((size_t)tsq_ld * tcols);
     }
     if (s) {
         s->ld = ld;
@@ -313,6 +343,13 @@ size_t layout(rsolve_seq* s, const rsolve_config& c, int64_t n, int64_t nnz_max,
         s->tsq[0] = t0;
         s->tsq[1] = t1;
         s->tsq_ld = tsq_ld;
+        s->rz_u = rz_u;
+        s->rz_q = rz_q;
+        s->rz_aq = rz_aq;
+        s->rz_tmp = rz_tmp;
+        s->rz_w = rz_w;
+        s->rz_g = rz_g;
+        s->rz_eig = rz_eig;
     }
     return align_up(cv.off, ALIGN);
 }
@@ -679,6 +716,115 @@ void residual_and_correct(rsolve_seq* s, const rsolve_csr* A, const double* b, i
     correct(s, Q, k);
 }
 
+// SVD step of Algorithm 1 on an n x c matrix X (section 5.2): TSQR of X to one c x c R factor,
+// one-sided Jacobi SVD of R, then W_out = X V_k Sigma_k^{-1} re-orthonormalised by the Cholesky
+// factor of its Gram matrix, k_eff = min(kmax, rank) with the rank cut sigma_i > sigma_1 max(n, c)
+// eps (the k_eff smallest above the cut when `smallest`).  The singular values land in s->hsig;
+// Wr (nullable) receives W row-major with leading dimension ldr.  Synchronous (two read-backs).
+int svd_basis_dev(rsolve_seq* s, const double* X, int64_t ldx, int c, int kmax, bool smallest, double* W_out,
+                  int64_t ldw, double* Wr, int ldr, int* keff_out, int* rank_out, int* nonfinite, int* lu_fail) {
+    hipStream_t stm = s->stream;
+    const int64_t n = s->n, ld = s->ld;
+    const double* M = X;
+    int64_t ldm = ldx, rows = n;
+    int lvl = 0;
+    const double* R = nullptr;
+    for (;;) {
+        const int pr = tsqr_panel_rows(c);
+        const int P = (int)((rows + pr - 1) / pr);
+        double* out = s->tsq[lvl & 1];
+        launch_tsqr_level(rows, M, ldm, c, out, s->tsq_ld, P, stm);
+        R = out;
+        if (P == 1) break;
+        M = out;
+        ldm = s->tsq_ld;
+        rows = (int64_t)P * c;
+        ++lvl;
+    }
+    HIP_TRY(hipMemsetAsync(s->ctl, 0, CTL_HEAD, stm));
+    launch_jacobi_svd(R, s->tsq_ld, c, kmax, n, s->ctl, stm, smallest);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(s->hsig, ctl_sigma(s->ctl), sizeof(double) * c, hipMemcpyDeviceToHost, stm));
+    int rc = read_head(s);
+    if (rc) return rc;
+    *rank_out = s->hctl->rank;
+    *nonfinite = s->hctl->nonfinite;
+    *lu_fail = 0;
+    const int keff = s->hctl->nonfinite ? 0 : s->hctl->k_eff;
+    *keff_out = keff;
+    if (keff > 0) {
+        launch_form_w(n, ld, X, ldx, c, keff, s->ctl, W_out, ldw, stm);
+        const int gb = launch_gram_tn(ld, W_out, ldw, keff, W_out, ldw, keff, s->gpart, s->gblk, stm);
+        launch_gram_reduce(s->gpart, gb, keff * keff, ctl_red(s->ctl), stm);
+        launch_cholesky(keff, s->ctl, stm);
+        launch_trsm_rows(ld, W_out, ldw, keff, s->ctl, stm, Wr, ldr);
+        HIP_TRY(hipGetLastError());
+        rc = read_head(s);
+        if (rc) return rc;
+        *lu_fail = s->hctl->lu_fail;
+    }
+    return RSOLVE_OK;
+}
+
+// Ritz or harmonic Ritz recycle basis for the next solve (section 5.1), prepared at the end of a
+// solve while A is valid: U = [W, D^{-1} V_j] (the solve's W and the x-space directions of its
+// last cycle), Q = an orthonormal basis of span(U) (its SVD, rank cut), A Q by sparse products,
+// the small (generalised) eigenproblem on the device, the kept pairs' real basis Q T, and its
+// orthonormal basis (SVD again) into rz_w.  W itself changes in rsolve_update_recycle.
+int ritz_prepare(rsolve_seq* s, const rsolve_csr* A, int kw) {
+    const rsolve_config& c = s->cfg;
+    hipStream_t stm = s->stream;
+    const int64_t n = s->n, ld = s->ld;
+    const int j = s->last_steps;
+    s->rz_pending = false;
+    if (j < 1) return RSOLVE_OK;   // no Krylov step: keep W
+    const int cu = kw + j;
+    if (kw > 0) HIP_TRY(hipMemcpyAsync(s->rz_u, s->W, sizeof(double) * ld * kw, hipMemcpyDeviceToDevice, stm));
+    const double* dv = c.precond == RSOLVE_PRECOND_JACOBI ? s->dinv : nullptr;
+    if (c.precision == RSOLVE_FP32_IR) launch_scale_cols<float>(n, ld, s->V32, j, dv, s->rz_u + (int64_t)kw * ld, ld, stm);
+    else launch_scale_cols<double>(n, ld, s->V, j, dv, s->rz_u + (int64_t)kw * ld, ld, stm);
+    int r = 0, rank = 0, bad = 0, luf = 0;
+    int rc = svd_basis_dev(s, s->rz_u, ld, cu, cu, false, s->rz_q, ld, nullptr, 0, &r, &rank, &bad, &luf);
+    if (rc) return rc;
+    if (bad) {
+        set_err("non-finite search space");
+        return RSOLVE_E_NONFINITE;
+    }
+    int keep = 0;
+    if (r > 0 && !luf) {
+        for (int i = 0; i < r; ++i)
+            launch_spmv(s->lpr, n, A->row_ptr, A->col_idx, A->val, s->rz_q + (int64_t)i * ld, s->rz_aq + (int64_t)i * ld,
+                        stm);
+        const bool harm = c.select == RSOLVE_SELECT_HARMONIC;
+        double* Ga = s->rz_g;
+        double* Gb = s->rz_g + SMAX * SMAX;
+        const double* left = harm ? s->rz_aq : s->rz_q;
+        int gb = launch_gram_tn(ld, left, ld, r, s->rz_aq, ld, r, s->gpart, s->gblk, stm);
+        launch_gram_reduce(s->gpart, gb, r * r, Ga, stm);
+        if (harm) {
+            gb = launch_gram_tn(ld, s->rz_aq, ld, r, s->rz_q, ld, r, s->gpart, s->gblk, stm);
+            launch_gram_reduce(s->gpart, gb, r * r, Gb, stm);
+        }
+        HIP_TRY(hipMemsetAsync(s->ctl, 0, CTL_HEAD, stm));
+        launch_small_eig(Ga, Gb, r, c.recycle_k, harm ? 1 : 0, s->rz_eig, s->ctl, stm);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipMemcpyAsync(s->hsig, ctl_sigma(s->ctl), sizeof(double) * SMAX, hipMemcpyDeviceToHost, stm));
+        rc = read_head(s);
+        if (rc) return rc;
+        const int kk = s->hctl->lu_fail ? 0 : s->hctl->k_eff;
+        for (int i = 0; i < kk; ++i) s->rz_theta[i] = s->hsig[i];
+        if (kk > 0) {
+            launch_form_w(n, ld, s->rz_q, ld, r, kk, s->ctl, s->rz_tmp, ld, stm);
+            rc = svd_basis_dev(s, s->rz_tmp, ld, kk, kk, false, s->rz_w, ld, nullptr, 0, &keep, &rank, &bad, &luf);
+            if (rc) return rc;
+            if (bad || luf) keep = 0;
+        }
+    }
+    s->rz_k = keep;
+    s->rz_pending = true;
+    return RSOLVE_OK;
+}
+
 double ms_since(std::chrono::steady_clock::time_point t0) {
     return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }
@@ -691,13 +837,13 @@ bool small_solve_ok(const rsolve_seq* s) {
     const rsolve_config& c = s->cfg;
     // the one-block solve implements the oblique projector (or none) only
     return c.precision == RSOLVE_FP64 && c.restart_m <= SMALL_MMAX && c.recycle_k <= SMALL_KMAX &&
-           s->n <= RSOLVE_SMALL_MAX_N && c.method <= RSOLVE_DEFL_OBLIQUE;
+           s->n <= RSOLVE_SMALL_MAX_N && c.method <= RSOLVE_DEFL_OBLIQUE && !ritz_mode(c);
 }
 
 bool small_update_ok(const rsolve_seq* s) {
     const rsolve_config& c = s->cfg;
     return c.precision == RSOLVE_FP64 && c.snapshots_s <= SMALL_SMAX && c.snapshots_s <= c.restart_m + 1 &&
-           s->n >= c.snapshots_s && s->n <= RSOLVE_SMALL_MAX_N && extrap_order(c.method) == 0;
+           s->n >= c.snapshots_s && s->n <= RSOLVE_SMALL_MAX_N && extrap_order(c.method) == 0 && !ritz_mode(c);
 }
 
 // Argument checks shared with rsolve_solve; returns RSOLVE_OK or E_INVALID (message set).
@@ -1026,6 +1172,8 @@ int rsolve_solve(rsolve_seq* s, const rsolve_csr* A, const double* b, const doub
     }
     HIP_TRY(hipMemsetAsync(s->ctl, 0, CTL_HEAD, stm));
     s->nnz_cur = A->nnz;
+    s->last_steps = 0;
+    s->rz_pending = false;
 
     // ||b||
     launch_norm2(n, b, s->partial, s->nblk, stm);
@@ -1234,6 +1382,7 @@ int rsolve_solve(rsolve_seq* s, const rsolve_csr* A, const double* b, const doub
         head_fresh = true;
         prof_collect(s, s->hctl->steps);
         its += s->hctl->steps;
+        s->last_steps = s->hctl->steps;
         cycles += 1;
         gimp = s->hctl->gimp;
         if (s->hctl->lucky) flags |= RSOLVE_FLAG_BREAKDOWN_LUCKY;
@@ -1246,6 +1395,11 @@ int rsolve_solve(rsolve_seq* s, const rsolve_csr* A, const double* b, const doub
     HIP_TRY(hipMemcpyAsync(x, s->xw, sizeof(double) * n, hipMemcpyDeviceToDevice, stm));
     HIP_TRY(hipStreamSynchronize(stm));
     s->have_x = true;
+    const double rnorm_final = s->hctl->rnorm;
+    if (ritz_mode(c) && c.recycle_k > 0 && status != RSOLVE_E_NONFINITE) {
+        rc = ritz_prepare(s, A, s->k_w);
+        if (rc) return rc;
+    }
     if (st) {
         st->iterations = its;
         st->cycles = cycles;
@@ -1253,7 +1407,7 @@ int rsolve_solve(rsolve_seq* s, const rsolve_csr* A, const double* b, const doub
         st->converged = converged ? 1 : 0;
         st->flags = flags;
         st->reserved = 0;
-        st->rel_res_true = s->hctl->rnorm / bnorm;
+        st->rel_res_true = rnorm_final / bnorm;
         st->rel_res_implicit = gimp / bnorm;
         st->t_setup_ms = t_setup;
         st->t_total_ms = ms_since(t0);
@@ -1275,6 +1429,26 @@ int rsolve_update_recycle(rsolve_seq* s, const double* x) {
     }
     const rsolve_config& c = s->cfg;
     const bool extrap = extrap_order(c.method) != 0;
+    if (ritz_mode(c)) {
+        // the basis the last solve prepared from its search space (x itself is not stored)
+        s->count++;
+        if (!s->rz_pending) return RSOLVE_OK;
+        HIP_TRY(hipSetDevice(s->device));
+        const int kk = s->rz_k;
+        if (kk > 0) {
+            HIP_TRY(hipMemcpyAsync(s->W, s->rz_w, sizeof(double) * s->ld * kk, hipMemcpyDeviceToDevice, s->stream));
+            if (s->W32) launch_to_f32(kk * s->ld, s->W, s->W32, s->stream);
+            HIP_TRY(hipGetLastError());
+        }
+        HIP_TRY(hipStreamSynchronize(s->stream));
+        s->wr_ok = false;
+        for (int i = 0; i < kk; ++i) s->sigma[i] = s->rz_theta[i];
+        s->nsig = kk;
+        s->rank = kk;
+        s->k_w = kk;
+        s->rz_pending = false;
+        return RSOLVE_OK;
+    }
     if ((c.recycle_k == 0 && !extrap) || c.snapshots_s == 0) {
         s->count++;
         return RSOLVE_OK;
@@ -1290,50 +1464,23 @@ int rsolve_update_recycle(rsolve_seq* s, const double* x) {
         return RSOLVE_OK;
     }
     const int cc = (int)std::min<int64_t>(s->count, c.snapshots_s);
-    // TSQR of the ring X (n x cc) down to one cc x cc R factor
-    const double* M = s->X;
-    int64_t ldm = ld, rows = n;
-    int lvl = 0;
-    const double* R = nullptr;
-    for (;;) {
-        const int pr = tsqr_panel_rows(cc);
-        const int P = (int)((rows + pr - 1) / pr);
-        double* out = s->tsq[lvl & 1];
-        launch_tsqr_level(rows, M, ldm, cc, out, s->tsq_ld, P, stm);
-        R = out;
-        if (P == 1) break;
-        M = out;
-        ldm = s->tsq_ld;
-        rows = (int64_t)P * cc;
-        ++lvl;
-    }
-    HIP_TRY(hipMemsetAsync(s->ctl, 0, CTL_HEAD, stm));
-    launch_jacobi_svd(R, s->tsq_ld, cc, c.recycle_k, n, s->ctl, stm, c.select == RSOLVE_SELECT_SMALLEST);
-    HIP_TRY(hipGetLastError());
-    HIP_TRY(hipMemcpyAsync(s->hsig, ctl_sigma(s->ctl), sizeof(double) * cc, hipMemcpyDeviceToHost, stm));
-    int rc = read_head(s);
+    int keff = 0, rank = 0, bad = 0, lu_fail = 0;
+    int rc = svd_basis_dev(s, s->X, ld, cc, c.recycle_k, c.select == RSOLVE_SELECT_SMALLEST, s->W, ld, s->Wr,
+                           s->ldr, &keff, &rank, &bad, &lu_fail);
     if (rc) return rc;
     for (int i = 0; i < cc; ++i) s->sigma[i] = s->hsig[i];
     s->nsig = cc;
-    s->rank = s->hctl->rank;
-    if (s->hctl->nonfinite) {
+    s->rank = rank;
+    if (bad) {
         s->k_w = 0;
         set_err("non-finite snapshot");
         return RSOLVE_E_NONFINITE;
     }
-    const int keff = s->hctl->k_eff;
     if (keff > 0) {
-        launch_form_w(n, ld, s->X, ld, cc, keff, s->ctl, s->W, ld, stm);
-        const int gb = launch_gram_tn(ld, s->W, ld, keff, s->W, ld, keff, s->gpart, s->gblk, stm);
-        launch_gram_reduce(s->gpart, gb, keff * keff, ctl_red(s->ctl), stm);
-        launch_cholesky(keff, s->ctl, stm);
-        launch_trsm_rows(ld, s->W, ld, keff, s->ctl, stm, s->Wr, s->ldr);
         s->wr_ok = true;
         if (s->W32) launch_to_f32(keff * ld, s->W, s->W32, stm);
         HIP_TRY(hipGetLastError());
-        rc = read_head(s);
-        if (rc) return rc;
-        if (s->hctl->lu_fail) {
+        if (lu_fail) {
             s->k_w = 0;
             return RSOLVE_OK;
         }
@@ -1342,11 +1489,6 @@ int rsolve_update_recycle(rsolve_seq* s, const double* x) {
     return RSOLVE_OK;
 }
 
-// ---------------------------------------------------------------------------
-// Batched one-block path: every qualifying item of a batch is one block of a single launch
-// (k_small.hip); the others go through the multi-kernel path, one after the other, while the
-// launch runs.
-// ---------------------------------------------------------------------------
 int rsolve_solve_batch(rsolve_batch_solve_item* items, int32_t count, void* hip_stream) {
     const auto t0 = std::chrono::steady_clock::now();
     g_err[0] = 0;

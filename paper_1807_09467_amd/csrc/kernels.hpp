@@ -34,6 +34,18 @@ void launch_spmv_bc(int E, int LPR, int remap, int64_t n, const int32_t* p, cons
                     const int32_t* cstart, const int16_t* dict, const T* val, const T* win, T* vout, T* y,
                     const Ctl* ctl, hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 
+// ---- Ritz and harmonic Ritz pairs (k_eig.hip) ----
+// The k pairs of smallest modulus of Ga z = theta z (harmonic = 0) or Ga z = theta Gb z (harmonic =
+// 1), Ga, Gb r x r column-major (r <= SMAX), written as the r x kk coefficients ctl->T of the
+// recycle basis, kk in ctl->k_eff, |theta| in ctl->sigma; scratch of 9 SMAX^2 doubles; one
+// wavefront.  ctl->lu_fail = 1 (kk = 0) for a singular Gb or QR steps that do not converge.
+void launch_small_eig(const double* Ga, const double* Gb, int r, int k, int harmonic, double* scratch, Ctl* ctl,
+                      hipStream_t st);
+// out[:, c] = dinv .* V[:, c] in float64, c < cols (dinv nullable: a plain conversion)
+template <typename T>
+void launch_scale_cols(int64_t n, int64_t ld, const T* V, int cols, const double* dinv, double* out, int64_t ldo,
+                       hipStream_t st);
+
 void launch_validate(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* ci, int32_t* diag_pos,
                      int32_t* err, hipStream_t st);
 void launch_diag_inv(int64_t n, const int32_t* diag_pos, const double* val, double* dinv, hipStream_t st);

@@ -20,7 +20,7 @@ E_INVALID, E_NONFINITE, E_WORKSPACE, E_DEVICE, E_STATE, E_BUDGET = -1, -2, -3, -
 PLAIN, AUG_OBLIQUE, DEFL_OBLIQUE, AUG_ORTHO, DEFL_ORTHO = 0, 1, 2, 3, 4
 GUESS_PROJECT, GUESS_EXTRAP2, GUESS_EXTRAP3, GUESS_EXTRAP4 = 5, 6, 7, 8
 AUG_LS, DEFL_LS = 9, 10
-SELECT_LARGEST, SELECT_SMALLEST = 0, 1
+SELECT_LARGEST, SELECT_SMALLEST, SELECT_RITZ, SELECT_HARMONIC = 0, 1, 2, 3
 PRECOND_NONE, PRECOND_JACOBI = 0, 1
 FP64, FP32_IR = 0, 1
 SAME_PATTERN = 1
@@ -32,7 +32,8 @@ FLAG_NONFINITE = 4
 _METHODS = {"plain": PLAIN, "aug_oblique": AUG_OBLIQUE, "defl_oblique": DEFL_OBLIQUE, "aug_ortho": AUG_ORTHO,
             "defl_ortho": DEFL_ORTHO, "guess_project": GUESS_PROJECT, "guess_extrap2": GUESS_EXTRAP2,
             "guess_extrap3": GUESS_EXTRAP3, "guess_extrap4": GUESS_EXTRAP4, "aug_ls": AUG_LS, "defl_ls": DEFL_LS}
-_SELECTS = {"largest": SELECT_LARGEST, "smallest": SELECT_SMALLEST}
+_SELECTS = {"largest": SELECT_LARGEST, "smallest": SELECT_SMALLEST, "ritz": SELECT_RITZ,
+            "harmonic_ritz": SELECT_HARMONIC}
 _PRECONDS = {"none": PRECOND_NONE, "jacobi": PRECOND_JACOBI}
 _PRECISIONS = {"fp64": FP64, "fp32_ir": FP32_IR}
 
