@@ -297,9 +297,12 @@ TRAFFIC = {
 }
 
 
-def measured_traffic(kernel):
+def measured_traffic(kernel, alg_bytes):
     """HBM bytes per launch of `kernel` from its committed rocprofv3 counter summary, or None when
-    there is none or the kernel's sources have changed since the counters were taken."""
+    there is none or the kernel's sources have changed since the counters were taken.  A summary
+    of a kernel whose launches differ in width (the sweeps, whose columns grow with the Arnoldi
+    step) gives the measured traffic as a multiple of the algorithmic bytes of the same launches,
+    applied here to `alg_bytes`, the algorithmic bytes per launch of this run."""
     import hashlib
     import re
     if kernel not in TRAFFIC:
@@ -309,14 +312,17 @@ def measured_traffic(kernel):
         text = open(os.path.join(ROOT, "profiles", summary)).read()
     except OSError:
         return None
-    m = re.search(r"^traffic_bytes_per_launch=(\d+) kernel=(\S+) sources_sha256=([0-9a-f]{64})$", text, re.M)
-    if not m or m.group(2) != kernel:
+    m = re.search(r"^traffic_bytes_per_launch=(\d+)(?: traffic_per_algorithmic=([0-9.]+))? kernel=(\S+) "
+                  r"sources_sha256=([0-9a-f]{64})$", text, re.M)
+    if not m or m.group(3) != kernel:
         return None
     h = hashlib.sha256()
     for f in sources:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
-    return float(m.group(1)) if h.hexdigest() == m.group(3) else None
+    if h.hexdigest() != m.group(4):
+        return None
+    return float(m.group(2)) * alg_bytes if m.group(2) else float(m.group(1))
 
 
 def generate_batched(prob, nseq, nsteps, dev):
@@ -808,7 +814,7 @@ def main():
             r["algorithmic_bytes"] = "(columns swept + 1) w n per launch (basis, recycle columns, vectors)"
         elif c["kernel"] in ("dcgs2_update", "update_dots"):
             r["algorithmic_bytes"] = "(j + k + 4) w n per launch (basis, A W columns, candidate in and out)"
-        tr = measured_traffic(c["kernel"]) if pname == "C3" and cfg.get("precision") == "fp32_ir" else None
+        tr = measured_traffic(c["kernel"], alg) if pname == "C3" and cfg.get("precision") == "fp32_ir" else None
         if tr is not None:
             r["traffic"] = tr
             r["traffic_unit"] = "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
