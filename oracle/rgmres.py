@@ -48,9 +48,16 @@ convection-diffusion problems using singular value decomposition"):
   |theta| are kept (the small eigenvalues the deflation targets), a complex
   pair as the real and imaginary parts of its vector.
 
+* Or the paper's SSOR preconditioner (section 6.1), in its multicolour form:
+  symmetric SOR on the matrix permuted so that rows of one colour come
+  together, the colouring first-fit in natural row order over the
+  symmetrised pattern (rows of one colour never couple, so each half-sweep
+  is a sequence of independent colour steps).
+
 Readings where the paper is silent (each also listed in the design notes):
-* right Jacobi preconditioning D^{-1} (operator P A D^{-1}, x = x0 + D^{-1} V y),
-  so the GMRES residual is the true deflated residual;
+* right preconditioning, Jacobi D^{-1} or multicolour SSOR M (operator
+  P A M^{-1}, x = x0 + M^{-1} V y), so the GMRES residual is the true
+  deflated residual;
 * Arnoldi orthogonalisation is classical Gram-Schmidt applied twice (CGS2);
 * every cycle ends with the correction x += W E^{-1} W^T r, r <- P r, so the
   explicit stop test ||b - A x|| <= tol ||b|| applies to the true residual
@@ -81,7 +88,7 @@ LS_METHODS = (AUG_LS, DEFL_LS)
 PROJECTED_START_METHODS = (DEFL_ORTHO, DEFL_LS)   # deflated rows: Krylov initial vector P r
 EXTRAP_ORDER = {GUESS_EXTRAP2: 2, GUESS_EXTRAP3: 3, GUESS_EXTRAP4: 4}
 GUESS_ONLY_METHODS = (GUESS_PROJECT, GUESS_EXTRAP2, GUESS_EXTRAP3, GUESS_EXTRAP4)
-PRECOND_NONE, PRECOND_JACOBI = 0, 1
+PRECOND_NONE, PRECOND_JACOBI, PRECOND_SSOR = 0, 1, 2
 
 SPACE_SVD, SPACE_RITZ, SPACE_HARMONIC = "svd", "ritz", "harmonic_ritz"
 
@@ -105,6 +112,7 @@ class Config:
     max_iters: int = 10000
     select_smallest: bool = False
     recycle_space: str = SPACE_SVD   # SPACE_SVD (Algorithm 1), SPACE_RITZ or SPACE_HARMONIC (section 5.1)
+    ssor_omega: float = 1.0          # relaxation factor of PRECOND_SSOR, 0 < omega < 2
 
 
 @dataclasses.dataclass
@@ -118,7 +126,7 @@ class Result:
     rel_res_true: float
     res_history: List[float]        # explicit ||r||/||b|| at the end of every cycle
     implicit_history: List[float]   # |g_{j+1}|/||b|| after every Arnoldi step
-    krylov_x: Optional[np.ndarray] = None   # D^{-1} V_j of the last cycle: its x-space directions
+    krylov_x: Optional[np.ndarray] = None   # M^{-1} V_j of the last cycle: its x-space directions
 
 
 # ---------------------------------------------------------------------------
@@ -130,6 +138,71 @@ def jacobi_inverse(A) -> np.ndarray:
     """1 / diag(A): the diagonal (Jacobi) preconditioner, applied on the right."""
     d = A.diagonal().astype(np.float64)
     return 1.0 / d
+
+
+def greedy_colouring(A) -> np.ndarray:
+    """First-fit colouring of the symmetrised sparsity pattern of A in natural row order: row i
+    takes the smallest colour held by none of its neighbours j < i (j couples to i when a_ij or
+    a_ji is stored).  Rows of one colour never couple."""
+    import scipy.sparse as sp
+    n = A.shape[0]
+    S = sp.csr_matrix((np.ones(A.nnz), A.indices, A.indptr), shape=A.shape)
+    S = (S + S.T).tocsr()
+    colour = np.full(n, -1, dtype=np.int64)
+    for i in range(n):
+        nb = S.indices[S.indptr[i]:S.indptr[i + 1]]
+        used = set(colour[nb[nb < i]].tolist())
+        c = 0
+        while c in used:
+            c += 1
+        colour[i] = c
+    return colour
+
+
+class MulticolourSSOR:
+    """Symmetric SOR with relaxation omega as a preconditioner (the paper's SSOR, section 6.1),
+    on the ordering that takes the colours of `greedy_colouring` one after the other.  With D
+    the diagonal and L, U the couplings of each row to rows of lower and of higher colour,
+
+        M = (D + omega L) D^{-1} (D + omega U) / (omega (2 - omega)),
+
+    and M^{-1} r is one forward SOR sweep over the colours in increasing order from a zero
+    start followed by one backward sweep in decreasing order: here the two triangular solves
+    (D + omega L) y = omega (2 - omega) r and (D + omega U) z = D y on the permuted matrix, whose
+    strict lower triangle is L because rows of one colour do not couple."""
+
+    def __init__(self, A, omega: float = 1.0):
+        import scipy.sparse as sp
+        if not 0.0 < omega < 2.0:
+            raise ValueError("SSOR needs 0 < omega < 2")
+        self.omega = float(omega)
+        self.colour = greedy_colouring(A)
+        self.perm = np.argsort(self.colour, kind="stable")
+        Ap = A.tocsr()[self.perm][:, self.perm].tocsr()
+        self.d = Ap.diagonal().astype(np.float64)
+        Dm = sp.diags(self.d)
+        self.lower = (Dm + self.omega * sp.tril(Ap, -1)).tocsr()
+        self.upper = (Dm + self.omega * sp.triu(Ap, 1)).tocsr()
+
+    def __call__(self, r: np.ndarray) -> np.ndarray:
+        from scipy.sparse.linalg import spsolve_triangular
+        w = self.omega
+        y = spsolve_triangular(self.lower, w * (2.0 - w) * r[self.perm], lower=True)
+        z = spsolve_triangular(self.upper, self.d * y, lower=False)
+        out = np.empty_like(z)
+        out[self.perm] = z
+        return out
+
+
+def preconditioner(A, cfg: Config):
+    """M^{-1} as a function of a vector: identity, Jacobi D^{-1} or multicolour SSOR; applied on
+    the right (operator A M^{-1}, x = x0 + M^{-1} V y)."""
+    if cfg.precond == PRECOND_JACOBI:
+        dinv = jacobi_inverse(A)
+        return lambda v: dinv * v
+    if cfg.precond == PRECOND_SSOR:
+        return MulticolourSSOR(A, cfg.ssor_omega)
+    return lambda v: v
 
 
 def recycle_setup(A, W: np.ndarray):
@@ -203,10 +276,10 @@ def projection_correction(W, Z, E, x, r):
     return x + W @ c, r - Z @ c
 
 
-def krylov_update(x, dinv, V, y):
-    """x <- x + D^{-1} V y: the Krylov correction of one cycle mapped back through the
-    right preconditioner (section 3, right preconditioning A M y = b, x = M^{-1} y)."""
-    return x + dinv * (V @ y)
+def krylov_update(x, minv, V, y):
+    """x <- x + M^{-1} V y: the Krylov correction of one cycle mapped back through the
+    right preconditioner (section 3, right preconditioning A M^{-1} u = b, x = M^{-1} u)."""
+    return x + minv(V @ y)
 
 
 def is_lucky_breakdown(h_next: float, colnorm: float) -> bool:
@@ -318,7 +391,7 @@ def solve(A, b: np.ndarray, x0: Optional[np.ndarray], tol: float, cfg: Config,
     if bnorm == 0.0:
         return Result(np.zeros(n), 0, 0, 0, True, 0, 0.0, [0.0], [])
     flags = 0
-    dinv = jacobi_inverse(A) if cfg.precond == PRECOND_JACOBI else np.ones(n)
+    minv = preconditioner(A, cfg)
     use_w = cfg.method != PLAIN and W is not None and W.shape[1] > 0
     Z = E = None
     k_eff = 0
@@ -343,7 +416,7 @@ def solve(A, b: np.ndarray, x0: Optional[np.ndarray], tol: float, cfg: Config,
     lsq = cfg.method in LS_METHODS
 
     def op(v):
-        w = A @ (dinv * v)
+        w = A @ minv(v)
         if use_w_krylov:
             if lsq:
                 w = ls_project(Z, w)
@@ -382,8 +455,8 @@ def solve(A, b: np.ndarray, x0: Optional[np.ndarray], tol: float, cfg: Config,
             flags |= FLAG_BREAKDOWN_LUCKY
         j = cyc.steps
         y = scipy.linalg.solve_triangular(cyc.R[:j, :j], cyc.g[:j], lower=False)
-        x = krylov_update(x, dinv, cyc.V[:, :j], y)
-        last_kx = krylov_directions(dinv, cyc.V[:, :j])
+        x = krylov_update(x, minv, cyc.V[:, :j], y)
+        last_kx = krylov_directions(minv, cyc.V[:, :j])
         r = b - A @ x
         if use_w_krylov:
             x, r = correct(x, r)
@@ -456,9 +529,11 @@ def pair_basis(y: np.ndarray):
     return [y.real.copy(), y.imag.copy()]
 
 
-def krylov_directions(dinv: np.ndarray, V: np.ndarray) -> np.ndarray:
-    """The x-space directions of a cycle's Krylov basis under right preconditioning: D^{-1} V."""
-    return dinv[:, None] * V
+def krylov_directions(minv, V: np.ndarray) -> np.ndarray:
+    """The x-space directions of a cycle's Krylov basis under right preconditioning: M^{-1} V."""
+    if V.shape[1] == 0:
+        return V.copy()
+    return np.column_stack([minv(V[:, i]) for i in range(V.shape[1])])
 
 
 def ritz_basis(A, U: np.ndarray, k: int, harmonic: bool):

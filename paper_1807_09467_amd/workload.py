@@ -54,6 +54,10 @@ class Problem:
     [-1, 1] at every step (seeded; see forcing_coefficients).  Since v lies in
     the discrete space, (v, P f) = (v, f) for the L2 projection P of the paper.
 
+    beta_projected: use the L2 projection of beta onto the continuous Lagrange space of
+    the mesh (every node, no boundary condition) in the convection term, as the paper's
+    discrete problem does (section 6.1, P_{V_h} b), instead of beta itself.
+
     u0: 'bump' (a seeded Gaussian bump) or 'zero' (the paper's zero initial value).
 
     nodes: support points of the 1-D Lagrange basis, 'equispaced' or 'gll'
@@ -69,6 +73,7 @@ class Problem:
     forcing: bool = False
     u0: str = "bump"
     nodes: str = "equispaced"
+    beta_projected: bool = False
 
     @property
     def n1(self) -> int:
@@ -93,11 +98,13 @@ C3_SMALL = Problem(p=3, N=16, eps=1e-4, dt=5e-3, beta="rotating")
 # forcing, zero initial value, dt = 0.5; first-order elements on a 64 x 64 grid
 # for nu = 1e-1, 1e-2, 1e-3, and a 2 x 2 grid of order-23 Legendre spectral
 # elements (section 6.3) for nu = 1e-2.
-PAPER_Q1 = {nu: Problem(p=1, N=64, eps=nu, dt=0.5, beta="vortex", forcing=True, u0="zero")
+PAPER_Q1 = {nu: Problem(p=1, N=64, eps=nu, dt=0.5, beta="vortex", forcing=True, u0="zero", beta_projected=True)
             for nu in (1e-1, 1e-2, 1e-3)}
-PAPER_SEM23 = Problem(p=23, N=2, eps=1e-2, dt=0.5, beta="vortex", forcing=True, u0="zero", nodes="gll")
+PAPER_SEM23 = Problem(p=23, N=2, eps=1e-2, dt=0.5, beta="vortex", forcing=True, u0="zero", nodes="gll",
+                      beta_projected=True)
 # reduced spectral-element shape for the CPU oracle (same family, lower order)
-PAPER_SEM8 = Problem(p=8, N=2, eps=1e-2, dt=0.5, beta="vortex", forcing=True, u0="zero", nodes="gll")
+PAPER_SEM8 = Problem(p=8, N=2, eps=1e-2, dt=0.5, beta="vortex", forcing=True, u0="zero", nodes="gll",
+                     beta_projected=True)
 
 FORCING_MODES = 16
 FORCING_C = 0.1
@@ -321,17 +328,45 @@ class Assembler:
         self._mass_vals = None
 
     def _beta_at_quad(self):
-        """beta_x, beta_y at every (element, quadrature point)."""
+        """beta_x, beta_y at every (element, quadrature point); with `beta_projected`, those of its
+        L2 projection onto the mesh's continuous Lagrange space."""
         t, prob = self.tab, self.prob
         if prob.beta == "const":
             bx, by = prob.beta_const
             return float(bx), float(by)
+        if prob.beta_projected:
+            if getattr(self, "_beta_proj", None) is None:
+                fx, fy = beta_field(prob)
+                cx, cy = self.l2_projection(fx), self.l2_projection(fy)
+                en = self.pat.elem_nodes
+                self._beta_proj = (cx[en] @ t.phi.T, cy[en] @ t.phi.T)
+            return self._beta_proj
         x, y = self.quad_points()
-        if prob.beta == "rotating":
-            return -2.0 * math.pi * (y - 0.5), 2.0 * math.pi * (x - 0.5)
-        if prob.beta == "vortex":
-            return (-np.sin(math.pi * x) * np.cos(math.pi * y), np.cos(math.pi * x) * np.sin(math.pi * y))
-        raise ValueError(prob.beta)
+        fx, fy = beta_field(prob)
+        return fx(x, y), fy(x, y)
+
+    def full_mass(self):
+        """The consistent mass matrix of the whole continuous Lagrange space (every node, no
+        boundary condition), CSC."""
+        if getattr(self, "_full_mass", None) is None:
+            import scipy.sparse as sp
+            en = self.pat.elem_nodes
+            E, nl = en.shape
+            rows = np.repeat(en, nl, axis=1).ravel()
+            cols = np.tile(en, (1, nl)).ravel()
+            vals = np.broadcast_to(self.mass_e[None, :], (E, nl * nl)).ravel()
+            self._full_mass = sp.csc_matrix((vals, (rows, cols)), shape=(self.pat.n, self.pat.n))
+        return self._full_mass
+
+    def l2_projection(self, f) -> np.ndarray:
+        """Nodal coefficients c of the L2 projection of f(x, y) onto the mesh's continuous
+        Lagrange space: M c = F with F_a the integral of phi_a f by the element quadrature."""
+        from scipy.sparse.linalg import spsolve
+        t, pat = self.tab, self.pat
+        x, y = self.quad_points()
+        fq = f(x, y) * (self.h * self.h) * t.w[None, :]
+        F = np.bincount(pat.elem_nodes.ravel(), weights=(fq @ t.phi).ravel(), minlength=pat.n)
+        return spsolve(self.full_mass(), F)
 
     def quad_points(self):
         """Physical x, y of every (element, quadrature point)."""
@@ -419,6 +454,16 @@ class Assembler:
     def system(self, u_prev: np.ndarray, coeffs: Optional[np.ndarray] = None):
         """(vals, b) of step i given u^{i-1} (and step i's forcing coefficients)."""
         return self.matrix_values(u_prev), self.rhs(u_prev, coeffs)
+
+
+def beta_field(prob: Problem):
+    """(beta_x, beta_y) of a non-constant velocity field as functions of (x, y)."""
+    if prob.beta == "rotating":
+        return (lambda x, y: -2.0 * math.pi * (y - 0.5)), (lambda x, y: 2.0 * math.pi * (x - 0.5))
+    if prob.beta == "vortex":
+        return ((lambda x, y: -np.sin(math.pi * x) * np.cos(math.pi * y)),
+                (lambda x, y: np.cos(math.pi * x) * np.sin(math.pi * y)))
+    raise ValueError(prob.beta)
 
 
 def forcing_coefficients(seed: int, steps: int) -> np.ndarray:

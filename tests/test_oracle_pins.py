@@ -808,6 +808,106 @@ def test_ritz_recycling_deflates_small_eigenvalues(space):
     assert st.W.shape[1] == 4 and _max_angle_sin(st.W, X_B) <= 0.05
 
 
+# -- multicolour SSOR (the paper's preconditioner, section 6.1) ---------------------------
+
+
+def _sor_sweeps(A, r, omega, order):
+    """One forward SOR sweep over `order` from a zero start, then one backward sweep over it
+    reversed: each row in turn takes the SOR update from the current values, in place."""
+    Ad = A.toarray()
+    z = np.zeros(len(r))
+    for seq in (order, order[::-1]):
+        for i in seq:
+            s = r[i] - Ad[i] @ z + Ad[i, i] * z[i]
+            z[i] = (1.0 - omega) * z[i] + omega * s / Ad[i, i]
+    return z
+
+
+@pytest.mark.parametrize("omega", [1.0, 1.4, 0.6])
+def test_ssor_is_one_symmetric_sor_sweep(omega):
+    """M^{-1} r equals one forward and one backward SOR sweep from zero in the colour order,
+    written as plain loops over the rows of a nonsymmetric matrix (where forward-then-backward
+    and backward-then-forward differ)."""
+    A, _ = rand_system(40, 31, density=0.12, shift=3.0)
+    ssor = O.MulticolourSSOR(A, omega)
+    r = np.random.default_rng(2).standard_normal(40)
+    z = _sor_sweeps(A, r, omega, list(np.argsort(ssor.colour, kind="stable")))
+    assert np.abs(ssor(r) - z).max() <= 1e-12 * np.abs(z).max()
+
+
+def test_ssor_rows_of_one_colour_are_independent():
+    """Any order of the rows inside each colour gives the same sweeps (rows of one colour never
+    couple), and the colouring has no coupled pair inside a colour."""
+    A, _ = rand_system(40, 32, density=0.12, shift=3.0)
+    col = O.greedy_colouring(A)
+    coo = A.tocoo()
+    off = coo.row != coo.col
+    assert not np.any(col[coo.row[off]] == col[coo.col[off]])
+    r = np.random.default_rng(3).standard_normal(40)
+    rng = np.random.default_rng(4)
+    base = _sor_sweeps(A, r, 1.2, list(np.argsort(col, kind="stable")))
+    for _ in range(3):
+        order = [i for c in range(col.max() + 1) for i in rng.permutation(np.flatnonzero(col == c))]
+        assert np.abs(_sor_sweeps(A, r, 1.2, order) - base).max() <= 1e-13 * np.abs(base).max()
+    assert np.abs(O.MulticolourSSOR(A, 1.2)(r) - base).max() <= 1e-12 * np.abs(base).max()
+
+
+def test_first_fit_colouring_of_the_q1_grid():
+    """The 9-point pattern of first-order elements, Dirichlet rows decoupled: first fit in
+    natural order gives boundary nodes colour 0 and interior node (I, J) the colour
+    2 ((J - 1) mod 2) + (I - 1) mod 2, four colours in all; a path gives red-black colours."""
+    prob = WL.Problem(p=1, N=12, eps=1e-2, dt=0.5, beta="vortex")
+    asm = WL.Assembler(prob)
+    A = asm.csr(asm.matrix_values(np.zeros(prob.n)))
+    col = O.greedy_colouring(A)
+    J, I = np.divmod(np.arange(prob.n), prob.n1)
+    expect = 2 * ((J - 1) % 2) + (I - 1) % 2
+    expect[asm.pat.boundary] = 0
+    assert np.array_equal(col, expect)
+    path = sp.diags([np.ones(9), 4 * np.ones(10), np.ones(9)], [-1, 0, 1], format="csr")
+    assert np.array_equal(O.greedy_colouring(path), np.arange(10) % 2)
+
+
+@pytest.mark.parametrize("upper", [False, True])
+def test_ssor_is_exact_on_a_colour_triangular_matrix(upper):
+    """Couplings of odd rows to their even neighbours only (path colouring: even 0, odd 1) make
+    A = D + L in the colour order, so with omega = 1 M = (D + L) D^{-1} D = A; the couplings of
+    even rows to odd neighbours make A = D + U and M = D D^{-1} (D + U) = A.  M^{-1} A is the
+    identity and GMRES with this preconditioner stops after one step."""
+    rng = np.random.default_rng(12)
+    n = 21
+    A = sp.lil_matrix((n, n))
+    for i in range(n):
+        A[i, i] = 2.0 + rng.random()
+        if (i % 2 == 0) == upper:
+            for j in (i - 1, i + 1):
+                if 0 <= j < n:
+                    A[i, j] = rng.standard_normal()
+    A = A.tocsr()
+    ssor = O.MulticolourSSOR(A, 1.0)
+    assert np.array_equal(ssor.colour, np.arange(n) % 2)
+    v = rng.standard_normal(n)
+    assert np.abs(ssor(A @ v) - v).max() <= 1e-13 * np.abs(v).max()
+    b = rng.standard_normal(n)
+    res = O.solve(A, b, None, 1e-12, O.Config(restart_m=10, method=O.PLAIN, precond=O.PRECOND_SSOR))
+    assert res.converged and res.iterations == 1
+    assert np.linalg.norm(A @ res.x - b) <= 1e-12 * np.linalg.norm(b)
+
+
+def test_ssor_preconditioned_gmres_solves_and_helps():
+    """Right SSOR: the solve meets the true-residual tolerance, and on a convection-diffusion
+    system of the paper's family it takes fewer steps than Jacobi."""
+    prob = WL.Problem(p=1, N=24, eps=1e-2, dt=0.5, beta="vortex", forcing=True, u0="zero", beta_projected=True)
+    asm, systems, _ = WL.march(prob, 3, 0)
+    A, b = asm.csr(systems[2][0]), systems[2][1]
+    its = {}
+    for pc in (O.PRECOND_JACOBI, O.PRECOND_SSOR):
+        r = O.solve(A, b, None, 1e-10, O.Config(restart_m=30, method=O.PLAIN, precond=pc))
+        assert r.converged and np.linalg.norm(b - A @ r.x) <= 1e-10 * np.linalg.norm(b)
+        its[pc] = r.iterations
+    assert its[O.PRECOND_SSOR] < 0.75 * its[O.PRECOND_JACOBI], its
+
+
 # -- planted mistakes: each plausible error in the oracle is caught by a pin ----------
 
 
@@ -831,6 +931,10 @@ def _pins_pass():
         test_ritz_space_recovers_an_invariant_subspace(True)
         test_harmonic_ritz_values_are_inverse_ritz_values_of_the_inverse()
         test_krylov_directions_carry_the_last_cycle_update()
+        test_ssor_is_one_symmetric_sor_sweep(1.4)
+        test_ssor_rows_of_one_colour_are_independent()
+        test_first_fit_colouring_of_the_q1_grid()
+        test_ssor_is_exact_on_a_colour_triangular_matrix(False)
     except AssertionError:
         return False
     return True
@@ -849,9 +953,40 @@ def test_pins_pass_on_unmodified_oracle():
                                       "ls_deflated_start_unprojected", "lucky_never", "lucky_absolute",
                                       "lucky_loose", "ritz_largest_first", "harmonic_as_plain_ritz",
                                       "ritz_pair_real_part_only", "ritz_left_eigenvectors",
-                                      "krylov_directions_unpreconditioned"])
+                                      "krylov_directions_unpreconditioned", "ssor_sweeps_swapped",
+                                      "ssor_middle_diagonal_dropped", "ssor_scale_dropped",
+                                      "colouring_by_parity", "ssor_colours_reversed"])
 def test_planted_mistakes_are_caught(monkeypatch, mutation):
-    if mutation == "ritz_largest_first":
+    if mutation == "ssor_sweeps_swapped":
+        def swapped(self, r):
+            from scipy.sparse.linalg import spsolve_triangular
+            w = self.omega
+            y = spsolve_triangular(self.upper, w * (2.0 - w) * r[self.perm], lower=False)
+            z = spsolve_triangular(self.lower, self.d * y, lower=True)
+            out = np.empty_like(z)
+            out[self.perm] = z
+            return out
+        monkeypatch.setattr(O.MulticolourSSOR, "__call__", swapped)
+    elif mutation == "ssor_middle_diagonal_dropped":
+        def nodiag(self, r):
+            from scipy.sparse.linalg import spsolve_triangular
+            w = self.omega
+            y = spsolve_triangular(self.lower, w * (2.0 - w) * r[self.perm], lower=True)
+            z = spsolve_triangular(self.upper, y, lower=False)
+            out = np.empty_like(z)
+            out[self.perm] = z
+            return out
+        monkeypatch.setattr(O.MulticolourSSOR, "__call__", nodiag)
+    elif mutation == "ssor_scale_dropped":
+        orig_call = O.MulticolourSSOR.__call__
+        monkeypatch.setattr(O.MulticolourSSOR, "__call__",
+                            lambda self, r: orig_call(self, r) / (self.omega * (2.0 - self.omega)))
+    elif mutation == "colouring_by_parity":
+        monkeypatch.setattr(O, "greedy_colouring", lambda A: np.arange(A.shape[0]) % 2)
+    elif mutation == "ssor_colours_reversed":
+        orig_col = O.greedy_colouring
+        monkeypatch.setattr(O, "greedy_colouring", lambda A: (lambda c: c.max() - c)(orig_col(A)))
+    elif mutation == "ritz_largest_first":
         orig_o = O.ritz_order
         monkeypatch.setattr(O, "ritz_order", lambda th: orig_o(th)[::-1])
     elif mutation == "harmonic_as_plain_ritz":

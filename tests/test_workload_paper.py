@@ -141,3 +141,50 @@ def test_device_assembler_refuses_paper_problems():
     asm = WL.Assembler(WL.PAPER_Q1[1e-2])
     with pytest.raises(ValueError):
         WL.GpuAssembler(asm, torch.device("cpu"))
+
+
+def _node_xy(prob):
+    """Coordinates of the mesh nodes, node (I, J) at index J n1 + I."""
+    s = WL.support_points(prob.p, prob.nodes)
+    I = np.arange(prob.n1)
+    e = np.minimum(I // prob.p, prob.N - 1)
+    x1 = (e + s[I - e * prob.p]) / prob.N
+    X, Y = np.meshgrid(x1, x1)
+    return X.ravel(), Y.ravel()
+
+
+@pytest.mark.parametrize("p,nodes", [(1, "equispaced"), (2, "equispaced"), (3, "gll")])
+def test_l2_projection_reproduces_the_discrete_space(p, nodes):
+    """Section 6.1's P_{V_h}: a function already in the continuous Q_p space (degree p in each
+    variable) is its own projection, so the coefficients are its nodal values."""
+    prob = WL.Problem(p=p, N=5, eps=1e-2, dt=0.5, beta="vortex", nodes=nodes)
+    asm = WL.Assembler(prob)
+    X, Y = _node_xy(prob)
+    f = lambda x, y: (1.0 + x ** p) * (2.0 - 3.0 * y ** p) + x * y
+    c = asm.l2_projection(f)
+    assert np.abs(c - f(X, Y)).max() <= 1e-12
+
+
+@pytest.mark.parametrize("p", [1, 2])
+def test_l2_projection_of_the_vortex_converges_at_order_p_plus_one(p):
+    """The L2 error of the projected vortex field falls as h^{p+1} (ratios near 2^{p+1} when h
+    halves); the projection differs from the nodal interpolant by O(h^{p+1}) too but is not it."""
+    errs = []
+    for N in (8, 16, 32):
+        prob = WL.Problem(p=p, N=N, eps=1e-2, dt=0.5, beta="vortex", beta_projected=True)
+        asm = WL.Assembler(prob)
+        bx, by = asm._beta_at_quad()
+        x, y = asm.quad_points()
+        fx, fy = WL.beta_field(prob)
+        wq = (asm.h ** 2) * asm.tab.w[None, :]
+        errs.append(math.sqrt(float(np.sum(((bx - fx(x, y)) ** 2 + (by - fy(x, y)) ** 2) * wq))))
+        if N == 8:
+            X, Y = _node_xy(prob)
+            assert np.abs(asm.l2_projection(fx) - fx(X, Y)).max() > 1e-6
+    for a, b in zip(errs, errs[1:]):
+        assert 2 ** (p + 1) * 0.8 <= a / b <= 2 ** (p + 1) * 1.25, errs
+
+
+def test_paper_problems_project_the_velocity():
+    assert all(prob.beta_projected for prob in WL.PAPER_Q1.values())
+    assert WL.PAPER_SEM23.beta_projected and WL.PAPER_SEM8.beta_projected
