@@ -90,6 +90,14 @@ extern "C" {
                                      and r before the first cycle, which leaves the same iterates */
 #define RSOLVE_PRECOND_NONE   0
 #define RSOLVE_PRECOND_JACOBI 1   /* right Jacobi: operator P A D^{-1}, x = x0 + D^{-1} V y */
+#define RSOLVE_PRECOND_SSOR   2   /* right multicolour SSOR (the paper's SSOR of section 6.1 on a
+                                     colour ordering): M = (D + w L) D^{-1} (D + w U) / (w (2 - w)) with
+                                     L, U the couplings of each row to rows of lower / higher colour,
+                                     the colouring first fit in natural row order over the symmetrised
+                                     pattern (computed on the host when the pattern is validated, so
+                                     pass RSOLVE_SAME_PATTERN for a repeated pattern); operator
+                                     P A M^{-1}, x = x0 + M^{-1} V y.  FP64 only, CSR product, not with
+                                     the Ritz selections, not on the one-block path, no graphs */
 #define RSOLVE_FP64           0   /* everything in float64 */
 #define RSOLVE_FP32_IR        1   /* float32 Arnoldi cycles inside float64 iterative refinement */
 #define RSOLVE_SELECT_LARGEST 0   /* W = leading left singular vectors (Algorithm 1) */
@@ -137,7 +145,7 @@ typedef struct {
     int32_t method;        /* RSOLVE_PLAIN / _AUG_OBLIQUE / _DEFL_OBLIQUE / _AUG_ORTHO / _DEFL_ORTHO /
                               _GUESS_PROJECT / _GUESS_EXTRAP2 / _GUESS_EXTRAP3 / _GUESS_EXTRAP4 /
                               _AUG_LS / _DEFL_LS */
-    int32_t precond;       /* RSOLVE_PRECOND_NONE / RSOLVE_PRECOND_JACOBI */
+    int32_t precond;       /* RSOLVE_PRECOND_NONE / RSOLVE_PRECOND_JACOBI / RSOLVE_PRECOND_SSOR */
     int32_t precision;     /* RSOLVE_FP64 / RSOLVE_FP32_IR */
     int32_t max_iters;     /* cap on Arnoldi steps per solve (>= 1) */
     int32_t select;        /* RSOLVE_SELECT_LARGEST / _SMALLEST (SVD of the ring) / _RITZ / _HARMONIC */
@@ -145,6 +153,8 @@ typedef struct {
                               of the multi-kernel path (the one-block path always uses CGS2) */
     double  inner_tol;     /* FP32_IR only: an FP32 cycle stops once its residual estimate has
                               dropped by this factor (0 < inner_tol < 1); ignored for FP64 */
+    double  ssor_omega;    /* RSOLVE_PRECOND_SSOR: relaxation factor w, 0 < w < 2 (0 selects 1, symmetric
+                              Gauss-Seidel); ignored otherwise */
 } rsolve_config;
 
 typedef struct {
@@ -163,7 +173,12 @@ typedef struct {
     int32_t k_eff;         /* recycle columns used by this solve */
     int32_t converged;     /* 1 if ||b - A x||_2 <= tol ||b||_2 (checked explicitly in FP64) */
     uint32_t flags;        /* RSOLVE_FLAG_* */
-    int32_t reserved;
+    int32_t its_estimate_met; /* Arnoldi steps taken when a cycle first ended with its residual estimate
+                              |g_{j+1}| <= tol ||b||_2 (the projected residual for the orthogonal and
+                              least-squares rows): the count of a solver that stops on that estimate,
+                              as a left-preconditioned GMRES stopping on its own residual does; 0 when
+                              the initial guess already meets tol, -1 when no cycle met it.  The
+                              one-block path reports the step count of a converged solve */
     double rel_res_true;   /* ||b - A x||_2 / ||b||_2 of the returned x (FP64) */
     double rel_res_implicit; /* last Givens residual estimate / ||b||_2 */
     double t_setup_ms;     /* validation, Jacobi scaling, A W, W^T A W, LU, initial guess */

@@ -55,6 +55,18 @@ int rsolve_gram_tn_noalloc(int64_t n, const double* A, int64_t lda, int32_t p, c
                            int32_t q, double* C_host, void* hip_stream);
 
 /*
+ * The colouring behind RSOLVE_PRECOND_SSOR (the multicolour form of the SSOR preconditioner of
+ * section 6.1): first fit in natural row order over the symmetrised pattern of an n x n CSR
+ * pattern (row i takes the smallest colour held by no row j < i with a_ij or a_ji stored), so
+ * rows of one colour never couple.  Host code on host arrays: row_ptr (n + 1 entries, from 0,
+ * nondecreasing), col_idx (row_ptr[n] entries in 0..n-1); colour (host, n entries) receives
+ * colours 0..*ncolours-1.  Does not use the GPU.  Errors: E_INVALID (null pointer, n < 1, a
+ * row pointer or column out of range).
+ */
+int rsolve_colour_first_fit(int64_t n, const int32_t* row_ptr, const int32_t* col_idx, int32_t* colour,
+                            int32_t* ncolours);
+
+/*
  * The SVD step of Algorithm 1 (section 5.2) on an arbitrary snapshot matrix
  * X (n x c, c <= 64): R from a Householder TSQR of X, one-sided Jacobi SVD of
  * R, then W = X V_k Sigma_k^{-1} re-orthonormalised, with

@@ -18,7 +18,8 @@ CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "librsolve.so")
 GEN_OUT = os.path.join(PKG, "libqkgen.so")
 BUILD_DIR = os.path.join(PKG, "_build")
-SOURCES = ["k_sparse.hip", "k_krylov.hip", "k_dense.hip", "k_eig.hip", "k_small.hip", "engine.hip", "server.hip"]
+SOURCES = ["k_sparse.hip", "k_krylov.hip", "k_dense.hip", "k_eig.hip", "k_ssor.hip", "k_small.hip", "engine.hip",
+           "server.hip"]
 ARCH = "gfx950"
 
 

@@ -17,6 +17,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <type_traits>
 #include <mutex>
 #include <unordered_map>
 #include <tuple>
@@ -91,7 +92,12 @@ int cfg_check(const rsolve_config* c) {
     // the extrapolation methods keep a ring of at least `order` solutions and no recycle space
     if (extrap_order(c->method) && (c->recycle_k != 0 || c->snapshots_s < extrap_order(c->method)))
         return RSOLVE_E_INVALID;
-    if (c->precond != RSOLVE_PRECOND_NONE && c->precond != RSOLVE_PRECOND_JACOBI) return RSOLVE_E_INVALID;
+    if (c->precond != RSOLVE_PRECOND_NONE && c->precond != RSOLVE_PRECOND_JACOBI && c->precond != RSOLVE_PRECOND_SSOR)
+        return RSOLVE_E_INVALID;
+    // multicolour SSOR: FP64 sweeps, and the Ritz search space would need M^{-1} of every basis vector
+    if (c->precond == RSOLVE_PRECOND_SSOR &&
+        (c->precision != RSOLVE_FP64 || ritz || !(c->ssor_omega == 0.0 || (c->ssor_omega > 0.0 && c->ssor_omega < 2.0))))
+        return RSOLVE_E_INVALID;
     if (c->precision != RSOLVE_FP64 && c->precision != RSOLVE_FP32_IR) return RSOLVE_E_INVALID;
     if (c->max_iters < 1) return RSOLVE_E_INVALID;
     if (c->select < RSOLVE_SELECT_LARGEST || c->select > RSOLVE_SELECT_HARMONIC) return RSOLVE_E_INVALID;
@@ -194,6 +200,13 @@ struct rsolve_seq {
     bool rz_pending = false;       // rz_w holds the next W
     double rz_theta[SMAX];         // |theta| of the kept pairs
     int last_steps = 0;            // Arnoldi steps of the last cycle of the last solve
+    // multicolour SSOR: the colouring of the current pattern (device arrays in the workspace, the
+    // colour offsets also on the host) and two work vectors
+    bool ssor = false;
+    SsorPlan sp;
+    int32_t *ss_colour = nullptr, *ss_rows = nullptr, *ss_coff = nullptr;
+    std::vector<int32_t> ss_coff_host;
+    double *ss_t = nullptr, *ss_u = nullptr;
     int k_w = 0, rank = 0, nsig = 0;
     int64_t count = 0;
     double sigma[SMAX];
@@ -298,6 +311,12 @@ size_t layout(rsolve_seq* s, const rsolve_config& c, int64_t n, int64_t nnz_max,
         rz_g = cv.take<double>((size_t)2 * SMAX * SMAX);
         rz_eig = cv.take<double>((size_t)9 * SMAX * SMAX);
     }
+    const bool ssor = c.precond == RSOLVE_PRECOND_SSOR;
+    int32_t* ss_colour = ssor ? cv.take<int32_t>((size_t)n) : nullptr;
+    int32_t* ss_rows = ssor ? cv.take<int32_t>((size_t)n) : nullptr;
+    int32_t* ss_coff = ssor ? cv.take<int32_t>((size_t)n + 1) : nullptr;
+    double* ss_t = ssor ? cv.take<double>((size_t)ld) : nullptr;
+    double* ss_u = ssor ? cv.take<double>((size_t)ld) : nullptr;
     const int tcols = std::max(rz ? rzc : 0, (k || extrap_order(c.method)) ? sn : 0);   // TSQR width
     int64_t tsq_rows = 0, tsq_ld = 0;
     double *t0 = nullptr, *t1 = nullptr;
@@ -350,8 +369,45 @@ size_t layout(rsolve_seq* s, const rsolve_config& c, int64_t n, int64_t nnz_max,
         s->rz_w = rz_w;
         s->rz_g = rz_g;
         s->rz_eig = rz_eig;
+        s->ssor = ssor;
+        s->ss_colour = ss_colour;
+        s->ss_rows = ss_rows;
+        s->ss_coff = ss_coff;
+        s->ss_t = ss_t;
+        s->ss_u = ss_u;
     }
     return align_up(cv.off, ALIGN);
+}
+
+// Multicolour SSOR: colour the (validated) pattern on the host and upload the colour of every row,
+// the rows grouped by colour and the colour offsets; the plan then serves every solve until the
+// pattern changes.
+int ssor_colour(rsolve_seq* s, const rsolve_csr* A) {
+    hipStream_t stm = s->stream;
+    const int64_t n = s->n;
+    std::vector<int32_t> rp((size_t)n + 1), ci((size_t)A->nnz), colour((size_t)n), rows;
+    HIP_TRY(hipMemcpyAsync(rp.data(), A->row_ptr, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToHost, stm));
+    HIP_TRY(hipMemcpyAsync(ci.data(), A->col_idx, sizeof(int32_t) * A->nnz, hipMemcpyDeviceToHost, stm));
+    HIP_TRY(hipStreamSynchronize(stm));
+    const int ncol = colour_first_fit(n, rp.data(), ci.data(), colour.data(), rows, s->ss_coff_host);
+    HIP_TRY(hipMemcpyAsync(s->ss_colour, colour.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, stm));
+    HIP_TRY(hipMemcpyAsync(s->ss_rows, rows.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, stm));
+    HIP_TRY(hipMemcpyAsync(s->ss_coff, s->ss_coff_host.data(), sizeof(int32_t) * (ncol + 1), hipMemcpyHostToDevice,
+                           stm));
+    HIP_TRY(hipStreamSynchronize(stm));   // the host vectors go out of scope
+    SsorPlan& p = s->sp;
+    p.n = n;
+    p.ncol = ncol;
+    p.lpr = ssor_lanes(n, A->nnz);
+    // one workgroup when the colours hold few rows on average (its barrier is cheaper than a
+    // launch), one launch per colour otherwise
+    p.single = n <= 16384 || (int64_t)ncol * 512 >= n;
+    p.omega = s->cfg.ssor_omega == 0.0 ? 1.0 : s->cfg.ssor_omega;
+    p.colour = s->ss_colour;
+    p.rows = s->ss_rows;
+    p.coff_dev = s->ss_coff;
+    p.coff_host = s->ss_coff_host.data();
+    return RSOLVE_OK;
 }
 
 // Pattern check on the device (row pointers, column range and order, diagonal present); on
@@ -371,6 +427,10 @@ int validate_pattern(rsolve_seq* s, const rsolve_csr* A) {
                 s->herr[2], s->herr[3]);
         return RSOLVE_E_INVALID;
     }
+    if (s->ssor) {
+        const int crc = ssor_colour(s, A);
+        if (crc) return crc;
+    }
     s->pat_rp = A->row_ptr;
     s->pat_ci = A->col_idx;
     s->pat_nnz = A->nnz;
@@ -380,8 +440,9 @@ int validate_pattern(rsolve_seq* s, const rsolve_csr* A) {
     s->cls_ok = false;
     if (!s->shape_set) {
         // banded padded format with 8-entry chunks and 4 lanes per row for finite-element rows of
-        // about a dozen entries or more; CSR otherwise
-        if (s->band_ok && (double)A->nnz >= 12.0 * (double)n) {
+        // about a dozen entries or more; CSR otherwise (always with SSOR, whose product takes the
+        // caller's values as they are)
+        if (s->band_ok && (double)A->nnz >= 12.0 * (double)n && !s->ssor) {
             s->sfmt = RSOLVE_SPMV_BANDED;
             s->svec = 8;
             s->lpr = 4;
@@ -500,6 +561,17 @@ double spmv_bytes(const rsolve_seq* s, double w, bool vout) {
 
 template <typename T>
 void arnoldi_product(rsolve_seq* s, const SpOp& op, const T* win, T* vout, T* y, hipEvent_t e0, hipEvent_t e1) {
+    if constexpr (std::is_same<T, double>::value) {
+        if (s->ssor) {
+            // y = s A M^{-1} win: the sweeps give M^{-1} win (and vout = s win), the product scales
+            launch_ssor_apply(s->sp, op.rp, op.ci, static_cast<const double*>(op.vals), s->diag_pos, win, s->ss_t,
+                              vout, s->ctl, s->stream);
+            launch_spmv_arnoldi<double>(s->lpr, s->svec, s->sremap, s->n, op.rp, op.ci,
+                                        static_cast<const double*>(op.vals), s->ss_t, nullptr, y, s->ctl, s->stream,
+                                        e0, e1);
+            return;
+        }
+    }
     if (op.fmt == RSOLVE_SPMV_BANDED && s->cls_ok)
         launch_spmv_bc<T>(s->svec, s->lpr, s->sremap, s->n, op.rp, s->cls_row, s->cls_start, s->cls_dict,
                           static_cast<const T*>(op.vals), win, vout, y, s->ctl, s->stream, e0, e1);
@@ -837,7 +909,8 @@ bool small_solve_ok(const rsolve_seq* s) {
     const rsolve_config& c = s->cfg;
     // the one-block solve implements the oblique projector (or none) only
     return c.precision == RSOLVE_FP64 && c.restart_m <= SMALL_MMAX && c.recycle_k <= SMALL_KMAX &&
-           s->n <= RSOLVE_SMALL_MAX_N && c.method <= RSOLVE_DEFL_OBLIQUE && !ritz_mode(c);
+           s->n <= RSOLVE_SMALL_MAX_N && c.method <= RSOLVE_DEFL_OBLIQUE && !ritz_mode(c) &&
+           c.precond != RSOLVE_PRECOND_SSOR;
 }
 
 bool small_update_ok(const rsolve_seq* s) {
@@ -1185,7 +1258,7 @@ int rsolve_solve(rsolve_seq* s, const rsolve_csr* A, const double* b, const doub
     if (jac) launch_diag_inv(n, s->diag_pos, A->val, s->dinv, stm);
     const double* dv = jac ? s->dinv : nullptr;
     SpOp op{RSOLVE_SPMV_CSR, A->row_ptr, A->col_idx, nullptr, A->val};
-    if (s->sfmt == RSOLVE_SPMV_BANDED) {
+    if (s->sfmt == RSOLVE_SPMV_BANDED && !s->ssor) {
         const int brc = bp_prepare(s, A, dv, ir);
         if (brc) return brc;
         op = SpOp{RSOLVE_SPMV_BANDED, s->bp_p, nullptr, s->bp_off, s->bp_val};
@@ -1280,6 +1353,7 @@ int rsolve_solve(rsolve_seq* s, const rsolve_csr* A, const double* b, const doub
     const double t_setup = ms_since(t0);
 
     int its = 0, cycles = 0;
+    int its_est = -1;   // steps when a cycle first ended with its estimate within tol ||b||
     bool converged = false;
     int status = RSOLVE_OK;
     double gimp = 0.0;
@@ -1302,6 +1376,7 @@ int rsolve_solve(rsolve_seq* s, const rsolve_csr* A, const double* b, const doub
         }
         if (rnorm <= stop_abs) {
             converged = true;
+            if (its_est < 0 && cycles == 0) its_est = 0;
             break;
         }
         if (its >= c.max_iters) {
@@ -1353,7 +1428,7 @@ int rsolve_solve(rsolve_seq* s, const rsolve_csr* A, const double* b, const doub
                     }
                 }
             };
-            if (s->graphs_on && !s->prof_on) {
+            if (s->graphs_on && !s->prof_on && !s->ssor) {
                 const rsolve_seq::GraphKey key{j0,      j1,         kry,       ir ? 1 : 0, s->lpr, s->svec, s->sremap,
                                                op.fmt,  (dg ? 1 : 0) | (orth ? 2 : 0) | (ls ? 4 : 0) | (s->cls_ok ? 8 : 0),
                                                dg ? max_steps : 0, op.rp, op.ci,
@@ -1373,8 +1448,18 @@ int rsolve_solve(rsolve_seq* s, const rsolve_csr* A, const double* b, const doub
             }
         }
         launch_cycle_solve(s->ctl, stm);
-        if (ir) launch_x_update<float>(n, s->V32, ld, jac ? s->dinv : nullptr, s->xw, s->ctl, stm);
-        else launch_x_update<double>(n, s->V, ld, jac ? s->dinv : nullptr, s->xw, s->ctl, stm);
+        if (ir) {
+            launch_x_update<float>(n, s->V32, ld, jac ? s->dinv : nullptr, s->xw, s->ctl, stm);
+        } else if (s->ssor) {
+            // x += M^{-1} (V y): V y into ss_u, the sweeps (not stopped by the cycle's done flag)
+            launch_fill(n, s->ss_u, 0.0, stm);
+            launch_x_update<double>(n, s->V, ld, nullptr, s->ss_u, s->ctl, stm);
+            launch_ssor_apply(s->sp, A->row_ptr, A->col_idx, A->val, s->diag_pos, s->ss_u, s->ss_t, nullptr,
+                              nullptr, stm);
+            launch_axpy(n, s->ss_t, s->xw, stm);
+        } else {
+            launch_x_update<double>(n, s->V, ld, jac ? s->dinv : nullptr, s->xw, s->ctl, stm);
+        }
         residual_and_correct(s, A, b, kry, Qd);
         HIP_TRY(hipGetLastError());
         rc = read_head(s);
@@ -1385,6 +1470,7 @@ int rsolve_solve(rsolve_seq* s, const rsolve_csr* A, const double* b, const doub
         s->last_steps = s->hctl->steps;
         cycles += 1;
         gimp = s->hctl->gimp;
+        if (its_est < 0 && s->hctl->steps > 0 && gimp <= stop_abs) its_est = its;
         if (s->hctl->lucky) flags |= RSOLVE_FLAG_BREAKDOWN_LUCKY;
         if (s->hctl->steps == 0) {
             // a cycle that cannot take a step cannot make progress
@@ -1406,7 +1492,7 @@ int rsolve_solve(rsolve_seq* s, const rsolve_csr* A, const double* b, const doub
         st->k_eff = k;
         st->converged = converged ? 1 : 0;
         st->flags = flags;
-        st->reserved = 0;
+        st->its_estimate_met = its_est;
         st->rel_res_true = rnorm_final / bnorm;
         st->rel_res_implicit = gimp / bnorm;
         st->t_setup_ms = t_setup;
@@ -1587,6 +1673,7 @@ int rsolve_solve_batch(rsolve_batch_solve_item* items, int32_t count, void* hip_
         o.cycles = J.cycles;
         o.k_eff = J.k_used;
         o.converged = J.converged;
+        o.its_estimate_met = J.converged ? J.iterations : -1;
         o.flags = J.flags;
         o.rel_res_true = J.bnorm > 0.0 ? J.rnorm / J.bnorm : 0.0;
         o.rel_res_implicit = J.bnorm > 0.0 ? J.gimp / J.bnorm : 0.0;
@@ -1718,6 +1805,20 @@ const char* rsolve_last_error(void) { return g_err; }
 // ---------------------------------------------------------------------------
 // kernel-level entry points
 // ---------------------------------------------------------------------------
+
+int rsolve_colour_first_fit(int64_t n, const int32_t* row_ptr, const int32_t* col_idx, int32_t* colour,
+                            int32_t* ncolours) {
+    g_err[0] = 0;
+    if (n < 1 || !row_ptr || !col_idx || !colour || !ncolours || row_ptr[0] != 0) return RSOLVE_E_INVALID;
+    for (int64_t i = 0; i < n; ++i) {
+        if (row_ptr[i + 1] < row_ptr[i]) return RSOLVE_E_INVALID;
+        for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e)
+            if (col_idx[e] < 0 || col_idx[e] >= n) return RSOLVE_E_INVALID;
+    }
+    std::vector<int32_t> rows, coff;
+    *ncolours = colour_first_fit(n, row_ptr, col_idx, colour, rows, coff);
+    return RSOLVE_OK;
+}
 
 int rsolve_spmv(const rsolve_csr* A, const double* x, double* y, void* hip_stream) {
     if (!A || !x || !y || !A->row_ptr || !A->col_idx || !A->val || A->n < 1) return RSOLVE_E_INVALID;

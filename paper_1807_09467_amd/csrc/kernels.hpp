@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "common.hpp"
 
 namespace rs {
@@ -33,6 +35,36 @@ template <typename T>
 void launch_spmv_bc(int E, int LPR, int remap, int64_t n, const int32_t* p, const uint16_t* cls,
                     const int32_t* cstart, const int16_t* dict, const T* val, const T* win, T* vout, T* y,
                     const Ctl* ctl, hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+
+// ---- multicolour SSOR (k_ssor.hip) ----
+// The colouring and grouping of one pattern: rows[coff[c] .. coff[c + 1]) are the rows of colour c
+// (no two of them couple).  `single`: the whole application in one workgroup that walks the
+// colours (small systems, or many colours of few rows); otherwise one launch per colour and sweep.
+struct SsorPlan {
+    int64_t n = 0;
+    int ncol = 0;
+    int lpr = 4;                          // lanes per row: 4, 16 or 64
+    bool single = true;
+    double omega = 1.0;
+    const int32_t* colour = nullptr;      // device, n
+    const int32_t* rows = nullptr;        // device, n
+    const int32_t* coff_dev = nullptr;    // device, ncol + 1
+    const int32_t* coff_host = nullptr;   // host, ncol + 1
+};
+// Lanes per row of the sweeps for a pattern of nnz entries over n rows.
+int ssor_lanes(int64_t n, int64_t nnz);
+// t = M^{-1} r (r and t distinct, n entries); when vout is given the forward sweep also writes
+// vout = ctl->inv_h r.  With ctl given every kernel returns at once once ctl->done is set.
+void launch_ssor_apply(const SsorPlan& p, const int32_t* rp, const int32_t* ci, const double* val,
+                       const int32_t* dpos, const double* r, double* t, double* vout, const Ctl* ctl,
+                       hipStream_t st);
+void launch_fill(int64_t n, double* x, double v, hipStream_t st);
+void launch_axpy(int64_t n, const double* t, double* x, hipStream_t st);   // x += t
+// First-fit colouring of the symmetrised pattern (host arrays) in natural row order: colour[i] is
+// the smallest colour held by no neighbour j < i; rows grouped by colour into rows / coff.
+// Returns the number of colours.
+int colour_first_fit(int64_t n, const int32_t* rp, const int32_t* ci, int32_t* colour, std::vector<int32_t>& rows,
+                     std::vector<int32_t>& coff);
 
 // ---- Ritz and harmonic Ritz pairs (k_eig.hip) ----
 // The k pairs of smallest modulus of Ga z = theta z (harmonic = 0) or Ga z = theta Gb z (harmonic =

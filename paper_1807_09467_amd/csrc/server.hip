@@ -104,7 +104,7 @@ struct Worker {
 
 bool fits_one_block(const rsolve_config& c, int64_t n) {
     return c.restart_m <= RSOLVE_SMALL_MAX_RESTART && c.recycle_k <= RSOLVE_SMALL_MAX_RECYCLE &&
-           n <= RSOLVE_SMALL_MAX_N && c.method <= RSOLVE_DEFL_OBLIQUE;
+           n <= RSOLVE_SMALL_MAX_N && c.method <= RSOLVE_DEFL_OBLIQUE && c.precond != RSOLVE_PRECOND_SSOR;
 }
 
 }  // namespace

@@ -21,7 +21,7 @@ PLAIN, AUG_OBLIQUE, DEFL_OBLIQUE, AUG_ORTHO, DEFL_ORTHO = 0, 1, 2, 3, 4
 GUESS_PROJECT, GUESS_EXTRAP2, GUESS_EXTRAP3, GUESS_EXTRAP4 = 5, 6, 7, 8
 AUG_LS, DEFL_LS = 9, 10
 SELECT_LARGEST, SELECT_SMALLEST, SELECT_RITZ, SELECT_HARMONIC = 0, 1, 2, 3
-PRECOND_NONE, PRECOND_JACOBI = 0, 1
+PRECOND_NONE, PRECOND_JACOBI, PRECOND_SSOR = 0, 1, 2
 FP64, FP32_IR = 0, 1
 SAME_PATTERN = 1
 
@@ -34,7 +34,7 @@ _METHODS = {"plain": PLAIN, "aug_oblique": AUG_OBLIQUE, "defl_oblique": DEFL_OBL
             "guess_extrap3": GUESS_EXTRAP3, "guess_extrap4": GUESS_EXTRAP4, "aug_ls": AUG_LS, "defl_ls": DEFL_LS}
 _SELECTS = {"largest": SELECT_LARGEST, "smallest": SELECT_SMALLEST, "ritz": SELECT_RITZ,
             "harmonic_ritz": SELECT_HARMONIC}
-_PRECONDS = {"none": PRECOND_NONE, "jacobi": PRECOND_JACOBI}
+_PRECONDS = {"none": PRECOND_NONE, "jacobi": PRECOND_JACOBI, "ssor": PRECOND_SSOR}
 _PRECISIONS = {"fp64": FP64, "fp32_ir": FP32_IR}
 
 # every symbol the two public headers declare
@@ -44,7 +44,7 @@ EXPORTS = [
     "rsolve_spmv", "rsolve_kernel_workspace_bytes", "rsolve_gram_tn", "rsolve_snapshot_svd",
     "rsolve_profile_enable", "rsolve_profile_read", "rsolve_solve_batch", "rsolve_update_recycle_batch",
     "rsolve_tune_spmv", "rsolve_set_spmv_shape", "rsolve_get_spmv_shape", "rsolve_enable_graphs",
-    "rsolve_graph_counts", "rsolve_gram_tn_noalloc",
+    "rsolve_graph_counts", "rsolve_gram_tn_noalloc", "rsolve_colour_first_fit",
     # serving loop (rsolve_server.h; bound in serve.py)
     "rsolve_server_create", "rsolve_server_open", "rsolve_server_submit", "rsolve_server_poll",
     "rsolve_server_close", "rsolve_server_info_get", "rsolve_server_destroy",
@@ -59,7 +59,7 @@ class Config(ctypes.Structure):
     _fields_ = [
         ("restart_m", c_int32), ("recycle_k", c_int32), ("snapshots_s", c_int32), ("svd_interval", c_int32),
         ("method", c_int32), ("precond", c_int32), ("precision", c_int32), ("max_iters", c_int32),
-        ("select", c_int32), ("ortho", c_int32), ("inner_tol", c_double),
+        ("select", c_int32), ("ortho", c_int32), ("inner_tol", c_double), ("ssor_omega", c_double),
     ]
 
 
@@ -73,7 +73,8 @@ class CSR(ctypes.Structure):
 class Stats(ctypes.Structure):
     _fields_ = [
         ("iterations", c_int32), ("cycles", c_int32), ("k_eff", c_int32), ("converged", c_int32),
-        ("flags", c_uint32), ("reserved", c_int32), ("rel_res_true", c_double), ("rel_res_implicit", c_double),
+        ("flags", c_uint32), ("its_estimate_met", c_int32), ("rel_res_true", c_double),
+        ("rel_res_implicit", c_double),
         ("t_setup_ms", c_double), ("t_cycles_ms", c_double), ("t_total_ms", c_double),
     ]
 
@@ -152,6 +153,8 @@ def load():
     lib.rsolve_gram_tn_noalloc.argtypes = [c_int64, c_void_p, c_int64, c_int32, c_void_p, c_int64, c_int32,
                                            POINTER(c_double), c_void_p]
     lib.rsolve_gram_tn_noalloc.restype = c_int
+    lib.rsolve_colour_first_fit.argtypes = [c_int64, c_void_p, c_void_p, c_void_p, POINTER(c_int32)]
+    lib.rsolve_colour_first_fit.restype = c_int
     lib.rsolve_snapshot_svd.argtypes = [c_int64, c_void_p, c_int64, c_int32, c_int32, c_void_p, c_int64,
                                         POINTER(c_double), POINTER(c_int32), POINTER(c_int32), c_void_p, c_size_t,
                                         c_void_p]
@@ -189,9 +192,11 @@ _ORTHOS = {"cgs2": 0, "dcgs2": 1}
 
 
 def make_config(restart_m=30, recycle_k=0, snapshots_s=0, svd_interval=1, method="aug_oblique", precond="none",
-                precision="fp64", max_iters=10000, inner_tol=1e-5, ortho="cgs2", select="largest") -> Config:
+                precision="fp64", max_iters=10000, inner_tol=1e-5, ortho="cgs2", select="largest",
+                ssor_omega=1.0) -> Config:
     return Config(restart_m, recycle_k, snapshots_s, svd_interval, _METHODS[method], _PRECONDS[precond],
-                  _PRECISIONS[precision], max_iters, _SELECTS[select], _ORTHOS[ortho], float(inner_tol))
+                  _PRECISIONS[precision], max_iters, _SELECTS[select], _ORTHOS[ortho], float(inner_tol),
+                  float(ssor_omega))
 
 
 def workspace_bytes(cfg: Config, n: int, nnz_max: int) -> int:
@@ -551,6 +556,20 @@ def gram_tn(A, B, stream=None):
 def last_error():
     """The library's description of the last error seen by this thread ("" if none)."""
     return load().rsolve_last_error().decode()
+
+
+def colour_first_fit(row_ptr, col_idx):
+    """The SSOR colouring of a CSR pattern (host numpy arrays): (colour per row, colours)."""
+    import numpy as np
+    lib = load()
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+    ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+    n = rp.size - 1
+    colour = np.empty(max(n, 1), dtype=np.int32)
+    nc = c_int32()
+    _check(lib.rsolve_colour_first_fit(n, c_void_p(rp.ctypes.data), c_void_p(ci.ctypes.data),
+                                       c_void_p(colour.ctypes.data), byref(nc)))
+    return colour[:n], nc.value
 
 
 def gram_tn_noalloc(A, B, stream=None, check=True):

@@ -43,7 +43,7 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 def test_struct_layouts():
-    assert ctypes.sizeof(rsolve.Config) == 48
+    assert ctypes.sizeof(rsolve.Config) == 56
     assert ctypes.sizeof(rsolve.CSR) == 48
     assert ctypes.sizeof(rsolve.Stats) == 64
 

@@ -34,8 +34,9 @@ def run_pair(dev, prob, steps, tol, seed=0, precision="fp64", oracle_tol=None, *
                             "guess_extrap2": O.GUESS_EXTRAP2, "guess_extrap3": O.GUESS_EXTRAP3,
                             "guess_extrap4": O.GUESS_EXTRAP4, "aug_ls": O.AUG_LS,
                             "defl_ls": O.DEFL_LS}[kw.get("method", "aug_oblique")],
-                    precond=O.PRECOND_JACOBI if kw.get("precond") == "jacobi" else O.PRECOND_NONE,
-                    select_smallest=kw.get("select") == "smallest")
+                    precond={"jacobi": O.PRECOND_JACOBI, "ssor": O.PRECOND_SSOR}.get(kw.get("precond"),
+                                                                                     O.PRECOND_NONE),
+                    select_smallest=kw.get("select") == "smallest", ssor_omega=kw.get("ssor_omega", 1.0))
     ost = O.RecycleState(pat.n, ocfg)
     import torch
     xg_prev = torch.zeros(pat.n, dtype=torch.float64, device=dev)
