@@ -1,7 +1,8 @@
 """GPU parity on the paper's own experiments (section 6.1 and Tables 2-4): the vortex field
 with random low-mode forcing from a zero initial value, dt = 0.5, first-order elements on a
 64 x 64 grid and a 2 x 2 grid of order-23 Legendre spectral elements (n = 2,209, about 506
-non-zeros per row).  Right Jacobi stands in for the paper's SSOR on both sides.
+non-zeros per row).  Right Jacobi on both sides here; the paper's SSOR, in its multicolour form,
+has its own parity tests (test_gpu_ssor.py).
 
 Bars: the oblique rows to the standard ones (float64 solutions within 1e-9 relative of the
 oracle at tol 1e-10, Arnoldi steps within 2, the same k_eff); the orthogonal row (the paper's
