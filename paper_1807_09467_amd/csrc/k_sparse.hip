@@ -242,14 +242,31 @@ __global__ __launch_bounds__(BLOCK) void k_bp_pack(int64_t n, const int32_t* __r
 // 16-byte store (padding positions get 0), so the row's region is written whole and in order.
 // The entry at row-local position t (chunk t / E, slot t % E) is the inverse of bp_pos: with
 // it = chunk / LPR, l = chunk % LPR and g the lanes of that round, entry it E LPR + slot g + l.
-template <typename T>
+constexpr int BPV_ROWS = BLOCK / 8;     // rows per block of the value refill
+constexpr int BPV_STAGE = 2048;         // CSR entries staged (32 rows of up to 64 entries)
+
+template <typename T, int E, int LPR>
 __global__ __launch_bounds__(BLOCK) void k_bp_values(int64_t n, const int32_t* __restrict__ rp,
                                                      const int32_t* __restrict__ ci, const double* __restrict__ val,
                                                      const double* __restrict__ dinv, const int32_t* __restrict__ p,
-                                                     int E, int LPR, T* __restrict__ out) {
-    const int64_t gt = (int64_t)xcd_block(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
-    const int64_t i = gt / 8;
-    const int sub = (int)(gt % 8);
+                                                     T* __restrict__ out) {
+    // the block's rows are one contiguous CSR slice: scaled and rounded once, by coalesced loads,
+    // into LDS when it fits, then written in the banded copy's order
+    __shared__ T lv[BPV_STAGE];
+    const int64_t row0 = (int64_t)xcd_block(blockIdx.x, gridDim.x) * BPV_ROWS;
+    const int64_t rowe = row0 + BPV_ROWS < n ? row0 + BPV_ROWS : n;
+    const int e0 = rp[row0], e1 = rp[rowe];
+    const bool staged = e1 - e0 <= BPV_STAGE;   // the same for the whole block
+    if (staged) {
+        for (int e = e0 + (int)threadIdx.x; e < e1; e += BLOCK) {
+            double v = val[e];
+            if (dinv) v *= dinv[ci[e]];
+            lv[e - e0] = (T)v;
+        }
+    }
+    __syncthreads();
+    const int64_t i = row0 + threadIdx.x / 8;
+    const int sub = (int)(threadIdx.x % 8);
     if (i >= n) return;
     const int a = rp[i], L = rp[i + 1] - a;
     const int c0 = p[i], LP = p[i + 1] - c0;
@@ -265,12 +282,17 @@ __global__ __launch_bounds__(BLOCK) void k_bp_values(int64_t n, const int32_t* _
             const int it = chunk / LPR, l = chunk - it * LPR;
             const int g = min(LPR, LP - LPR * it);
             const int kk = it * R + slot * g + l;
-            double v = 0.0;
+            T v = (T)0;
             if (kk < L) {
-                v = val[a + kk];
-                if (dinv) v *= dinv[ci[a + kk]];
+                if (staged) {
+                    v = lv[a - e0 + kk];
+                } else {
+                    double d = val[a + kk];
+                    if (dinv) d *= dinv[ci[a + kk]];
+                    v = (T)d;
+                }
             }
-            o[e] = (T)v;
+            o[e] = v;
         }
         __builtin_memcpy(dst + t0, o, sizeof(o));
     }
@@ -307,22 +329,18 @@ __global__ __launch_bounds__(BLOCK) void k_spmv(int64_t n, const int32_t* __rest
 
 // Z[:, c0 + c] = A W[:, c0 + c], c < kc <= 16, with W given row-major (Wr[row * ldr + col],
 // ldr a multiple of 16): four lanes per row, lane s owning columns c0 + 4 s .. c0 + 4 s + 3;
-// every lane walks all entries of its row (two at a time), so each entry costs the four lanes one
-// 128-byte line of W between them and no reduction across lanes is needed.  (Measured on Q3 with
-// k = 16: 0.88 ms, against 1.1 ms for lanes that split the row's entries and take all 16 columns.)
-__global__ __launch_bounds__(BLOCK) void k_spmm_rows(int64_t n, const int32_t* __restrict__ rp,
-                                                     const int32_t* __restrict__ ci, const double* __restrict__ val,
-                                                     const double* __restrict__ Wr, int ldr, int c0, int kc,
-                                                     double* __restrict__ Z, int64_t ld) {
-    // XCD-aware rows: each XCD takes a contiguous share, so the W rows a block gathers (the columns
-    // near its rows) are fetched into that XCD's L2 once rather than once per XCD
-    const int64_t gt = (int64_t)xcd_block(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
-    const int64_t row = gt / 4;
-    const int sub = (int)(gt % 4);
-    if (row >= n) return;
-    const int a = rp[row], e = rp[row + 1];
-    const double* wb = Wr + c0 + 4 * sub;
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+// every lane walks all entries of its row, so each entry costs the four lanes one 128-byte line of
+// W between them and no reduction across lanes is needed.  (Measured on Q3 with k = 16: 0.88 ms,
+// against 1.1 ms for lanes that split the row's entries and take all 16 columns.)  The column
+// indices and values of the block's rows, one contiguous CSR slice, are first staged in LDS by
+// coalesced loads when the slice fits, so the four lanes of a row read them from LDS rather than
+// each loading them again.
+constexpr int SPMM_ROWS = BLOCK / 4;      // rows per block
+constexpr int SPMM_STAGE = 3200;          // CSR entries staged (64 rows of up to 50 entries)
+
+template <typename I, typename V>
+__device__ __forceinline__ void spmm_row(const I* __restrict__ cs, const V* __restrict__ vs, int a, int e,
+                                         const double* __restrict__ wb, int ldr, double acc[4]) {
     int j = a;
     // eight entries at a time: their column indices and values first, then the eight W gathers
     // together, so each round trip to memory carries eight entries rather than two
@@ -331,8 +349,8 @@ __global__ __launch_bounds__(BLOCK) void k_spmm_rows(int64_t n, const int32_t* _
         double v[8], w[8][4];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
-            c[u] = ci[j + u];
-            v[u] = val[j + u];
+            c[u] = cs[j + u];
+            v[u] = vs[j + u];
         }
 #pragma unroll
         for (int u = 0; u < 8; ++u)
@@ -343,21 +361,42 @@ __global__ __launch_bounds__(BLOCK) void k_spmm_rows(int64_t n, const int32_t* _
             for (int cc = 0; cc < 4; ++cc) acc[cc] += v[u] * w[u][cc];
         }
     }
-    for (; j + 1 < e; j += 2) {
-        const double v0 = val[j], v1 = val[j + 1];
-        double w0[4], w1[4];
-        __builtin_memcpy(w0, __builtin_assume_aligned(wb + (int64_t)ci[j] * ldr, 32), sizeof(w0));
-        __builtin_memcpy(w1, __builtin_assume_aligned(wb + (int64_t)ci[j + 1] * ldr, 32), sizeof(w1));
-#pragma unroll
-        for (int c = 0; c < 4; ++c) acc[c] += v0 * w0[c] + v1 * w1[c];
-    }
-    if (j < e) {
-        const double v0 = val[j];
+    for (; j < e; ++j) {
+        const double v0 = vs[j];
         double w0[4];
-        __builtin_memcpy(w0, __builtin_assume_aligned(wb + (int64_t)ci[j] * ldr, 32), sizeof(w0));
+        __builtin_memcpy(w0, __builtin_assume_aligned(wb + (int64_t)cs[j] * ldr, 32), sizeof(w0));
 #pragma unroll
         for (int c = 0; c < 4; ++c) acc[c] += v0 * w0[c];
     }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_spmm_rows(int64_t n, const int32_t* __restrict__ rp,
+                                                     const int32_t* __restrict__ ci, const double* __restrict__ val,
+                                                     const double* __restrict__ Wr, int ldr, int c0, int kc,
+                                                     double* __restrict__ Z, int64_t ld) {
+    __shared__ int32_t lci[SPMM_STAGE];
+    __shared__ double lval[SPMM_STAGE];
+    // XCD-aware rows: each XCD takes a contiguous share, so the W rows a block gathers (the columns
+    // near its rows) are fetched into that XCD's L2 once rather than once per XCD
+    const int64_t row0 = (int64_t)xcd_block(blockIdx.x, gridDim.x) * SPMM_ROWS;
+    const int64_t rowe = row0 + SPMM_ROWS < n ? row0 + SPMM_ROWS : n;
+    const int e0 = rp[row0], e1 = rp[rowe];
+    const bool staged = e1 - e0 <= SPMM_STAGE;   // the same for the whole block
+    if (staged) {
+        for (int e = e0 + (int)threadIdx.x; e < e1; e += BLOCK) {
+            lci[e - e0] = ci[e];
+            lval[e - e0] = val[e];
+        }
+    }
+    __syncthreads();
+    const int64_t row = row0 + threadIdx.x / 4;
+    const int sub = (int)(threadIdx.x % 4);
+    if (row >= n) return;
+    const int a = rp[row], e = rp[row + 1];
+    const double* wb = Wr + c0 + 4 * sub;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    if (staged) spmm_row(lci, lval, a - e0, e - e0, wb, ldr, acc);
+    else spmm_row(ci, val, a, e, wb, ldr, acc);
 #pragma unroll
     for (int c = 0; c < 4; ++c)
         if (4 * sub + c < kc) Z[(int64_t)(c0 + 4 * sub + c) * ld + row] = acc[c];
@@ -438,7 +477,18 @@ int bp_setup(int64_t n, const int32_t* rp, const int32_t* ci, int E, int LPR, in
 template <typename T>
 void launch_bp_values(int64_t n, const int32_t* rp, const int32_t* ci, const double* val, const double* dinv,
                       const int32_t* p, int E, int LPR, T* out, hipStream_t st) {
-    k_bp_values<T><<<grid_for(n * 8), BLOCK, 0, st>>>(n, rp, ci, val, dinv, p, E, LPR, out);
+    const unsigned g = (unsigned)((n + BPV_ROWS - 1) / BPV_ROWS);
+#define RS_BPV(EE, L) k_bp_values<T, EE, L><<<g, BLOCK, 0, st>>>(n, rp, ci, val, dinv, p, out)
+    if (E == 4) {
+        if (LPR == 2) RS_BPV(4, 2);
+        else if (LPR == 4) RS_BPV(4, 4);
+        else RS_BPV(4, 8);
+    } else {
+        if (LPR == 2) RS_BPV(8, 2);
+        else if (LPR == 4) RS_BPV(8, 4);
+        else RS_BPV(8, 8);
+    }
+#undef RS_BPV
 }
 template void launch_bp_values<double>(int64_t, const int32_t*, const int32_t*, const double*, const double*,
                                        const int32_t*, int, int, double*, hipStream_t);
@@ -474,7 +524,8 @@ void launch_spmm_rows(int64_t n, const int32_t* rp, const int32_t* ci, const dou
                       int k, double* Z, int64_t ld, hipStream_t st) {
     for (int c0 = 0; c0 < k; c0 += 16) {
         const int kc = (k - c0) < 16 ? (k - c0) : 16;
-        k_spmm_rows<<<grid_for(n * 4), BLOCK, 0, st>>>(n, rp, ci, val, Wr, ldr, c0, kc, Z, ld);
+        k_spmm_rows<<<(unsigned)((n + SPMM_ROWS - 1) / SPMM_ROWS), BLOCK, 0, st>>>(n, rp, ci, val, Wr, ldr, c0, kc,
+                                                                                Z, ld);
     }
 }
 
