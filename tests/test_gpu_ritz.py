@@ -80,17 +80,19 @@ def _c3_small(steps):
     return [asm.csr(v) for v, _ in systems], [b for _, b in systems]
 
 
+@pytest.mark.parametrize("ortho", ["cgs2", "dcgs2"])
 @pytest.mark.parametrize("precond", ["none", "jacobi"])
 @pytest.mark.parametrize("select", ["ritz", "harmonic_ritz"])
-def test_ritz_step_matches_oracle(gpu_ctx, select, precond):
+def test_ritz_step_matches_oracle(gpu_ctx, select, precond, ortho):
     """Twelve steps of the small Q3 sequence, GMRES(56) with k = 8 (the widest search space, 64),
-    the oracle conditioned on the GPU's W and x0 at every step: the same Arnoldi step count (one
+    the oracle conditioned on the GPU's W and x0 at every step, with either Arnoldi scheme (the
+    search space is the last cycle's basis either way): the same Arnoldi step count (one
     either side where the last residual sits on the tolerance), solutions within 1e-9, the same
     recycle dimension, the kept moduli |theta| within 1e-6 and the next W within a subspace angle
     of 1e-9 (measured: 6e-11 at most).  The restart length is one each solve ends within: a solve whose last cycle is a
     short one started from a residual near 1e-6 builds its search space from few directions."""
     mats, bs = _c3_small(12)
-    out = _pair(gpu_ctx, mats, bs, 1e-10, 1e-10, select, 56, 8, precond=precond, conditioned=True)
+    out = _pair(gpu_ctx, mats, bs, 1e-10, 1e-10, select, 56, 8, precond=precond, conditioned=True, ortho=ortho)
     for r in out:
         ang = _max_angle_sin(r["W_gpu"], r["W_or"]) if r["k_gpu"] == r["k_or"] and r["k_gpu"] else -1.0
         print(f"  step {r['step']}: rel {r['rel']:.2e} its {r['st']['iterations']}/{r['ores'].iterations} "

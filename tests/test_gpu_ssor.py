@@ -57,6 +57,20 @@ def test_ssor_one_launch_per_colour(gpu_ctx):
     _check_parity(out)
 
 
+@pytest.mark.parametrize("method,k,s", [("guess_project", 4, 4), ("guess_extrap3", 0, 3), ("defl_ls", 6, 8),
+                                        ("defl_ortho", 6, 8)])
+def test_ssor_other_rows(gpu_ctx, method, k, s):
+    """The preconditioner under the section 4 guesses and the least-squares and orthogonal
+    projectors (Table 1): the same bars, one step per cycle more for the orthogonal row."""
+    print(f"[ssor] {method}", flush=True)
+    out = run_pair(gpu_ctx, WL.C2_SMALL, 6, 1e-10, restart_m=30, recycle_k=k, snapshots_s=s, precond="ssor",
+                   method=method, ortho="dcgs2")
+    if method == "defl_ortho":
+        _check_ortho(out)
+    else:
+        _check_parity(out)
+
+
 @pytest.mark.parametrize("omega", [0.7, 1.5])
 def test_ssor_relaxation(gpu_ctx, omega):
     print(f"[ssor] omega {omega}", flush=True)
