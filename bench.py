@@ -716,7 +716,8 @@ def main():
                     help="skip the attribution legs (plain GMRES in mixed precision, recycled FP64)")
     ap.add_argument("--roctx", action="store_true",
                     help="mark each timed region with a roctx range (for rocprofv3 --marker-trace)")
-    ap.add_argument("--oracle-steps", type=int, default=3, help="time steps the oracle solves for the CPU baseline")
+    ap.add_argument("--oracle-steps", type=int, default=4,
+                    help="time steps the oracle solves for the CPU baseline (about 25 s of host work at the default)")
     ap.add_argument("--no-profile", action="store_true",
                     help="run the timed solves without per-kernel event timing (roofline then null)")
     ap.add_argument("--calib-copy", action="store_true",
