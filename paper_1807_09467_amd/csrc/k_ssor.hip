@@ -25,6 +25,7 @@ namespace rs {
 namespace {
 
 constexpr int SSOR_BLOCK_THREADS = 1024;
+constexpr int64_t SSOR_LDS_ROWS = 3640;   // 18 bytes a row within 64 KB of LDS
 
 template <int LPR>
 __device__ __forceinline__ double lane_group_sum(double v) {
@@ -34,14 +35,30 @@ __device__ __forceinline__ double lane_group_sum(double v) {
 }
 
 // The part of row i's sum that a sweep takes: couplings to lower colours (forward) or higher
-// colours (backward); lane `sub` of LPR takes entries rp[i] + sub, rp[i] + sub + LPR, ...
+// colours (backward); lane `sub` of LPR takes entries rp[i] + sub, rp[i] + sub + LPR, ..., four at a
+// time.
 template <bool FWD, int LPR>
 __device__ __forceinline__ double colour_part(int i, int c, const int32_t* __restrict__ rp,
                                               const int32_t* __restrict__ ci, const double* __restrict__ val,
                                               const int32_t* __restrict__ colour, const double* t, int sub) {
     double acc = 0.0;
     const int e1 = rp[i + 1];
-    for (int e = rp[i] + sub; e < e1; e += LPR) {
+    int e = rp[i] + sub;
+    for (; e + 3 * LPR < e1; e += 4 * LPR) {   // four entries' indices and values before any use
+        int jj[4];
+        double vv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            jj[u] = ci[e + u * LPR];
+            vv[u] = val[e + u * LPR];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int cj = colour[jj[u]];
+            if (FWD ? (cj < c) : (cj > c)) acc += vv[u] * t[jj[u]];
+        }
+    }
+    for (; e < e1; e += LPR) {
         const int j = ci[e];
         const int cj = colour[j];
         if (FWD ? (cj < c) : (cj > c)) acc += val[e] * t[j];
@@ -119,6 +136,93 @@ __global__ __launch_bounds__(SSOR_BLOCK_THREADS) void k_ssor_block(int ncol, con
     }
 }
 
+// Row i's couplings to lower (FWD) or higher colours than c, with the colours and t in LDS; the
+// lane's entries are taken eight at a time, their indices and values loaded before any is used.
+template <bool FWD, int LPR>
+__device__ __forceinline__ double colour_part_lds(int a, int e1, int c, const int32_t* __restrict__ ci,
+                                                  const double* __restrict__ val, const uint16_t* cls,
+                                                  const double* ts, int sub) {
+    double acc = 0.0;
+    int e = a + sub;
+    for (; e + 7 * LPR < e1; e += 8 * LPR) {
+        int jj[8];
+        double vv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            jj[u] = ci[e + u * LPR];
+            vv[u] = val[e + u * LPR];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int cj = cls[jj[u]];
+            if (FWD ? (cj < c) : (cj > c)) acc += vv[u] * ts[jj[u]];
+        }
+    }
+    for (; e < e1; e += LPR) {
+        const int j = ci[e];
+        const int cj = cls[j];
+        if (FWD ? (cj < c) : (cj > c)) acc += val[e] * ts[j];
+    }
+    return acc;
+}
+
+// The one-workgroup application for systems of at most SSOR_LDS_ROWS rows, with t, the colours,
+// the rows grouped by colour and the row pointers held in LDS (18 bytes a row): each colour
+// step then waits on one global load, the row's entries, instead of four.  t is written back
+// to global memory at the end.
+template <int LPR>
+__global__ __launch_bounds__(SSOR_BLOCK_THREADS) void k_ssor_block_lds(int ncol, int n, const int32_t* __restrict__ coff,
+                                                                      const int32_t* __restrict__ rows,
+                                                                      const int32_t* __restrict__ rp,
+                                                                      const int32_t* __restrict__ ci,
+                                                                      const double* __restrict__ val,
+                                                                      const int32_t* __restrict__ dpos,
+                                                                      const int32_t* __restrict__ colour,
+                                                                      const double* __restrict__ r, double* __restrict__ t,
+                                                                      double* __restrict__ vout, double omega,
+                                                                      const Ctl* __restrict__ ctl) {
+    if (ctl && ctl->done) return;
+    extern __shared__ double lds_ssor[];
+    double* ts = lds_ssor;                                                  // n
+    int32_t* rps = reinterpret_cast<int32_t*>(ts + n);                      // n + 1
+    int32_t* rws = rps + (n + 1);                                           // n
+    uint16_t* cls = reinterpret_cast<uint16_t*>(rws + n);                   // n
+    for (int i = threadIdx.x; i <= n; i += SSOR_BLOCK_THREADS) rps[i] = rp[i];
+    for (int i = threadIdx.x; i < n; i += SSOR_BLOCK_THREADS) {
+        rws[i] = rows[i];
+        cls[i] = (uint16_t)colour[i];
+    }
+    __syncthreads();
+    constexpr int GROUPS = SSOR_BLOCK_THREADS / LPR;
+    const int group = threadIdx.x / LPR;
+    const int sub = threadIdx.x % LPR;
+    const double alpha = omega * (2.0 - omega);
+    for (int c = 0; c < ncol; ++c) {
+        const int q1 = coff[c + 1];
+        for (int q = coff[c] + group; q < q1; q += GROUPS) {
+            const int i = rws[q];
+            const double acc =
+                lane_group_sum<LPR>(colour_part_lds<true, LPR>(rps[i], rps[i + 1], c, ci, val, cls, ts, sub));
+            if (sub == 0) {
+                ts[i] = (alpha * r[i] - omega * acc) / val[dpos[i]];
+                if (vout) vout[i] = ctl->inv_h * r[i];
+            }
+        }
+        __syncthreads();
+    }
+    for (int c = ncol - 2; c >= 0; --c) {
+        const int q1 = coff[c + 1];
+        for (int q = coff[c] + group; q < q1; q += GROUPS) {
+            const int i = rws[q];
+            const double acc =
+                lane_group_sum<LPR>(colour_part_lds<false, LPR>(rps[i], rps[i + 1], c, ci, val, cls, ts, sub));
+            if (sub == 0) ts[i] -= omega * acc / val[dpos[i]];
+        }
+        __syncthreads();
+    }
+    for (int i = threadIdx.x; i < n; i += SSOR_BLOCK_THREADS) t[i] = ts[i];
+}
+
 __global__ __launch_bounds__(BLOCK) void k_fill(int64_t n, double* __restrict__ x, double v) {
     const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
     if (i < n) x[i] = v;
@@ -141,6 +245,17 @@ int ssor_lanes(int64_t n, int64_t nnz) {
 void launch_ssor_apply(const SsorPlan& p, const int32_t* rp, const int32_t* ci, const double* val,
                        const int32_t* dpos, const double* r, double* t, double* vout, const Ctl* ctl,
                        hipStream_t st) {
+    if (p.single && p.n <= SSOR_LDS_ROWS && p.ncol <= 65535) {
+        const size_t bytes = (size_t)p.n * 18 + 4;
+#define RS_SSOR_L(L)                                                                                          \
+    k_ssor_block_lds<L><<<1, SSOR_BLOCK_THREADS, bytes, st>>>(p.ncol, (int)p.n, p.coff_dev, p.rows, rp, ci, val, dpos, \
+                                                              p.colour, r, t, vout, p.omega, ctl)
+        if (p.lpr == 4) RS_SSOR_L(4);
+        else if (p.lpr == 16) RS_SSOR_L(16);
+        else RS_SSOR_L(64);
+#undef RS_SSOR_L
+        return;
+    }
     if (p.single) {
 #define RS_SSOR_B(L)                                                                                           \
     k_ssor_block<L><<<1, SSOR_BLOCK_THREADS, 0, st>>>(p.ncol, p.coff_dev, p.rows, rp, ci, val, dpos, p.colour, r, \
