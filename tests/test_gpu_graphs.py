@@ -53,3 +53,32 @@ def test_graph_replay_equals_eager(gpu_ctx, kw):
     for i, (a, b) in enumerate(zip(out[False], out[True])):
         assert torch.equal(a[0], b[0]), i
         assert a[1:] == b[1:], i
+
+
+def test_graphs_requested_for_ssor_run_eagerly(gpu_ctx):
+    """Multicolour SSOR sequences capture no graphs (their sweeps depend on the pattern's colour
+    count); with graphs requested they run eagerly and give bitwise the eager results."""
+    import torch
+    from paper_1807_09467_amd import rsolve
+    prob = WL.C3_SMALL
+    asm, systems, _ = WL.march(prob, 3, 4)
+    rp, ci = _t(asm.pat.row_ptr, gpu_ctx), _t(asm.pat.col_idx, gpu_ctx)
+    out = {}
+    for on in (False, True):
+        seq = rsolve.Sequence(asm.pat.n, asm.pat.nnz, device=gpu_ctx, restart_m=30, recycle_k=6, snapshots_s=8,
+                              precond="ssor")
+        seq.graphs(on)
+        x_prev = torch.zeros(asm.pat.n, dtype=torch.float64, device=gpu_ctx)
+        res = []
+        for i, (v, b) in enumerate(systems):
+            x, st, status = seq.solve(rp, ci, _t(v, gpu_ctx), _t(b, gpu_ctx), x0=x_prev, tol=1e-10,
+                                      same_pattern=i > 0)
+            assert status == 0 and st["converged"] == 1
+            seq.update()
+            res.append((x.clone(), st["iterations"]))
+            x_prev = x
+        assert seq.graph_counts() == (0, 0)
+        out[on] = res
+        seq.close()
+    for a, b in zip(out[False], out[True]):
+        assert torch.equal(a[0], b[0]) and a[1] == b[1]

@@ -129,3 +129,23 @@ def test_failed_request_is_isolated(gpu_ctx):
     for sid in ids:
         srv.close(sid)
     srv.destroy()
+
+
+def test_serving_ssor_sequences(gpu_ctx):
+    """Sequences configured with multicolour SSOR are served on the multi-kernel path (none is
+    batched) and give bitwise the same solutions alone and in the mix."""
+    import torch
+    from paper_1807_09467_amd import serve
+    specs = [serve.SeqSpec(0, 0.000, 1, 32, 1e-2, 4, 31), serve.SeqSpec(1, 0.002, 2, 64, 1e-3, 3, 32),
+             serve.SeqSpec(2, 0.004, 1, 96, 5e-3, 3, 33)]
+    cfg = dict(restart_m=30, recycle_k=6, snapshots_s=8, precond="ssor")
+    cache = serve.AssemblerCache(gpu_ctx)
+    _, summ, mixed = serve.run_serving(specs, cfg, 1e-8, gpu_ctx, 2 << 30, large_workers=2, cache=cache,
+                                       keep_solutions={s.idx for s in specs})
+    assert summ["all_converged"] and summ["batched_fraction"] == 0.0
+    for sp in specs:
+        alone_spec = serve.SeqSpec(sp.idx, 0.0, sp.p, sp.N, sp.eps, sp.steps, sp.seed)
+        _, _, alone = serve.run_serving([alone_spec], cfg, 1e-8, gpu_ctx, 2 << 30, large_workers=2, cache=cache,
+                                        keep_solutions={sp.idx})
+        for i, (xa, xm) in enumerate(zip(alone[sp.idx], mixed[sp.idx])):
+            assert torch.equal(xa, xm), (sp.idx, i)
