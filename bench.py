@@ -606,6 +606,32 @@ def bench_guess_table(args, gasm, u0, systems, tol, cfg, desc, dev):
     print(json.dumps(out), flush=True)
 
 
+def stream_triad(dev, n=1 << 27, reps=20):
+    """The library's streaming reference kernel (a = b + s c, 24 n bytes a launch) timed with HIP
+    events: the HBM rate a plain stream reaches on this device, beside the 8 TB/s peak the
+    rooflines are quoted against."""
+    import torch
+
+    from paper_1807_09467_amd import rsolve
+    a = torch.empty(n, dtype=torch.float64, device=dev)
+    b = torch.ones(n, dtype=torch.float64, device=dev)
+    c = torch.ones(n, dtype=torch.float64, device=dev)
+    stm = torch.cuda.current_stream(dev)
+    for _ in range(2):
+        rsolve.triad(a, b, c, 0.5, stream=stm)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stm)
+    for _ in range(reps):
+        rsolve.triad(a, b, c, 0.5, stream=stm)
+    e1.record(stm)
+    e1.synchronize()
+    us = 1e3 * e0.elapsed_time(e1) / reps
+    gbs = 24.0 * n / (us * 1e-6) / 1e9
+    del a, b, c
+    return {"gbs": round(gbs, 1), "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4), "bytes_per_launch": 24 * n,
+            "us_per_launch": round(us, 2), "kernel": "k_triad (rsolve_triad), float64, 16-byte accesses"}
+
+
 def cpu_baseline(prob, asm_host, tol, cfg, steps=3):
     """The oracle on the host cores: its own recycled solves of the first `steps` time steps of the
     same sequence (same restart, recycle dimension, snapshots, Jacobi and tolerance; Algorithm 1 update
@@ -838,6 +864,9 @@ def main():
         e["avg_us"] = 1e3 * e["ms"] / e["launches"]
         e["gb_per_s"] = e["bytes"] / (e["ms"] * 1e-3) / 1e9
 
+    triad = stream_triad(dev)
+    log(f"stream triad: {triad['gbs']:.0f} GB/s ({triad['frac_of_peak']:.3f} of {HBM_PEAK_GBS:.0f})")
+
     cpu = None
     err = None
     if not args.no_cpu_baseline and pname == "C3":
@@ -879,6 +908,7 @@ def main():
         "rooflines": rooflines,
         "kernels": [{k: (round(v, 3) if isinstance(v, float) else v) for k, v in e.items()} for e in prof],
         "err_vs_oracle": err,
+        "stream_triad": triad,
         "cpu_baseline": cpu,
     }
     if legs and plain_sum:

@@ -55,6 +55,14 @@ int rsolve_gram_tn_noalloc(int64_t n, const double* A, int64_t lda, int32_t p, c
                            int32_t q, double* C_host, void* hip_stream);
 
 /*
+ * a = b + s c over n float64 values (a, b, c device arrays, 16-byte aligned, a not overlapping b
+ * or c): a streaming kernel with 16-byte loads and stores, the measured reference for the HBM
+ * roofline of the hot kernels (24 n bytes per call).  Asynchronous on `hip_stream`.  Errors:
+ * E_INVALID (null or misaligned pointer, n < 1).
+ */
+int rsolve_triad(int64_t n, double* a, const double* b, const double* c, double s, void* hip_stream);
+
+/*
  * The colouring behind RSOLVE_PRECOND_SSOR (the multicolour form of the SSOR preconditioner of
  * section 6.1): first fit in natural row order over the symmetrised pattern of an n x n CSR
  * pattern (row i takes the smallest colour held by no row j < i with a_ij or a_ji stored), so

@@ -757,10 +757,12 @@ void dcgs2_step(rsolve_seq* s, int j, int allowed, const SpOp& op, T* V, T* cons
         launch_dots2<T>(ld, ld, V, j, Wt, Zt, k, kz, zskip, u, has_z ? z : u, s->partial, nb1, s->ctl, st, pe.e0,
                         pe.e1);
     }
-    launch_dcgs2_reduce(s->partial, nb1, j, k, kz, orth, has_z, s->ctl, st, zskip ? zpart : nullptr, s->nblk, s->gz);
+    // the update's grid: one 32-byte slice of every column per thread; its A W partials number the same
+    const int nbu = dcgs2_update_blocks(ld, (int)sizeof(T), s->nblk);
+    launch_dcgs2_reduce(s->partial, nb1, j, k, kz, orth, has_z, s->ctl, st, zskip ? zpart : nullptr, nbu, s->gz);
     if (has_z) {
         ProfEv pe(s, RSOLVE_PROF_UPDATE_DOTS, j, var_of(j + 1), (j + k + 4.0) * w * nn);
-        launch_dcgs2_update<T>(ld, V, ld, j, orth ? Wt : Zt, k, u, z, s->nblk, s->ctl, st, pe.e0, pe.e1, zpart);
+        launch_dcgs2_update<T>(ld, V, ld, j, orth ? Wt : Zt, k, u, z, nbu, s->ctl, st, pe.e0, pe.e1, zpart);
     }
 }
 
@@ -1805,6 +1807,18 @@ const char* rsolve_last_error(void) { return g_err; }
 // ---------------------------------------------------------------------------
 // kernel-level entry points
 // ---------------------------------------------------------------------------
+
+int rsolve_triad(int64_t n, double* a, const double* b, const double* c, double s, void* hip_stream) {
+    g_err[0] = 0;
+    const auto mis = [](const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) != 0; };
+    if (n < 1 || !a || !b || !c || mis(a) || mis(b) || mis(c)) return RSOLVE_E_INVALID;
+    int dev = 0, cus = 256;
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    launch_triad(n, a, b, c, s, cus, reinterpret_cast<hipStream_t>(hip_stream));
+    HIP_TRY(hipGetLastError());
+    return RSOLVE_OK;
+}
 
 int rsolve_colour_first_fit(int64_t n, const int32_t* row_ptr, const int32_t* col_idx, int32_t* colour,
                             int32_t* ncolours) {

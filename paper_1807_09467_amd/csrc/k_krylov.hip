@@ -8,6 +8,8 @@
 // Per-block partial sums go to partial[c * nblk + block]; the last block to
 // finish (arrival counter) sums them in a fixed order, so results are bitwise
 // reproducible for a given launch shape.
+#include <algorithm>
+
 #include "kernels.hpp"
 
 namespace rs {
@@ -863,8 +865,10 @@ __global__ __launch_bounds__(BLOCK) void k_dcgs2_update(int64_t npad, T* __restr
     const double inv = ctl->inv_nu;
     __syncthreads();
     T* vj = V + (int64_t)j * ld;
-    // VEC consecutive rows per thread, 16-byte loads and stores (npad is a multiple of 64)
-    constexpr int VEC = 16 / sizeof(T);
+    // VEC consecutive rows per thread, 32 bytes of each column (two 16-byte loads; npad is a
+    // multiple of 64): a wavefront reads 2 KB runs of every column, which streams measurably
+    // faster than 1 KB runs on this memory system
+    constexpr int VEC = 32 / sizeof(T);
     const int64_t nvec = npad / VEC;
     for (int64_t q = (int64_t)blockIdx.x * BLOCK + threadIdx.x; q < nvec; q += (int64_t)nblk * BLOCK) {
         const int64_t i = q * VEC;
@@ -928,7 +932,7 @@ __global__ __launch_bounds__(BLOCK) void k_dcgs2_update_zd(int64_t npad, T* __re
     const double inv = ctl->inv_nu;
     __syncthreads();
     T* vj = V + (int64_t)j * ld;
-    constexpr int VEC = 16 / sizeof(T);
+    constexpr int VEC = 32 / sizeof(T);   // 32 bytes of each column per thread
     double acc[KZ];
 #pragma unroll
     for (int c = 0; c < KZ; ++c) acc[c] = 0.0;
@@ -1116,6 +1120,11 @@ void launch_dcgs2_reduce(double* partial, int nblk, int j, int k, int kz, bool o
     double* dsum = partial + (int64_t)nent * nblk;
     k_colsum<<<(nent + 15) / 16, 1024, 0, st>>>(partial, nblk, nent, dsum, ctl, zpart, nblk_z, j + k, kz, gz);
     k_dcgs2_reduce<<<1, RED_T, 0, st>>>(dsum, j, k, kz, orth ? 1 : 0, has_z ? 1 : 0, ctl);
+}
+
+int dcgs2_update_blocks(int64_t npad, int elem_bytes, int max_blocks) {
+    const int64_t want = (npad / (32 / elem_bytes) + BLOCK - 1) / BLOCK;   // one 32-byte slice per thread
+    return (int)std::max<int64_t>(1, std::min<int64_t>(want, max_blocks));
 }
 
 template <typename T>

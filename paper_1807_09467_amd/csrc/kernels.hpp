@@ -36,6 +36,9 @@ void launch_spmv_bc(int E, int LPR, int remap, int64_t n, const int32_t* p, cons
                     const int32_t* cstart, const int16_t* dict, const T* val, const T* win, T* vout, T* y,
                     const Ctl* ctl, hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 
+// a = b + s c (n doubles, 16-byte aligned arrays): the streaming reference kernel.
+void launch_triad(int64_t n, double* a, const double* b, const double* c, double s, int cus, hipStream_t st);
+
 // ---- multicolour SSOR (k_ssor.hip) ----
 // The colouring and grouping of one pattern: rows[coff[c] .. coff[c + 1]) are the rows of colour c
 // (no two of them couple).  `single`: the whole application in one workgroup that walks the
@@ -147,6 +150,9 @@ void launch_dcgs2_reduce(double* partial, int nblk, int j, int k, int kz, bool o
                          hipStream_t st, const double* zpart = nullptr, int nblk_z = 0, const double* gz = nullptr);
 // with zpart (k <= DCGS2_ZD_KMAX), also the per-block dots of the k columns of Z with
 // z / nu - V dq - v_j dq_j (the new candidate u plus (A W) cw / nu): zpart[c * nblk + b]
+// Blocks of the update sweep for npad rows of elem_bytes-byte values (at most max_blocks): one
+// 32-byte slice of every column per thread.  The A W partials it writes number the same.
+int dcgs2_update_blocks(int64_t npad, int elem_bytes, int max_blocks);
 template <typename T>
 void launch_dcgs2_update(int64_t npad, T* V, int64_t ld, int j, const T* Z, int k, T* u, const T* z, int nblk,
                          const Ctl* ctl, hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr,

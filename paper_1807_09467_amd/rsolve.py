@@ -44,7 +44,7 @@ EXPORTS = [
     "rsolve_spmv", "rsolve_kernel_workspace_bytes", "rsolve_gram_tn", "rsolve_snapshot_svd",
     "rsolve_profile_enable", "rsolve_profile_read", "rsolve_solve_batch", "rsolve_update_recycle_batch",
     "rsolve_tune_spmv", "rsolve_set_spmv_shape", "rsolve_get_spmv_shape", "rsolve_enable_graphs",
-    "rsolve_graph_counts", "rsolve_gram_tn_noalloc", "rsolve_colour_first_fit",
+    "rsolve_graph_counts", "rsolve_gram_tn_noalloc", "rsolve_colour_first_fit", "rsolve_triad",
     # serving loop (rsolve_server.h; bound in serve.py)
     "rsolve_server_create", "rsolve_server_open", "rsolve_server_submit", "rsolve_server_poll",
     "rsolve_server_close", "rsolve_server_info_get", "rsolve_server_destroy",
@@ -155,6 +155,8 @@ def load():
     lib.rsolve_gram_tn_noalloc.restype = c_int
     lib.rsolve_colour_first_fit.argtypes = [c_int64, c_void_p, c_void_p, c_void_p, POINTER(c_int32)]
     lib.rsolve_colour_first_fit.restype = c_int
+    lib.rsolve_triad.argtypes = [c_int64, c_void_p, c_void_p, c_void_p, c_double, c_void_p]
+    lib.rsolve_triad.restype = c_int
     lib.rsolve_snapshot_svd.argtypes = [c_int64, c_void_p, c_int64, c_int32, c_int32, c_void_p, c_int64,
                                         POINTER(c_double), POINTER(c_int32), POINTER(c_int32), c_void_p, c_size_t,
                                         c_void_p]
@@ -556,6 +558,14 @@ def gram_tn(A, B, stream=None):
 def last_error():
     """The library's description of the last error seen by this thread ("" if none)."""
     return load().rsolve_last_error().decode()
+
+
+def triad(a, b, c, s, stream=None):
+    """a = b + s c on the device (float64 CUDA tensors of one length), asynchronous."""
+    import torch
+    n = a.numel()
+    _check(load().rsolve_triad(n, c_void_p(_ptr(a, torch.float64, n, "a")), c_void_p(_ptr(b, torch.float64, n, "b")),
+                               c_void_p(_ptr(c, torch.float64, n, "c")), float(s), _stream_handle(stream)))
 
 
 def colour_first_fit(row_ptr, col_idx):

@@ -116,3 +116,24 @@ def test_singular_E_drops_recycle_space(gpu_ctx, path, k):
     print(f"[edges] rel={rel:.2e} its gpu={st['iterations']} oracle={ores.iterations}", flush=True)
     assert rel <= 1e-9
     assert np.linalg.norm(b - A @ xg) <= 1e-10 * np.linalg.norm(b) * (1 + 1e-6)
+
+
+@pytest.mark.parametrize("n", [1, 2, 1001, 1 << 20])
+def test_triad_reference_kernel(gpu_ctx, n):
+    """The streaming reference kernel: a = b + s c to one rounding of the host's value (the device
+    fuses the multiply and add), odd lengths included; a misaligned pointer is refused."""
+    import torch
+    from paper_1807_09467_amd import rsolve
+    rng = np.random.default_rng(n)
+    b, c = rng.standard_normal(n), rng.standard_normal(n)
+    tb, tc = torch.from_numpy(b).to(gpu_ctx), torch.from_numpy(c).to(gpu_ctx)
+    ta = torch.empty(n, dtype=torch.float64, device=gpu_ctx)
+    rsolve.triad(ta, tb, tc, 0.75, stream=torch.cuda.current_stream(gpu_ctx))
+    torch.cuda.synchronize(gpu_ctx)
+    ref = b + 0.75 * c
+    # a fused and an unfused b + s c differ by at most an ulp of the terms' size
+    assert np.all(np.abs(ta.cpu().numpy() - ref) <= 2.3e-16 * (np.abs(b) + 0.75 * np.abs(c)))
+    if n > 2:
+        big = torch.empty(n + 1, dtype=torch.float64, device=gpu_ctx)
+        with pytest.raises(rsolve.RsolveError):
+            rsolve.triad(big[1:], tb, tc, 1.0)
