@@ -15,6 +15,8 @@
 * Q3 512x512 in the same launch configuration with the refinement run to an outer tol of 1e-10:
   the solution within a flat 1e-8 of the oracle solved to 1e-12 (relative 2-norm and entry by
   entry), first two steps.
+* Q3 512x512 with multicolour SSOR (one launch per colour): a valid 16-colour first-fit colouring
+  and an FP64 solve to a true residual of 1e-10.
 
 The sequence is advanced along the oracle's own solutions (A_i is assembled from the oracle's
 x_{i-1}), and both sides start each solve from that x_{i-1}: no input of the oracle comes from the
@@ -105,3 +107,37 @@ def test_q3_full_size_mixed_refined_flat_bar(gpu_ctx):
         assert r["ores"].converged
         assert r["rel"] <= 1e-8 and r["max_entry"] <= 1e-8, (r["step"], r["rel"], r["max_entry"])
         assert r["st"]["k_eff"] == r["ores"].k_eff == r["step"]
+
+
+def test_q3_full_size_ssor_one_launch_per_colour(gpu_ctx):
+    """Multicolour SSOR at the headline mesh (n = 2,362,369: one launch per colour and sweep), FP64
+    GMRES(50) with right SSOR, first step: a valid first-fit colouring of the whole pattern (no
+    coupled pair inside a colour, every colour used, 16 colours as the 4 x 4 node types of cubic
+    elements allow), and the true residual within 1e-10 (a host FP64 product, a property at any
+    size).  The oracle's own colouring and triangular solves at this size would take minutes, so
+    the parity of the application itself is covered by the reduced meshes."""
+    import torch
+
+    from paper_1807_09467_amd import rsolve
+    prob = WL.C3
+    asm = WL.Assembler(prob)
+    pat = asm.pat
+    colour, ncol = rsolve.colour_first_fit(pat.row_ptr, pat.col_idx)
+    rows = np.repeat(np.arange(pat.n, dtype=np.int64), np.diff(pat.row_ptr.astype(np.int64)))
+    off = rows != pat.col_idx
+    assert not np.any(colour[rows[off]] == colour[pat.col_idx[off]])
+    assert ncol == 16 and np.array_equal(np.unique(colour), np.arange(16))
+    u = WL.initial_condition(prob, 0)
+    vals, b = asm.system(u)
+    A = asm.csr(vals)
+    seq = rsolve.Sequence(pat.n, pat.nnz, device=gpu_ctx, restart_m=50, precond="ssor", method="plain",
+                          ortho="dcgs2")
+    print("[fullsize] Q3 512 SSOR", flush=True)
+    x, st, status = seq.solve(_t(pat.row_ptr, gpu_ctx), _t(pat.col_idx, gpu_ctx), _t(vals, gpu_ctx), _t(b, gpu_ctx),
+                              x0=_t(u, gpu_ctx), tol=1e-10)
+    seq.close()
+    xg = x.cpu().numpy()
+    res = np.linalg.norm(b - A @ xg) / np.linalg.norm(b)
+    print(f"[fullsize] SSOR its {st['iterations']} cycles {st['cycles']} true residual {res:.2e}", flush=True)
+    assert status == 0 and st["converged"] == 1
+    assert res <= 1e-10 * (1 + 1e-6)
