@@ -179,10 +179,9 @@ struct rsolve_seq {
     int64_t bp_cap = 0;            // 0: the format is not available for this size
     bool band_ok = false;          // the current pattern fits the 16-bit offsets
     int bp_e = 0, bp_l = 0;        // chunk size and lanes the copy is laid out for (0: not built)
-    // shared offset lists of the banded copy: rows of equal offsets form a class (cls_row), each
-    // class keeps one list in cls_dict starting at chunk cls_start[c]
-    uint16_t* cls_row = nullptr;
-    int32_t* cls_start = nullptr;
+    // shared offset lists of the banded copy: rows of equal offsets form a class, each class keeps
+    // one list in cls_dict, and cls_first[r] is the chunk where row r's list starts
+    uint16_t* cls_first = nullptr;
     int16_t* cls_dict = nullptr;
     bool cls_ok = false;           // the classes describe the banded copy as laid out now
     bool cls_allowed = true;       // build them at all (the serving loop turns this off)
@@ -291,8 +290,7 @@ size_t layout(rsolve_seq* s, const rsolve_config& c, int64_t n, int64_t nnz_max,
     void* bp_val = bp_cap ? (ir ? static_cast<void*>(cv.take<float>((size_t)bp_cap))
                                 : static_cast<void*>(cv.take<double>((size_t)bp_cap)))
                           : nullptr;
-    uint16_t* cls_row = bp_cap ? cv.take<uint16_t>((size_t)n) : nullptr;
-    int32_t* cls_start = bp_cap ? cv.take<int32_t>((size_t)CLS_MAX) : nullptr;
+    uint16_t* cls_first = bp_cap ? cv.take<uint16_t>((size_t)n) : nullptr;
     int16_t* cls_dict = bp_cap ? cv.take<int16_t>((size_t)CLS_DICT_CHUNKS * 8) : nullptr;
     double* partial = cv.take<double>((size_t)PARTIAL_DOUBLES);
     double* gpart = cv.take<double>((size_t)GRAM_PARTIAL);
@@ -356,8 +354,7 @@ size_t layout(rsolve_seq* s, const rsolve_config& c, int64_t n, int64_t nnz_max,
         s->bp_off = bp_off;
         s->bp_val = bp_val;
         s->bp_cap = bp_cap;
-        s->cls_row = cls_row;
-        s->cls_start = cls_start;
+        s->cls_first = cls_first;
         s->cls_dict = cls_dict;
         s->tsq[0] = t0;
         s->tsq[1] = t1;
@@ -470,7 +467,7 @@ struct SpOp {
 // matrix's values (times D^{-1} by column when dinv is given) into it.
 // The offset classes of the banded copy just laid out (chunk size E): the copy's chunk offsets
 // and column offsets are read back once, rows are grouped by their offset lists (hash, then an
-// exact comparison), and the row classes, class starts and lists are written to the workspace.
+// exact comparison), and each row's list start and the lists are written to the workspace.
 // Leaves cls_ok false (no error) when the pattern has more than CLS_MAX classes or their lists
 // exceed CLS_DICT_CHUNKS chunks: the product then reads the copy's own offsets.
 int cls_build(rsolve_seq* s, int E) {
@@ -506,17 +503,17 @@ int cls_build(rsolve_seq* s, int E) {
         }
         if (id < 0) {
             const int64_t chunks = (int64_t)dict.size() / E;
-            if ((int)cstart.size() >= CLS_MAX || chunks + LP > CLS_DICT_CHUNKS) return RSOLVE_OK;
+            // every list start stays below CLS_DICT_CHUNKS, so it fits the 16-bit row entry
+            if ((int)cstart.size() >= CLS_MAX || chunks + std::max(LP, 1) > CLS_DICT_CHUNKS) return RSOLVE_OK;
             id = (int)cstart.size();
             cstart.push_back((int32_t)chunks);
             clen.push_back(LP);
             dict.insert(dict.end(), sp, sp + len);
             by_hash.emplace(h, id);
         }
-        rowc[r] = (uint16_t)id;
+        rowc[r] = (uint16_t)cstart[id];
     }
-    HIP_TRY(hipMemcpyAsync(s->cls_row, rowc.data(), sizeof(uint16_t) * n, hipMemcpyHostToDevice, stm));
-    HIP_TRY(hipMemcpyAsync(s->cls_start, cstart.data(), sizeof(int32_t) * cstart.size(), hipMemcpyHostToDevice, stm));
+    HIP_TRY(hipMemcpyAsync(s->cls_first, rowc.data(), sizeof(uint16_t) * n, hipMemcpyHostToDevice, stm));
     if (!dict.empty())
         HIP_TRY(hipMemcpyAsync(s->cls_dict, dict.data(), sizeof(int16_t) * dict.size(), hipMemcpyHostToDevice, stm));
     HIP_TRY(hipStreamSynchronize(stm));   // the host vectors go out of scope
@@ -573,7 +570,7 @@ void arnoldi_product(rsolve_seq* s, const SpOp& op, const T* win, T* vout, T* y,
         }
     }
     if (op.fmt == RSOLVE_SPMV_BANDED && s->cls_ok)
-        launch_spmv_bc<T>(s->svec, s->lpr, s->sremap, s->n, op.rp, s->cls_row, s->cls_start, s->cls_dict,
+        launch_spmv_bc<T>(s->svec, s->lpr, s->sremap, s->n, op.rp, s->cls_first, s->cls_dict,
                           static_cast<const T*>(op.vals), win, vout, y, s->ctl, s->stream, e0, e1);
     else if (op.fmt == RSOLVE_SPMV_BANDED)
         launch_spmv_bp<T>(s->svec, s->lpr, s->sremap, s->n, op.rp, op.off, static_cast<const T*>(op.vals), win, vout,
@@ -1146,7 +1143,7 @@ int rsolve_tune_spmv(rsolve_seq* s, const rsolve_csr* A, int32_t reps, rsolve_sp
                     time_it(
                         [&] {
                             if (ir && s->cls_ok)
-                                launch_spmv_bc<float>(v, l, rm, n, s->bp_p, s->cls_row, s->cls_start, s->cls_dict,
+                                launch_spmv_bc<float>(v, l, rm, n, s->bp_p, s->cls_first, s->cls_dict,
                                                       static_cast<const float*>(s->bp_val), s->w32[0], s->V32,
                                                       s->w32[1], s->ctl, stm);
                             else if (ir)
@@ -1154,7 +1151,7 @@ int rsolve_tune_spmv(rsolve_seq* s, const rsolve_csr* A, int32_t reps, rsolve_sp
                                                       static_cast<const float*>(s->bp_val), s->w32[0], s->V32,
                                                       s->w32[1], s->ctl, stm);
                             else if (s->cls_ok)
-                                launch_spmv_bc<double>(v, l, rm, n, s->bp_p, s->cls_row, s->cls_start, s->cls_dict,
+                                launch_spmv_bc<double>(v, l, rm, n, s->bp_p, s->cls_first, s->cls_dict,
                                                        static_cast<const double*>(s->bp_val), s->wb[0], s->V,
                                                        s->wb[1], s->ctl, stm);
                             else

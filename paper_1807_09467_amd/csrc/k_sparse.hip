@@ -526,12 +526,12 @@ template void launch_spmv_bp<double>(int, int, int, int64_t, const int32_t*, con
                                      const double*, double*, double*, const Ctl*, hipStream_t, hipEvent_t, hipEvent_t);
 template void launch_spmv_bp<float>(int, int, int, int64_t, const int32_t*, const int16_t*, const float*,
                                     const float*, float*, float*, const Ctl*, hipStream_t, hipEvent_t, hipEvent_t);
-template void launch_spmv_bc<double>(int, int, int, int64_t, const int32_t*, const uint16_t*, const int32_t*,
-                                     const int16_t*, const double*, const double*, double*, double*, const Ctl*,
-                                     hipStream_t, hipEvent_t, hipEvent_t);
-template void launch_spmv_bc<float>(int, int, int, int64_t, const int32_t*, const uint16_t*, const int32_t*,
-                                    const int16_t*, const float*, const float*, float*, float*, const Ctl*,
-                                    hipStream_t, hipEvent_t, hipEvent_t);
+template void launch_spmv_bc<double>(int, int, int, int64_t, const int32_t*, const uint16_t*, const int16_t*,
+                                     const double*, const double*, double*, double*, const Ctl*, hipStream_t,
+                                     hipEvent_t, hipEvent_t);
+template void launch_spmv_bc<float>(int, int, int, int64_t, const int32_t*, const uint16_t*, const int16_t*,
+                                    const float*, const float*, float*, float*, const Ctl*, hipStream_t, hipEvent_t,
+                                    hipEvent_t);
 
 void launch_residual(int lpr, int64_t n, const int32_t* rp, const int32_t* ci, const double* val, const double* x,
                      const double* b, double* r, hipStream_t st) {

@@ -29,12 +29,12 @@ template <typename T>
 void launch_spmv_bp(int E, int LPR, int remap, int64_t n, const int32_t* p, const int16_t* off, const T* val,
                     const T* win, T* vout, T* y, const Ctl* ctl, hipStream_t st, hipEvent_t ev0 = nullptr,
                     hipEvent_t ev1 = nullptr);
-// the same product with the offsets of row r read from dict + cstart[cls[r]] E (rows of equal
-// offsets share one list)
+// the same product with the offsets of row r read from dict + first[r] E (rows of equal offsets
+// share one list)
 template <typename T>
-void launch_spmv_bc(int E, int LPR, int remap, int64_t n, const int32_t* p, const uint16_t* cls,
-                    const int32_t* cstart, const int16_t* dict, const T* val, const T* win, T* vout, T* y,
-                    const Ctl* ctl, hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+void launch_spmv_bc(int E, int LPR, int remap, int64_t n, const int32_t* p, const uint16_t* first,
+                    const int16_t* dict, const T* val, const T* win, T* vout, T* y, const Ctl* ctl, hipStream_t st,
+                    hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 
 // a = b + s c (n doubles, 16-byte aligned arrays): the streaming reference kernel.
 void launch_triad(int64_t n, double* a, const double* b, const double* c, double s, int cus, hipStream_t st);
