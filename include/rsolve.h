@@ -249,6 +249,41 @@ int rsolve_update_recycle(rsolve_seq* s, const double* x);
 int rsolve_get_recycle(rsolve_seq* s, int32_t* k_eff, int32_t* rank, double* sigma_host,
                        int32_t cap, double* W_out, int64_t ld_out);
 
+/* ---- checkpoint and resume ----
+ *
+ * The state a sequence carries from one solve to the next: Algorithm 1's snapshot ring and
+ * counter (section 5.2), the recycle basis W with its singular values and rank, the last
+ * solution, a Ritz basis prepared by the last solve and not yet taken by an update (section
+ * 5.1), and an SpMV shape set with rsolve_set_spmv_shape.  For callers that must stop a sequence
+ * and resume it later or elsewhere (an evicted serving slot, a process restart): a sequence that
+ * imports the state of another with the same configuration and size, and then sees the same
+ * systems, gives bitwise the same results as the original would have.
+ */
+
+/* Bytes of the state of s as it is now (0 for a null handle).  It changes with every solve and
+ * update: query it right before rsolve_export_state. */
+size_t rsolve_state_bytes(rsolve_seq* s);
+
+/*
+ * Copy the state of s into `buf` (host memory, any alignment, `bytes` long): a header (format
+ * version, the configuration fields the state depends on, n, the counters, a checksum) followed
+ * by float64 columns of n values (W, the ring by slot, the last solution, a pending Ritz basis),
+ * in native byte order.  *written (nullable) receives the bytes used.  Synchronous; s is
+ * unchanged.  Errors: E_INVALID (null pointer, bytes < rsolve_state_bytes(s)), E_DEVICE.
+ */
+int rsolve_export_state(rsolve_seq* s, void* buf, size_t bytes, size_t* written);
+
+/*
+ * Replace the state of s with one written by rsolve_export_state.  s must have the same n and
+ * the same recycle_k, snapshots_s, svd_interval, method, select and precision as the exporting
+ * sequence (restart length, tolerances, preconditioner and orthogonalisation may differ, at the
+ * price of bitwise equality).  The pattern caches of s are kept: its next solve checks the
+ * pattern as usual.  Synchronous.  Errors: E_INVALID (null pointer, not a state of this format
+ * version, another configuration or size, inconsistent counters, truncated buffer, checksum
+ * mismatch: s is then unchanged), E_DEVICE.
+ */
+int rsolve_import_state(rsolve_seq* s, const void* buf, size_t bytes);
+
 /* ---- batched solves of many sequences in one launch ---- */
 
 /* One-block limits: an item whose sequence is FP64 with method RSOLVE_PLAIN, _AUG_OBLIQUE or

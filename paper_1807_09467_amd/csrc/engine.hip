@@ -1785,6 +1785,188 @@ int rsolve_get_recycle(rsolve_seq* s, int32_t* k_eff, int32_t* rank, double* sig
     return RSOLVE_OK;
 }
 
+// ---- checkpoint / resume of a sequence's recycling state ----
+
+namespace {
+
+// The state blob: this header, then float64 columns of n values each: W (k_w columns), the
+// snapshot ring by slot (ring_cols columns), the last solution (if have_x) and a pending Ritz
+// basis (rz_k columns, if rz_pending).  Native byte order; the checksum is FNV-1a over the columns.
+struct StateHeader {
+    uint64_t magic;
+    uint32_t version, header_bytes;
+    int32_t recycle_k, snapshots_s, svd_interval, method, select, precision;
+    int64_t n, count;
+    int32_t k_w, rank, nsig, have_x;
+    int32_t ring_cols, rz_pending, rz_k, shape_set;
+    int32_t lpr, svec, sremap, sfmt;
+    double sigma[SMAX];
+    double rz_theta[SMAX];
+    uint64_t payload_bytes, checksum;
+};
+constexpr uint64_t STATE_MAGIC = 0x31545345564c4f53ull;   // "SOLVEST1"
+constexpr uint32_t STATE_VERSION = 1;
+
+// stored solutions of the snapshot ring (the Ritz spaces keep none)
+int state_ring_cols(const rsolve_seq* s, int64_t count) {
+    return (s->X && !ritz_mode(s->cfg)) ? (int)std::min<int64_t>(count, s->cfg.snapshots_s) : 0;
+}
+
+uint64_t state_columns(const rsolve_seq* s, int ring, int have_x, int rz_pending, int rz_k, int k_w) {
+    return (uint64_t)k_w + (uint64_t)ring + (uint64_t)have_x + (rz_pending ? (uint64_t)rz_k : 0);
+}
+
+uint64_t fnv1a(const unsigned char* p, size_t n) {
+    uint64_t h = 1469598103934665603ull;
+    for (size_t i = 0; i < n; ++i) h = (h ^ p[i]) * 1099511628211ull;
+    return h;
+}
+
+}  // namespace
+
+size_t rsolve_state_bytes(rsolve_seq* s) {
+    if (!s) return 0;
+    const uint64_t cols = state_columns(s, state_ring_cols(s, s->count), s->have_x ? 1 : 0, s->rz_pending ? 1 : 0, s->rz_k,
+                                        s->k_w);
+    return sizeof(StateHeader) + sizeof(double) * (size_t)s->n * (size_t)cols;
+}
+
+int rsolve_export_state(rsolve_seq* s, void* buf, size_t bytes, size_t* written) {
+    g_err[0] = 0;
+    if (written) *written = 0;
+    if (!s || !buf) return RSOLVE_E_INVALID;
+    const size_t need = rsolve_state_bytes(s);
+    if (bytes < need) {
+        set_err("state buffer of %zu bytes, %zu needed", bytes, need);
+        return RSOLVE_E_INVALID;
+    }
+    HIP_TRY(hipSetDevice(s->device));
+    StateHeader h{};
+    h.magic = STATE_MAGIC;
+    h.version = STATE_VERSION;
+    h.header_bytes = (uint32_t)sizeof(StateHeader);
+    const rsolve_config& c = s->cfg;
+    h.recycle_k = c.recycle_k;
+    h.snapshots_s = c.snapshots_s;
+    h.svd_interval = c.svd_interval;
+    h.method = c.method;
+    h.select = c.select;
+    h.precision = c.precision;
+    h.n = s->n;
+    h.count = s->count;
+    h.k_w = s->k_w;
+    h.rank = s->rank;
+    h.nsig = s->nsig;
+    h.have_x = s->have_x ? 1 : 0;
+    h.ring_cols = state_ring_cols(s, s->count);
+    h.rz_pending = s->rz_pending ? 1 : 0;
+    h.rz_k = s->rz_pending ? s->rz_k : 0;
+    h.shape_set = s->shape_set ? 1 : 0;
+    h.lpr = s->lpr;
+    h.svec = s->svec;
+    h.sremap = s->sremap;
+    h.sfmt = s->sfmt;
+    for (int i = 0; i < SMAX; ++i) {
+        h.sigma[i] = i < s->nsig ? s->sigma[i] : 0.0;
+        h.rz_theta[i] = i < h.rz_k ? s->rz_theta[i] : 0.0;
+    }
+    const size_t col = sizeof(double) * (size_t)s->n;
+    h.payload_bytes = need - sizeof(StateHeader);
+    unsigned char* out = static_cast<unsigned char*>(buf) + sizeof(StateHeader);
+    const size_t pitch = sizeof(double) * (size_t)s->ld;
+    auto take = [&](const double* src, int cols) -> int {
+        if (cols > 0) {
+            HIP_TRY(hipMemcpy2DAsync(out, col, src, pitch, col, cols, hipMemcpyDeviceToHost, s->stream));
+            out += col * (size_t)cols;
+        }
+        return RSOLVE_OK;
+    };
+    int rc = take(s->W, h.k_w);
+    if (rc == RSOLVE_OK) rc = take(s->X, h.ring_cols);
+    if (rc == RSOLVE_OK) rc = take(s->xw, h.have_x);
+    if (rc == RSOLVE_OK && h.rz_pending) rc = take(s->rz_w, h.rz_k);
+    if (rc) return rc;
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    h.checksum = fnv1a(static_cast<const unsigned char*>(buf) + sizeof(StateHeader), (size_t)h.payload_bytes);
+    std::memcpy(buf, &h, sizeof(h));
+    if (written) *written = need;
+    return RSOLVE_OK;
+}
+
+int rsolve_import_state(rsolve_seq* s, const void* buf, size_t bytes) {
+    g_err[0] = 0;
+    if (!s || !buf) return RSOLVE_E_INVALID;
+    StateHeader h;
+    if (bytes < sizeof(h)) {
+        set_err("state of %zu bytes is shorter than its header", bytes);
+        return RSOLVE_E_INVALID;
+    }
+    std::memcpy(&h, buf, sizeof(h));
+    const rsolve_config& c = s->cfg;
+    if (h.magic != STATE_MAGIC || h.version != STATE_VERSION || h.header_bytes != sizeof(StateHeader)) {
+        set_err("not a sequence state of this library version");
+        return RSOLVE_E_INVALID;
+    }
+    if (h.n != s->n || h.recycle_k != c.recycle_k || h.snapshots_s != c.snapshots_s ||
+        h.svd_interval != c.svd_interval || h.method != c.method || h.select != c.select ||
+        h.precision != c.precision) {
+        set_err("state of another configuration or size (n %lld, k %d, s %d, method %d)", (long long)h.n,
+                h.recycle_k, h.snapshots_s, h.method);
+        return RSOLVE_E_INVALID;
+    }
+    const int ring = state_ring_cols(s, std::max<int64_t>(h.count, 0));
+    const bool ranges_ok = h.count >= 0 && h.k_w >= 0 && h.k_w <= c.recycle_k && h.rank >= 0 &&
+                           h.nsig >= 0 && h.nsig <= SMAX && (h.have_x == 0 || h.have_x == 1) &&
+                           h.ring_cols == ring && (h.rz_pending == 0 || h.rz_pending == 1) && h.rz_k >= 0 &&
+                           h.rz_k <= c.recycle_k && (h.rz_pending || h.rz_k == 0) &&
+                           (h.shape_set == 0 || h.shape_set == 1);
+    const uint64_t cols = ranges_ok ? state_columns(s, ring, h.have_x, h.rz_pending, h.rz_k, h.k_w) : 0;
+    const uint64_t payload = sizeof(double) * (uint64_t)s->n * cols;
+    if (!ranges_ok || h.payload_bytes != payload || bytes < sizeof(h) + payload) {
+        set_err("inconsistent or truncated sequence state");
+        return RSOLVE_E_INVALID;
+    }
+    const unsigned char* in = static_cast<const unsigned char*>(buf) + sizeof(h);
+    if (fnv1a(in, (size_t)payload) != h.checksum) {
+        set_err("sequence state checksum mismatch");
+        return RSOLVE_E_INVALID;
+    }
+    if (h.shape_set) {
+        const rsolve_spmv_shape shape{h.lpr, h.svec, h.sremap, 1, h.sfmt, 0, 0.0};
+        const int rc = rsolve_set_spmv_shape(s, &shape);
+        if (rc) return rc;
+    }
+    HIP_TRY(hipSetDevice(s->device));
+    const size_t col = sizeof(double) * (size_t)s->n;
+    const size_t pitch = sizeof(double) * (size_t)s->ld;
+    auto put = [&](double* dst, int ncols) -> int {
+        if (ncols > 0) {
+            HIP_TRY(hipMemcpy2DAsync(dst, pitch, in, col, col, ncols, hipMemcpyHostToDevice, s->stream));
+            in += col * (size_t)ncols;
+        }
+        return RSOLVE_OK;
+    };
+    int rc = put(s->W, h.k_w);
+    if (rc == RSOLVE_OK) rc = put(s->X, ring);
+    if (rc == RSOLVE_OK) rc = put(s->xw, h.have_x);
+    if (rc == RSOLVE_OK && h.rz_pending) rc = put(s->rz_w, h.rz_k);
+    if (rc) return rc;
+    if (s->W32 && h.k_w > 0) launch_to_f32((int64_t)h.k_w * s->ld, s->W, s->W32, s->stream);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    s->count = h.count;
+    s->k_w = h.k_w;
+    s->rank = h.rank;
+    s->nsig = h.nsig;
+    for (int i = 0; i < SMAX; ++i) s->sigma[i] = h.sigma[i];
+    s->have_x = h.have_x != 0;
+    s->rz_pending = h.rz_pending != 0;
+    s->rz_k = h.rz_k;
+    for (int i = 0; i < SMAX; ++i) s->rz_theta[i] = h.rz_theta[i];
+    s->wr_ok = false;   // the row-major copy of W is rebuilt by the next solve
+    return RSOLVE_OK;
+}
+
 const char* rsolve_status_string(int status) {
     switch (status) {
         case RSOLVE_OK: return "ok";

@@ -45,6 +45,7 @@ EXPORTS = [
     "rsolve_profile_enable", "rsolve_profile_read", "rsolve_solve_batch", "rsolve_update_recycle_batch",
     "rsolve_tune_spmv", "rsolve_set_spmv_shape", "rsolve_get_spmv_shape", "rsolve_enable_graphs",
     "rsolve_graph_counts", "rsolve_gram_tn_noalloc", "rsolve_colour_first_fit", "rsolve_triad",
+    "rsolve_state_bytes", "rsolve_export_state", "rsolve_import_state",
     # serving loop (rsolve_server.h; bound in serve.py)
     "rsolve_server_create", "rsolve_server_open", "rsolve_server_submit", "rsolve_server_poll",
     "rsolve_server_close", "rsolve_server_info_get", "rsolve_server_destroy",
@@ -137,6 +138,12 @@ def load():
     lib.rsolve_get_recycle.argtypes = [c_void_p, POINTER(c_int32), POINTER(c_int32), POINTER(c_double), c_int32,
                                        c_void_p, c_int64]
     lib.rsolve_get_recycle.restype = c_int
+    lib.rsolve_state_bytes.argtypes = [c_void_p]
+    lib.rsolve_state_bytes.restype = c_size_t
+    lib.rsolve_export_state.argtypes = [c_void_p, c_void_p, c_size_t, POINTER(c_size_t)]
+    lib.rsolve_export_state.restype = c_int
+    lib.rsolve_import_state.argtypes = [c_void_p, c_void_p, c_size_t]
+    lib.rsolve_import_state.restype = c_int
     lib.rsolve_destroy_sequence.argtypes = [c_void_p]
     lib.rsolve_destroy_sequence.restype = c_int
     lib.rsolve_status_string.argtypes = [c_int]
@@ -294,6 +301,22 @@ class Sequence:
                                                        c_void_p(W.data_ptr()), self.n))
             out["W"] = W
         return out
+
+    def export_state(self):
+        """The sequence's recycling state as bytes (rsolve_export_state)."""
+        size = self.lib.rsolve_state_bytes(self.handle)
+        buf = ctypes.create_string_buffer(size)
+        written = c_size_t()
+        _check(self.lib.rsolve_export_state(self.handle, buf, size, byref(written)))
+        return buf.raw[:written.value]
+
+    def import_state(self, blob, check=True):
+        """Replace the recycling state with bytes from export_state (rsolve_import_state)."""
+        buf = ctypes.create_string_buffer(bytes(blob), len(blob))
+        status = self.lib.rsolve_import_state(self.handle, buf, len(blob))
+        if check:
+            _check(status)
+        return status
 
     def tune_spmv(self, row_ptr, col_idx, val, reps=20):
         """Time every Arnoldi SpMV shape on this matrix (rsolve_tune_spmv); fastest first."""

@@ -8,9 +8,9 @@
 //                    grid of configurations, status strings;
 //   host_check gpu   every entry point on a small convection-diffusion time-stepping sequence: each
 //                    valid solver configuration (method x preconditioner x precision x recycle
-//                    selection x orthogonalisation), the recycle read-back, profiling, graph
-//                    replay, the SpMV tuner, batched solves, the serving loop, the kernel-level
-//                    calls and the documented error returns.
+//                    selection x orthogonalisation), the recycle read-back, a checkpoint moved to a
+//                    fresh sequence, profiling, graph replay, the SpMV tuner, batched solves, the
+//                    serving loop, the kernel-level calls and the documented error returns.
 // Every residual a solve reports is recomputed on the host in float64.  Exit status 0 when all
 // checks hold; a sanitizer report ends the run with a non-zero status.
 #include <hip/hip_runtime_api.h>
@@ -139,6 +139,10 @@ void cpu_phase() {
     rsolve_seq* seq = nullptr;
     EXPECT(rsolve_create_sequence(&bad, 10, 10, nullptr, nullptr, 0, &seq) == RSOLVE_E_INVALID && !seq,
            "create with a zero configuration");
+    unsigned char blob[64] = {};
+    EXPECT(rsolve_state_bytes(nullptr) == 0, "state_bytes(null)");
+    EXPECT(rsolve_export_state(nullptr, blob, sizeof blob, nullptr) == RSOLVE_E_INVALID, "export(null)");
+    EXPECT(rsolve_import_state(nullptr, blob, sizeof blob) == RSOLVE_E_INVALID, "import(null)");
     rsolve_server* srv = nullptr;
     rsolve_server_config sc{};
     EXPECT(rsolve_server_create(&sc, &srv) == RSOLVE_E_INVALID && !srv, "server without a pool");
@@ -359,6 +363,28 @@ void solver_configurations(Problem& p, DeviceProblem& dp, hipStream_t stream) {
                                        launches >= 0,
                                    name);
                         }
+                        // checkpoint: the state moves to a fresh sequence of the same configuration
+                        std::vector<unsigned char> blob(rsolve_state_bytes(s));
+                        size_t written = 0;
+                        EXPECT(rsolve_export_state(s, blob.data(), blob.size(), &written) == RSOLVE_OK &&
+                                   written == blob.size(),
+                               name);
+                        void* w2 = nullptr;
+                        HIP_OK(hipMalloc(&w2, ws));
+                        rsolve_seq* s2 = nullptr;
+                        EXPECT(rsolve_create_sequence(&c, p.n, dp.nnz, stream, w2, ws, &s2) == RSOLVE_OK, name);
+                        if (s2) {
+                            EXPECT(rsolve_import_state(s2, blob.data(), blob.size() / 2) == RSOLVE_E_INVALID, name);
+                            EXPECT(rsolve_import_state(s2, blob.data(), blob.size()) == RSOLVE_OK, name);
+                            int32_t k2 = -1, rank2 = -1;
+                            double sigma2[64];
+                            EXPECT(rsolve_get_recycle(s2, &k2, &rank2, sigma2, 64, nullptr, 0) == RSOLVE_OK &&
+                                       k2 == k_eff && rank2 == rank &&
+                                       std::memcmp(sigma, sigma2, sizeof(double) * std::min(64, std::max(rank, 0))) == 0,
+                                   name);
+                            EXPECT(rsolve_destroy_sequence(s2) == RSOLVE_OK, name);
+                        }
+                        HIP_OK(hipFree(w2));
                         EXPECT(rsolve_destroy_sequence(s) == RSOLVE_OK, name);
                         HIP_OK(hipFree(w));
                     }

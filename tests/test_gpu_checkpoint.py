@@ -1,0 +1,178 @@
+"""GPU tests of checkpoint and resume (rsolve_state_bytes / rsolve_export_state /
+rsolve_import_state).
+
+A sequence that imports another's state and then sees the same systems must give bitwise the same
+solutions, Arnoldi step counts and recycle spaces (k_eff, rank, singular values) as the original
+running on.  The original sequence is the one the parity tests check against the oracle, so this
+carries their bars over to resumed runs.  Also: the state survives a round trip through a file, a
+shape set by the caller moves with it, and truncated, corrupt or foreign states are refused with
+the importing sequence left unchanged."""
+import numpy as np
+import pytest
+
+from paper_1807_09467_amd import workload as WL
+
+pytestmark = pytest.mark.gpu
+
+CASES = {
+    "fp64_oblique": dict(method="aug_oblique", restart_m=30, recycle_k=8, snapshots_s=12, precond="jacobi"),
+    "mixed_dcgs2": dict(method="aug_oblique", restart_m=30, recycle_k=8, snapshots_s=12, precond="jacobi",
+                        precision="fp32_ir", inner_tol=1e-5, ortho="dcgs2"),
+    "svd_every_3": dict(method="defl_oblique", restart_m=30, recycle_k=6, snapshots_s=9, svd_interval=3,
+                        precond="jacobi"),
+    "extrapolation": dict(method="guess_extrap3", restart_m=30, recycle_k=0, snapshots_s=3, precond="jacobi"),
+    "harmonic_ritz": dict(method="aug_oblique", restart_m=30, recycle_k=6, snapshots_s=0, select="harmonic_ritz",
+                          precond="jacobi"),
+    "ssor_ortho": dict(method="aug_ortho", restart_m=30, recycle_k=8, snapshots_s=12, precond="ssor"),
+    "plain_no_preconditioner": dict(method="plain", restart_m=30, precond="none"),
+}
+
+
+def _t(a, dev):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+
+def _systems(prob, steps, seed, dev):
+    asm, systems, _ = WL.march(prob, steps, seed)
+    pat = asm.pat
+    return pat, _t(pat.row_ptr, dev), _t(pat.col_idx, dev), [(_t(v, dev), _t(b, dev)) for v, b in systems]
+
+
+def _step(seq, rp, ci, vals, b, x0, first):
+    x, st, status = seq.solve(rp, ci, vals, b, x0=x0, tol=1e-10, same_pattern=not first)
+    assert status == 0, (status, st)
+    return x, st
+
+
+def _same_recycle(a, b):
+    ra, rb = a.recycle(with_basis=True), b.recycle(with_basis=True)
+    assert ra["k_eff"] == rb["k_eff"] and ra["rank"] == rb["rank"] and ra["sigma"] == rb["sigma"]
+    import torch
+    assert torch.equal(ra["W"], rb["W"])
+
+
+def _resume(dev, prob, cfg, cut, steps, mid=False, via_file=None, shape=None):
+    """Run `steps` systems through sequence A; after step cut's update (mid: after its solve,
+    before its update) copy A's state into a fresh sequence B; run the remaining steps through
+    both and require bitwise equality."""
+    from paper_1807_09467_amd import rsolve
+    pat, rp, ci, systems = _systems(prob, steps, 3, dev)
+    a = rsolve.Sequence(pat.n, pat.nnz, device=dev, **cfg)
+    if shape:
+        a.set_spmv_shape(*shape)
+    b = rsolve.Sequence(pat.n, pat.nnz, device=dev, **cfg)
+    x = None
+    for i in range(cut + 1):
+        x, _ = _step(a, rp, ci, *systems[i], x, i == 0)
+        if not (mid and i == cut):
+            a.update()
+    blob = a.export_state()
+    if via_file is not None:
+        via_file.write_bytes(blob)
+        blob = via_file.read_bytes()
+    b.import_state(blob)
+    if shape:
+        assert b.spmv_shape() == a.spmv_shape()
+    if mid:
+        a.update()
+        b.update()
+    _same_recycle(a, b)
+    xa = xb = x
+    for i in range(cut + 1, steps):
+        xa, sa = _step(a, rp, ci, *systems[i], xa, False)
+        xb, sb = _step(b, rp, ci, *systems[i], xb, i == cut + 1)
+        import torch
+        assert torch.equal(xa, xb), i
+        assert sa["iterations"] == sb["iterations"] and sa["k_eff"] == sb["k_eff"], (i, sa, sb)
+        assert sa["rel_res_true"] == sb["rel_res_true"], i
+        a.update()
+        b.update()
+        _same_recycle(a, b)
+    a.close()
+    b.close()
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_resume_is_bitwise(gpu_ctx, case):
+    """Q2 32x32 (n = 4,225): eight steps, the state taken after the fourth (the ring not yet full
+    for s = 12; for s = 9 with an SVD every third step, between two SVDs)."""
+    _resume(gpu_ctx, WL.C2_SMALL, CASES[case], cut=3, steps=8)
+
+
+def test_resume_with_a_full_ring(gpu_ctx):
+    """The ring of s = 5 has wrapped twice when the state is taken (slot order matters)."""
+    cfg = dict(method="aug_oblique", restart_m=30, recycle_k=4, snapshots_s=5, precond="jacobi")
+    _resume(gpu_ctx, WL.C3_SMALL, cfg, cut=11, steps=15)
+
+
+def test_resume_between_solve_and_update(gpu_ctx):
+    """Taken after a solve and before its update: the last solution (SVD spaces) and the pending
+    Ritz basis (Ritz spaces) move with the state, and update(NULL) on the new sequence uses them."""
+    _resume(gpu_ctx, WL.C2_SMALL, CASES["fp64_oblique"], cut=3, steps=7, mid=True)
+    _resume(gpu_ctx, WL.C2_SMALL, CASES["harmonic_ritz"], cut=3, steps=7, mid=True)
+
+
+def test_resume_through_a_file_with_a_set_shape(gpu_ctx, tmp_path):
+    _resume(gpu_ctx, WL.C3_SMALL, CASES["mixed_dcgs2"], cut=4, steps=8, via_file=tmp_path / "state.bin",
+            shape=(2, 4, 1, "csr"))
+
+
+def test_state_size_tracks_the_sequence(gpu_ctx):
+    from paper_1807_09467_amd import rsolve
+    pat, rp, ci, systems = _systems(WL.C3_SMALL, 3, 1, gpu_ctx)
+    cfg = CASES["fp64_oblique"]
+    seq = rsolve.Sequence(pat.n, pat.nnz, device=gpu_ctx, **cfg)
+    lib = rsolve.load()
+    header = lib.rsolve_state_bytes(seq.handle)
+    assert header > 0 and len(seq.export_state()) == header     # nothing stored yet
+    x = None
+    for i in range(3):
+        x, _ = _step(seq, rp, ci, *systems[i], x, i == 0)
+        seq.update()
+    k = seq.recycle()["k_eff"]
+    # W (k columns), the ring (3 solutions) and the last solution, n float64 values each
+    assert len(seq.export_state()) == header + 8 * pat.n * (k + 3 + 1)
+    assert lib.rsolve_state_bytes(None) == 0
+    seq.close()
+
+
+def test_bad_states_are_refused(gpu_ctx):
+    import ctypes
+
+    from paper_1807_09467_amd import rsolve
+    pat, rp, ci, systems = _systems(WL.C3_SMALL, 3, 2, gpu_ctx)
+    cfg = CASES["fp64_oblique"]
+    a = rsolve.Sequence(pat.n, pat.nnz, device=gpu_ctx, **cfg)
+    x = None
+    for i in range(3):
+        x, _ = _step(a, rp, ci, *systems[i], x, i == 0)
+        a.update()
+    blob = a.export_state()
+    b = rsolve.Sequence(pat.n, pat.nnz, device=gpu_ctx, **cfg)
+    before = b.recycle()
+    bad = bytearray(blob)
+    bad[-5] ^= 0x40                                                   # one payload bit
+    hdr = bytearray(blob)
+    hdr[0] ^= 1                                                       # the format tag
+    for state in (blob[:-8], blob[:100], bytes(bad), bytes(hdr), b"\0" * len(blob)):
+        assert b.import_state(state, check=False) == rsolve.E_INVALID
+        assert b.recycle() == before
+    # another recycle dimension, another size
+    other = rsolve.Sequence(pat.n, pat.nnz, device=gpu_ctx, **dict(cfg, recycle_k=4))
+    assert other.import_state(blob, check=False) == rsolve.E_INVALID
+    pat2, *_ = _systems(WL.C2_SMALL, 1, 0, gpu_ctx)
+    small = rsolve.Sequence(pat2.n, pat2.nnz, device=gpu_ctx, **cfg)
+    assert small.import_state(blob, check=False) == rsolve.E_INVALID
+    # a buffer one byte short for the export
+    lib = rsolve.load()
+    need = lib.rsolve_state_bytes(a.handle)
+    buf = ctypes.create_string_buffer(need)
+    written = ctypes.c_size_t(7)
+    assert lib.rsolve_export_state(a.handle, buf, need - 1, ctypes.byref(written)) == rsolve.E_INVALID
+    assert written.value == 0
+    # the good state still imports after the refusals
+    assert b.import_state(blob, check=False) == rsolve.OK
+    _same_recycle(a, b)
+    for s in (a, b, other, small):
+        s.close()
