@@ -841,11 +841,11 @@ def main():
              "algorithmic_bytes_per_launch": round(alg), "avg_launch_us": round(avg_us, 2),
              "launches": c["launches"], "ms_sampled": round(c["ms"], 3)}
         if c["kernel"] == "spmv_arnoldi":
-            # the storage format's bytes (values, chunk offsets, class numbers, x read, y written); the
-            # CSR figure (w + 4) nnz + 4 (n + 1) + 2 w n of the same product is reported beside it
+            # the storage format's bytes (values, chunk offsets, 16-bit list starts, x read, y written);
+            # the CSR figure (w + 4) nnz + 4 (n + 1) + 2 w n of the same product is reported beside it
             nn, nz = float(asm.pat.n), float(asm.pat.nnz)
             csr = (wsz + 4.0) * nz + 4.0 * (nn + 1.0) + 2.0 * wsz * nn
-            r["algorithmic_bytes"] = "w nnz + 4 (n + 1) + 2 n + 2 w n (banded copy with class offset lists)"
+            r["algorithmic_bytes"] = "w nnz + 4 (n + 1) + 2 n + 2 w n (banded copy with shared offset lists)"
             r["csr_equivalent_bytes_per_launch"] = round(csr)
             r["csr_equivalent_gbs"] = round(csr / (avg_us * 1e-6) / 1e9, 1)
         elif c["kernel"] in ("dots2", "dots"):

@@ -550,7 +550,7 @@ int bp_prepare(rsolve_seq* s, const rsolve_csr* A, const double* dinv, bool f32)
 // Algorithmic bytes of one Arnoldi product (entries counted without padding), w = value width.
 double spmv_bytes(const rsolve_seq* s, double w, bool vout) {
     const double nn = (double)s->n, nz = (double)s->nnz_cur;
-    if (s->sfmt == RSOLVE_SPMV_BANDED && s->cls_ok)   // values, chunk offsets, class numbers
+    if (s->sfmt == RSOLVE_SPMV_BANDED && s->cls_ok)   // values, chunk offsets, 16-bit list starts
         return w * nz + 4.0 * (nn + 1.0) + 2.0 * nn + (vout ? 3.0 : 2.0) * w * nn;
     const double idx = s->sfmt == RSOLVE_SPMV_BANDED ? 2.0 : 4.0;
     return (w + idx) * nz + 4.0 * (nn + 1.0) + (vout ? 3.0 : 2.0) * w * nn;
