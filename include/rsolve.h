@@ -266,9 +266,9 @@ size_t rsolve_state_bytes(rsolve_seq* s);
 
 /*
  * Copy the state of s into `buf` (host memory, any alignment, `bytes` long): a header (format
- * version, the configuration fields the state depends on, n, the counters, a checksum) followed
- * by float64 columns of n values (W, the ring by slot, the last solution, a pending Ritz basis),
- * in native byte order.  *written (nullable) receives the bytes used.  Synchronous; s is
+ * version, the configuration fields the state depends on, n, the counters, a checksum of the
+ * header and the columns) followed by float64 columns of n values (W, the ring by slot, the last
+ * solution, a pending Ritz basis), in native byte order.  *written (nullable) receives the bytes used.  Synchronous; s is
  * unchanged.  Errors: E_INVALID (null pointer, bytes < rsolve_state_bytes(s)), E_DEVICE.
  */
 int rsolve_export_state(rsolve_seq* s, void* buf, size_t bytes, size_t* written);

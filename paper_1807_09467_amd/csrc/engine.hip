@@ -1791,7 +1791,8 @@ namespace {
 
 // The state blob: this header, then float64 columns of n values each: W (k_w columns), the
 // snapshot ring by slot (ring_cols columns), the last solution (if have_x) and a pending Ritz
-// basis (rz_k columns, if rz_pending).  Native byte order; the checksum is FNV-1a over the columns.
+// basis (rz_k columns, if rz_pending).  Native byte order; the checksum is FNV-1a over the header
+// (its checksum field zero) followed by the columns.
 struct StateHeader {
     uint64_t magic;
     uint32_t version, header_bytes;
@@ -1816,10 +1817,14 @@ uint64_t state_columns(const rsolve_seq* s, int ring, int have_x, int rz_pending
     return (uint64_t)k_w + (uint64_t)ring + (uint64_t)have_x + (rz_pending ? (uint64_t)rz_k : 0);
 }
 
-uint64_t fnv1a(const unsigned char* p, size_t n) {
-    uint64_t h = 1469598103934665603ull;
+uint64_t fnv1a(const unsigned char* p, size_t n, uint64_t h = 1469598103934665603ull) {
     for (size_t i = 0; i < n; ++i) h = (h ^ p[i]) * 1099511628211ull;
     return h;
+}
+
+uint64_t state_checksum(StateHeader h, const unsigned char* payload) {
+    h.checksum = 0;
+    return fnv1a(payload, (size_t)h.payload_bytes, fnv1a(reinterpret_cast<const unsigned char*>(&h), sizeof(h)));
 }
 
 }  // namespace
@@ -1887,7 +1892,7 @@ int rsolve_export_state(rsolve_seq* s, void* buf, size_t bytes, size_t* written)
     if (rc == RSOLVE_OK && h.rz_pending) rc = take(s->rz_w, h.rz_k);
     if (rc) return rc;
     HIP_TRY(hipStreamSynchronize(s->stream));
-    h.checksum = fnv1a(static_cast<const unsigned char*>(buf) + sizeof(StateHeader), (size_t)h.payload_bytes);
+    h.checksum = state_checksum(h, static_cast<const unsigned char*>(buf) + sizeof(StateHeader));
     std::memcpy(buf, &h, sizeof(h));
     if (written) *written = need;
     return RSOLVE_OK;
@@ -1927,7 +1932,7 @@ int rsolve_import_state(rsolve_seq* s, const void* buf, size_t bytes) {
         return RSOLVE_E_INVALID;
     }
     const unsigned char* in = static_cast<const unsigned char*>(buf) + sizeof(h);
-    if (fnv1a(in, (size_t)payload) != h.checksum) {
+    if (state_checksum(h, in) != h.checksum) {
         set_err("sequence state checksum mismatch");
         return RSOLVE_E_INVALID;
     }

@@ -155,7 +155,9 @@ def test_bad_states_are_refused(gpu_ctx):
     bad[-5] ^= 0x40                                                   # one payload bit
     hdr = bytearray(blob)
     hdr[0] ^= 1                                                       # the format tag
-    for state in (blob[:-8], blob[:100], bytes(bad), bytes(hdr), b"\0" * len(blob)):
+    sig = bytearray(blob)
+    sig[200] ^= 0x10                                                  # a singular value in the header
+    for state in (blob[:-8], blob[:100], bytes(bad), bytes(hdr), bytes(sig), b"\0" * len(blob)):
         assert b.import_state(state, check=False) == rsolve.E_INVALID
         assert b.recycle() == before
     # another recycle dimension, another size
