@@ -1813,7 +1813,7 @@ int state_ring_cols(const rsolve_seq* s, int64_t count) {
     return (s->X && !ritz_mode(s->cfg)) ? (int)std::min<int64_t>(count, s->cfg.snapshots_s) : 0;
 }
 
-uint64_t state_columns(const rsolve_seq* s, int ring, int have_x, int rz_pending, int rz_k, int k_w) {
+uint64_t state_columns(int ring, int have_x, int rz_pending, int rz_k, int k_w) {
     return (uint64_t)k_w + (uint64_t)ring + (uint64_t)have_x + (rz_pending ? (uint64_t)rz_k : 0);
 }
 
@@ -1831,7 +1831,7 @@ uint64_t state_checksum(StateHeader h, const unsigned char* payload) {
 
 size_t rsolve_state_bytes(rsolve_seq* s) {
     if (!s) return 0;
-    const uint64_t cols = state_columns(s, state_ring_cols(s, s->count), s->have_x ? 1 : 0, s->rz_pending ? 1 : 0, s->rz_k,
+    const uint64_t cols = state_columns(state_ring_cols(s, s->count), s->have_x ? 1 : 0, s->rz_pending ? 1 : 0, s->rz_k,
                                         s->k_w);
     return sizeof(StateHeader) + sizeof(double) * (size_t)s->n * (size_t)cols;
 }
@@ -1925,7 +1925,7 @@ int rsolve_import_state(rsolve_seq* s, const void* buf, size_t bytes) {
                            h.ring_cols == ring && (h.rz_pending == 0 || h.rz_pending == 1) && h.rz_k >= 0 &&
                            h.rz_k <= c.recycle_k && (h.rz_pending || h.rz_k == 0) &&
                            (h.shape_set == 0 || h.shape_set == 1);
-    const uint64_t cols = ranges_ok ? state_columns(s, ring, h.have_x, h.rz_pending, h.rz_k, h.k_w) : 0;
+    const uint64_t cols = ranges_ok ? state_columns(ring, h.have_x, h.rz_pending, h.rz_k, h.k_w) : 0;
     const uint64_t payload = sizeof(double) * (uint64_t)s->n * cols;
     if (!ranges_ok || h.payload_bytes != payload || bytes < sizeof(h) + payload) {
         set_err("inconsistent or truncated sequence state");
