@@ -178,3 +178,37 @@ def test_bad_states_are_refused(gpu_ctx):
     _same_recycle(a, b)
     for s in (a, b, other, small):
         s.close()
+
+
+def test_resume_on_the_batched_path(gpu_ctx):
+    """The one-block batched path (rsolve_solve_batch / rsolve_update_recycle_batch) reads the same
+    state: Q2 32x32 FP64 oblique GMRES(30), k = 5, s = 10, run batched; after the fourth step the
+    state moves to a fresh sequence, and from then on both run in the same batched launches."""
+    import torch
+
+    from paper_1807_09467_amd import rsolve
+    cfg = dict(method="aug_oblique", restart_m=30, recycle_k=5, snapshots_s=10, precond="jacobi")
+    pat, rp, ci, systems = _systems(WL.C2_SMALL, 8, 5, gpu_ctx)
+    a = rsolve.Sequence(pat.n, pat.nnz, device=gpu_ctx, **cfg)
+    b = rsolve.Sequence(pat.n, pat.nnz, device=gpu_ctx, **cfg)
+    x = None
+    for i in range(4):
+        (x, st, status), = rsolve.solve_batch([dict(seq=a, row_ptr=rp, col_idx=ci, val=systems[i][0],
+                                                    b=systems[i][1], x0=x, tol=1e-10, same_pattern=i > 0)])
+        assert status == 0, st
+        rsolve.update_batch([a])
+    b.import_state(a.export_state())
+    _same_recycle(a, b)
+    xa = xb = x
+    for i in range(4, 8):
+        vals, rhs = systems[i]
+        (xa, sa, qa), (xb, sb, qb) = rsolve.solve_batch([
+            dict(seq=a, row_ptr=rp, col_idx=ci, val=vals, b=rhs, x0=xa, tol=1e-10, same_pattern=True),
+            dict(seq=b, row_ptr=rp, col_idx=ci, val=vals, b=rhs, x0=xb, tol=1e-10, same_pattern=i > 4)])
+        assert qa == qb == 0
+        assert torch.equal(xa, xb), i
+        assert sa["iterations"] == sb["iterations"] and sa["k_eff"] == sb["k_eff"], (i, sa, sb)
+        rsolve.update_batch([a, b])
+        _same_recycle(a, b)
+    a.close()
+    b.close()
