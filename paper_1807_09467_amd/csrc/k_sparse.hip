@@ -419,7 +419,7 @@ __global__ __launch_bounds__(BLOCK) void k_to_f32(int64_t count, const double* _
 }
 
 // a = b + s c over n doubles, two per thread (16-byte loads and stores; grid-stride if the grid is
-// capped): the streaming rate the hot kernels are judged against.
+// capped): the streaming rate the hot kernels are measured against.
 __global__ __launch_bounds__(BLOCK) void k_triad(int64_t n, double* __restrict__ a, const double* __restrict__ b,
                                                  const double* __restrict__ c, double s) {
     const int64_t npair = n / 2;
