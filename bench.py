@@ -431,6 +431,9 @@ def bench_batched(args):
     from paper_1807_09467_amd import workload as WL
     dev = torch.device("cuda:0")
     pname, nseq, cfg, tol, desc = BATCH_WORKLOADS[args.workload]
+    if args.batch_size is not None:
+        desc = desc.replace(f"{nseq} independent", f"{args.batch_size} independent")
+        nseq = args.batch_size
     prob = getattr(WL, pname)
     nsteps = args.warmup + args.steps
     asm, gasm, u0s, systems = generate_batched(prob, nseq, nsteps, dev)
@@ -707,6 +710,8 @@ def main():
                     choices=sorted(WORKLOADS) + sorted(BATCH_WORKLOADS) + sorted(SERVE_WORKLOADS)
                     + sorted(PAPER_WORKLOADS))
     ap.add_argument("--sequences", type=int, default=512, help="serving workload: sequences to replay")
+    ap.add_argument("--batch-size", type=int, default=None,
+                    help="batched workload: sequences per batched launch (default: the workload's 256)")
     ap.add_argument("--pool-gb", type=float, default=96.0, help="serving workload: the server's HBM pool")
     ap.add_argument("--workers", type=int, default=4, help="serving workload: large-sequence worker streams")
     ap.add_argument("--nu", type=float, default=1e-2, choices=[1e-1, 1e-2, 1e-3],
