@@ -793,7 +793,8 @@ void residual_and_correct(rsolve_seq* s, const rsolve_csr* A, const double* b, i
 // eps (the k_eff smallest above the cut when `smallest`).  The singular values land in s->hsig;
 // Wr (nullable) receives W row-major with leading dimension ldr.  Synchronous (two read-backs).
 int svd_basis_dev(rsolve_seq* s, const double* X, int64_t ldx, int c, int kmax, bool smallest, double* W_out,
-                  int64_t ldw, double* Wr, int ldr, int* keff_out, int* rank_out, int* nonfinite, int* lu_fail) {
+                  int64_t ldw, double* Wr, int ldr, int* keff_out, int* rank_out, int* nonfinite, int* lu_fail,
+                  float* W32_out = nullptr) {
     hipStream_t stm = s->stream;
     const int64_t n = s->n, ld = s->ld;
     const double* M = X;
@@ -828,7 +829,7 @@ int svd_basis_dev(rsolve_seq* s, const double* X, int64_t ldx, int c, int kmax, 
         const int gb = launch_gram_tn(ld, W_out, ldw, keff, W_out, ldw, keff, s->gpart, s->gblk, stm);
         launch_gram_reduce(s->gpart, gb, keff * keff, ctl_red(s->ctl), stm);
         launch_cholesky(keff, s->ctl, stm);
-        launch_trsm_rows(ld, W_out, ldw, keff, s->ctl, stm, Wr, ldr);
+        launch_trsm_rows(ld, W_out, ldw, keff, s->ctl, stm, Wr, ldr, W32_out);
         HIP_TRY(hipGetLastError());
         rc = read_head(s);
         if (rc) return rc;
@@ -1277,11 +1278,11 @@ int rsolve_solve(rsolve_seq* s, const rsolve_csr* A, const double* b, const doub
             launch_to_rows(n, s->W, ld, k, s->Wr, s->ldr, stm);
             s->wr_ok = true;
         }
-        launch_spmm_rows(n, A->row_ptr, A->col_idx, A->val, s->Wr, s->ldr, k, s->Z, ld, stm);
+        // A W, and in mixed precision its float copy for the inner cycles, in one pass
+        launch_spmm_rows(n, A->row_ptr, A->col_idx, A->val, s->Wr, s->ldr, k, s->Z, ld, stm, ir ? s->Z32 : nullptr);
         const int gb = launch_gram_tn(ld, s->W, ld, k, s->Z, ld, k, s->gpart, s->gblk, stm);
         launch_gram_reduce(s->gpart, gb, k * k, ctl_red(s->ctl), stm);
         launch_small_lu(ctl_red(s->ctl), k, s->ctl, stm);
-        if (ir) launch_to_f32(k * ld, s->Z, s->Z32, stm);
     }
     // a3: r = b - A x0, x0 the caller's or (extrapolation methods, once solutions are stored) the
     // extrapolation of the most recent ones: order min(q, stored), weights (-1)^{j+1} C(order, j)
@@ -1553,8 +1554,9 @@ int rsolve_update_recycle(rsolve_seq* s, const double* x) {
     }
     const int cc = (int)std::min<int64_t>(s->count, c.snapshots_s);
     int keff = 0, rank = 0, bad = 0, lu_fail = 0;
+    // the re-orthonormalised W is also written rounded to float (the inner cycles' copy in mixed precision)
     int rc = svd_basis_dev(s, s->X, ld, cc, c.recycle_k, c.select == RSOLVE_SELECT_SMALLEST, s->W, ld, s->Wr,
-                           s->ldr, &keff, &rank, &bad, &lu_fail);
+                           s->ldr, &keff, &rank, &bad, &lu_fail, s->W32);
     if (rc) return rc;
     for (int i = 0; i < cc; ++i) s->sigma[i] = s->hsig[i];
     s->nsig = cc;
@@ -1566,7 +1568,6 @@ int rsolve_update_recycle(rsolve_seq* s, const double* x) {
     }
     if (keff > 0) {
         s->wr_ok = true;
-        if (s->W32) launch_to_f32(keff * ld, s->W, s->W32, stm);
         HIP_TRY(hipGetLastError());
         if (lu_fail) {
             s->k_w = 0;

@@ -565,7 +565,8 @@ __global__ __launch_bounds__(WAVE) void k_cholesky(int k, Ctl* __restrict__ ctl)
 // register array shifts down after each step.
 template <int K>
 __global__ __launch_bounds__(BLOCK) void k_trsm_rows(int64_t npad, double* __restrict__ W, int64_t ldw, int k,
-                                                     const Ctl* __restrict__ ctl, double* __restrict__ Wr, int ldr) {
+                                                     const Ctl* __restrict__ ctl, double* __restrict__ Wr, int ldr,
+                                                     float* __restrict__ W32) {
     __shared__ double Ls[K * K];
     for (int t = threadIdx.x; t < k * k; t += BLOCK) Ls[(t / k) * K + (t % k)] = ctl->L[(t / k) * KMAX + (t % k)];
     __syncthreads();
@@ -587,6 +588,11 @@ __global__ __launch_bounds__(BLOCK) void k_trsm_rows(int64_t npad, double* __res
 #pragma unroll
     for (int j = 0; j < K; ++j)
         if (j < k) W[(int64_t)j * ldw + r] = w[j];
+    if (W32) {
+#pragma unroll
+        for (int j = 0; j < K; ++j)
+            if (j < k) W32[(int64_t)j * ldw + r] = (float)w[j];
+    }
     if (Wr) {
         // the row-major copy: this row's ldr-wide slot, written as 16-byte stores (zeros past k)
         double* dst = Wr + r * ldr;
@@ -663,12 +669,12 @@ void launch_form_w(int64_t n, int64_t npad, const double* X, int64_t ldx, int c,
 void launch_cholesky(int k, Ctl* ctl, hipStream_t st) { k_cholesky<<<1, WAVE, 0, st>>>(k, ctl); }
 
 void launch_trsm_rows(int64_t npad, double* W, int64_t ldw, int k, const Ctl* ctl, hipStream_t st, double* Wr,
-                      int ldr) {
+                      int ldr, float* W32) {
     const unsigned g = (unsigned)((npad + BLOCK - 1) / BLOCK);
-    if (k <= 8) k_trsm_rows<8><<<g, BLOCK, 0, st>>>(npad, W, ldw, k, ctl, Wr, ldr);
-    else if (k <= 16) k_trsm_rows<16><<<g, BLOCK, 0, st>>>(npad, W, ldw, k, ctl, Wr, ldr);
-    else if (k <= 32) k_trsm_rows<32><<<g, BLOCK, 0, st>>>(npad, W, ldw, k, ctl, Wr, ldr);
-    else k_trsm_rows<64><<<g, BLOCK, 0, st>>>(npad, W, ldw, k, ctl, Wr, ldr);
+    if (k <= 8) k_trsm_rows<8><<<g, BLOCK, 0, st>>>(npad, W, ldw, k, ctl, Wr, ldr, W32);
+    else if (k <= 16) k_trsm_rows<16><<<g, BLOCK, 0, st>>>(npad, W, ldw, k, ctl, Wr, ldr, W32);
+    else if (k <= 32) k_trsm_rows<32><<<g, BLOCK, 0, st>>>(npad, W, ldw, k, ctl, Wr, ldr, W32);
+    else k_trsm_rows<64><<<g, BLOCK, 0, st>>>(npad, W, ldw, k, ctl, Wr, ldr, W32);
 }
 
 }  // namespace rs

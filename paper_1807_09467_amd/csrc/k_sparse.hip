@@ -375,7 +375,7 @@ __device__ __forceinline__ void spmm_row(const I* __restrict__ cs, const V* __re
 __global__ __launch_bounds__(BLOCK) void k_spmm_rows(int64_t n, const int32_t* __restrict__ rp,
                                                      const int32_t* __restrict__ ci, const double* __restrict__ val,
                                                      const double* __restrict__ Wr, int ldr, int c0, int kc,
-                                                     double* __restrict__ Z, int64_t ld) {
+                                                     double* __restrict__ Z, float* __restrict__ Z32, int64_t ld) {
     __shared__ int32_t lci[SPMM_STAGE];
     __shared__ double lval[SPMM_STAGE];
     // XCD-aware rows: each XCD takes a contiguous share, so the W rows a block gathers (the columns
@@ -401,7 +401,10 @@ __global__ __launch_bounds__(BLOCK) void k_spmm_rows(int64_t n, const int32_t* _
     else spmm_row(ci, val, a, e, wb, ldr, acc);
 #pragma unroll
     for (int c = 0; c < 4; ++c)
-        if (4 * sub + c < kc) Z[(int64_t)(c0 + 4 * sub + c) * ld + row] = acc[c];
+        if (4 * sub + c < kc) {
+            Z[(int64_t)(c0 + 4 * sub + c) * ld + row] = acc[c];
+            if (Z32) Z32[(int64_t)(c0 + 4 * sub + c) * ld + row] = (float)acc[c];
+        }
 }
 
 // Wr[r * ldr + c] = W[c * ld + r] for r < n, c < k.
@@ -548,11 +551,11 @@ void launch_spmv(int lpr, int64_t n, const int32_t* rp, const int32_t* ci, const
 }
 
 void launch_spmm_rows(int64_t n, const int32_t* rp, const int32_t* ci, const double* val, const double* Wr, int ldr,
-                      int k, double* Z, int64_t ld, hipStream_t st) {
+                      int k, double* Z, int64_t ld, hipStream_t st, float* Z32) {
     for (int c0 = 0; c0 < k; c0 += 16) {
         const int kc = (k - c0) < 16 ? (k - c0) : 16;
         k_spmm_rows<<<(unsigned)((n + SPMM_ROWS - 1) / SPMM_ROWS), BLOCK, 0, st>>>(n, rp, ci, val, Wr, ldr, c0, kc,
-                                                                                Z, ld);
+                                                                                Z, Z32, ld);
     }
 }
 

@@ -207,12 +207,13 @@ void launch_form_w(int64_t n, int64_t npad, const double* X, int64_t ldx, int c,
 void launch_cholesky(int k, Ctl* ctl, hipStream_t st);
 // W[r, :k] <- L^{-1} W[r, :k]^T (rows < npad)
 // W <- W L^{-T} row by row; also writes the result row-major to Wr (row r at Wr + r ldr) when
-// Wr is not null.
+// Wr is not null, and rounded to float into W32 (same layout as W) when W32 is not null.
 void launch_trsm_rows(int64_t npad, double* W, int64_t ldw, int k, const Ctl* ctl, hipStream_t st,
-                      double* Wr = nullptr, int ldr = 0);
-// Z = A W for W kept row-major (ldr a multiple of 16, 128-byte aligned rows); Z column-major (ld).
+                      double* Wr = nullptr, int ldr = 0, float* W32 = nullptr);
+// Z = A W for W kept row-major (ldr a multiple of 16, 128-byte aligned rows); Z column-major (ld),
+// and rounded to float into Z32 (same layout) when Z32 is not null.
 void launch_spmm_rows(int64_t n, const int32_t* rp, const int32_t* ci, const double* val, const double* Wr, int ldr,
-                      int k, double* Z, int64_t ld, hipStream_t st);
+                      int k, double* Z, int64_t ld, hipStream_t st, float* Z32 = nullptr);
 // Wr (row-major, ldr) = W (column-major, ld), n rows, k columns.
 void launch_to_rows(int64_t n, const double* W, int64_t ld, int k, double* Wr, int ldr, hipStream_t st);
 
