@@ -219,3 +219,20 @@ def test_status_strings(lib):
     for code in (0, 1, -1, -2, -3, -4, -5, -6):
         assert lib.rsolve_status_string(code)
     assert lib.rsolve_status_string(12345) == b"unknown status"
+
+
+def test_binding_fails_loudly_without_the_library(monkeypatch, tmp_path):
+    """No fallback: with the library missing, load() raises instead of computing anything elsewhere."""
+    monkeypatch.setattr(rsolve, "_lib", None)
+    monkeypatch.setattr(rsolve, "LIB_PATH", str(tmp_path / "librsolve.so"))
+    with pytest.raises(RuntimeError, match="not built"):
+        rsolve.load()
+
+
+def test_binding_refuses_host_tensors():
+    """Arguments must be device tensors of the right type, size and layout; nothing is copied silently."""
+    import torch
+    with pytest.raises(TypeError, match="CUDA"):
+        rsolve._ptr(torch.zeros(4, dtype=torch.float64), torch.float64, 4, "b")
+    with pytest.raises(TypeError, match="CUDA"):
+        rsolve._ptr(torch.zeros(4, dtype=torch.float32), torch.float64, 4, "b")
