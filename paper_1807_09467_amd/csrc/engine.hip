@@ -199,6 +199,7 @@ struct rsolve_seq {
     bool rz_pending = false;       // rz_w holds the next W
     double rz_theta[SMAX];         // |theta| of the kept pairs
     int last_steps = 0;            // Arnoldi steps of the last cycle of the last solve
+    int cycle_hint = 0;            // Arnoldi steps of the last cycle that took any (kept across solves)
     // multicolour SSOR: the colouring of the current pattern (device arrays in the workspace, the
     // colour offsets also on the host) and two work vectors
     bool ssor = false;
@@ -1406,13 +1407,14 @@ int rsolve_solve(rsolve_seq* s, const rsolve_csr* A, const double* b, const doub
         if (ir) launch_to_f32(ld, s->wb[0], s->w32[0], stm);
         // Enqueue the cycle in chunks; after chunk c the done flag is copied to pinned memory, and
         // before chunk c + 2 is enqueued the host waits for chunk c (chunk c + 1 keeps the GPU busy),
-        // so at most two chunks of early-exiting kernels follow the step that converges.  Small
-        // systems take two-step chunks: their steps last a few microseconds, so the launches of the
-        // steps after the stop cost as much as real ones (Q1 32x32: 6 and 19 percent more solves/s
-        // recycled and plain); larger ones take four, which waits on the host half as often.
+        // so at most two chunks of early-exiting kernels follow the step that converges.  Chunks of
+        // four steps, or of two when the sequence's last cycle took at most 12: there the steps after
+        // the stop are a large share of the launches (Q1 32x32, about 7 steps a solve: 6 and 19
+        // percent more solves/s recycled and plain), while on longer cycles the extra waits of short
+        // chunks cost more than they save (Q1 64x64 with Jacobi, 29-53 steps: 6 percent slower).
         // with delayed reorthogonalisation step max_steps closes the last column (no product)
         const int nsteps = dg ? max_steps + 1 : max_steps;
-        const int CHUNK = n <= RSOLVE_SMALL_MAX_N ? 2 : 4;
+        const int CHUNK = (s->cycle_hint > 0 && s->cycle_hint <= 12) ? 2 : 4;
         int chunk = 0;
         for (int j0 = 0; j0 < nsteps; j0 += CHUNK, ++chunk) {
             if (chunk >= 2) {
@@ -1471,6 +1473,7 @@ int rsolve_solve(rsolve_seq* s, const rsolve_csr* A, const double* b, const doub
         prof_collect(s, s->hctl->steps);
         its += s->hctl->steps;
         s->last_steps = s->hctl->steps;
+        if (s->hctl->steps > 0) s->cycle_hint = s->hctl->steps;
         cycles += 1;
         gimp = s->hctl->gimp;
         if (its_est < 0 && s->hctl->steps > 0 && gimp <= stop_abs) its_est = its;
